@@ -1,0 +1,575 @@
+/*
+ * oracle.c -- plain, slow, obviously-correct CPU implementation of what the
+ * hybrid MSD-radix / quicksort / merge sort computes.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may call, link or
+ * load this file: only the tests, the smoke check and the CPU-baseline leg of
+ * the benchmark use it.  It shares no code, header or table with the GPU
+ * library.
+ *
+ * Paper: Alghamdi & Alaghband, "High Performance Parallel Sort for Shared and
+ * Distributed Memory MIMD" (arXiv 2003.01216).
+ *
+ * What it computes (all integer, so every result is exact and unique):
+ *   - sorted keys: the ascending rearrangement of the input (Section 3.1,
+ *     Figure 1; ascending order is the reading of the garbled quicksort
+ *     sentence in Section 3.1);
+ *   - stable pairs: keys ascending, equal keys keep their input order
+ *     (merge sort's stability, Section 2.1);
+ *   - the one-step decimal MSD partition into ten buckets (abstract,
+ *     Section 2.1, Section 3.4): the bucket of key k is the decimal digit in
+ *     position D-1 of u = k - beta, where beta = min(min key, 0) and D is the
+ *     number of decimal digits of max(u) (fixed-position digit reading).
+ *
+ * How it computes the sort (following the paper's algorithms, sequentially):
+ *   1. split the array into CHUNKS contiguous partitions, one per "thread" of
+ *      the shared-memory hybrid (Section 3.2, power-of-two thread count);
+ *   2. quicksort each partition (Figure 1c): choose a pivot (median of
+ *      three), partition around it, recurse on the smaller side and loop on
+ *      the larger; tiny ranges by insertion;
+ *   3. non-recursive (bottom-up) merge (Figure 1b, Section 3.2 merge rounds):
+ *      merge neighbouring sorted lists pairwise, carrying an odd last list,
+ *      until one list remains; ties are taken from the left list.
+ * Every element is ordered by the composite (key, original index), a strict
+ * total order, so the result is the stable sort whatever the pivot choice
+ * (the paper's quicksort alone is not stable).
+ *
+ * The "radix mode" runs the paper's fourth model sequentially (Section 3.4):
+ * stable counting scatter into the ten buckets, the same sort inside every
+ * bucket, then the buckets in digit order.  It must equal the plain mode,
+ * which pins that the bucket rule preserves order.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define CHUNKS 16      /* partitions sorted independently before merging */
+#define SMALL_RANGE 16 /* ranges below this are sorted by insertion */
+
+typedef struct {
+    int64_t key;  /* int32 keys are widened exactly */
+    uint64_t idx; /* position in the input: the tie-break */
+} item;
+
+static int item_lt(const item* a, const item* b) {
+    if (a->key != b->key) return a->key < b->key;
+    return a->idx < b->idx;
+}
+
+static void item_swap(item* a, item* b) {
+    item t = *a;
+    *a = *b;
+    *b = t;
+}
+
+/* ---------------------------------------------------------------- quicksort
+ * Figure 1c: pick a pivot V, partition into S1 (< V) and S2 (> V), sort both.
+ * Sorts s[low..high] inclusive. */
+static void insertion_sort(item* s, int64_t low, int64_t high) {
+    for (int64_t i = low + 1; i <= high; i++) {
+        item x = s[i];
+        int64_t j = i - 1;
+        while (j >= low && item_lt(&x, &s[j])) {
+            s[j + 1] = s[j];
+            j--;
+        }
+        s[j + 1] = x;
+    }
+}
+
+static void quicksort(item* s, int64_t low, int64_t high) {
+    while (high - low + 1 > SMALL_RANGE) {
+        /* median of three, moved to s[high] as the pivot */
+        int64_t mid = low + (high - low) / 2;
+        if (item_lt(&s[mid], &s[low])) item_swap(&s[mid], &s[low]);
+        if (item_lt(&s[high], &s[low])) item_swap(&s[high], &s[low]);
+        if (item_lt(&s[mid], &s[high])) item_swap(&s[mid], &s[high]);
+        item v = s[high];
+        /* partition: everything smaller than v goes left of position p */
+        int64_t p = low;
+        for (int64_t j = low; j < high; j++) {
+            if (item_lt(&s[j], &v)) {
+                item_swap(&s[p], &s[j]);
+                p++;
+            }
+        }
+        item_swap(&s[p], &s[high]);
+        /* S1 = [low, p-1], S2 = [p+1, high]; recurse on the smaller one */
+        if (p - low < high - p) {
+            quicksort(s, low, p - 1);
+            low = p + 1;
+        } else {
+            quicksort(s, p + 1, high);
+            high = p - 1;
+        }
+    }
+    insertion_sort(s, low, high);
+}
+
+/* ------------------------------------------------------------------- merge
+ * Merge of two sorted lists a[0..na) and b[0..nb) into out; on equal
+ * elements the left list goes first (merge sort's stability). */
+static void merge_two(const item* a, int64_t na, const item* b, int64_t nb, item* out) {
+    int64_t i = 0, j = 0, k = 0;
+    while (i < na && j < nb) {
+        if (item_lt(&b[j], &a[i]))
+            out[k++] = b[j++];
+        else
+            out[k++] = a[i++];
+    }
+    while (i < na) out[k++] = a[i++];
+    while (j < nb) out[k++] = b[j++];
+}
+
+/* Chunked quicksort followed by the bottom-up merge rounds (Figures 1b, 1c;
+ * Section 3.2).  Sorts s[0..n). */
+static int hybrid_sort(item* s, int64_t n) {
+    if (n < 2) return 0;
+    int64_t nchunks = CHUNKS;
+    if (nchunks > n) nchunks = n;
+    int64_t* starts = (int64_t*)malloc(sizeof(int64_t) * (size_t)(nchunks + 1));
+    if (!starts) return -1;
+    for (int64_t c = 0; c <= nchunks; c++) starts[c] = (n * c) / nchunks;
+    for (int64_t c = 0; c < nchunks; c++) quicksort(s, starts[c], starts[c + 1] - 1);
+
+    item* buf = (item*)malloc(sizeof(item) * (size_t)n);
+    if (!buf) {
+        free(starts);
+        return -1;
+    }
+    item* src = s;
+    item* dst = buf;
+    int64_t nruns = nchunks;
+    while (nruns > 1) {
+        int64_t r = 0, w = 0;
+        for (; r + 1 < nruns; r += 2) {
+            merge_two(src + starts[r], starts[r + 1] - starts[r], src + starts[r + 1],
+                      starts[r + 2] - starts[r + 1], dst + starts[r]);
+            starts[w++] = starts[r];
+        }
+        if (r < nruns) { /* odd list carried to the next round */
+            memcpy(dst + starts[r], src + starts[r], sizeof(item) * (size_t)(starts[r + 1] - starts[r]));
+            starts[w++] = starts[r];
+        }
+        starts[w] = n;
+        nruns = w;
+        item* t = src;
+        src = dst;
+        dst = t;
+    }
+    if (src != s) memcpy(s, src, sizeof(item) * (size_t)n);
+    free(buf);
+    free(starts);
+    return 0;
+}
+
+/* ------------------------------------------------------- decimal digit plan
+ * Section 3.4 divides the data into ten parts by the most significant digit.
+ * Reading: beta = min(min key, 0); u = k - beta (exact as unsigned 64-bit);
+ * D = number of decimal digits of max u (1 for 0); the bucket of k is
+ * floor(u / 10^(D-1)), computed here with a real division. */
+static const uint64_t POW10[20] = {1ULL,
+                                   10ULL,
+                                   100ULL,
+                                   1000ULL,
+                                   10000ULL,
+                                   100000ULL,
+                                   1000000ULL,
+                                   10000000ULL,
+                                   100000000ULL,
+                                   1000000000ULL,
+                                   10000000000ULL,
+                                   100000000000ULL,
+                                   1000000000000ULL,
+                                   10000000000000ULL,
+                                   100000000000000ULL,
+                                   1000000000000000ULL,
+                                   10000000000000000ULL,
+                                   100000000000000000ULL,
+                                   1000000000000000000ULL,
+                                   10000000000000000000ULL};
+
+static int decimal_digits(uint64_t x) {
+    int d = 1;
+    while (d < 20 && x >= POW10[d]) d++;
+    return d;
+}
+
+typedef struct {
+    int64_t beta;
+    int32_t D;
+    uint64_t p;
+} plan;
+
+static plan make_plan(int64_t mn, int64_t mx) {
+    plan pl;
+    pl.beta = mn < 0 ? mn : 0;
+    uint64_t top = (uint64_t)mx - (uint64_t)pl.beta;
+    pl.D = decimal_digits(top);
+    pl.p = POW10[pl.D - 1];
+    return pl;
+}
+
+static int bucket_of(const plan* pl, int64_t k) {
+    uint64_t u = (uint64_t)k - (uint64_t)pl->beta;
+    return (int)(u / pl->p);
+}
+
+/* ------------------------------------------------------- exported: helpers */
+static item* load_items_i32(const int32_t* k, int64_t n) {
+    item* s = (item*)malloc(sizeof(item) * (size_t)(n > 0 ? n : 1));
+    if (!s) return NULL;
+    for (int64_t i = 0; i < n; i++) {
+        s[i].key = k[i];
+        s[i].idx = (uint64_t)i;
+    }
+    return s;
+}
+
+static item* load_items_i64(const int64_t* k, int64_t n) {
+    item* s = (item*)malloc(sizeof(item) * (size_t)(n > 0 ? n : 1));
+    if (!s) return NULL;
+    for (int64_t i = 0; i < n; i++) {
+        s[i].key = k[i];
+        s[i].idx = (uint64_t)i;
+    }
+    return s;
+}
+
+/* Plan of an array: *beta, *D, *p.  n == 0 gives beta 0, D 1, p 1. */
+static plan plan_of(const item* s, int64_t n) {
+    if (n == 0) return make_plan(0, 0);
+    int64_t mn = s[0].key, mx = s[0].key;
+    for (int64_t i = 1; i < n; i++) {
+        if (s[i].key < mn) mn = s[i].key;
+        if (s[i].key > mx) mx = s[i].key;
+    }
+    return make_plan(mn, mx);
+}
+
+/* bounds[b] = number of keys whose bucket is below b, b = 0..10 */
+static void bounds_of(const item* s, int64_t n, const plan* pl, int64_t bounds[11]) {
+    int64_t cnt[10] = {0};
+    for (int64_t i = 0; i < n; i++) cnt[bucket_of(pl, s[i].key)]++;
+    bounds[0] = 0;
+    for (int b = 0; b < 10; b++) bounds[b + 1] = bounds[b] + cnt[b];
+}
+
+/* Stable counting scatter of s[0..n) into the ten buckets (the master's
+ * one-step MSD radix, Section 3.4).  out must hold n items. */
+static void stable_scatter(const item* s, int64_t n, const plan* pl, const int64_t bounds[11], item* out) {
+    int64_t next[10];
+    for (int b = 0; b < 10; b++) next[b] = bounds[b];
+    for (int64_t i = 0; i < n; i++) out[next[bucket_of(pl, s[i].key)]++] = s[i];
+}
+
+/* ------------------------------------------------------- exported functions */
+int oracle_plan_i32(const int32_t* k, int64_t n, int64_t* beta, int32_t* D, uint64_t* p) {
+    item* s = load_items_i32(k, n);
+    if (!s) return -1;
+    plan pl = plan_of(s, n);
+    *beta = pl.beta;
+    *D = pl.D;
+    *p = pl.p;
+    free(s);
+    return 0;
+}
+
+int oracle_plan_i64(const int64_t* k, int64_t n, int64_t* beta, int32_t* D, uint64_t* p) {
+    item* s = load_items_i64(k, n);
+    if (!s) return -1;
+    plan pl = plan_of(s, n);
+    *beta = pl.beta;
+    *D = pl.D;
+    *p = pl.p;
+    free(s);
+    return 0;
+}
+
+int oracle_bounds_i32(const int32_t* k, int64_t n, int64_t bounds[11]) {
+    item* s = load_items_i32(k, n);
+    if (!s) return -1;
+    plan pl = plan_of(s, n);
+    bounds_of(s, n, &pl, bounds);
+    free(s);
+    return 0;
+}
+
+int oracle_bounds_i64(const int64_t* k, int64_t n, int64_t bounds[11]) {
+    item* s = load_items_i64(k, n);
+    if (!s) return -1;
+    plan pl = plan_of(s, n);
+    bounds_of(s, n, &pl, bounds);
+    free(s);
+    return 0;
+}
+
+/* Plain mode: chunked quicksort + bottom-up merge on (key, index). */
+int oracle_sort_keys_i32(int32_t* k, int64_t n) {
+    item* s = load_items_i32(k, n);
+    if (!s) return -1;
+    if (hybrid_sort(s, n)) {
+        free(s);
+        return -1;
+    }
+    for (int64_t i = 0; i < n; i++) k[i] = (int32_t)s[i].key;
+    free(s);
+    return 0;
+}
+
+int oracle_sort_keys_i64(int64_t* k, int64_t n) {
+    item* s = load_items_i64(k, n);
+    if (!s) return -1;
+    if (hybrid_sort(s, n)) {
+        free(s);
+        return -1;
+    }
+    for (int64_t i = 0; i < n; i++) k[i] = s[i].key;
+    free(s);
+    return 0;
+}
+
+/* Stable key + payload sort: the payload travels with its key. */
+int oracle_sort_pairs_i32(int32_t* k, uint32_t* v, int64_t n) {
+    item* s = load_items_i32(k, n);
+    if (!s) return -1;
+    uint32_t* v0 = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1));
+    if (!v0) {
+        free(s);
+        return -1;
+    }
+    memcpy(v0, v, sizeof(uint32_t) * (size_t)n);
+    if (hybrid_sort(s, n)) {
+        free(s);
+        free(v0);
+        return -1;
+    }
+    for (int64_t i = 0; i < n; i++) {
+        k[i] = (int32_t)s[i].key;
+        v[i] = v0[s[i].idx];
+    }
+    free(v0);
+    free(s);
+    return 0;
+}
+
+/* Radix mode (Section 3.4 run sequentially): stable scatter into ten buckets,
+ * the plain sort inside each bucket, buckets in digit order.  Also returns
+ * the bucket bounds when bounds != NULL. */
+static int radix_mode(item* s, int64_t n, int64_t* bounds_out) {
+    plan pl = plan_of(s, n);
+    int64_t bounds[11];
+    bounds_of(s, n, &pl, bounds);
+    item* t = (item*)malloc(sizeof(item) * (size_t)(n > 0 ? n : 1));
+    if (!t) return -1;
+    stable_scatter(s, n, &pl, bounds, t);
+    for (int b = 0; b < 10; b++) {
+        if (hybrid_sort(t + bounds[b], bounds[b + 1] - bounds[b])) {
+            free(t);
+            return -1;
+        }
+    }
+    memcpy(s, t, sizeof(item) * (size_t)n);
+    free(t);
+    if (bounds_out)
+        for (int b = 0; b < 11; b++) bounds_out[b] = bounds[b];
+    return 0;
+}
+
+int oracle_radix_sort_keys_i32(int32_t* k, int64_t n, int64_t* bounds) {
+    item* s = load_items_i32(k, n);
+    if (!s) return -1;
+    if (radix_mode(s, n, bounds)) {
+        free(s);
+        return -1;
+    }
+    for (int64_t i = 0; i < n; i++) k[i] = (int32_t)s[i].key;
+    free(s);
+    return 0;
+}
+
+int oracle_radix_sort_keys_i64(int64_t* k, int64_t n, int64_t* bounds) {
+    item* s = load_items_i64(k, n);
+    if (!s) return -1;
+    if (radix_mode(s, n, bounds)) {
+        free(s);
+        return -1;
+    }
+    for (int64_t i = 0; i < n; i++) k[i] = s[i].key;
+    free(s);
+    return 0;
+}
+
+int oracle_radix_sort_pairs_i32(int32_t* k, uint32_t* v, int64_t n, int64_t* bounds) {
+    item* s = load_items_i32(k, n);
+    if (!s) return -1;
+    uint32_t* v0 = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1));
+    if (!v0) {
+        free(s);
+        return -1;
+    }
+    memcpy(v0, v, sizeof(uint32_t) * (size_t)n);
+    if (radix_mode(s, n, bounds)) {
+        free(s);
+        free(v0);
+        return -1;
+    }
+    for (int64_t i = 0; i < n; i++) {
+        k[i] = (int32_t)s[i].key;
+        v[i] = v0[s[i].idx];
+    }
+    free(v0);
+    free(s);
+    return 0;
+}
+
+/* The intermediate after the one-step MSD radix alone: the stable scatter of
+ * the input into bucket order (vals may be NULL).  Writes bounds[11]. */
+static int scatter_only(item* s, int64_t n, int64_t bounds[11]) {
+    plan pl = plan_of(s, n);
+    bounds_of(s, n, &pl, bounds);
+    item* t = (item*)malloc(sizeof(item) * (size_t)(n > 0 ? n : 1));
+    if (!t) return -1;
+    stable_scatter(s, n, &pl, bounds, t);
+    memcpy(s, t, sizeof(item) * (size_t)n);
+    free(t);
+    return 0;
+}
+
+int oracle_scatter_i32(int32_t* k, uint32_t* v, int64_t n, int64_t bounds[11]) {
+    item* s = load_items_i32(k, n);
+    if (!s) return -1;
+    uint32_t* v0 = NULL;
+    if (v) {
+        v0 = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1));
+        if (!v0) {
+            free(s);
+            return -1;
+        }
+        memcpy(v0, v, sizeof(uint32_t) * (size_t)n);
+    }
+    if (scatter_only(s, n, bounds)) {
+        free(s);
+        free(v0);
+        return -1;
+    }
+    for (int64_t i = 0; i < n; i++) {
+        k[i] = (int32_t)s[i].key;
+        if (v) v[i] = v0[s[i].idx];
+    }
+    free(v0);
+    free(s);
+    return 0;
+}
+
+int oracle_scatter_i64(int64_t* k, int64_t n, int64_t bounds[11]) {
+    item* s = load_items_i64(k, n);
+    if (!s) return -1;
+    if (scatter_only(s, n, bounds)) {
+        free(s);
+        return -1;
+    }
+    for (int64_t i = 0; i < n; i++) k[i] = s[i].key;
+    free(s);
+    return 0;
+}
+
+/* The intermediate after the local sorts: the input is scattered into
+ * buckets, then every bucket is cut into consecutive partitions of `tile`
+ * keys starting at the bucket's first key, and each partition is sorted
+ * (stably) on its own (Section 3.4: each thread sorts its partition). */
+int oracle_bucket_tiles_i32(int32_t* k, uint32_t* v, int64_t n, int64_t tile, int64_t bounds[11]) {
+    if (tile < 1) return -1;
+    item* s = load_items_i32(k, n);
+    if (!s) return -1;
+    uint32_t* v0 = NULL;
+    if (v) {
+        v0 = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1));
+        if (!v0) {
+            free(s);
+            return -1;
+        }
+        memcpy(v0, v, sizeof(uint32_t) * (size_t)n);
+    }
+    if (scatter_only(s, n, bounds)) {
+        free(s);
+        free(v0);
+        return -1;
+    }
+    for (int b = 0; b < 10; b++) {
+        for (int64_t t = bounds[b]; t < bounds[b + 1]; t += tile) {
+            int64_t e = t + tile < bounds[b + 1] ? t + tile : bounds[b + 1];
+            quicksort(s, t, e - 1);
+        }
+    }
+    for (int64_t i = 0; i < n; i++) {
+        k[i] = (int32_t)s[i].key;
+        if (v) v[i] = v0[s[i].idx];
+    }
+    free(v0);
+    free(s);
+    return 0;
+}
+
+int oracle_bucket_tiles_i64(int64_t* k, int64_t n, int64_t tile, int64_t bounds[11]) {
+    if (tile < 1) return -1;
+    item* s = load_items_i64(k, n);
+    if (!s) return -1;
+    if (scatter_only(s, n, bounds)) {
+        free(s);
+        return -1;
+    }
+    for (int b = 0; b < 10; b++) {
+        for (int64_t t = bounds[b]; t < bounds[b + 1]; t += tile) {
+            int64_t e = t + tile < bounds[b + 1] ? t + tile : bounds[b + 1];
+            quicksort(s, t, e - 1);
+        }
+    }
+    for (int64_t i = 0; i < n; i++) k[i] = s[i].key;
+    free(s);
+    return 0;
+}
+
+/* Segmented: every [off[i], off[i+1]) sorted on its own; bounds (may be
+ * NULL) receives eleven bucket bounds per segment, relative to its start. */
+int oracle_sort_segmented_i32(int32_t* k, const int64_t* off, int64_t nseg, int64_t* bounds) {
+    for (int64_t g = 0; g < nseg; g++) {
+        int64_t a = off[g], m = off[g + 1] - off[g];
+        if (m < 0) return -1;
+        if (bounds && oracle_bounds_i32(k + a, m, bounds + 11 * g)) return -1;
+        if (oracle_sort_keys_i32(k + a, m)) return -1;
+    }
+    return 0;
+}
+
+int oracle_sort_segmented_i64(int64_t* k, const int64_t* off, int64_t nseg, int64_t* bounds) {
+    for (int64_t g = 0; g < nseg; g++) {
+        int64_t a = off[g], m = off[g + 1] - off[g];
+        if (m < 0) return -1;
+        if (bounds && oracle_bounds_i64(k + a, m, bounds + 11 * g)) return -1;
+        if (oracle_sort_keys_i64(k + a, m)) return -1;
+    }
+    return 0;
+}
+
+/* Order statistic by definition: the j-th smallest key o[j] is the value x
+ * with #{k < x} <= j < #{k <= x}.  Returns both counts for a given x. */
+void oracle_count_lt_le_i32(const int32_t* k, int64_t n, int32_t x, int64_t* lt, int64_t* le) {
+    int64_t a = 0, b = 0;
+    for (int64_t i = 0; i < n; i++) {
+        a += k[i] < x;
+        b += k[i] <= x;
+    }
+    *lt = a;
+    *le = b;
+}
+
+void oracle_count_lt_le_i64(const int64_t* k, int64_t n, int64_t x, int64_t* lt, int64_t* le) {
+    int64_t a = 0, b = 0;
+    for (int64_t i = 0; i < n; i++) {
+        a += k[i] < x;
+        b += k[i] <= x;
+    }
+    *lt = a;
+    *le = b;
+}
