@@ -1,0 +1,143 @@
+/*
+ * hsort.h -- C ABI of the MI355X (gfx950) hybrid MSD-radix / tile-sort /
+ * merge-path integer sort.
+ *
+ * Method (Alghamdi & Alaghband, "High Performance Parallel Sort for Shared
+ * and Distributed Memory MIMD", arXiv 2003.01216, Section 3.4 with Sections
+ * 3.1-3.2): a one-step decimal most-significant-digit partition of the keys
+ * into ten non-overlapping buckets, a local sort of each bucket's partitions,
+ * then non-recursive (bottom-up) merge rounds of the sorted runs inside each
+ * bucket.  The buckets' order equals the key order, so the concatenation of
+ * the sorted buckets is the sorted array (Section 3.4: each sorted bucket goes
+ * "to its place in the original array").
+ *
+ * Conventions for every entry point:
+ *   - keys, vals, offsets and scratch are DEVICE pointers (hipMalloc'd or
+ *     torch tensors); `stream` is a hipStream_t (NULL = the null stream).
+ *   - sorts are in place, ascending, in signed integer order.
+ *   - work is enqueued asynchronously on `stream`; the caller synchronises.
+ *   - the library allocates no device memory: it works in the caller's
+ *     `scratch` buffer of at least hsort_scratch_bytes(...) bytes.  Scratch
+ *     contents are undefined after a call, except the bucket bounds (see
+ *     hsort_bounds_offset) and the error word read by hsort_check.
+ *   - argument errors (null pointer with n > 0, negative sizes, n or a
+ *     segment above HSORT_MAX_KEYS, scratch too small) are returned
+ *     synchronously before anything is enqueued; n == 0 or nseg == 0 is a
+ *     no-op returning HSORT_OK.  A failed launch returns HSORT_ERR_HIP with a
+ *     message in hsort_last_error().  Invalid segment offsets are detected on
+ *     the device: every kernel of the call then does nothing, and
+ *     hsort_check() reports HSORT_ERR_INVALID.  No C++ exception crosses
+ *     this boundary.
+ *   - calls on distinct scratch buffers may run concurrently on distinct
+ *     streams; the host-side state (configuration, timing records) is
+ *     guarded by a mutex.
+ */
+#ifndef HSORT_H
+#define HSORT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HSORT_OK = 0,
+    HSORT_ERR_INVALID = 1,     /* bad argument or bad offsets */
+    HSORT_ERR_SCRATCH = 2,     /* scratch buffer too small */
+    HSORT_ERR_HIP = 3,         /* a HIP runtime call failed */
+    HSORT_ERR_UNSUPPORTED = 4, /* size beyond HSORT_MAX_KEYS */
+    HSORT_ERR_BUDGET = 5       /* serving layer: request larger than the memory budget */
+} hsort_status;
+
+typedef enum {
+    HSORT_KEYS_I32 = 0,      /* int32 keys */
+    HSORT_KEYS_I64 = 1,      /* int64 keys */
+    HSORT_PAIRS_I32_U32 = 2, /* int32 keys + uint32 payload, stable */
+    HSORT_SEG_I32 = 3,       /* segmented int32 keys */
+    HSORT_SEG_I64 = 4        /* segmented int64 keys */
+} hsort_kind;
+
+/* Largest number of keys in one call (and in one segment). */
+#define HSORT_MAX_KEYS ((int64_t)2147483647)
+
+/* Bytes of scratch a call of `kind` over n keys in nseg segments needs
+ * (nseg is ignored for the non-segmented kinds).  Pure host function. */
+size_t hsort_scratch_bytes(int kind, int64_t n, int64_t nseg);
+
+/* Sorts keys[0..n) ascending (Section 3.4 method). */
+int hsort_keys_i32(int32_t* keys, int64_t n, void* scratch, size_t scratch_bytes, void* stream);
+int hsort_keys_i64(int64_t* keys, int64_t n, void* scratch, size_t scratch_bytes, void* stream);
+
+/* Sorts keys[0..n) ascending and permutes vals[0..n) with them.  Stable:
+ * equal keys keep their input order (merge sort's stability, Section 2.1). */
+int hsort_pairs(int32_t* keys, uint32_t* vals, int64_t n, void* scratch, size_t scratch_bytes, void* stream);
+
+/* Sorts each segment keys[offsets[i] .. offsets[i+1]) independently, for
+ * i in [0, nseg).  offsets: nseg+1 device int64, non-decreasing, with
+ * 0 <= offsets[0] and offsets[nseg] <= n (n = length of `keys`); keys
+ * outside [offsets[0], offsets[nseg]) are untouched.  Every segment gets the
+ * full method; the independent buckets of all segments are scheduled as one
+ * flat work list.  max_seg_len: an upper bound on the largest segment that
+ * the caller knows (it bounds the number of merge rounds launched), or 0 if
+ * unknown. */
+int hsort_segmented(int32_t* keys, int64_t n, const int64_t* offsets, int64_t nseg, int64_t max_seg_len,
+                    void* scratch, size_t scratch_bytes, void* stream);
+int hsort_segmented_i64(int64_t* keys, int64_t n, const int64_t* offsets, int64_t nseg, int64_t max_seg_len,
+                        void* scratch, size_t scratch_bytes, void* stream);
+
+/* Byte offset inside scratch of the bucket bounds the last call on that
+ * scratch left behind: int64 bounds[nseg][11] (nseg = 1 for the plain
+ * kinds), bounds[s][b] = number of keys of segment s whose one-step decimal
+ * MSD bucket (Section 3.4) is below b.  Valid after the call completes and
+ * until the scratch is reused. */
+size_t hsort_bounds_offset(int kind, int64_t n, int64_t nseg);
+
+/* Synchronises `stream` and reads the device-side error word of the last
+ * call that used `scratch`: HSORT_ERR_INVALID if its offsets were invalid,
+ * HSORT_ERR_HIP if the synchronisation failed, HSORT_OK otherwise. */
+int hsort_check(const void* scratch, void* stream);
+
+/* Message for the last error on the calling thread ("" if none). */
+const char* hsort_last_error(void);
+
+/* ---------------------------------------------------------------- tuning
+ * The shape of the local sort and of the merge, per key kind.  tile = keys
+ * per local-sort partition (T); merge_nv = outputs per merge workgroup;
+ * small_max = segments up to this size are sorted wholly in LDS.  Only the
+ * compiled shapes are accepted (HSORT_ERR_UNSUPPORTED otherwise); the
+ * current values are returned by hsort_get_config. */
+int hsort_set_config(int kind, int64_t tile, int64_t merge_nv, int64_t small_max);
+int hsort_get_config(int kind, int64_t* tile, int64_t* merge_nv, int64_t* small_max);
+
+/* ----------------------------------------------------- test observability
+ * Runs the plain-sort pipeline (kinds HSORT_KEYS_I32, HSORT_KEYS_I64,
+ * HSORT_PAIRS_I32_U32) only up to `stage` and leaves that intermediate in
+ * keys (and vals): 1 = after the one-step stable bucket scatter (keys in
+ * bucket order, input order inside each bucket); 2 = after the local sorts
+ * (every `tile`-key partition of every bucket, counted from the bucket's
+ * first key, sorted on its own); 3 = the full sort.  vals may be NULL
+ * except for pairs. */
+int hsort_debug_stage(int kind, void* keys, uint32_t* vals, int64_t n, int stage, void* scratch,
+                      size_t scratch_bytes, void* stream);
+
+/* Per-kernel timing.  While enabled, every kernel launch of the library is
+ * bracketed by HIP events recorded on the call's stream.  hsort_timing_read
+ * synchronises those events and writes, for each kernel name, the number of
+ * launches, the total milliseconds and the algorithmic HBM bytes those
+ * launches had to move, as text lines "name launches total_ms bytes"; it
+ * returns the number of bytes written (or needed, if cap is too small) and
+ * clears the records. */
+int hsort_timing_enable(int on);
+int64_t hsort_timing_read(char* out, int64_t cap);
+
+/* Plain device-to-device copy of `bytes` (multiple of 16) with the library's
+ * copy kernel, used to calibrate hardware byte counters. */
+int hsort_copy(const void* src, void* dst, int64_t bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HSORT_H */

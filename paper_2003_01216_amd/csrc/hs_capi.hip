@@ -1,0 +1,523 @@
+// hs_capi.hip -- the C ABI (include/hsort.h): argument checks, the scratch
+// layout, the launch sequence of one call, per-kernel timing records.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/hsort.h"
+#include "hs_launch.h"
+
+using namespace hs;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+// ------------------------------------------------------------- configuration
+struct Config {
+    int64_t tile;       // local-sort tile (T)
+    int64_t merge_nv;   // outputs per merge workgroup
+    int64_t small_max;  // segments up to this size never leave LDS
+};
+
+std::mutex g_mu;
+// index: 0 = int32 keys, 1 = int64 keys, 2 = int32 pairs
+Config g_cfg[3] = {{8192, 4096, 8192}, {4096, 4096, 4096}, {4096, 4096, 4096}};
+
+int cfg_index(int kind) {
+    switch (kind) {
+        case HSORT_KEYS_I32:
+        case HSORT_SEG_I32:
+            return 0;
+        case HSORT_KEYS_I64:
+        case HSORT_SEG_I64:
+            return 1;
+        case HSORT_PAIRS_I32_U32:
+            return 2;
+    }
+    return -1;
+}
+
+Config get_cfg(int kind) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    return g_cfg[cfg_index(kind)];
+}
+
+bool tile_shape_ok(int ci, int64_t t) {
+    if (ci == 1 || ci == 2) return t == 8192 || t == 4096 || t == 2048 || t == 256;
+    return t == 8192 || t == 4096 || t == 2048 || t == 256;
+}
+
+// --------------------------------------------------------------- timing
+struct Rec {
+    std::string name;
+    hipEvent_t a, b;
+    double bytes;
+};
+bool g_timing = false;
+std::vector<Rec> g_recs;
+
+struct Timer {
+    hipStream_t st;
+    bool on;
+    std::string name;
+    double bytes;
+    hipEvent_t a = nullptr, b = nullptr;
+    Timer(hipStream_t s, const char* n, double by) : st(s), name(n), bytes(by) {
+        {
+            std::lock_guard<std::mutex> lk(g_mu);
+            on = g_timing;
+        }
+        if (on) {
+            hipEventCreate(&a);
+            hipEventCreate(&b);
+            hipEventRecord(a, st);
+        }
+    }
+    ~Timer() {
+        if (!on) return;
+        hipEventRecord(b, st);
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_recs.push_back({name, a, b, bytes});
+    }
+};
+
+// ------------------------------------------------------------ scratch layout
+constexpr size_t kAlign = 256;
+size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+struct Layout {
+    // byte offsets into scratch
+    size_t err, own_off, skeys, svals, segmin, segmax, plans, tilecnt, tilepre, bounds, counts, pos, bstart, bsize, tsc,
+        tsp, mcc, msp, split, part32, part64, total;
+    // item bounds
+    int64_t large_bound, tiles_bound, buckets, ts_bound, chunks_bound;
+};
+
+Layout make_layout(int kind, int64_t n, int64_t nseg, const Config& c) {
+    // A plain sort may be forced through the full pipeline (small_max 0), so
+    // at least one segment is always counted as large.
+    const bool seg = kind == HSORT_SEG_I32 || kind == HSORT_SEG_I64;
+    if (!seg) nseg = 1;
+    const size_t ksz = (kind == HSORT_KEYS_I64 || kind == HSORT_SEG_I64) ? 8 : 4;
+    const bool pairs = kind == HSORT_PAIRS_I32_U32;
+    Layout L{};
+    L.large_bound = std::min<int64_t>(nseg, std::max<int64_t>(1, n / (c.small_max + 1)));
+    L.tiles_bound = cdiv(n, kHistTile) + L.large_bound;
+    L.buckets = 10 * nseg;
+    L.ts_bound = cdiv(n, c.tile) + 10 * L.large_bound;
+    L.chunks_bound = cdiv(n, c.merge_nv) + 10 * L.large_bound;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o += up(bytes);
+        return at;
+    };
+    L.err = take(8);  // error word at offset 0 (hsort_check reads it there)
+    L.own_off = take(16);
+    L.bounds = take(sizeof(int64_t) * 11 * nseg);
+    L.skeys = take(ksz * n);
+    L.svals = pairs ? take(4 * n) : 0;
+    L.segmin = take(ksz * nseg);
+    L.segmax = take(ksz * nseg);
+    L.plans = take((ksz == 8 ? sizeof(DigitPlan<int64_t>) : sizeof(DigitPlan<int32_t>)) * nseg);
+    L.tilecnt = take(4 * nseg);
+    L.tilepre = take(4 * (nseg + 1));
+    L.counts = take(4 * 10 * L.tiles_bound);
+    L.pos = take(8 * (10 * L.tiles_bound + 1));
+    L.bstart = take(8 * L.buckets);
+    L.bsize = take(8 * L.buckets);
+    L.tsc = take(4 * L.buckets);
+    L.tsp = take(4 * (L.buckets + 1));
+    L.mcc = take(4 * L.buckets);
+    L.msp = take(4 * (L.buckets + 1));
+    L.split = take(4 * (L.chunks_bound + 1));
+    const int64_t p32 = std::max(scan_partial_count(nseg), scan_partial_count(L.buckets));
+    L.part32 = take(4 * p32);
+    L.part64 = take(8 * scan_partial_count(10 * L.tiles_bound));
+    L.total = o;
+    return L;
+}
+
+template <typename K>
+Work<K> make_work(const Layout& L, char* scr, K* keys, uint32_t* vals, const int64_t* off, int64_t n, int64_t nseg,
+                  const Config& c, int64_t small_max) {
+    Work<K> w{};
+    w.keys = keys;
+    w.vals = vals;
+    w.skeys = (K*)(scr + L.skeys);
+    w.svals = vals ? (uint32_t*)(scr + L.svals) : nullptr;
+    w.off = off ? off : (const int64_t*)(scr + L.own_off);
+    w.n = n;
+    w.nseg = (int32_t)nseg;
+    w.segmin = (K*)(scr + L.segmin);
+    w.segmax = (K*)(scr + L.segmax);
+    w.plans = (DigitPlan<K>*)(scr + L.plans);
+    w.tilecnt = (int32_t*)(scr + L.tilecnt);
+    w.tilepre = (int32_t*)(scr + L.tilepre);
+    w.bounds_out = (int64_t*)(scr + L.bounds);
+    w.counts = (uint32_t*)(scr + L.counts);
+    w.pos = (int64_t*)(scr + L.pos);
+    w.bstart = (int64_t*)(scr + L.bstart);
+    w.bsize = (int64_t*)(scr + L.bsize);
+    w.tsc = (int32_t*)(scr + L.tsc);
+    w.tsp = (int32_t*)(scr + L.tsp);
+    w.mcc = (int32_t*)(scr + L.mcc);
+    w.msp = (int32_t*)(scr + L.msp);
+    w.split = (int32_t*)(scr + L.split);
+    w.err = (uint32_t*)(scr + L.err);
+    w.tile = (int32_t)c.tile;
+    w.nv = (int32_t)c.merge_nv;
+    w.small_max = small_max;
+    return w;
+}
+
+// ------------------------------------------------------------- dispatchers
+template <typename K, bool PAIRS>
+hipError_t tilesort_by_shape(int64_t tile, const Work<K>& w, int64_t items, hipStream_t st) {
+    switch (tile) {
+        case 8192:
+            return launch_tilesort<K, PAIRS, 512, 16>(w, items, st);
+        case 4096:
+            return launch_tilesort<K, PAIRS, 256, 16>(w, items, st);
+        case 2048:
+            return launch_tilesort<K, PAIRS, 256, 8>(w, items, st);
+        case 256:
+            return launch_tilesort<K, PAIRS, 64, 4>(w, items, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename K, bool PAIRS>
+hipError_t small_by_shape(int64_t cap, const Work<K>& w, int64_t lo, int64_t hi, int64_t segs, hipStream_t st) {
+    switch (cap) {
+        case 8192:
+            return launch_small<K, PAIRS, 512, 16>(w, lo, hi, segs, st);
+        case 4096:
+            return launch_small<K, PAIRS, 256, 16>(w, lo, hi, segs, st);
+        case 2048:
+            return launch_small<K, PAIRS, 256, 8>(w, lo, hi, segs, st);
+        case 256:
+            return launch_small<K, PAIRS, 64, 4>(w, lo, hi, segs, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename K, bool PAIRS>
+hipError_t merge_by_shape(int64_t nv, const Work<K>& w, int pass, int64_t chunks, hipStream_t st) {
+    if (nv == 4096) return launch_merge<K, PAIRS, 256, 16>(w, pass, chunks, st);
+    return hipErrorInvalidValue;
+}
+
+// Small-segment size classes: (lo, hi] -> LDS capacity.
+struct SmallClass {
+    int64_t lo, hi, cap;
+};
+std::vector<SmallClass> small_classes(int64_t small_max) {
+    std::vector<SmallClass> v;
+    int64_t lo = -1;
+    for (int64_t cap : {256, 2048, 4096, 8192}) {
+        if (lo >= small_max) break;
+        const int64_t hi = std::min(cap, small_max);
+        if (hi > lo) v.push_back({lo, hi, cap});
+        lo = hi;
+    }
+    return v;
+}
+
+#define HS_TRY(expr)                                                                         \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess) return fail(HSORT_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// One call: plain (off == nullptr, one segment) or segmented.
+template <typename K, bool PAIRS>
+int run(int kind, K* keys, uint32_t* vals, int64_t n, const int64_t* off, int64_t nseg, int64_t max_seg_len,
+        void* scratch, size_t scratch_bytes, hipStream_t st, int stage, int64_t small_override) {
+    const Config c = get_cfg(kind);
+    const bool seg = off != nullptr;
+    if (!seg) nseg = 1;
+    const Layout L = make_layout(kind, n, nseg, c);
+    if (scratch_bytes < L.total)
+        return fail(HSORT_ERR_SCRATCH, "scratch too small: need " + std::to_string(L.total) + " bytes, got " +
+                                           std::to_string(scratch_bytes));
+    const int64_t small_max = small_override >= 0 ? small_override : c.small_max;
+    char* scr = (char*)scratch;
+    Work<K> w = make_work<K>(L, scr, keys, vals, off, n, nseg, c, small_max);
+    const double kb = sizeof(K) + (PAIRS ? 4.0 : 0.0);
+    {
+        Timer t(st, "setup", 0);
+        HS_TRY(launch_setup<K>(w, seg ? nullptr : (int64_t*)(scr + L.own_off), st));
+    }
+    const bool any_large = seg ? (n > small_max) : (n > small_max);
+    if (!seg && !any_large) {  // a plain sort that fits one tile
+        for (const SmallClass& sc : small_classes(small_max)) {
+            if (n > sc.lo && n <= sc.hi) {
+                Timer t(st, "small", 2 * kb * n);
+                HS_TRY((small_by_shape<K, PAIRS>(sc.cap, w, sc.lo, sc.hi, 1, st)));
+            }
+        }
+        return HSORT_OK;
+    }
+    {
+        Timer t(st, "scan", 0);
+        HS_TRY(launch_scan_i32(ScanSpec{nullptr, 0, nseg}, nseg, w.tilecnt, w.tilepre, (int32_t*)(scr + L.part32), st));
+    }
+    if (any_large) {
+        {
+            Timer t(st, "range", sizeof(K) * (double)n);
+            HS_TRY(launch_range<K>(w, L.tiles_bound, st));
+            HS_TRY(launch_plans<K>(w, st));
+        }
+        {
+            Timer t(st, "hist", sizeof(K) * (double)n);
+            HS_TRY(launch_hist<K>(w, L.tiles_bound, st));
+        }
+        {
+            Timer t(st, "scan", 0);
+            HS_TRY(launch_scan_u32_i64(ScanSpec{w.tilepre + nseg, 10, 0}, 10 * L.tiles_bound, w.counts, w.pos,
+                                       (int64_t*)(scr + L.part64), st));
+        }
+        {
+            Timer t(st, "btab", 0);
+            HS_TRY(launch_btab<K>(w, st));
+            HS_TRY(launch_scan_i32(ScanSpec{nullptr, 0, L.buckets}, L.buckets, w.tsc, w.tsp, (int32_t*)(scr + L.part32), st));
+            HS_TRY(launch_scan_i32(ScanSpec{nullptr, 0, L.buckets}, L.buckets, w.mcc, w.msp, (int32_t*)(scr + L.part32), st));
+        }
+        {
+            Timer t(st, "scatter", 2 * kb * n);
+            HS_TRY((launch_scatter<K, PAIRS>(w, L.tiles_bound, st)));
+        }
+        if (stage == 1) {
+            HS_TRY(launch_collect<K>(w, 1, st));
+            return HSORT_OK;
+        }
+        {
+            Timer t(st, "tilesort", 2 * kb * n);
+            HS_TRY((tilesort_by_shape<K, PAIRS>(c.tile, w, L.ts_bound, st)));
+        }
+        if (stage == 2) {
+            HS_TRY(launch_collect<K>(w, 2, st));
+            return HSORT_OK;
+        }
+        int64_t biggest = n;
+        if (seg && max_seg_len > 0) biggest = std::min(biggest, max_seg_len);
+        const int rounds = merge_rounds(biggest, c.tile);
+        for (int p = 0; p < rounds; p++) {
+            {
+                Timer t(st, "partition", 0);
+                HS_TRY(launch_partition<K>(w, p, L.chunks_bound, st));
+            }
+            {
+                Timer t(st, "merge", 2 * kb * n);
+                HS_TRY((merge_by_shape<K, PAIRS>(c.merge_nv, w, p, L.chunks_bound, st)));
+            }
+        }
+    }
+    if (seg) {
+        for (const SmallClass& sc : small_classes(small_max)) {
+            Timer t(st, "small", 0);
+            HS_TRY((small_by_shape<K, PAIRS>(sc.cap, w, sc.lo, sc.hi, nseg, st)));
+        }
+    }
+    return HSORT_OK;
+}
+
+int check_common(const void* keys, int64_t n, const void* scratch) {
+    if (n < 0) return fail(HSORT_ERR_INVALID, "n < 0");
+    if (n > HSORT_MAX_KEYS) return fail(HSORT_ERR_UNSUPPORTED, "n above HSORT_MAX_KEYS");
+    if (n > 0 && (!keys || !scratch)) return fail(HSORT_ERR_INVALID, "null pointer");
+    return HSORT_OK;
+}
+
+}  // namespace
+
+// ===================================================================== C ABI
+extern "C" {
+
+size_t hsort_scratch_bytes(int kind, int64_t n, int64_t nseg) {
+    if (cfg_index(kind) < 0 || n < 0 || nseg < 0) return 0;
+    return make_layout(kind, n, nseg, get_cfg(kind)).total;
+}
+
+size_t hsort_bounds_offset(int kind, int64_t n, int64_t nseg) {
+    if (cfg_index(kind) < 0) return 0;
+    return make_layout(kind, n, nseg, get_cfg(kind)).bounds;
+}
+
+int hsort_keys_i32(int32_t* keys, int64_t n, void* scratch, size_t scratch_bytes, void* stream) {
+    g_err.clear();
+    int rc = check_common(keys, n, scratch);
+    if (rc || n == 0) return rc;
+    return run<int32_t, false>(HSORT_KEYS_I32, keys, nullptr, n, nullptr, 1, 0, scratch, scratch_bytes,
+                               (hipStream_t)stream, 3, -1);
+}
+
+int hsort_keys_i64(int64_t* keys, int64_t n, void* scratch, size_t scratch_bytes, void* stream) {
+    g_err.clear();
+    int rc = check_common(keys, n, scratch);
+    if (rc || n == 0) return rc;
+    return run<int64_t, false>(HSORT_KEYS_I64, keys, nullptr, n, nullptr, 1, 0, scratch, scratch_bytes,
+                               (hipStream_t)stream, 3, -1);
+}
+
+int hsort_pairs(int32_t* keys, uint32_t* vals, int64_t n, void* scratch, size_t scratch_bytes, void* stream) {
+    g_err.clear();
+    int rc = check_common(keys, n, scratch);
+    if (rc || n == 0) return rc;
+    if (!vals) return fail(HSORT_ERR_INVALID, "null vals");
+    return run<int32_t, true>(HSORT_PAIRS_I32_U32, keys, vals, n, nullptr, 1, 0, scratch, scratch_bytes,
+                              (hipStream_t)stream, 3, -1);
+}
+
+static int seg_args(const void* keys, int64_t n, const int64_t* offsets, int64_t nseg, const void* scratch) {
+    if (nseg < 0) return fail(HSORT_ERR_INVALID, "nseg < 0");
+    if (nseg > HSORT_MAX_KEYS) return fail(HSORT_ERR_UNSUPPORTED, "nseg above HSORT_MAX_KEYS");
+    if (nseg > 0 && !offsets) return fail(HSORT_ERR_INVALID, "null offsets");
+    return check_common(keys, n, scratch);
+}
+
+int hsort_segmented(int32_t* keys, int64_t n, const int64_t* offsets, int64_t nseg, int64_t max_seg_len,
+                    void* scratch, size_t scratch_bytes, void* stream) {
+    g_err.clear();
+    int rc = seg_args(keys, n, offsets, nseg, scratch);
+    if (rc || n == 0 || nseg == 0) return rc;
+    return run<int32_t, false>(HSORT_SEG_I32, keys, nullptr, n, offsets, nseg, max_seg_len, scratch, scratch_bytes,
+                               (hipStream_t)stream, 3, -1);
+}
+
+int hsort_segmented_i64(int64_t* keys, int64_t n, const int64_t* offsets, int64_t nseg, int64_t max_seg_len,
+                        void* scratch, size_t scratch_bytes, void* stream) {
+    g_err.clear();
+    int rc = seg_args(keys, n, offsets, nseg, scratch);
+    if (rc || n == 0 || nseg == 0) return rc;
+    return run<int64_t, false>(HSORT_SEG_I64, keys, nullptr, n, offsets, nseg, max_seg_len, scratch, scratch_bytes,
+                               (hipStream_t)stream, 3, -1);
+}
+
+int hsort_check(const void* scratch, void* stream) {
+    g_err.clear();
+    if (!scratch) return fail(HSORT_ERR_INVALID, "null scratch");
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return fail(HSORT_ERR_HIP, std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
+    uint32_t flag = 0;
+    e = hipMemcpy(&flag, scratch, sizeof(flag), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return fail(HSORT_ERR_HIP, std::string("hipMemcpy: ") + hipGetErrorString(e));
+    if (flag) return fail(HSORT_ERR_INVALID, "invalid segment offsets");
+    return HSORT_OK;
+}
+
+const char* hsort_last_error(void) { return g_err.c_str(); }
+
+int hsort_set_config(int kind, int64_t tile, int64_t merge_nv, int64_t small_max) {
+    g_err.clear();
+    const int ci = cfg_index(kind);
+    if (ci < 0) return fail(HSORT_ERR_INVALID, "unknown kind");
+    if (!tile_shape_ok(ci, tile) || merge_nv != 4096 || tile % merge_nv != 0)
+        return fail(HSORT_ERR_UNSUPPORTED, "tile/merge shape not compiled");
+    if (small_max < 0 || small_max > 8192) return fail(HSORT_ERR_UNSUPPORTED, "small_max must be in [0, 8192]");
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_cfg[ci] = Config{tile, merge_nv, small_max};
+    return HSORT_OK;
+}
+
+int hsort_get_config(int kind, int64_t* tile, int64_t* merge_nv, int64_t* small_max) {
+    const int ci = cfg_index(kind);
+    if (ci < 0 || !tile || !merge_nv || !small_max) return fail(HSORT_ERR_INVALID, "bad arguments");
+    Config c = get_cfg(kind);
+    *tile = c.tile;
+    *merge_nv = c.merge_nv;
+    *small_max = c.small_max;
+    return HSORT_OK;
+}
+
+int hsort_debug_stage(int kind, void* keys, uint32_t* vals, int64_t n, int stage, void* scratch,
+                      size_t scratch_bytes, void* stream) {
+    g_err.clear();
+    int rc = check_common(keys, n, scratch);
+    if (rc || n == 0) return rc;
+    if (stage < 1 || stage > 3) return fail(HSORT_ERR_INVALID, "stage must be 1, 2 or 3");
+    hipStream_t st = (hipStream_t)stream;
+    switch (kind) {
+        case HSORT_KEYS_I32:
+            return run<int32_t, false>(kind, (int32_t*)keys, nullptr, n, nullptr, 1, 0, scratch, scratch_bytes, st,
+                                       stage, 0);
+        case HSORT_KEYS_I64:
+            return run<int64_t, false>(kind, (int64_t*)keys, nullptr, n, nullptr, 1, 0, scratch, scratch_bytes, st,
+                                       stage, 0);
+        case HSORT_PAIRS_I32_U32:
+            if (!vals) return fail(HSORT_ERR_INVALID, "null vals");
+            return run<int32_t, true>(kind, (int32_t*)keys, vals, n, nullptr, 1, 0, scratch, scratch_bytes, st,
+                                      stage, 0);
+    }
+    return fail(HSORT_ERR_INVALID, "kind must be a plain kind");
+}
+
+int hsort_timing_enable(int on) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_timing = on != 0;
+    return HSORT_OK;
+}
+
+int64_t hsort_timing_read(char* out, int64_t cap) {
+    std::vector<Rec> recs;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        recs.swap(g_recs);
+    }
+    struct Agg {
+        std::string name;
+        int64_t launches;
+        double ms, bytes;
+    };
+    std::vector<Agg> agg;
+    for (Rec& r : recs) {
+        float ms = 0;
+        hipEventSynchronize(r.b);
+        hipEventElapsedTime(&ms, r.a, r.b);
+        hipEventDestroy(r.a);
+        hipEventDestroy(r.b);
+        auto it = std::find_if(agg.begin(), agg.end(), [&](const Agg& a) { return a.name == r.name; });
+        if (it == agg.end()) {
+            agg.push_back({r.name, 0, 0, 0});
+            it = agg.end() - 1;
+        }
+        it->launches++;
+        it->ms += ms;
+        it->bytes += r.bytes;
+    }
+    std::string s;
+    for (const Agg& a : agg) {
+        char line[256];
+        snprintf(line, sizeof line, "%s %lld %.6f %.0f\n", a.name.c_str(), (long long)a.launches, a.ms, a.bytes);
+        s += line;
+    }
+    if (out && cap > 0) {
+        const int64_t m = std::min<int64_t>(cap - 1, (int64_t)s.size());
+        memcpy(out, s.data(), (size_t)m);
+        out[m] = 0;
+    }
+    return (int64_t)s.size() + 1;
+}
+
+int hsort_copy(const void* src, void* dst, int64_t bytes, void* stream) {
+    g_err.clear();
+    if (!src || !dst || bytes < 0 || bytes % 16) return fail(HSORT_ERR_INVALID, "bad copy arguments");
+    Timer t((hipStream_t)stream, "copy", 2.0 * bytes);
+    HS_TRY(launch_copy(src, dst, bytes, (hipStream_t)stream));
+    return HSORT_OK;
+}
+
+}  // extern "C"

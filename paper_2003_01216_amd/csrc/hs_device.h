@@ -1,0 +1,259 @@
+// hs_device.h -- device-side building blocks of the gfx950 hybrid sort.
+//
+// The sort follows the cluster method of Section 3.4 of Alghamdi & Alaghband
+// (arXiv 2003.01216) on one GPU: a one-step decimal MSD partition of the keys
+// into ten non-overlapping buckets, a local sort of fixed-size partitions of
+// each bucket (here an LDS tile sort, where the paper quicksorts per thread),
+// then non-recursive merge rounds of the sorted runs inside each bucket
+// (Figure 1b, Section 3.2), each round split over all compute units by
+// merge-path co-ranks instead of one thread per pair of lists.
+//
+// Everything here is integer work; nothing is a dense contraction, so there is
+// no MFMA.  Wavefronts are 64 lanes wide.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hs {
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------- key traits
+template <typename K>
+struct Traits;
+template <>
+struct Traits<int32_t> {
+    using U = uint32_t;  // the biased (unsigned) key domain
+    static constexpr int32_t kMin = INT32_MIN;
+    static constexpr int32_t kMax = INT32_MAX;
+};
+template <>
+struct Traits<int64_t> {
+    using U = uint64_t;
+    static constexpr int64_t kMin = INT64_MIN;
+    static constexpr int64_t kMax = INT64_MAX;
+};
+
+// ------------------------------------------------------ decimal digit plan
+// Section 3.4: the master divides the keys into ten parts by their most
+// significant digit.  Reading used throughout: the digit is the fixed-position
+// decimal digit D-1 of u = k - beta, beta = min(min key, 0), D = number of
+// decimal digits of max u.  With p = 10^(D-1) (the largest power of ten not
+// above max u, or 1), the digit is the number of thresholds b*p, b = 1..9,
+// that u reaches -- nine unsigned compares, no division on the hot path.
+// thr[b-1] holds b*p - 1 saturated at the type's maximum, so that a threshold
+// beyond the unsigned range is never passed: digit = sum_b [u > thr[b-1]].
+template <typename K>
+struct DigitPlan {
+    using U = typename Traits<K>::U;
+    U beta;    // (U)beta
+    U thr[9];  // b*p - 1, saturated
+};
+
+template <typename K>
+__host__ __device__ inline DigitPlan<K> make_digit_plan(K mn, K mx) {
+    using U = typename Traits<K>::U;
+    DigitPlan<K> pl;
+    K beta = mn < 0 ? mn : K(0);
+    pl.beta = (U)beta;
+    U top = (U)mx - (U)beta;  // exact: mx >= beta
+    U p = 1;
+    while (p <= top / 10) p *= 10;  // largest power of ten <= top
+    const U umax = ~U(0);
+    for (int b = 1; b <= 9; b++) {
+        // b*p - 1, or umax when b*p does not fit
+        pl.thr[b - 1] = (p > umax / (U)b) ? umax : (U)((U)b * p - 1);
+    }
+    return pl;
+}
+
+template <typename K>
+__device__ __forceinline__ int digit_of(const DigitPlan<K>& pl, K k) {
+    using U = typename Traits<K>::U;
+    U u = (U)k - pl.beta;
+    int d = 0;
+#pragma unroll
+    for (int b = 0; b < 9; b++) d += (u > pl.thr[b]) ? 1 : 0;
+    return d;
+}
+
+// ----------------------------------------------------------------- sort words
+// The LDS sorts work on a "word" W with a plain '<'.  Keys-only sorts use the
+// key itself.  Stable key+payload sorts use a 64-bit composite
+// (sign-flipped key << 32 | position), which is a strict total order, so any
+// correct sorting network or merge produces the stable order; the payload is
+// fetched by position afterwards.
+__device__ __forceinline__ uint64_t pair_word(int32_t k, uint32_t pos) {
+    return ((uint64_t)((uint32_t)k ^ 0x80000000u) << 32) | (uint64_t)pos;
+}
+__device__ __forceinline__ int32_t pair_key(uint64_t w) { return (int32_t)((uint32_t)(w >> 32) ^ 0x80000000u); }
+__device__ __forceinline__ uint32_t pair_pos(uint64_t w) { return (uint32_t)w; }
+
+template <typename W>
+struct WordMax;
+template <>
+struct WordMax<int32_t> {
+    static constexpr int32_t v = INT32_MAX;
+};
+template <>
+struct WordMax<int64_t> {
+    static constexpr int64_t v = INT64_MAX;
+};
+template <>
+struct WordMax<uint64_t> {
+    static constexpr uint64_t v = ~0ull;
+};
+
+template <typename W>
+__device__ __forceinline__ void cas_up(W& a, W& b) {  // a <- min, b <- max
+    W lo = b < a ? b : a;
+    W hi = b < a ? a : b;
+    a = lo;
+    b = hi;
+}
+
+// LDS index padding: one pad word per 128 bytes, so that lanes reading
+// VT-strided positions spread over the banks.
+template <typename W>
+__device__ __forceinline__ int lds_pad(int i) {
+    constexpr int per = 128 / (int)sizeof(W);
+    return i + i / per;
+}
+template <typename W>
+constexpr int lds_padded_size(int n) {
+    return n + n / (128 / (int)sizeof(W)) + 1;
+}
+
+// Bitonic sorting network over VT registers (VT a power of two), fully
+// unrolled: log2(VT)*(log2(VT)+1)/2 stages of VT/2 compare-exchanges.
+template <typename W, int VT>
+__device__ __forceinline__ void register_sort(W (&v)[VT]) {
+#pragma unroll
+    for (int k = 2; k <= VT; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+#pragma unroll
+            for (int i = 0; i < VT; i++) {
+                const int l = i ^ j;
+                if (l > i) {
+                    if ((i & k) == 0)
+                        cas_up(v[i], v[l]);
+                    else
+                        cas_up(v[l], v[i]);
+                }
+            }
+        }
+    }
+}
+
+// Sorts a bitonic sequence of VT registers ascending (half-cleaner cascade).
+template <typename W, int VT>
+__device__ __forceinline__ void bitonic_merge(W (&v)[VT]) {
+#pragma unroll
+    for (int j = VT >> 1; j > 0; j >>= 1) {
+#pragma unroll
+        for (int i = 0; i < VT; i++) {
+            const int l = i ^ j;
+            if (l > i) cas_up(v[i], v[l]);
+        }
+    }
+}
+
+// Merge path (co-rank): of the first `diag` outputs of the stable merge of
+// sorted A[0..na) and B[0..nb), how many come from A.  Ties go to A.
+// Accessors read A[i] / B[j].
+template <typename W, typename FA, typename FB>
+__device__ __forceinline__ int merge_path(int diag, int na, int nb, FA A, FB B) {
+    int lo = diag > nb ? diag - nb : 0;
+    int hi = diag < na ? diag : na;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (!(B(diag - 1 - mid) < A(mid)))
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// 64-bit variant for global-memory co-ranks over long runs.
+template <typename FA, typename FB>
+__device__ __forceinline__ int64_t merge_path64(int64_t diag, int64_t na, int64_t nb, FA A, FB B) {
+    int64_t lo = diag > nb ? diag - nb : 0;
+    int64_t hi = diag < na ? diag : na;
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (!(B(diag - 1 - mid) < A(mid)))
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// --------------------------------------------------------- wave/block helpers
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan_add(T x) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        T y = __shfl_up(x, d, kWave);
+        if (lane >= d) x += y;
+    }
+    return x;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_reduce_add(T x) {
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) x += __shfl_xor(x, d, kWave);
+    return x;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_reduce_min(T x) {
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) {
+        T y = __shfl_xor(x, d, kWave);
+        x = y < x ? y : x;
+    }
+    return x;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_reduce_max(T x) {
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) {
+        T y = __shfl_xor(x, d, kWave);
+        x = y > x ? y : x;
+    }
+    return x;
+}
+
+// Index of the last entry of pre[0..n] (non-decreasing, pre[0] = 0) that is
+// <= x, i.e. the owner of flat item x in a prefix of per-owner item counts.
+template <typename T>
+__device__ __forceinline__ int owner_of(const T* pre, int n, T x) {
+    int lo = 0, hi = n;  // invariant: pre[lo] <= x < pre[hi] (pre[n] > x)
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (pre[mid] <= x)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// Number of bottom-up merge rounds a bucket of `size` keys needs when its
+// local sort leaves runs of `tile` keys and each round halves the run count.
+__host__ __device__ __forceinline__ int merge_rounds(int64_t size, int64_t tile) {
+    int64_t runs = (size + tile - 1) / tile;
+    int r = 0;
+    while (((int64_t)1 << r) < runs) r++;
+    return r;
+}
+
+}  // namespace hs

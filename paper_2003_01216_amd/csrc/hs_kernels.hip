@@ -1,0 +1,950 @@
+// hs_kernels.hip -- gfx950 kernels of the hybrid MSD-radix / tile-sort /
+// merge-path sort, and the host launchers the C ABI calls.
+//
+// Pipeline for the keys of one call (every array is a segment; a plain sort
+// is one segment):
+//   k_init, k_classify, scan       per-segment size class and histogram tiles
+//   k_range, k_plans               min/max -> decimal digit plan (Section 3.4)
+//   k_hist, scan                   per-tile counts of the ten buckets
+//   k_btab, scan x2                bucket table, local-sort tiles, merge chunks
+//   k_scatter                      stable one-step MSD scatter into buckets
+//   k_tilesort                     LDS sort of each T-key partition of a bucket
+//   k_partition + k_merge          bottom-up merge rounds (Figure 1b), per round
+//   k_small                        segments that fit a tile: one LDS sort each
+// All flat-list kernels are persistent (grid-stride over a device-side item
+// count), so the launch sequence and its grid sizes depend only on host-side
+// sizes and can be captured in a graph.
+#include <hip/hip_runtime.h>
+
+#include "hs_device.h"
+#include "hs_launch.h"
+#include "hs_work.h"
+
+namespace hs {
+
+// ------------------------------------------------------------------ helpers
+__device__ __forceinline__ void atomic_min_k(int32_t* p, int32_t v) { atomicMin((int*)p, (int)v); }
+__device__ __forceinline__ void atomic_max_k(int32_t* p, int32_t v) { atomicMax((int*)p, (int)v); }
+__device__ __forceinline__ void atomic_min_k(int64_t* p, int64_t v) { atomicMin((long long*)p, (long long)v); }
+__device__ __forceinline__ void atomic_max_k(int64_t* p, int64_t v) { atomicMax((long long*)p, (long long)v); }
+
+template <typename K, bool PAIRS>
+struct WordOf {
+    using type = K;
+};
+template <>
+struct WordOf<int32_t, true> {
+    using type = uint64_t;
+};
+
+template <typename K, bool PAIRS>
+__device__ __forceinline__ typename WordOf<K, PAIRS>::type make_word(K k, int q) {
+    if constexpr (PAIRS)
+        return pair_word(k, (uint32_t)q);
+    else
+        return k;
+}
+template <typename K, bool PAIRS>
+__device__ __forceinline__ K word_key(typename WordOf<K, PAIRS>::type w) {
+    if constexpr (PAIRS)
+        return pair_key(w);
+    else
+        return w;
+}
+
+// Per-thread digit counters: ten 5-bit fields in one 64-bit word (a thread
+// counts at most 16 keys).  Packed words: two 16-bit fields per 32-bit word.
+__device__ __forceinline__ void unpack5(uint64_t c, uint32_t (&wd)[5]) {
+#pragma unroll
+    for (int m = 0; m < 5; m++) {
+        uint32_t lo = (uint32_t)(c >> (10 * m)) & 31u;
+        uint32_t hi = (uint32_t)(c >> (10 * m + 5)) & 31u;
+        wd[m] = lo | (hi << 16);
+    }
+}
+__device__ __forceinline__ uint32_t field16(const uint32_t (&wd)[5], int d) {
+    uint32_t w = wd[0];
+#pragma unroll
+    for (int m = 1; m < 5; m++) w = ((d >> 1) == m) ? wd[m] : w;
+    return (w >> ((d & 1) * 16)) & 0xFFFFu;
+}
+
+// Block-wide sum of five packed words; every thread gets the totals.
+template <int NT>
+__device__ __forceinline__ void block_sum5(uint32_t (&wd)[5], uint32_t (*red)[5]) {
+    constexpr int NW = NT / kWave;
+    const int lane = lane_id(), wave = threadIdx.x / kWave;
+#pragma unroll
+    for (int m = 0; m < 5; m++) {
+        uint32_t s = wave_reduce_add(wd[m]);
+        if (lane == 0) red[wave][m] = s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < 5; m++) {
+        uint32_t s = 0;
+#pragma unroll
+        for (int q = 0; q < NW; q++) s += red[q][m];
+        wd[m] = s;
+    }
+    __syncthreads();
+}
+
+// Block-wide exclusive scan of five packed words; tot receives the totals.
+template <int NT>
+__device__ __forceinline__ void block_excl5(uint32_t (&wd)[5], uint32_t (&tot)[5], uint32_t (*red)[5]) {
+    constexpr int NW = NT / kWave;
+    const int lane = lane_id(), wave = threadIdx.x / kWave;
+    uint32_t inc[5];
+#pragma unroll
+    for (int m = 0; m < 5; m++) {
+        inc[m] = wave_incl_scan_add(wd[m]);
+        if (lane == kWave - 1) red[wave][m] = inc[m];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < 5; m++) {
+        uint32_t before = 0, all = 0;
+#pragma unroll
+        for (int q = 0; q < NW; q++) {
+            uint32_t r = red[q][m];
+            before += (q < wave) ? r : 0u;
+            all += r;
+        }
+        wd[m] = inc[m] - wd[m] + before;
+        tot[m] = all;
+    }
+    __syncthreads();
+}
+
+template <typename T, int NT>
+__device__ __forceinline__ T block_excl_scan(T x, T& total, T* red) {
+    constexpr int NW = NT / kWave;
+    const int lane = lane_id(), wave = threadIdx.x / kWave;
+    T inc = wave_incl_scan_add(x);
+    if (lane == kWave - 1) red[wave] = inc;
+    __syncthreads();
+    T before = 0, all = 0;
+#pragma unroll
+    for (int q = 0; q < NW; q++) {
+        T r = red[q];
+        before += (q < wave) ? r : T(0);
+        all += r;
+    }
+    __syncthreads();
+    total = all;
+    return inc - x + before;
+}
+
+// -------------------------------------------------------- LDS merge blocks
+// Gathers this thread's `c` outputs of the merge of A = words[a0 + ai ...]
+// (x of them) and B = words[b0 + bi ...] (c - x of them) as an ascending run
+// followed by sentinels and the B part reversed -- a bitonic sequence -- and
+// sorts it with a half-cleaner cascade.  No data-dependent loop, so the VT
+// LDS reads are independent.
+template <typename W, int VT>
+__device__ __forceinline__ void gather_merge(const W* words, int a0, int b0, int ai, int bi, int x, int c,
+                                             W (&v)[VT]) {
+    const int gap = VT - c;
+#pragma unroll
+    for (int i = 0; i < VT; i++) {
+        const bool from_a = i < x;
+        const bool sentinel = !from_a && i < x + gap;
+        int idx = from_a ? (a0 + ai + i) : (b0 + bi + (VT - 1 - i));
+        idx = sentinel ? a0 : idx;
+        W val = words[lds_pad<W>(idx)];
+        v[i] = sentinel ? WordMax<W>::v : val;
+    }
+    bitonic_merge<W, VT>(v);
+}
+
+// Sorts words[0..NT*VT) (padded layout) ascending in LDS: a register sorting
+// network per thread, then log2(NT) merge levels.  Result in blocked layout.
+template <typename W, int NT, int VT>
+__device__ __forceinline__ void block_sort(W* words, int* sp) {
+    constexpr int NV = NT * VT;
+    const int tid = threadIdx.x;
+    W v[VT];
+#pragma unroll
+    for (int i = 0; i < VT; i++) v[i] = words[lds_pad<W>(tid * VT + i)];
+    register_sort<W, VT>(v);
+#pragma unroll 1
+    for (int L = VT; L < NV; L <<= 1) {
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < VT; i++) words[lds_pad<W>(tid * VT + i)] = v[i];
+        __syncthreads();
+        const int gb = (tid * VT) & ~(2 * L - 1);
+        const int diag = tid * VT - gb;
+        auto A = [&](int i) { return words[lds_pad<W>(gb + i)]; };
+        auto B = [&](int i) { return words[lds_pad<W>(gb + L + i)]; };
+        const int ai = merge_path<W>(diag, L, L, A, B);
+        sp[tid] = ai;
+        __syncthreads();
+        const int an = (diag + VT == 2 * L) ? L : sp[tid + 1];
+        gather_merge<W, VT>(words, gb, gb + L, ai, diag - ai, an - ai, VT, v);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < VT; i++) words[lds_pad<W>(tid * VT + i)] = v[i];
+    __syncthreads();
+}
+
+// ------------------------------------------------------------- setup kernels
+// own_off: where a plain sort's one-segment offsets live (w.off points there).
+template <typename K>
+__global__ void k_init(Work<K> w, int64_t* own_off) {
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid == 0) {
+        *w.err = 0;
+        if (own_off) {  // a plain sort is one segment [0, n)
+            own_off[0] = 0;
+            own_off[1] = w.n;
+        }
+    }
+    for (int s = gid; s < w.nseg; s += gridDim.x * blockDim.x) {
+        w.segmin[s] = Traits<K>::kMax;
+        w.segmax[s] = Traits<K>::kMin;
+    }
+}
+
+// Size class of every segment, histogram-tile count of the large ones, and
+// validation of the offsets (non-decreasing, inside [0, n]).
+template <typename K>
+__global__ void k_classify(Work<K> w) {
+    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < w.nseg; s += gridDim.x * blockDim.x) {
+        const int64_t a = w.off[s], b = w.off[s + 1];
+        const bool bad = (b < a) || (s == 0 && a < 0) || (s == w.nseg - 1 && b > w.n);
+        if (bad) atomicOr(w.err, 1u);
+        const int64_t m = b - a;
+        w.tilecnt[s] = (!bad && m > w.small_max) ? (int32_t)((m + kHistTile - 1) / kHistTile) : 0;
+    }
+}
+
+// min/max of every large segment.  Each workgroup takes a contiguous run of
+// histogram tiles and flushes one atomic pair per segment it touched.
+template <typename K>
+__global__ __launch_bounds__(kHistNT) void k_range(Work<K> w) {
+    __shared__ K rmin[kHistNT / kWave], rmax[kHistNT / kWave];
+    if (*w.err) return;
+    const int total = w.tilepre[w.nseg];
+    const int per = (total + gridDim.x - 1) / gridDim.x;
+    const int t0 = blockIdx.x * per;
+    const int t1 = min(t0 + per, total);
+    if (t0 >= t1) return;
+    const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+    int s = owner_of(w.tilepre, w.nseg, t0);
+    K mn = Traits<K>::kMax, mx = Traits<K>::kMin;
+    auto flush = [&](int seg) {
+        K a = wave_reduce_min(mn), b = wave_reduce_max(mx);
+        if (lane == 0) {
+            rmin[wave] = a;
+            rmax[wave] = b;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            for (int q = 1; q < kHistNT / kWave; q++) {
+                a = rmin[q] < a ? rmin[q] : a;
+                b = rmax[q] > b ? rmax[q] : b;
+            }
+            atomic_min_k(&w.segmin[seg], a);
+            atomic_max_k(&w.segmax[seg], b);
+        }
+        __syncthreads();
+        mn = Traits<K>::kMax;
+        mx = Traits<K>::kMin;
+    };
+    for (int t = t0; t < t1; t++) {
+        while (t >= w.tilepre[s + 1]) {
+            flush(s);
+            s++;
+        }
+        const int64_t base = w.off[s] + (int64_t)(t - w.tilepre[s]) * kHistTile;
+        const int cnt = (int)min((int64_t)kHistTile, w.off[s + 1] - base);
+        const K* src = w.keys + base;
+#pragma unroll
+        for (int j = 0; j < kHistVT; j++) {
+            const int q = j * kHistNT + tid;
+            if (q < cnt) {
+                K k = src[q];
+                mn = k < mn ? k : mn;
+                mx = k > mx ? k : mx;
+            }
+        }
+    }
+    flush(s);
+}
+
+template <typename K>
+__global__ void k_plans(Work<K> w) {
+    if (*w.err) return;
+    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < w.nseg; s += gridDim.x * blockDim.x)
+        if (w.tilecnt[s] > 0) w.plans[s] = make_digit_plan<K>(w.segmin[s], w.segmax[s]);
+}
+
+// ------------------------------------------------------------- histogram
+// Per tile: how many keys fall in each of the ten buckets.  Layout: for
+// segment s, counts[10*tilepre[s] + d*tilecnt[s] + i] (bucket-major, tile
+// minor), so one exclusive scan of the whole array yields every tile's write
+// offset inside its bucket.
+template <typename K>
+__global__ __launch_bounds__(kHistNT) void k_hist(Work<K> w) {
+    __shared__ uint32_t red[kHistNT / kWave][5];
+    if (*w.err) return;
+    const int total = w.tilepre[w.nseg];
+    const int tid = threadIdx.x;
+    for (int t = blockIdx.x; t < total; t += gridDim.x) {
+        const int s = owner_of(w.tilepre, w.nseg, t);
+        const int i = t - w.tilepre[s];
+        const int64_t base = w.off[s] + (int64_t)i * kHistTile;
+        const int cnt = (int)min((int64_t)kHistTile, w.off[s + 1] - base);
+        const DigitPlan<K> pl = w.plans[s];
+        const K* src = w.keys + base;
+        uint64_t c = 0;
+#pragma unroll
+        for (int j = 0; j < kHistVT; j++) {
+            const int q = j * kHistNT + tid;
+            if (q < cnt) c += 1ull << (5 * digit_of(pl, src[q]));
+        }
+        uint32_t wd[5];
+        unpack5(c, wd);
+        block_sum5<kHistNT>(wd, red);
+        if (tid < 10) w.counts[10 * w.tilepre[s] + tid * w.tilecnt[s] + i] = field16(wd, tid);
+    }
+}
+
+// Bucket table: start and size of each of the ten buckets of every segment,
+// its local-sort tiles and merge chunks, and the bounds output.
+template <typename K>
+__global__ void k_btab(Work<K> w) {
+    if (*w.err) return;
+    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < w.nseg; s += gridDim.x * blockDim.x) {
+        const int nt = w.tilecnt[s];
+        const int64_t a = w.off[s];
+        if (nt == 0) {
+            for (int d = 0; d < 10; d++) {
+                w.bstart[10 * s + d] = a;
+                w.bsize[10 * s + d] = 0;
+                w.tsc[10 * s + d] = 0;
+                w.mcc[10 * s + d] = 0;
+            }
+            continue;
+        }
+        const int64_t base = 10 * (int64_t)w.tilepre[s];
+        const int64_t p0 = w.pos[base];
+        for (int d = 0; d < 10; d++) {
+            const int64_t st = w.pos[base + (int64_t)d * nt] - p0;
+            const int64_t en = w.pos[base + (int64_t)(d + 1) * nt] - p0;
+            const int64_t sz = en - st;
+            w.bstart[10 * s + d] = a + st;
+            w.bsize[10 * s + d] = sz;
+            w.tsc[10 * s + d] = (int32_t)((sz + w.tile - 1) / w.tile);
+            w.mcc[10 * s + d] = (int32_t)((sz + w.nv - 1) / w.nv);
+            w.bounds_out[11 * (int64_t)s + d] = st;
+        }
+        w.bounds_out[11 * (int64_t)s + 10] = w.off[s + 1] - a;
+    }
+}
+
+// ---------------------------------------------------------------- scatter
+// Stable one-step MSD scatter (Section 3.4: the master divides the keys into
+// ten parts by most significant digit).  Per tile: blocked ranks from packed
+// per-thread counters and a block scan, staging in LDS grouped by bucket,
+// then runs of consecutive keys written to their bucket in the scratch copy.
+template <typename K, bool PAIRS>
+__global__ __launch_bounds__(kHistNT) void k_scatter(Work<K> w) {
+    constexpr int NT = kHistNT, VT = kHistVT, HT = kHistTile;
+    __shared__ K sk[lds_padded_size<K>(HT)];
+    __shared__ uint32_t sv[PAIRS ? HT : 1];
+    __shared__ uint8_t sd[HT];
+    __shared__ uint32_t red[NT / kWave][5];
+    __shared__ int64_t dbase[10];
+    if (*w.err) return;
+    const int total = w.tilepre[w.nseg];
+    const int tid = threadIdx.x;
+    for (int t = blockIdx.x; t < total; t += gridDim.x) {
+        const int s = owner_of(w.tilepre, w.nseg, t);
+        const int i = t - w.tilepre[s];
+        const int nt = w.tilecnt[s];
+        const int64_t base = w.off[s] + (int64_t)i * HT;
+        const int cnt = (int)min((int64_t)HT, w.off[s + 1] - base);
+        const DigitPlan<K> pl = w.plans[s];
+        // 1. coalesced load, natural order
+#pragma unroll
+        for (int j = 0; j < VT; j++) {
+            const int q = j * NT + tid;
+            if (q < cnt) {
+                sk[lds_pad<K>(q)] = w.keys[base + q];
+                if constexpr (PAIRS) sv[q] = w.vals[base + q];
+            }
+        }
+        __syncthreads();
+        // 2. blocked: digits and ranks among this thread's own keys
+        K key[VT];
+        uint32_t val[VT];
+        int dg[VT];
+        uint32_t rank[VT];
+        uint64_t c = 0;
+#pragma unroll
+        for (int v = 0; v < VT; v++) {
+            const int q = tid * VT + v;
+            const bool ok = q < cnt;
+            key[v] = sk[lds_pad<K>(ok ? q : 0)];
+            if constexpr (PAIRS) val[v] = sv[ok ? q : 0];
+            const int d = ok ? digit_of(pl, key[v]) : 10;
+            dg[v] = d;
+            rank[v] = ok ? (uint32_t)(c >> (5 * d)) & 31u : 0u;
+            c += ok ? (1ull << (5 * d)) : 0ull;
+        }
+        // 3. exclusive scan over threads, and the tile's bucket totals
+        uint32_t wd[5], tot[5];
+        unpack5(c, wd);
+        block_excl5<NT>(wd, tot, red);  // ends with a barrier: sk is free
+        // 4. tile-local bucket starts, folded into the packed prefix
+        uint32_t tst[10];
+        uint32_t run = 0;
+#pragma unroll
+        for (int d = 0; d < 10; d++) {
+            tst[d] = run;
+            run += field16(tot, d);
+        }
+#pragma unroll
+        for (int m = 0; m < 5; m++) wd[m] += tst[2 * m] | (tst[2 * m + 1] << 16);
+        if (tid < 10) {
+            const int64_t pbase = 10 * (int64_t)w.tilepre[s];
+            const int64_t dst0 = w.off[s] + w.pos[pbase + (int64_t)tid * nt + i] - w.pos[pbase];
+            uint32_t my = 0;
+#pragma unroll
+            for (int d = 0; d < 10; d++) my = (d == tid) ? tst[d] : my;
+            dbase[tid] = dst0 - (int64_t)my;
+        }
+        // 5. stage grouped by bucket
+#pragma unroll
+        for (int v = 0; v < VT; v++) {
+            if (dg[v] < 10) {
+                const int sp = (int)(field16(wd, dg[v]) + rank[v]);
+                sk[lds_pad<K>(sp)] = key[v];
+                sd[sp] = (uint8_t)dg[v];
+                if constexpr (PAIRS) sv[sp] = val[v];
+            }
+        }
+        __syncthreads();
+        // 6. coalesced runs out to the buckets
+#pragma unroll
+        for (int j = 0; j < VT; j++) {
+            const int q = j * NT + tid;
+            if (q < cnt) {
+                const int64_t dst = dbase[sd[q]] + q;
+                w.skeys[dst] = sk[lds_pad<K>(q)];
+                if constexpr (PAIRS) w.svals[dst] = sv[q];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// -------------------------------------------------------------- tile sort
+// Local sort of each T-key partition of every bucket (Section 3.4: each
+// thread of a node sorts its partition; here one workgroup per partition, in
+// LDS).  Partitions start at the bucket's first key.  A bucket that needs P
+// merge rounds is written to the caller's buffer when P is even and to the
+// scratch copy when P is odd, so that its last round lands in the caller's
+// buffer with no final copy.
+template <typename K, bool PAIRS, int NT, int VT>
+__global__ __launch_bounds__(NT) void k_tilesort(Work<K> w) {
+    using W = typename WordOf<K, PAIRS>::type;
+    constexpr int NV = NT * VT;
+    __shared__ W words[lds_padded_size<W>(NV)];
+    __shared__ uint32_t sv[PAIRS ? NV : 1];
+    __shared__ int sp[NT + 1];
+    if (*w.err) return;
+    const int nb = 10 * w.nseg;
+    const int total = w.tsp[nb];
+    const int tid = threadIdx.x;
+    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+        const int j = owner_of(w.tsp, nb, item);
+        const int i = item - w.tsp[j];
+        const int64_t size = w.bsize[j];
+        const int64_t start = w.bstart[j] + (int64_t)i * NV;
+        const int cnt = (int)min((int64_t)NV, size - (int64_t)i * NV);
+        const int P = merge_rounds(size, NV);
+        K* dk = (P & 1) ? w.skeys : w.keys;
+        uint32_t* dv = (P & 1) ? w.svals : w.vals;
+#pragma unroll
+        for (int jj = 0; jj < VT; jj++) {
+            const int q = jj * NT + tid;
+            W word = WordMax<W>::v;
+            if (q < cnt) {
+                word = make_word<K, PAIRS>(w.skeys[start + q], q);
+                if constexpr (PAIRS) sv[q] = w.svals[start + q];
+            }
+            words[lds_pad<W>(q)] = word;
+        }
+        __syncthreads();
+        block_sort<W, NT, VT>(words, sp);
+#pragma unroll
+        for (int jj = 0; jj < VT; jj++) {
+            const int q = jj * NT + tid;
+            if (q < cnt) {
+                const W word = words[lds_pad<W>(q)];
+                dk[start + q] = word_key<K, PAIRS>(word);
+                if constexpr (PAIRS) dv[start + q] = sv[pair_pos(word)];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------ merge rounds
+// Round `pass` of the non-recursive merge (Figure 1b; Section 3.2 merge
+// rounds): inside every bucket still holding more than one run, runs of
+// L = T*2^pass keys are merged pairwise (an odd last run is carried).  The
+// output of each pair is cut into chunks of NV keys; one workgroup per chunk.
+// k_partition finds, for every chunk start, how many of its preceding
+// outputs come from the left run (co-rank, ties to the left run = stable).
+template <typename K>
+__global__ void k_partition(Work<K> w, int pass) {
+    if (*w.err) return;
+    const int nb = 10 * w.nseg;
+    const int total = w.msp[nb];
+    const int64_t T = w.tile, NV = w.nv;
+    const int64_t L = T << pass;
+    for (int item = blockIdx.x * blockDim.x + threadIdx.x; item < total; item += gridDim.x * blockDim.x) {
+        const int j = owner_of(w.msp, nb, item);
+        const int64_t i = item - w.msp[j];
+        const int64_t size = w.bsize[j];
+        const int P = merge_rounds(size, T);
+        if (P <= pass) continue;
+        const int64_t o = i * NV;
+        const int64_t ps = (o / (2 * L)) * (2 * L);
+        const int64_t a_len = min(L, size - ps);
+        const int64_t b_len = max((int64_t)0, min(L, size - ps - L));
+        const K* src = ((P - pass) & 1) ? w.skeys : w.keys;
+        const K* A = src + w.bstart[j] + ps;
+        const K* B = A + L;
+        const int64_t co =
+            merge_path64(o - ps, a_len, b_len, [&](int64_t x) { return A[x]; }, [&](int64_t x) { return B[x]; });
+        w.split[item] = (int32_t)co;
+    }
+}
+
+template <typename K, bool PAIRS, int NT, int VT>
+__global__ __launch_bounds__(NT) void k_merge(Work<K> w, int pass) {
+    using W = typename WordOf<K, PAIRS>::type;
+    constexpr int NV = NT * VT;
+    __shared__ W words[lds_padded_size<W>(NV)];
+    __shared__ uint32_t sv[PAIRS ? NV : 1];
+    __shared__ int sp[NT + 1];
+    if (*w.err) return;
+    const int nb = 10 * w.nseg;
+    const int total = w.msp[nb];
+    const int64_t T = w.tile;
+    const int64_t L = T << pass;
+    const int tid = threadIdx.x;
+    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+        const int j = owner_of(w.msp, nb, item);
+        const int64_t i = item - w.msp[j];
+        const int64_t size = w.bsize[j];
+        const int P = merge_rounds(size, T);
+        if (P <= pass) continue;
+        const int64_t o = i * NV;
+        const int64_t ps = (o / (2 * L)) * (2 * L);
+        const int64_t a_len = min(L, size - ps);
+        const int64_t b_len = max((int64_t)0, min(L, size - ps - L));
+        const int64_t diag = o - ps;
+        const int64_t dend = min(o + NV, size) - ps;
+        const int64_t a_s = w.split[item];
+        const int64_t a_e = (dend == a_len + b_len) ? a_len : (int64_t)w.split[item + 1];
+        const int na = (int)(a_e - a_s);
+        const int tot = (int)(dend - diag);
+        const int64_t b_s = diag - a_s;
+        const bool odd = (P - pass) & 1;
+        const K* sk = odd ? w.skeys : w.keys;
+        const uint32_t* svv = odd ? w.svals : w.vals;
+        K* dk = odd ? w.keys : w.skeys;
+        uint32_t* dv = odd ? w.vals : w.svals;
+        const int64_t base = w.bstart[j] + ps;
+        const int64_t ga = base + a_s;
+        const int64_t gb = base + L + b_s;
+#pragma unroll
+        for (int jj = 0; jj < VT; jj++) {
+            const int q = jj * NT + tid;
+            if (q < tot) {
+                const int64_t g = q < na ? ga + q : gb + (q - na);
+                words[lds_pad<W>(q)] = make_word<K, PAIRS>(sk[g], q);
+                if constexpr (PAIRS) sv[q] = svv[g];
+            }
+        }
+        __syncthreads();
+        const int nbb = tot - na;
+        const int dt = min(tid * VT, tot);
+        auto A = [&](int x) { return words[lds_pad<W>(x)]; };
+        auto B = [&](int x) { return words[lds_pad<W>(na + x)]; };
+        const int ai = merge_path<W>(dt, na, nbb, A, B);
+        sp[tid] = ai;
+        __syncthreads();
+        const int an = (tid == NT - 1) ? na : sp[tid + 1];
+        const int c = min(tid * VT + VT, tot) - dt;
+        W v[VT];
+        gather_merge<W, VT>(words, 0, na, ai, dt - ai, an - ai, c, v);
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < VT; q++)
+            if (q < c) words[lds_pad<W>(tid * VT + q)] = v[q];
+        __syncthreads();
+        const int64_t out = w.bstart[j] + o;
+#pragma unroll
+        for (int jj = 0; jj < VT; jj++) {
+            const int q = jj * NT + tid;
+            if (q < tot) {
+                const W word = words[lds_pad<W>(q)];
+                dk[out + q] = word_key<K, PAIRS>(word);
+                if constexpr (PAIRS) dv[out + q] = sv[pair_pos(word)];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// --------------------------------------------------------- small segments
+// A segment with at most NT*VT keys never leaves LDS: one workgroup sorts it
+// and writes it back in place.  Its ten buckets are then contiguous ranges of
+// the sorted segment (the digit never decreases with the key), so the
+// one-step partition is realised by the same sort; the bucket bounds are
+// counted from the sorted keys.  Handles segments with lo < size <= hi.
+template <typename K, bool PAIRS, int NT, int VT>
+__global__ __launch_bounds__(NT) void k_small(Work<K> w, int64_t lo, int64_t hi) {
+    using W = typename WordOf<K, PAIRS>::type;
+    constexpr int NV = NT * VT;
+    static_assert(VT <= 16, "5-bit digit counters");
+    __shared__ W words[lds_padded_size<W>(NV)];
+    __shared__ uint32_t sv[PAIRS ? NV : 1];
+    __shared__ int sp[NT + 1];
+    __shared__ uint32_t red[NT / kWave][5];
+    if (*w.err) return;
+    const int tid = threadIdx.x;
+    for (int s = blockIdx.x; s < w.nseg; s += gridDim.x) {
+        const int64_t a = w.off[s];
+        const int64_t m64 = w.off[s + 1] - a;
+        if (!(m64 > lo && m64 <= hi)) continue;
+        const int m = (int)m64;
+        if (m > 1) {
+#pragma unroll
+            for (int jj = 0; jj < VT; jj++) {
+                const int q = jj * NT + tid;
+                W word = WordMax<W>::v;
+                if (q < m) {
+                    word = make_word<K, PAIRS>(w.keys[a + q], q);
+                    if constexpr (PAIRS) sv[q] = w.vals[a + q];
+                }
+                words[lds_pad<W>(q)] = word;
+            }
+            __syncthreads();
+            block_sort<W, NT, VT>(words, sp);
+#pragma unroll
+            for (int jj = 0; jj < VT; jj++) {
+                const int q = jj * NT + tid;
+                if (q < m) {
+                    const W word = words[lds_pad<W>(q)];
+                    w.keys[a + q] = word_key<K, PAIRS>(word);
+                    if constexpr (PAIRS) w.vals[a + q] = sv[pair_pos(word)];
+                }
+            }
+        } else {
+            if (tid == 0 && m == 1) words[lds_pad<W>(0)] = make_word<K, PAIRS>(w.keys[a], 0);
+            __syncthreads();
+        }
+        // bucket bounds of the segment, from its sorted keys
+        uint64_t c = 0;
+        if (m > 0) {
+            const K mn = word_key<K, PAIRS>(words[lds_pad<W>(0)]);
+            const K mx = word_key<K, PAIRS>(words[lds_pad<W>(m - 1)]);
+            const DigitPlan<K> pl = make_digit_plan<K>(mn, mx);
+#pragma unroll
+            for (int v = 0; v < VT; v++) {
+                const int q = tid * VT + v;
+                if (q < m) c += 1ull << (5 * digit_of(pl, word_key<K, PAIRS>(words[lds_pad<W>(q)])));
+            }
+        }
+        uint32_t wd[5];
+        unpack5(c, wd);
+        block_sum5<NT>(wd, red);
+        if (tid == 0) {
+            int64_t run = 0;
+            for (int d = 0; d < 10; d++) {
+                w.bounds_out[11 * (int64_t)s + d] = run;
+                run += field16(wd, d);
+            }
+            w.bounds_out[11 * (int64_t)s + 10] = run;
+        }
+        __syncthreads();
+    }
+}
+
+// Brings buckets left in the scratch copy back to the caller's buffer when a
+// debug run stops early: stage 1 (after the scatter) copies every large
+// segment's keys; stage 2 (after the local sorts) copies the buckets whose
+// round count is odd.
+template <typename K>
+__global__ void k_collect(Work<K> w, int stage) {
+    if (*w.err) return;
+    const int nb = 10 * w.nseg;
+    for (int j = blockIdx.x; j < nb; j += gridDim.x) {
+        const int64_t size = w.bsize[j];
+        if (size == 0) continue;
+        if (stage == 2 && !(merge_rounds(size, w.tile) & 1)) continue;
+        const int64_t st = w.bstart[j];
+        for (int64_t q = threadIdx.x; q < size; q += blockDim.x) {
+            w.keys[st + q] = w.skeys[st + q];
+            if (w.vals) w.vals[st + q] = w.svals[st + q];
+        }
+    }
+}
+
+// ------------------------------------------------------------ device scan
+// Exclusive prefix sum of `in` (length L read on the device as
+// len_mul * *len_ptr, or len_const when len_ptr is null); out[L] = total.
+constexpr int kScanNT = 256, kScanVT = 16, kScanTile = kScanNT * kScanVT;
+constexpr int kScanTopNT = 1024, kScanTopVT = 16;
+
+__device__ __forceinline__ int64_t scan_len(const ScanSpec& sp) {
+    return sp.len_ptr ? sp.len_mul * (int64_t)(*sp.len_ptr) : sp.len_const;
+}
+
+template <typename Tin, typename Tout>
+__global__ __launch_bounds__(kScanNT) void k_scan_reduce(ScanSpec sp, const Tin* in, Tout* partial) {
+    __shared__ Tout red[kScanNT / kWave];
+    const int64_t L = scan_len(sp);
+    const int64_t b0 = (int64_t)blockIdx.x * kScanTile;
+    if (b0 >= L) return;
+    Tout s = 0;
+#pragma unroll
+    for (int j = 0; j < kScanVT; j++) {
+        const int64_t q = b0 + j * kScanNT + threadIdx.x;
+        if (q < L) s += (Tout)in[q];
+    }
+    s = wave_reduce_add(s);
+    if (lane_id() == 0) red[threadIdx.x / kWave] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        Tout t = 0;
+        for (int q = 0; q < kScanNT / kWave; q++) t += red[q];
+        partial[blockIdx.x] = t;
+    }
+}
+
+// One workgroup: exclusive scan of up to kScanTopNT*kScanTopVT values in
+// place (the partials, or a short input when in != out).
+template <typename Tin, typename Tout>
+__global__ __launch_bounds__(kScanTopNT) void k_scan_single(ScanSpec sp, const Tin* in, Tout* out, int per_block) {
+    __shared__ Tout red[kScanTopNT / kWave];
+    const int64_t Lfull = scan_len(sp);
+    const int64_t L = per_block > 0 ? (Lfull + per_block - 1) / per_block : Lfull;
+    const int tid = threadIdx.x;
+    Tout v[kScanTopVT];
+    Tout run = 0;
+#pragma unroll
+    for (int i = 0; i < kScanTopVT; i++) {
+        const int64_t q = (int64_t)tid * kScanTopVT + i;
+        v[i] = q < L ? (Tout)in[q] : Tout(0);
+        run += v[i];
+    }
+    Tout total;
+    Tout pre = block_excl_scan<Tout, kScanTopNT>(run, total, red);
+#pragma unroll
+    for (int i = 0; i < kScanTopVT; i++) {
+        const int64_t q = (int64_t)tid * kScanTopVT + i;
+        if (q < L) out[q] = pre;
+        pre += v[i];
+    }
+    if (tid == 0) out[L] = total;
+}
+
+template <typename Tin, typename Tout>
+__global__ __launch_bounds__(kScanNT) void k_scan_down(ScanSpec sp, const Tin* in, const Tout* partial, Tout* out) {
+    __shared__ Tout red[kScanNT / kWave];
+    const int64_t L = scan_len(sp);
+    const int64_t b0 = (int64_t)blockIdx.x * kScanTile;
+    if (L == 0 && blockIdx.x == 0 && threadIdx.x == 0) out[0] = 0;
+    if (b0 >= L) return;
+    const int tid = threadIdx.x;
+    Tout v[kScanVT];
+    Tout run = 0;
+#pragma unroll
+    for (int i = 0; i < kScanVT; i++) {
+        const int64_t q = b0 + (int64_t)tid * kScanVT + i;
+        v[i] = q < L ? (Tout)in[q] : Tout(0);
+        run += v[i];
+    }
+    Tout total;
+    Tout pre = block_excl_scan<Tout, kScanNT>(run, total, red) + partial[blockIdx.x];
+#pragma unroll
+    for (int i = 0; i < kScanVT; i++) {
+        const int64_t q = b0 + (int64_t)tid * kScanVT + i;
+        if (q < L) out[q] = pre;
+        pre += v[i];
+    }
+    const int64_t nblk = (L + kScanTile - 1) / kScanTile;
+    if (blockIdx.x == nblk - 1 && tid == 0) out[L] = partial[nblk];
+}
+
+// Plain copy, used to calibrate the HBM byte counters.
+__global__ void k_copy(const uint4* __restrict__ src, uint4* __restrict__ dst, int64_t n16) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+// =================================================================== host
+static inline int cdiv64(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+template <typename Tin, typename Tout>
+static hipError_t scan_impl(const ScanSpec& sp, int64_t len_bound, const Tin* in, Tout* out, Tout* partial,
+                            hipStream_t st) {
+    if (len_bound <= (int64_t)kScanTopNT * kScanTopVT) {
+        k_scan_single<Tin, Tout><<<1, kScanTopNT, 0, st>>>(sp, in, out, 0);
+        return hipGetLastError();
+    }
+    const int nblk = cdiv64(len_bound, kScanTile);
+    if (nblk > kScanTopNT * kScanTopVT) return hipErrorInvalidValue;
+    k_scan_reduce<Tin, Tout><<<nblk, kScanNT, 0, st>>>(sp, in, partial);
+    k_scan_single<Tout, Tout><<<1, kScanTopNT, 0, st>>>(sp, partial, partial, kScanTile);
+    k_scan_down<Tin, Tout><<<nblk, kScanNT, 0, st>>>(sp, in, partial, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan_i32(const ScanSpec& sp, int64_t len_bound, const int32_t* in, int32_t* out, int32_t* partial,
+                           hipStream_t st) {
+    return scan_impl<int32_t, int32_t>(sp, len_bound, in, out, partial, st);
+}
+hipError_t launch_scan_u32_i64(const ScanSpec& sp, int64_t len_bound, const uint32_t* in, int64_t* out,
+                               int64_t* partial, hipStream_t st) {
+    return scan_impl<uint32_t, int64_t>(sp, len_bound, in, out, partial, st);
+}
+int64_t scan_partial_count(int64_t len_bound) { return cdiv64(len_bound, kScanTile) + 1; }
+
+// Persistent grid: enough workgroups to fill every compute unit at the
+// kernel's occupancy, but no more than there are items.
+static int cu_count() {
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
+    }
+    return cus;
+}
+
+template <typename F>
+static int fill_grid(F kernel, int nt, int64_t items) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, nt, 0) != hipSuccess || per_cu <= 0) per_cu = 1;
+    int64_t g = (int64_t)cu_count() * per_cu;
+    if (items < g) g = items;
+    return g < 1 ? 1 : (int)g;
+}
+
+template <typename K>
+hipError_t launch_setup(const Work<K>& w, int64_t* own_off, hipStream_t st) {
+    const int g = (int)min((int64_t)1024, (int64_t)cdiv64(w.nseg, 256));
+    k_init<K><<<g < 1 ? 1 : g, 256, 0, st>>>(w, own_off);
+    k_classify<K><<<g < 1 ? 1 : g, 256, 0, st>>>(w);
+    return hipGetLastError();
+}
+
+template <typename K>
+hipError_t launch_range(const Work<K>& w, int64_t tiles_bound, hipStream_t st) {
+    const int g = (int)min(tiles_bound, (int64_t)4 * cu_count());
+    k_range<K><<<g < 1 ? 1 : g, kHistNT, 0, st>>>(w);
+    return hipGetLastError();
+}
+
+template <typename K>
+hipError_t launch_plans(const Work<K>& w, hipStream_t st) {
+    const int g = (int)min((int64_t)1024, (int64_t)cdiv64(w.nseg, 256));
+    k_plans<K><<<g < 1 ? 1 : g, 256, 0, st>>>(w);
+    return hipGetLastError();
+}
+
+template <typename K>
+hipError_t launch_hist(const Work<K>& w, int64_t tiles_bound, hipStream_t st) {
+    k_hist<K><<<fill_grid(k_hist<K>, kHistNT, tiles_bound), kHistNT, 0, st>>>(w);
+    return hipGetLastError();
+}
+
+template <typename K>
+hipError_t launch_btab(const Work<K>& w, hipStream_t st) {
+    const int g = (int)min((int64_t)1024, (int64_t)cdiv64(w.nseg, 256));
+    k_btab<K><<<g < 1 ? 1 : g, 256, 0, st>>>(w);
+    return hipGetLastError();
+}
+
+template <typename K, bool PAIRS>
+hipError_t launch_scatter(const Work<K>& w, int64_t tiles_bound, hipStream_t st) {
+    k_scatter<K, PAIRS><<<fill_grid(k_scatter<K, PAIRS>, kHistNT, tiles_bound), kHistNT, 0, st>>>(w);
+    return hipGetLastError();
+}
+
+template <typename K, bool PAIRS, int NT, int VT>
+hipError_t launch_tilesort(const Work<K>& w, int64_t items_bound, hipStream_t st) {
+    k_tilesort<K, PAIRS, NT, VT><<<fill_grid(k_tilesort<K, PAIRS, NT, VT>, NT, items_bound), NT, 0, st>>>(w);
+    return hipGetLastError();
+}
+
+template <typename K>
+hipError_t launch_partition(const Work<K>& w, int pass, int64_t chunks_bound, hipStream_t st) {
+    const int64_t blocks = (chunks_bound + 255) / 256;
+    const int g = (int)min(blocks, (int64_t)8 * cu_count());
+    k_partition<K><<<g < 1 ? 1 : g, 256, 0, st>>>(w, pass);
+    return hipGetLastError();
+}
+
+template <typename K, bool PAIRS, int NT, int VT>
+hipError_t launch_merge(const Work<K>& w, int pass, int64_t chunks_bound, hipStream_t st) {
+    k_merge<K, PAIRS, NT, VT><<<fill_grid(k_merge<K, PAIRS, NT, VT>, NT, chunks_bound), NT, 0, st>>>(w, pass);
+    return hipGetLastError();
+}
+
+template <typename K, bool PAIRS, int NT, int VT>
+hipError_t launch_small(const Work<K>& w, int64_t lo, int64_t hi, int64_t segs_bound, hipStream_t st) {
+    k_small<K, PAIRS, NT, VT><<<fill_grid(k_small<K, PAIRS, NT, VT>, NT, segs_bound), NT, 0, st>>>(w, lo, hi);
+    return hipGetLastError();
+}
+
+template <typename K>
+hipError_t launch_collect(const Work<K>& w, int stage, hipStream_t st) {
+    const int g = (int)min((int64_t)4096, (int64_t)10 * w.nseg);
+    k_collect<K><<<g < 1 ? 1 : g, 256, 0, st>>>(w, stage);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t st) {
+    const int64_t n16 = bytes / 16;
+    k_copy<<<4 * cu_count(), 256, 0, st>>>((const uint4*)src, (uint4*)dst, n16);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------- explicit instances
+#define HS_INST_K(K)                                                                 \
+    template hipError_t launch_setup<K>(const Work<K>&, int64_t*, hipStream_t);          \
+    template hipError_t launch_range<K>(const Work<K>&, int64_t, hipStream_t);           \
+    template hipError_t launch_plans<K>(const Work<K>&, hipStream_t);                    \
+    template hipError_t launch_hist<K>(const Work<K>&, int64_t, hipStream_t);            \
+    template hipError_t launch_btab<K>(const Work<K>&, hipStream_t);                     \
+    template hipError_t launch_partition<K>(const Work<K>&, int, int64_t, hipStream_t);  \
+    template hipError_t launch_collect<K>(const Work<K>&, int, hipStream_t);
+HS_INST_K(int32_t)
+HS_INST_K(int64_t)
+
+template hipError_t launch_scatter<int32_t, false>(const Work<int32_t>&, int64_t, hipStream_t);
+template hipError_t launch_scatter<int32_t, true>(const Work<int32_t>&, int64_t, hipStream_t);
+template hipError_t launch_scatter<int64_t, false>(const Work<int64_t>&, int64_t, hipStream_t);
+
+#define HS_INST_TILE(K, PAIRS, NT, VT)                                                       \
+    template hipError_t launch_tilesort<K, PAIRS, NT, VT>(const Work<K>&, int64_t, hipStream_t); \
+    template hipError_t launch_small<K, PAIRS, NT, VT>(const Work<K>&, int64_t, int64_t, int64_t, hipStream_t);
+HS_TILE_VARIANTS(HS_INST_TILE)
+#define HS_INST_MERGE(K, PAIRS, NT, VT) \
+    template hipError_t launch_merge<K, PAIRS, NT, VT>(const Work<K>&, int, int64_t, hipStream_t);
+HS_MERGE_VARIANTS(HS_INST_MERGE)
+
+}  // namespace hs

@@ -1,0 +1,60 @@
+// hs_launch.h -- host-side launchers of the kernels in hs_kernels.hip.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hs_work.h"
+
+namespace hs {
+
+// Length of a scan: len_mul * (*len_ptr) read on the device, or len_const.
+struct ScanSpec {
+    const int32_t* len_ptr;
+    int64_t len_mul;
+    int64_t len_const;
+};
+
+// Compiled (key, stable pairs, threads, keys per thread) shapes of the LDS
+// sort (local-sort tiles and whole small segments) and of the merge.
+#define HS_TILE_VARIANTS(X)                                                                  \
+    X(int32_t, false, 512, 16)                                                               \
+    X(int32_t, false, 256, 16) X(int32_t, false, 256, 8) X(int32_t, false, 64, 4)            \
+    X(int64_t, false, 512, 16)                                                               \
+    X(int64_t, false, 256, 16) X(int64_t, false, 256, 8) X(int64_t, false, 64, 4)            \
+    X(int32_t, true, 512, 16) X(int32_t, true, 256, 16) X(int32_t, true, 256, 8) X(int32_t, true, 64, 4)
+#define HS_MERGE_VARIANTS(X) \
+    X(int32_t, false, 256, 16) X(int64_t, false, 256, 16) X(int32_t, true, 256, 16)
+
+// Each launcher sizes its own (persistent) grid from an upper bound on the
+// number of work items it can be handed.
+template <typename K>
+hipError_t launch_setup(const Work<K>& w, int64_t* own_off, hipStream_t st);
+template <typename K>
+hipError_t launch_range(const Work<K>& w, int64_t tiles_bound, hipStream_t st);
+template <typename K>
+hipError_t launch_plans(const Work<K>& w, hipStream_t st);
+template <typename K>
+hipError_t launch_hist(const Work<K>& w, int64_t tiles_bound, hipStream_t st);
+template <typename K>
+hipError_t launch_btab(const Work<K>& w, hipStream_t st);
+template <typename K, bool PAIRS>
+hipError_t launch_scatter(const Work<K>& w, int64_t tiles_bound, hipStream_t st);
+template <typename K, bool PAIRS, int NT, int VT>
+hipError_t launch_tilesort(const Work<K>& w, int64_t items_bound, hipStream_t st);
+template <typename K>
+hipError_t launch_partition(const Work<K>& w, int pass, int64_t chunks_bound, hipStream_t st);
+template <typename K, bool PAIRS, int NT, int VT>
+hipError_t launch_merge(const Work<K>& w, int pass, int64_t chunks_bound, hipStream_t st);
+template <typename K, bool PAIRS, int NT, int VT>
+hipError_t launch_small(const Work<K>& w, int64_t lo, int64_t hi, int64_t segs_bound, hipStream_t st);
+template <typename K>
+hipError_t launch_collect(const Work<K>& w, int stage, hipStream_t st);
+
+hipError_t launch_scan_i32(const ScanSpec& sp, int64_t len_bound, const int32_t* in, int32_t* out, int32_t* partial,
+                           hipStream_t st);
+hipError_t launch_scan_u32_i64(const ScanSpec& sp, int64_t len_bound, const uint32_t* in, int64_t* out,
+                               int64_t* partial, hipStream_t st);
+int64_t scan_partial_count(int64_t len_bound);
+hipError_t launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t st);
+
+}  // namespace hs

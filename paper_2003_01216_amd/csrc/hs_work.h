@@ -1,0 +1,53 @@
+// hs_work.h -- the per-call working set shared by the kernels and the host
+// launcher (plain device pointers into the caller's scratch buffer).
+#pragma once
+#include <stdint.h>
+
+#include "hs_device.h"
+
+namespace hs {
+
+// Keys per histogram / scatter tile (256 threads x 16 keys).
+constexpr int kHistNT = 256;
+constexpr int kHistVT = 16;
+constexpr int kHistTile = kHistNT * kHistVT;
+
+template <typename K>
+struct Work {
+    K* keys;          // the caller's keys (sorted in place)
+    uint32_t* vals;   // the caller's payload (stable pairs) or null
+    K* skeys;         // scratch copy of the keys (ping-pong partner)
+    uint32_t* svals;  // scratch payload (pairs) or null
+    const int64_t* off;  // segment offsets [nseg + 1]
+    int64_t n;           // keys addressable through `keys`
+    int32_t nseg;
+
+    // per segment
+    K* segmin;                // [nseg]
+    K* segmax;                // [nseg]
+    DigitPlan<K>* plans;      // [nseg]
+    int32_t* tilecnt;         // [nseg] histogram tiles of a large segment, 0 otherwise
+    int32_t* tilepre;         // [nseg + 1] exclusive prefix of tilecnt
+    int64_t* bounds_out;      // [nseg * 11] bucket bounds relative to the segment start
+
+    // per histogram tile (flat over all large segments, bucket-major inside a segment)
+    uint32_t* counts;  // [10 * tiles]
+    int64_t* pos;      // [10 * tiles + 1] exclusive prefix of counts
+
+    // per bucket (10 per segment)
+    int64_t* bstart;  // absolute first key of the bucket
+    int64_t* bsize;
+    int32_t* tsc;  // local-sort tiles of the bucket
+    int32_t* tsp;  // [10 * nseg + 1] prefix
+    int32_t* mcc;  // merge chunks of the bucket
+    int32_t* msp;  // [10 * nseg + 1] prefix
+
+    int32_t* split;  // co-rank at the start of each merge chunk of the current round
+    uint32_t* err;   // device-side validation flag (bad offsets)
+
+    int32_t tile;       // keys per local-sort tile (T)
+    int32_t nv;         // outputs per merge workgroup (divides T)
+    int64_t small_max;  // segments up to this size are sorted wholly in LDS
+};
+
+}  // namespace hs

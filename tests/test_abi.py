@@ -1,0 +1,79 @@
+"""The C-ABI library loads on the CPU and exports every symbol its header
+declares; host-only entry points behave (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hsort.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hsort_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2003_01216_amd as hs
+
+    return hs.load_library()
+
+
+def test_header_lists_the_boundary():
+    names = declared_functions()
+    for must in ["hsort_keys_i32", "hsort_keys_i64", "hsort_pairs", "hsort_segmented", "hsort_segmented_i64",
+                 "hsort_scratch_bytes", "hsort_check", "hsort_last_error"]:
+        assert must in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_binding_names_match_header():
+    import paper_2003_01216_amd as hs
+
+    assert sorted(hs.EXPORTS) == declared_functions()
+
+
+def test_scratch_bytes_host_only(lib):
+    import paper_2003_01216_amd as hs
+
+    small = hs.scratch_bytes(hs.KEYS_I32, 1000)
+    big = hs.scratch_bytes(hs.KEYS_I32, 1 << 20)
+    assert 0 < small < big
+    assert big >= 4 * (1 << 20)  # at least the ping-pong copy of the keys
+    assert hs.scratch_bytes(hs.PAIRS_I32_U32, 1 << 20) >= 8 * (1 << 20)
+    assert hs.scratch_bytes(hs.KEYS_I64, 1 << 20) >= 8 * (1 << 20)
+    assert hs.scratch_bytes(hs.SEG_I32, 1 << 20, 5000) > hs.scratch_bytes(hs.SEG_I32, 1 << 20, 1)
+    assert hs.scratch_bytes(99, 10, 1) == 0
+
+
+def test_argument_errors_are_synchronous(lib):
+    # rejected before any device work: no GPU is touched
+    assert lib.hsort_keys_i32(None, 10, None, 0, None) == 1
+    assert b"null" in lib.hsort_last_error()
+    assert lib.hsort_keys_i32(None, -1, None, 0, None) == 1
+    assert lib.hsort_keys_i32(None, 0, None, 0, None) == 0  # n == 0 is a no-op
+    assert lib.hsort_keys_i64(None, 1 << 40, None, 0, None) == 4
+    assert lib.hsort_segmented(None, 10, None, -1, 0, None, 0, None) == 1
+    assert lib.hsort_segmented(None, 0, None, 0, 0, None, 0, None) == 0
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.hsort_keys_i32(fake, 1 << 20, fake, 16, None) == 2  # scratch too small
+    assert b"scratch" in lib.hsort_last_error()
+
+
+def test_config_roundtrip(lib):
+    import paper_2003_01216_amd as hs
+
+    t, m, s = hs.hsort_get_config(hs.KEYS_I32)
+    assert t % m == 0 and s <= 8192
+    with pytest.raises(hs.HsortError):
+        hs.hsort_set_config(hs.KEYS_I32, 1000, 4096, 100)
+    hs.hsort_set_config(hs.KEYS_I32, t, m, s)
+    assert hs.hsort_get_config(hs.KEYS_I32) == (t, m, s)

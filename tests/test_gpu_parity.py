@@ -1,0 +1,309 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Integer sorting has one correct answer, so every comparison is bit-exact.
+Sizes the oracle finishes in seconds are compared element by element; the
+full-size workloads (2^28 keys) are checked through properties that fix the
+result uniquely (sorted + same multiset, and for stable pairs with
+payload = index: keys sorted, payload a permutation, every pair an input
+pair, payload increasing inside equal keys) plus order statistics sampled by
+the oracle's counting definition.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def hs():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2003_01216_amd as hs
+
+    hs.load_library()
+    return hs
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def gpu_keys(hs, k):
+    t = dev(k)
+    hs.hsort_keys(t)
+    return t.cpu().numpy()
+
+
+def gpu_pairs(hs, k, v):
+    tk = dev(k)
+    tv = dev(v.view(np.int32))
+    hs.hsort_pairs(tk, tv)
+    return tk.cpu().numpy(), tv.cpu().numpy().view(np.uint32)
+
+
+# ------------------------------------------------------------ plain int32
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_uniform_2e20_matches_oracle(hs, orc, seed):
+    k = W.uniform_i32(2**20, seed)
+    say(f"uniform 2^20 seed {seed}")
+    assert np.array_equal(gpu_keys(hs, k), orc.sort_keys(k))
+
+
+@pytest.mark.parametrize("name", sorted(W.adversarial_i32().keys()))
+def test_adversarial_i32(hs, orc, name):
+    k = W.adversarial_i32()[name]
+    say(f"adversarial {name} n={k.size}")
+    assert np.array_equal(gpu_keys(hs, k), orc.sort_keys(k))
+
+
+@pytest.mark.parametrize("n", [1, 2, 255, 256, 257, 2047, 2048, 2049, 4095, 4096, 4097, 8191, 8192, 8193, 12289, 40000])
+def test_sizes_around_tiles_i32(hs, orc, n):
+    k = W.uniform_i32(n, n)
+    say(f"sizes n={n}")
+    assert np.array_equal(gpu_keys(hs, k), orc.sort_keys(k))
+
+
+# ------------------------------------------------------------ plain int64
+def _i64_cases():
+    r = np.random.default_rng(5)
+    I = np.iinfo(np.int64)
+    cases = {}
+    for n in [1, 3, 300, 4095, 4096, 4097, 9000, 100_003, 2**20]:
+        cases[f"full_n{n}"] = r.integers(I.min, I.max, n, dtype=np.int64, endpoint=True)
+    cases["extremes"] = r.choice(np.array([I.min, I.min + 1, -1, 0, 1, I.max - 1, I.max], np.int64), 30000)
+    cases["small_range"] = r.integers(-500, 500, 50000).astype(np.int64)
+    cases["all_equal"] = np.full(20000, -77, np.int64)
+    cases["reverse"] = np.sort(r.integers(I.min, I.max, 50000, dtype=np.int64))[::-1].copy()
+    cases["nonneg_19digit"] = r.integers(0, I.max, 50000, dtype=np.int64)
+    return cases
+
+
+@pytest.mark.parametrize("name", sorted(_i64_cases().keys()))
+def test_int64(hs, orc, name):
+    k = _i64_cases()[name]
+    say(f"int64 {name} n={k.size}")
+    assert np.array_equal(gpu_keys(hs, k), orc.sort_keys(k))
+
+
+# ------------------------------------------------------------ stable pairs
+@pytest.mark.parametrize("n", [1, 5, 1000, 4095, 4096, 4097, 65537, 2**20 + 11])
+def test_pairs_duplicates(hs, orc, n):
+    k, v = W.dup_pairs_i32(n, n)
+    say(f"pairs dup n={n}")
+    gk, gv = gpu_pairs(hs, k, v)
+    ok, ov = orc.sort_pairs(k, v)
+    assert np.array_equal(gk, ok) and np.array_equal(gv, ov)
+
+
+@pytest.mark.parametrize("kind", ["uniform", "all_equal", "two_values", "random_payload"])
+def test_pairs_variants(hs, orc, kind):
+    r = np.random.default_rng(9)
+    n = 300_001
+    if kind == "uniform":
+        k = W.uniform_i32(n, 4)
+    elif kind == "all_equal":
+        k = np.full(n, 5, np.int32)
+    elif kind == "two_values":
+        k = r.choice(np.array([-3, 1 << 30], np.int32), n)
+    else:
+        k = r.integers(-1000, 1000, n).astype(np.int32)
+    v = np.arange(n, dtype=np.uint32) if kind != "random_payload" else r.integers(0, 2**32, n, dtype=np.uint32)
+    say(f"pairs {kind}")
+    gk, gv = gpu_pairs(hs, k, v)
+    ok, ov = orc.sort_pairs(k, v)
+    assert np.array_equal(gk, ok) and np.array_equal(gv, ov)
+
+
+# -------------------------------------------------- intermediate results
+def _stage_inputs():
+    return {
+        "uniform": W.uniform_i32(100_000, 21),
+        "three_digit": np.random.default_rng(22).integers(0, 1000, 70_000).astype(np.int32),
+        "loguniform": W.loguniform_i32(90_000, 23),
+        "negatives": np.random.default_rng(24).integers(-(2**31), 2**31 - 1, 50_000, dtype=np.int32),
+        "tiny": np.array([523, 17, 999, 0, 140, 523, 88, 301], np.int32),
+    }
+
+
+@pytest.mark.parametrize("name", sorted(_stage_inputs().keys()))
+def test_bounds_match_oracle(hs, orc, name):
+    k = _stage_inputs()[name]
+    say(f"bounds {name}")
+    t = dev(k)
+    s = torch.empty(hs.scratch_bytes(hs.KEYS_I32, k.size), dtype=torch.uint8, device="cuda")
+    hs.hsort_keys(t, scratch=s)
+    torch.cuda.synchronize()
+    got = hs.read_bounds(s, hs.KEYS_I32, k.size).cpu().numpy()[0]
+    assert np.array_equal(got, orc.bounds(k))
+
+
+@pytest.mark.parametrize("name", sorted(_stage_inputs().keys()))
+def test_stage_scatter_matches_oracle(hs, orc, name):
+    k = _stage_inputs()[name]
+    say(f"stage scatter {name}")
+    t = dev(k)
+    hs.hsort_debug_stage(t, 1)
+    ok, _, _ = orc.scatter(k)
+    assert np.array_equal(t.cpu().numpy(), ok)
+
+
+@pytest.mark.parametrize("name", sorted(_stage_inputs().keys()))
+def test_stage_local_sorts_match_oracle(hs, orc, name):
+    k = _stage_inputs()[name]
+    tile, _, _ = hs.hsort_get_config(hs.KEYS_I32)
+    say(f"stage tiles {name} tile={tile}")
+    t = dev(k)
+    hs.hsort_debug_stage(t, 2)
+    ok, _, _ = orc.bucket_tiles(k, tile)
+    assert np.array_equal(t.cpu().numpy(), ok)
+
+
+def test_stage_pairs_scatter_and_tiles(hs, orc):
+    k, v = W.dup_pairs_i32(200_003, 31)
+    tile, _, _ = hs.hsort_get_config(hs.PAIRS_I32_U32)
+    for stage in (1, 2):
+        say(f"pairs stage {stage}")
+        tk, tv = dev(k), dev(v.view(np.int32))
+        hs.hsort_debug_stage(tk, stage, vals=tv)
+        if stage == 1:
+            ok, ov, _ = orc.scatter(k, v)
+        else:
+            ok, ov, _ = orc.bucket_tiles(k, tile, v)
+        assert np.array_equal(tk.cpu().numpy(), ok)
+        assert np.array_equal(tv.cpu().numpy().view(np.uint32), ov)
+
+
+def test_stage_int64(hs, orc):
+    k = _i64_cases()["full_n100003"]
+    tile, _, _ = hs.hsort_get_config(hs.KEYS_I64)
+    for stage in (1, 2):
+        say(f"int64 stage {stage}")
+        t = dev(k)
+        hs.hsort_debug_stage(t, stage)
+        ok = orc.scatter(k)[0] if stage == 1 else orc.bucket_tiles(k, tile)[0]
+        assert np.array_equal(t.cpu().numpy(), ok)
+
+
+# --------------------------------------------------------------- segmented
+def _segmented_case(dtype, nseg, max_len, seed):
+    keys, off = W.segments_i32(nseg, max_len, seed)
+    sizes = np.diff(off)
+    r = np.random.default_rng(seed)
+    sizes[r.integers(0, nseg, max(1, nseg // 20))] = 0  # some empty segments
+    sizes[r.integers(0, nseg, max(1, nseg // 20))] = 1
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    n = int(off[-1])
+    if dtype == np.int64:
+        I = np.iinfo(np.int64)
+        keys = r.integers(I.min, I.max, n, dtype=np.int64, endpoint=True)
+    else:
+        keys = keys[:n].copy()
+    return keys, off
+
+
+@pytest.mark.parametrize("dtype", [np.int32, np.int64])
+@pytest.mark.parametrize("nseg,max_len", [(1, 100_000), (7, 3000), (300, 2**16), (2000, 2**13)])
+def test_segmented_matches_oracle(hs, orc, dtype, nseg, max_len):
+    keys, off = _segmented_case(dtype, nseg, max_len, 40 + nseg)
+    say(f"segmented {np.dtype(dtype).name} nseg={nseg} n={keys.size}")
+    t, o = dev(keys), dev(off)
+    kind = hs.SEG_I32 if dtype == np.int32 else hs.SEG_I64
+    s = torch.empty(hs.scratch_bytes(kind, keys.size, nseg), dtype=torch.uint8, device="cuda")
+    hs.hsort_segmented(t, o, scratch=s)
+    hs.hsort_check(s)
+    ok, ob = orc.sort_segmented(keys, off)
+    assert np.array_equal(t.cpu().numpy(), ok)
+    assert np.array_equal(hs.read_bounds(s, kind, keys.size, nseg).cpu().numpy(), ob)
+
+
+def test_segmented_subrange_leaves_outside_untouched(hs, orc):
+    r = np.random.default_rng(3)
+    keys = r.integers(0, 10**9, 50_000).astype(np.int32)
+    off = np.array([1000, 1000, 5000, 30000, 45000], np.int64)
+    say("segmented subrange")
+    t = dev(keys)
+    hs.hsort_segmented(t, dev(off))
+    got = t.cpu().numpy()
+    assert np.array_equal(got[:1000], keys[:1000]) and np.array_equal(got[45000:], keys[45000:])
+    ok, _ = orc.sort_segmented(keys, off)
+    assert np.array_equal(got[1000:45000], ok[1000:45000])
+
+
+def test_invalid_offsets_are_reported(hs):
+    keys = np.arange(1000, 0, -1).astype(np.int32)
+    off = np.array([0, 600, 300, 1000], np.int64)  # decreasing
+    say("invalid offsets")
+    t = dev(keys)
+    s = torch.empty(hs.scratch_bytes(hs.SEG_I32, 1000, 3), dtype=torch.uint8, device="cuda")
+    hs.hsort_segmented(t, dev(off), scratch=s)
+    with pytest.raises(hs.HsortError) as e:
+        hs.hsort_check(s)
+    assert e.value.code == hs.HSORT_ERR_INVALID
+    assert np.array_equal(t.cpu().numpy(), keys)  # nothing was touched
+    off2 = np.array([0, 600, 1001], np.int64)  # past the end
+    hs.hsort_segmented(t, dev(off2), scratch=s)
+    with pytest.raises(hs.HsortError):
+        hs.hsort_check(s)
+
+
+def test_repeat_is_deterministic(hs):
+    k = W.uniform_i32(3_000_001, 8)
+    a = gpu_keys(hs, k)
+    b = gpu_keys(hs, k)
+    assert np.array_equal(a, b)
+
+
+# ------------------------------------------------------------- full sizes
+@pytest.mark.parametrize("dist", ["uniform", "loguniform"])
+def test_2e26_matches_oracle(hs, orc, dist):
+    n = 2**26
+    k = W.uniform_i32(n, 0) if dist == "uniform" else W.loguniform_i32(n, 0)
+    say(f"2^26 {dist}")
+    got = gpu_keys(hs, k)
+    assert np.array_equal(got, orc.sort_keys(k))
+
+
+def _sampled_order_statistics(orc, inp, out, count=12, seed=0):
+    r = np.random.default_rng(seed)
+    js = np.concatenate([[0, out.size - 1], r.integers(0, out.size, count)])
+    for j in js:
+        lt, le = orc.count_lt_le(inp, out[j])
+        assert lt <= j < le, (j, out[j], lt, le)
+
+
+def test_2e28_uniform_properties_and_samples(hs, orc):
+    n = 2**28
+    k = W.uniform_i32(n, 0)
+    say("2^28 uniform keys")
+    out = gpu_keys(hs, k)
+    assert out.size == n
+    assert np.all(out[1:] >= out[:-1])
+    for f in (lambda a: int(a.astype(np.int64).sum()), lambda a: int(np.bitwise_xor.reduce(a)),
+              lambda a: int((a.astype(np.uint64) * a.astype(np.uint64)).sum())):
+        assert f(out) == f(k)
+    _sampled_order_statistics(orc, k, out)
+
+
+def test_2e28_stable_pairs_properties(hs):
+    n = 2**28
+    k, v = W.dup_pairs_i32(n, 0)
+    say("2^28 pairs")
+    gk, gv = gpu_pairs(hs, k, v)
+    assert np.all(gk[1:] >= gk[:-1])
+    seen = np.zeros(n, np.bool_)
+    seen[gv] = True
+    assert seen.all()  # payload is a permutation of the indices
+    assert np.array_equal(k[gv], gk)  # every output pair is an input pair
+    same = gk[1:] == gk[:-1]
+    assert np.all(gv[1:][same] > gv[:-1][same])  # input order kept inside equal keys
