@@ -1,0 +1,246 @@
+#!/usr/bin/env python
+"""Benchmark of the hsort hot path on one MI355X.
+
+Workload (the headline metric): n = 2^28 int32 keys uniform in [0, 2^31-1),
+keys only, sorted by the full method (one-step decimal MSD partition into ten
+buckets, LDS tile sort of each bucket's partitions, merge-path merge rounds).
+A step is one complete sort of one resident copy of that array; every step
+sorts its own pristine copy, all copies in HBM before the timed region.
+
+Prints ONE JSON line on stdout:
+  value      Gkeys/s over the K timed steps (n * K / elapsed)
+  roofline   the dominant kernel's algorithmic bytes per launch / its average
+             launch time (HIP events on the sorting stream) vs 8 TB/s HBM peak
+  cpu_baseline  the CPU oracle (single-threaded) on a bounded sample of the
+             same workload
+  extra      per-kernel table and the other workloads (stable pairs with
+             heavy duplicates, skewed keys, int64 keys, batched segmented vs
+             a per-array loop of the plain method)
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+import workloads as W
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_table(rec, steps):
+    """{name: {launches, ms_per_launch, GB/s, frac}} from hsort_timing_read()."""
+    out = {}
+    for name, (launches, ms, by) in rec.items():
+        d = {"launches_per_step": launches / steps, "ms_per_step": ms / steps,
+             "avg_ms_per_launch": ms / max(launches, 1)}
+        if by > 0 and ms > 0:
+            gbs = by / (ms * 1e-3) / 1e9
+            d["GBps"] = round(gbs, 1)
+            d["frac_hbm_peak"] = round(gbs / HBM_PEAK_GBS, 4)
+            d["bytes_per_launch"] = by / launches
+        out[name] = d
+    return out
+
+
+def timed_sorts(hs, torch, make_copies, run_one, steps, warmup, timing=True):
+    """Run `warmup` untimed then `steps` timed calls, each on its own copy."""
+    copies = make_copies(steps + warmup)
+    for i in range(warmup):
+        run_one(copies[i])
+    torch.cuda.synchronize()
+    hs.hsort_timing_read()  # drop warm-up records
+    hs.hsort_timing_enable(timing)
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    for i in range(steps):
+        run_one(copies[warmup + i])
+    b.record()
+    torch.cuda.synchronize()
+    hs.hsort_timing_enable(False)
+    rec = hs.hsort_timing_read()
+    return a.elapsed_time(b), rec, copies
+
+
+def bench_metric(hs, torch, n, steps, warmup):
+    k = W.uniform_i32(n, 0)
+    base = torch.from_numpy(k).cuda()
+    scratch = torch.empty(hs.scratch_bytes(hs.KEYS_I32, n), dtype=torch.uint8, device="cuda")
+
+    def make(m):
+        return [base.clone() for _ in range(m)]
+
+    ms, rec, copies = timed_sorts(hs, torch, make, lambda t: hs.hsort_keys(t, scratch), steps, warmup)
+    last = copies[-1]
+    ok = bool(torch.all(last[1:] >= last[:-1]).item()) and int(last.to(torch.int64).sum()) == int(k.astype(np.int64).sum())
+    del copies
+    torch.cuda.empty_cache()
+    return ms, rec, ok
+
+
+def bench_pairs(hs, torch, n, steps, warmup):
+    k, v = W.dup_pairs_i32(n, 0)
+    bk, bv = torch.from_numpy(k).cuda(), torch.from_numpy(v.view(np.int32)).cuda()
+    scratch = torch.empty(hs.scratch_bytes(hs.PAIRS_I32_U32, n), dtype=torch.uint8, device="cuda")
+
+    def make(m):
+        return [(bk.clone(), bv.clone()) for _ in range(m)]
+
+    ms, rec, copies = timed_sorts(hs, torch, make, lambda kv: hs.hsort_pairs(kv[0], kv[1], scratch), steps, warmup)
+    del copies
+    torch.cuda.empty_cache()
+    return n * steps / (ms * 1e-3) / 1e9, kernel_table(rec, steps)
+
+
+def bench_keys(hs, torch, k, steps, warmup):
+    base = torch.from_numpy(k).cuda()
+    kind = hs.KEYS_I32 if k.dtype == np.int32 else hs.KEYS_I64
+    scratch = torch.empty(hs.scratch_bytes(kind, k.size), dtype=torch.uint8, device="cuda")
+    ms, rec, copies = timed_sorts(hs, torch, lambda m: [base.clone() for _ in range(m)],
+                                  lambda t: hs.hsort_keys(t, scratch), steps, warmup)
+    del copies
+    torch.cuda.empty_cache()
+    return k.size * steps / (ms * 1e-3) / 1e9, kernel_table(rec, steps)
+
+
+def bench_segmented(hs, torch, steps, warmup):
+    """16384 arrays, log-uniform sizes in [1, 2^16]: one batched call vs a loop of plain calls."""
+    keys, off = W.segments_i32(16384, 2**16, 0)
+    n = keys.size
+    base = torch.from_numpy(keys).cuda()
+    doff = torch.from_numpy(off).cuda()
+    max_len = int(np.diff(off).max())
+    scratch = torch.empty(hs.scratch_bytes(hs.SEG_I32, n, 16384), dtype=torch.uint8, device="cuda")
+    ms, rec, copies = timed_sorts(hs, torch, lambda m: [base.clone() for _ in range(m)],
+                                  lambda t: hs.hsort_segmented(t, doff, max_seg_len=max_len, scratch=scratch),
+                                  steps, warmup)
+    batched = n * steps / (ms * 1e-3) / 1e9
+    del copies
+    # per-array loop of the plain method on sub-views, same stream, same scratch
+    loop_scratch = torch.empty(hs.scratch_bytes(hs.KEYS_I32, max_len), dtype=torch.uint8, device="cuda")
+    offs = off.tolist()
+    work = base.clone()
+
+    def loop(t):
+        for i in range(16384):
+            a, b = offs[i], offs[i + 1]
+            if b > a:
+                hs.hsort_keys(t[a:b], loop_scratch)
+
+    loop(base.clone())  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loop(work)
+    torch.cuda.synchronize()
+    loop_s = time.perf_counter() - t0
+    per_loop = n / loop_s / 1e9
+    torch.cuda.empty_cache()
+    return {"workload": "16384 int32 arrays, sizes log-uniform [1, 2^16], keys uniform [0, 2^31-1)",
+            "keys": int(n), "batched_Gkeys_s": round(batched, 3), "per_array_loop_Gkeys_s": round(per_loop, 4),
+            "speedup": round(batched / per_loop, 1), "batched_kernels": kernel_table(rec, steps)}
+
+
+def cpu_baseline(samples=4, n=2**24):
+    """The oracle (single-threaded C) on `samples` arrays of n keys of the metric's distribution."""
+    import oracle
+
+    total = 0.0
+    for s in range(samples):
+        k = W.uniform_i32(n, 100 + s)
+        t0 = time.perf_counter()
+        oracle.sort_keys(k)
+        total += time.perf_counter() - t0
+    return {"value": round(samples * n / total / 1e9, 5), "unit": "Gkeys/s", "cores": 1, "kind": "oracle",
+            "sample": f"{samples} arrays of 2^{int(np.log2(n))} int32 keys uniform in [0, 2^31-1) "
+                      f"(seeds 100..{99 + samples}), {total:.1f} s of CPU"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--log2n", type=int, default=28, help="keys in the metric workload (2^log2n)")
+    ap.add_argument("--no-extras", action="store_true", help="only the metric workload")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}, WORLD_SIZE {world}); "
+              "the sort has no multi-GPU path in this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2003_01216_amd as hs
+
+    hs.load_library()
+    n = 1 << args.log2n
+    log(f"[bench] metric workload: 2^{args.log2n} int32 uniform keys, {args.steps} steps, {args.warmup} warm-up")
+    ms, rec, ok = bench_metric(hs, torch, n, args.steps, args.warmup)
+    if not ok:
+        log("[bench] ERROR: output of the last step is not sorted")
+        sys.exit(1)
+    ms_step = ms / args.steps
+    value = n / (ms_step * 1e-3) / 1e9
+    table = kernel_table(rec, args.steps)
+    log(f"[bench] {value:.2f} Gkeys/s, {ms_step:.3f} ms/step")
+    for name, d in table.items():
+        log(f"[bench]   {name:10s} {d['ms_per_step']:.3f} ms/step  {d.get('GBps', '-')} GB/s")
+    dom = max((kv for kv in table.items() if "GBps" in kv[1]), key=lambda kv: kv[1]["ms_per_step"])
+    roof = {"bound": "hbm", "kernel": dom[0], "achieved": dom[1]["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(dom[1]["GBps"] / HBM_PEAK_GBS, 4), "traffic": None}
+    total_bytes = sum(d.get("bytes_per_launch", 0) * d["launches_per_step"] for d in table.values())
+    extra = {"kernels": table, "algorithmic_bytes_per_key": round(total_bytes / n, 2),
+             "whole_sort_frac_hbm_peak": round(total_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+    if not args.no_extras:
+        log("[bench] stable pairs 2^28, keys in [0,1000), payload = index")
+        extra["pairs_dup_2e28_Gkeys_s"], extra["pairs_kernels"] = bench_pairs(hs, torch, 2**28, 5, 1)
+        log("[bench] 2^26 uniform / log-uniform / int64 full range")
+        extra["uniform_2e26_Gkeys_s"] = round(bench_keys(hs, torch, W.uniform_i32(2**26, 0), 10, 2)[0], 3)
+        extra["loguniform_2e26_Gkeys_s"] = round(bench_keys(hs, torch, W.loguniform_i32(2**26, 0), 10, 2)[0], 3)
+        extra["int64_full_range_2e26_Gkeys_s"] = round(bench_keys(hs, torch, W.uniform_i64(2**26, 0), 10, 2)[0], 3)
+        log("[bench] batched segmented vs per-array loop")
+        extra["segmented"] = bench_segmented(hs, torch, 10, 2)
+
+    cpu = None
+    if not args.no_cpu:
+        log("[bench] CPU oracle baseline")
+        cpu = cpu_baseline()
+
+    line = {
+        "metric": "Gkeys/s + % HBM peak, int32 n=2^28; batched segmented vs per-array plain",
+        "value": round(value, 3),
+        "unit": "Gkeys/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": f"sort 2^{args.log2n} int32 keys uniform in [0, 2^31-1), keys only, seed 0",
+                   "n": n, "parallelism": "one GPU"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "extra": extra,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -63,6 +63,12 @@ struct Rec {
     std::string name;
     hipEvent_t a, b;
     double bytes;
+    // merge rounds: bytes = per_key * keys of the buckets still merging,
+    // read from the bucket table left in scratch when the records are read
+    const int64_t* bsize = nullptr;
+    int64_t nb = 0, tile = 0;
+    int pass = 0;
+    double per_key = 0;
 };
 bool g_timing = false;
 std::vector<Rec> g_recs;
@@ -73,6 +79,7 @@ struct Timer {
     std::string name;
     double bytes;
     hipEvent_t a = nullptr, b = nullptr;
+    Rec deferred{};
     Timer(hipStream_t s, const char* n, double by) : st(s), name(n), bytes(by) {
         {
             std::lock_guard<std::mutex> lk(g_mu);
@@ -87,8 +94,20 @@ struct Timer {
     ~Timer() {
         if (!on) return;
         hipEventRecord(b, st);
+        Rec r = deferred;
+        r.name = name;
+        r.a = a;
+        r.b = b;
+        r.bytes = bytes;
         std::lock_guard<std::mutex> lk(g_mu);
-        g_recs.push_back({name, a, b, bytes});
+        g_recs.push_back(r);
+    }
+    void per_active_key(const int64_t* bsize, int64_t nb, int64_t tile, int pass, double per_key) {
+        deferred.bsize = bsize;
+        deferred.nb = nb;
+        deferred.tile = tile;
+        deferred.pass = pass;
+        deferred.per_key = per_key;
     }
 };
 
@@ -321,7 +340,8 @@ int run(int kind, K* keys, uint32_t* vals, int64_t n, const int64_t* off, int64_
                 HS_TRY(launch_partition<K>(w, p, L.chunks_bound, st));
             }
             {
-                Timer t(st, "merge", 2 * kb * n);
+                Timer t(st, "merge", 0);
+                t.per_active_key(w.bsize, L.buckets, c.tile, p, 2 * kb);
                 HS_TRY((merge_by_shape<K, PAIRS>(c.merge_nv, w, p, L.chunks_bound, st)));
             }
         }
@@ -483,9 +503,22 @@ int64_t hsort_timing_read(char* out, int64_t cap) {
         double ms, bytes;
     };
     std::vector<Agg> agg;
+    const int64_t* cached_ptr = nullptr;
+    std::vector<int64_t> sizes;
     for (Rec& r : recs) {
         float ms = 0;
         hipEventSynchronize(r.b);
+        if (r.bsize) {
+            if (r.bsize != cached_ptr || (int64_t)sizes.size() != r.nb) {
+                sizes.assign((size_t)r.nb, 0);
+                hipMemcpy(sizes.data(), r.bsize, sizeof(int64_t) * r.nb, hipMemcpyDeviceToHost);
+                cached_ptr = r.bsize;
+            }
+            double active = 0;
+            for (int64_t v : sizes)
+                if (merge_rounds(v, r.tile) > r.pass) active += (double)v;
+            r.bytes = r.per_key * active;
+        }
         hipEventElapsedTime(&ms, r.a, r.b);
         hipEventDestroy(r.a);
         hipEventDestroy(r.b);
