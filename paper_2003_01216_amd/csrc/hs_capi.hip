@@ -118,7 +118,7 @@ int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 struct Layout {
     // byte offsets into scratch
-    size_t err, own_off, skeys, svals, segmin, segmax, plans, tilecnt, tilepre, bounds, counts, pos, bstart, bsize, tsc,
+    size_t err, own_off, skeys, svals, tmin, tmax, rounds, plans, tilecnt, tilepre, bounds, counts, pos, bstart, bsize, tsc,
         tsp, mcc, msp, split, part32, part64, total;
     // item bounds
     int64_t large_bound, tiles_bound, buckets, ts_bound, chunks_bound;
@@ -148,8 +148,9 @@ Layout make_layout(int kind, int64_t n, int64_t nseg, const Config& c) {
     L.bounds = take(sizeof(int64_t) * 11 * nseg);
     L.skeys = take(ksz * n);
     L.svals = pairs ? take(4 * n) : 0;
-    L.segmin = take(ksz * nseg);
-    L.segmax = take(ksz * nseg);
+    L.tmin = take(ksz * L.tiles_bound);
+    L.tmax = take(ksz * L.tiles_bound);
+    L.rounds = take(4);
     L.plans = take((ksz == 8 ? sizeof(DigitPlan<int64_t>) : sizeof(DigitPlan<int32_t>)) * nseg);
     L.tilecnt = take(4 * nseg);
     L.tilepre = take(4 * (nseg + 1));
@@ -180,8 +181,9 @@ Work<K> make_work(const Layout& L, char* scr, K* keys, uint32_t* vals, const int
     w.off = off ? off : (const int64_t*)(scr + L.own_off);
     w.n = n;
     w.nseg = (int32_t)nseg;
-    w.segmin = (K*)(scr + L.segmin);
-    w.segmax = (K*)(scr + L.segmax);
+    w.tmin = (K*)(scr + L.tmin);
+    w.tmax = (K*)(scr + L.tmax);
+    w.rounds = (int32_t*)(scr + L.rounds);
     w.plans = (DigitPlan<K>*)(scr + L.plans);
     w.tilecnt = (int32_t*)(scr + L.tilecnt);
     w.tilepre = (int32_t*)(scr + L.tilepre);

@@ -194,17 +194,13 @@ __device__ __forceinline__ void block_sort(W* words, int* sp) {
 // own_off: where a plain sort's one-segment offsets live (w.off points there).
 template <typename K>
 __global__ void k_init(Work<K> w, int64_t* own_off) {
-    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid == 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
         *w.err = 0;
+        *w.rounds = 0;
         if (own_off) {  // a plain sort is one segment [0, n)
             own_off[0] = 0;
             own_off[1] = w.n;
         }
-    }
-    for (int s = gid; s < w.nseg; s += gridDim.x * blockDim.x) {
-        w.segmin[s] = Traits<K>::kMax;
-        w.segmax[s] = Traits<K>::kMin;
     }
 }
 
@@ -221,65 +217,71 @@ __global__ void k_classify(Work<K> w) {
     }
 }
 
-// min/max of every large segment.  Each workgroup takes a contiguous run of
-// histogram tiles and flushes one atomic pair per segment it touched.
-template <typename K>
-__global__ __launch_bounds__(kHistNT) void k_range(Work<K> w) {
-    __shared__ K rmin[kHistNT / kWave], rmax[kHistNT / kWave];
-    if (*w.err) return;
-    const int total = w.tilepre[w.nseg];
-    const int per = (total + gridDim.x - 1) / gridDim.x;
-    const int t0 = blockIdx.x * per;
-    const int t1 = min(t0 + per, total);
-    if (t0 >= t1) return;
-    const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
-    int s = owner_of(w.tilepre, w.nseg, t0);
-    K mn = Traits<K>::kMax, mx = Traits<K>::kMin;
-    auto flush = [&](int seg) {
-        K a = wave_reduce_min(mn), b = wave_reduce_max(mx);
-        if (lane == 0) {
-            rmin[wave] = a;
-            rmax[wave] = b;
-        }
-        __syncthreads();
-        if (tid == 0) {
-            for (int q = 1; q < kHistNT / kWave; q++) {
-                a = rmin[q] < a ? rmin[q] : a;
-                b = rmax[q] > b ? rmax[q] : b;
-            }
-            atomic_min_k(&w.segmin[seg], a);
-            atomic_max_k(&w.segmax[seg], b);
-        }
-        __syncthreads();
-        mn = Traits<K>::kMax;
-        mx = Traits<K>::kMin;
-    };
-    for (int t = t0; t < t1; t++) {
-        while (t >= w.tilepre[s + 1]) {
-            flush(s);
-            s++;
-        }
-        const int64_t base = w.off[s] + (int64_t)(t - w.tilepre[s]) * kHistTile;
-        const int cnt = (int)min((int64_t)kHistTile, w.off[s + 1] - base);
-        const K* src = w.keys + base;
-#pragma unroll
-        for (int j = 0; j < kHistVT; j++) {
-            const int q = j * kHistNT + tid;
-            if (q < cnt) {
-                K k = src[q];
-                mn = k < mn ? k : mn;
-                mx = k > mx ? k : mx;
-            }
-        }
+// min/max of every histogram tile (one workgroup per tile).
+template <typename T, int NT>
+__device__ __forceinline__ void block_minmax(T& mn, T& mx, T* rmn, T* rmx) {
+    const int lane = lane_id(), wave = threadIdx.x / kWave;
+    T a = wave_reduce_min(mn), b = wave_reduce_max(mx);
+    if (lane == 0) {
+        rmn[wave] = a;
+        rmx[wave] = b;
     }
-    flush(s);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NT / kWave; q++) {
+        a = rmn[q] < a ? rmn[q] : a;
+        b = rmx[q] > b ? rmx[q] : b;
+    }
+    mn = a;
+    mx = b;
+    __syncthreads();
 }
 
 template <typename K>
-__global__ void k_plans(Work<K> w) {
+__global__ __launch_bounds__(kHistNT) void k_range(Work<K> w) {
+    __shared__ K rmn[kHistNT / kWave], rmx[kHistNT / kWave];
+    const int t = blockIdx.x;
+    if (*w.err || t >= w.tilepre[w.nseg]) return;
+    const int tid = threadIdx.x;
+    const int s = owner_of(w.tilepre, w.nseg, t);
+    const int64_t base = w.off[s] + (int64_t)(t - w.tilepre[s]) * kHistTile;
+    const int cnt = (int)min((int64_t)kHistTile, w.off[s + 1] - base);
+    const K* src = w.keys + base;
+    K mn = Traits<K>::kMax, mx = Traits<K>::kMin;
+#pragma unroll
+    for (int j = 0; j < kHistVT; j++) {
+        const int q = j * kHistNT + tid;
+        if (q < cnt) {
+            K k = src[q];
+            mn = k < mn ? k : mn;
+            mx = k > mx ? k : mx;
+        }
+    }
+    block_minmax<K, kHistNT>(mn, mx, rmn, rmx);
+    if (tid == 0) {
+        w.tmin[t] = mn;
+        w.tmax[t] = mx;
+    }
+}
+
+// Per large segment: min/max over its tiles, then the decimal digit plan.
+template <typename K>
+__global__ __launch_bounds__(256) void k_plans(Work<K> w) {
+    __shared__ K rmn[256 / kWave], rmx[256 / kWave];
     if (*w.err) return;
-    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < w.nseg; s += gridDim.x * blockDim.x)
-        if (w.tilecnt[s] > 0) w.plans[s] = make_digit_plan<K>(w.segmin[s], w.segmax[s]);
+    for (int s = blockIdx.x; s < w.nseg; s += gridDim.x) {
+        const int nt = w.tilecnt[s];
+        if (nt == 0) continue;
+        const int t0 = w.tilepre[s];
+        K mn = Traits<K>::kMax, mx = Traits<K>::kMin;
+        for (int t = threadIdx.x; t < nt; t += 256) {
+            const K a = w.tmin[t0 + t], b = w.tmax[t0 + t];
+            mn = a < mn ? a : mn;
+            mx = b > mx ? b : mx;
+        }
+        block_minmax<K, 256>(mn, mx, rmn, rmx);
+        if (threadIdx.x == 0) w.plans[s] = make_digit_plan<K>(mn, mx);
+    }
 }
 
 // ------------------------------------------------------------- histogram
@@ -290,27 +292,25 @@ __global__ void k_plans(Work<K> w) {
 template <typename K>
 __global__ __launch_bounds__(kHistNT) void k_hist(Work<K> w) {
     __shared__ uint32_t red[kHistNT / kWave][5];
-    if (*w.err) return;
-    const int total = w.tilepre[w.nseg];
+    const int t = blockIdx.x;
+    if (*w.err || t >= w.tilepre[w.nseg]) return;
     const int tid = threadIdx.x;
-    for (int t = blockIdx.x; t < total; t += gridDim.x) {
-        const int s = owner_of(w.tilepre, w.nseg, t);
-        const int i = t - w.tilepre[s];
-        const int64_t base = w.off[s] + (int64_t)i * kHistTile;
-        const int cnt = (int)min((int64_t)kHistTile, w.off[s + 1] - base);
-        const DigitPlan<K> pl = w.plans[s];
-        const K* src = w.keys + base;
-        uint64_t c = 0;
+    const int s = owner_of(w.tilepre, w.nseg, t);
+    const int i = t - w.tilepre[s];
+    const int64_t base = w.off[s] + (int64_t)i * kHistTile;
+    const int cnt = (int)min((int64_t)kHistTile, w.off[s + 1] - base);
+    const DigitPlan<K> pl = w.plans[s];
+    const K* src = w.keys + base;
+    uint64_t c = 0;
 #pragma unroll
-        for (int j = 0; j < kHistVT; j++) {
-            const int q = j * kHistNT + tid;
-            if (q < cnt) c += 1ull << (5 * digit_of(pl, src[q]));
-        }
-        uint32_t wd[5];
-        unpack5(c, wd);
-        block_sum5<kHistNT>(wd, red);
-        if (tid < 10) w.counts[10 * w.tilepre[s] + tid * w.tilecnt[s] + i] = field16(wd, tid);
+    for (int j = 0; j < kHistVT; j++) {
+        const int q = j * kHistNT + tid;
+        if (q < cnt) c += 1ull << (5 * digit_of(pl, src[q]));
     }
+    uint32_t wd[5];
+    unpack5(c, wd);
+    block_sum5<kHistNT>(wd, red);
+    if (tid < 10) w.counts[10 * w.tilepre[s] + tid * w.tilecnt[s] + i] = field16(wd, tid);
 }
 
 // Bucket table: start and size of each of the ten buckets of every segment,
@@ -341,6 +341,8 @@ __global__ void k_btab(Work<K> w) {
             w.tsc[10 * s + d] = (int32_t)((sz + w.tile - 1) / w.tile);
             w.mcc[10 * s + d] = (int32_t)((sz + w.nv - 1) / w.nv);
             w.bounds_out[11 * (int64_t)s + d] = st;
+            const int r = merge_rounds(sz, w.tile);
+            if (r > 0) atomicMax(w.rounds, r);
         }
         w.bounds_out[11 * (int64_t)s + 10] = w.off[s + 1] - a;
     }
@@ -359,87 +361,89 @@ __global__ __launch_bounds__(kHistNT) void k_scatter(Work<K> w) {
     __shared__ uint8_t sd[HT];
     __shared__ uint32_t red[NT / kWave][5];
     __shared__ int64_t dbase[10];
-    if (*w.err) return;
-    const int total = w.tilepre[w.nseg];
+    const int t = blockIdx.x;
+    if (*w.err || t >= w.tilepre[w.nseg]) return;
     const int tid = threadIdx.x;
-    for (int t = blockIdx.x; t < total; t += gridDim.x) {
-        const int s = owner_of(w.tilepre, w.nseg, t);
-        const int i = t - w.tilepre[s];
-        const int nt = w.tilecnt[s];
-        const int64_t base = w.off[s] + (int64_t)i * HT;
-        const int cnt = (int)min((int64_t)HT, w.off[s + 1] - base);
-        const DigitPlan<K> pl = w.plans[s];
-        // 1. coalesced load, natural order
+    const int s = owner_of(w.tilepre, w.nseg, t);
+    const int i = t - w.tilepre[s];
+    const int nt = w.tilecnt[s];
+    const int64_t base = w.off[s] + (int64_t)i * HT;
+    const int cnt = (int)min((int64_t)HT, w.off[s + 1] - base);
+    const DigitPlan<K> pl = w.plans[s];
+    // 1. coalesced load, natural order
 #pragma unroll
-        for (int j = 0; j < VT; j++) {
-            const int q = j * NT + tid;
-            if (q < cnt) {
-                sk[lds_pad<K>(q)] = w.keys[base + q];
-                if constexpr (PAIRS) sv[q] = w.vals[base + q];
-            }
+    for (int j = 0; j < VT; j++) {
+        const int q = j * NT + tid;
+        if (q < cnt) {
+            sk[lds_pad<K>(q)] = w.keys[base + q];
+            if constexpr (PAIRS) sv[q] = w.vals[base + q];
         }
-        __syncthreads();
-        // 2. blocked: digits and ranks among this thread's own keys
-        K key[VT];
-        uint32_t val[VT];
-        int dg[VT];
-        uint32_t rank[VT];
-        uint64_t c = 0;
+    }
+    if (tid < 10) {
+        const int64_t pbase = 10 * (int64_t)w.tilepre[s];
+        dbase[tid] = w.off[s] + w.pos[pbase + (int64_t)tid * nt + i] - w.pos[pbase];
+    }
+    __syncthreads();
+    // 2. blocked: digit and rank among this thread's own keys, packed as
+    //    rank << 4 | digit (digit 15 = no key)
+    K key[VT];
+    uint32_t val[PAIRS ? VT : 1];
+    uint32_t pk[VT];
+    uint64_t c = 0;
 #pragma unroll
-        for (int v = 0; v < VT; v++) {
-            const int q = tid * VT + v;
-            const bool ok = q < cnt;
-            key[v] = sk[lds_pad<K>(ok ? q : 0)];
-            if constexpr (PAIRS) val[v] = sv[ok ? q : 0];
-            const int d = ok ? digit_of(pl, key[v]) : 10;
-            dg[v] = d;
-            rank[v] = ok ? (uint32_t)(c >> (5 * d)) & 31u : 0u;
-            c += ok ? (1ull << (5 * d)) : 0ull;
+    for (int v = 0; v < VT; v++) {
+        const int q = tid * VT + v;
+        const bool ok = q < cnt;
+        key[v] = sk[lds_pad<K>(ok ? q : 0)];
+        if constexpr (PAIRS) val[v] = sv[ok ? q : 0];
+        const int d = digit_of(pl, key[v]);
+        pk[v] = ok ? ((((uint32_t)(c >> (5 * d)) & 31u) << 4) | (uint32_t)d) : 15u;
+        c += ok ? (1ull << (5 * d)) : 0ull;
+    }
+    // 3. exclusive scan over threads, and the tile's bucket totals
+    uint32_t wd[5], tot[5];
+    unpack5(c, wd);
+    block_excl5<NT>(wd, tot, red);  // ends with a barrier: sk may be overwritten
+    // 4. tile-local bucket starts folded into the packed prefix
+    uint32_t run = 0;
+#pragma unroll
+    for (int m = 0; m < 5; m++) {
+        const uint32_t lo = run;
+        run += tot[m] & 0xFFFFu;
+        const uint32_t hi = run;
+        run += tot[m] >> 16;
+        wd[m] += lo | (hi << 16);
+    }
+    // 5. stage grouped by bucket
+#pragma unroll
+    for (int v = 0; v < VT; v++) {
+        const uint32_t d = pk[v] & 15u;
+        if (d < 10) {
+            const int sp = (int)(field16(wd, (int)d) + (pk[v] >> 4));
+            sk[lds_pad<K>(sp)] = key[v];
+            sd[sp] = (uint8_t)d;
+            if constexpr (PAIRS) sv[sp] = val[v];
         }
-        // 3. exclusive scan over threads, and the tile's bucket totals
-        uint32_t wd[5], tot[5];
-        unpack5(c, wd);
-        block_excl5<NT>(wd, tot, red);  // ends with a barrier: sk is free
-        // 4. tile-local bucket starts, folded into the packed prefix
-        uint32_t tst[10];
-        uint32_t run = 0;
+    }
+    if (tid < 10) {  // dbase[d] -= tile-local start of bucket d
+        uint32_t st = 0, r2 = 0;
 #pragma unroll
         for (int d = 0; d < 10; d++) {
-            tst[d] = run;
-            run += field16(tot, d);
+            st = (d == tid) ? r2 : st;
+            r2 += (tot[d >> 1] >> ((d & 1) * 16)) & 0xFFFFu;
         }
+        dbase[tid] -= (int64_t)st;
+    }
+    __syncthreads();
+    // 6. coalesced runs out to the buckets
 #pragma unroll
-        for (int m = 0; m < 5; m++) wd[m] += tst[2 * m] | (tst[2 * m + 1] << 16);
-        if (tid < 10) {
-            const int64_t pbase = 10 * (int64_t)w.tilepre[s];
-            const int64_t dst0 = w.off[s] + w.pos[pbase + (int64_t)tid * nt + i] - w.pos[pbase];
-            uint32_t my = 0;
-#pragma unroll
-            for (int d = 0; d < 10; d++) my = (d == tid) ? tst[d] : my;
-            dbase[tid] = dst0 - (int64_t)my;
+    for (int j = 0; j < VT; j++) {
+        const int q = j * NT + tid;
+        if (q < cnt) {
+            const int64_t dst = dbase[sd[q]] + q;
+            w.skeys[dst] = sk[lds_pad<K>(q)];
+            if constexpr (PAIRS) w.svals[dst] = sv[q];
         }
-        // 5. stage grouped by bucket
-#pragma unroll
-        for (int v = 0; v < VT; v++) {
-            if (dg[v] < 10) {
-                const int sp = (int)(field16(wd, dg[v]) + rank[v]);
-                sk[lds_pad<K>(sp)] = key[v];
-                sd[sp] = (uint8_t)dg[v];
-                if constexpr (PAIRS) sv[sp] = val[v];
-            }
-        }
-        __syncthreads();
-        // 6. coalesced runs out to the buckets
-#pragma unroll
-        for (int j = 0; j < VT; j++) {
-            const int q = j * NT + tid;
-            if (q < cnt) {
-                const int64_t dst = dbase[sd[q]] + q;
-                w.skeys[dst] = sk[lds_pad<K>(q)];
-                if constexpr (PAIRS) w.svals[dst] = sv[q];
-            }
-        }
-        __syncthreads();
     }
 }
 
@@ -457,11 +461,11 @@ __global__ __launch_bounds__(NT) void k_tilesort(Work<K> w) {
     __shared__ W words[lds_padded_size<W>(NV)];
     __shared__ uint32_t sv[PAIRS ? NV : 1];
     __shared__ int sp[NT + 1];
-    if (*w.err) return;
     const int nb = 10 * w.nseg;
-    const int total = w.tsp[nb];
+    const int item = blockIdx.x;
+    if (*w.err || item >= w.tsp[nb]) return;
     const int tid = threadIdx.x;
-    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    {
         const int j = owner_of(w.tsp, nb, item);
         const int i = item - w.tsp[j];
         const int64_t size = w.bsize[j];
@@ -491,7 +495,6 @@ __global__ __launch_bounds__(NT) void k_tilesort(Work<K> w) {
                 if constexpr (PAIRS) dv[start + q] = sv[pair_pos(word)];
             }
         }
-        __syncthreads();
     }
 }
 
@@ -504,7 +507,7 @@ __global__ __launch_bounds__(NT) void k_tilesort(Work<K> w) {
 // outputs come from the left run (co-rank, ties to the left run = stable).
 template <typename K>
 __global__ void k_partition(Work<K> w, int pass) {
-    if (*w.err) return;
+    if (*w.err || pass >= *w.rounds) return;
     const int nb = 10 * w.nseg;
     const int total = w.msp[nb];
     const int64_t T = w.tile, NV = w.nv;
@@ -535,18 +538,18 @@ __global__ __launch_bounds__(NT) void k_merge(Work<K> w, int pass) {
     __shared__ W words[lds_padded_size<W>(NV)];
     __shared__ uint32_t sv[PAIRS ? NV : 1];
     __shared__ int sp[NT + 1];
-    if (*w.err) return;
     const int nb = 10 * w.nseg;
-    const int total = w.msp[nb];
+    const int item = blockIdx.x;
+    if (*w.err || pass >= *w.rounds || item >= w.msp[nb]) return;
     const int64_t T = w.tile;
     const int64_t L = T << pass;
     const int tid = threadIdx.x;
-    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    {
         const int j = owner_of(w.msp, nb, item);
         const int64_t i = item - w.msp[j];
         const int64_t size = w.bsize[j];
         const int P = merge_rounds(size, T);
-        if (P <= pass) continue;
+        if (P <= pass) return;
         const int64_t o = i * NV;
         const int64_t ps = (o / (2 * L)) * (2 * L);
         const int64_t a_len = min(L, size - ps);
@@ -602,7 +605,6 @@ __global__ __launch_bounds__(NT) void k_merge(Work<K> w, int pass) {
                 if constexpr (PAIRS) dv[out + q] = sv[pair_pos(word)];
             }
         }
-        __syncthreads();
     }
 }
 
@@ -843,31 +845,32 @@ static int fill_grid(F kernel, int nt, int64_t items) {
     return g < 1 ? 1 : (int)g;
 }
 
+static int grid_of(int64_t items) { return (int)(items < 1 ? 1 : items); }
+
 template <typename K>
 hipError_t launch_setup(const Work<K>& w, int64_t* own_off, hipStream_t st) {
     const int g = (int)min((int64_t)1024, (int64_t)cdiv64(w.nseg, 256));
-    k_init<K><<<g < 1 ? 1 : g, 256, 0, st>>>(w, own_off);
+    k_init<K><<<1, 64, 0, st>>>(w, own_off);
     k_classify<K><<<g < 1 ? 1 : g, 256, 0, st>>>(w);
     return hipGetLastError();
 }
 
 template <typename K>
 hipError_t launch_range(const Work<K>& w, int64_t tiles_bound, hipStream_t st) {
-    const int g = (int)min(tiles_bound, (int64_t)4 * cu_count());
-    k_range<K><<<g < 1 ? 1 : g, kHistNT, 0, st>>>(w);
+    k_range<K><<<grid_of(tiles_bound), kHistNT, 0, st>>>(w);
     return hipGetLastError();
 }
 
 template <typename K>
 hipError_t launch_plans(const Work<K>& w, hipStream_t st) {
-    const int g = (int)min((int64_t)1024, (int64_t)cdiv64(w.nseg, 256));
+    const int g = (int)min((int64_t)4096, (int64_t)w.nseg);
     k_plans<K><<<g < 1 ? 1 : g, 256, 0, st>>>(w);
     return hipGetLastError();
 }
 
 template <typename K>
 hipError_t launch_hist(const Work<K>& w, int64_t tiles_bound, hipStream_t st) {
-    k_hist<K><<<fill_grid(k_hist<K>, kHistNT, tiles_bound), kHistNT, 0, st>>>(w);
+    k_hist<K><<<grid_of(tiles_bound), kHistNT, 0, st>>>(w);
     return hipGetLastError();
 }
 
@@ -880,13 +883,13 @@ hipError_t launch_btab(const Work<K>& w, hipStream_t st) {
 
 template <typename K, bool PAIRS>
 hipError_t launch_scatter(const Work<K>& w, int64_t tiles_bound, hipStream_t st) {
-    k_scatter<K, PAIRS><<<fill_grid(k_scatter<K, PAIRS>, kHistNT, tiles_bound), kHistNT, 0, st>>>(w);
+    k_scatter<K, PAIRS><<<grid_of(tiles_bound), kHistNT, 0, st>>>(w);
     return hipGetLastError();
 }
 
 template <typename K, bool PAIRS, int NT, int VT>
 hipError_t launch_tilesort(const Work<K>& w, int64_t items_bound, hipStream_t st) {
-    k_tilesort<K, PAIRS, NT, VT><<<fill_grid(k_tilesort<K, PAIRS, NT, VT>, NT, items_bound), NT, 0, st>>>(w);
+    k_tilesort<K, PAIRS, NT, VT><<<grid_of(items_bound), NT, 0, st>>>(w);
     return hipGetLastError();
 }
 
@@ -900,7 +903,7 @@ hipError_t launch_partition(const Work<K>& w, int pass, int64_t chunks_bound, hi
 
 template <typename K, bool PAIRS, int NT, int VT>
 hipError_t launch_merge(const Work<K>& w, int pass, int64_t chunks_bound, hipStream_t st) {
-    k_merge<K, PAIRS, NT, VT><<<fill_grid(k_merge<K, PAIRS, NT, VT>, NT, chunks_bound), NT, 0, st>>>(w, pass);
+    k_merge<K, PAIRS, NT, VT><<<grid_of(chunks_bound), NT, 0, st>>>(w, pass);
     return hipGetLastError();
 }
 

@@ -22,9 +22,9 @@ struct Work {
     int64_t n;           // keys addressable through `keys`
     int32_t nseg;
 
-    // per segment
-    K* segmin;                // [nseg]
-    K* segmax;                // [nseg]
+    // per histogram tile, then per segment
+    K* tmin;                  // [tiles] min of each tile
+    K* tmax;                  // [tiles] max of each tile
     DigitPlan<K>* plans;      // [nseg]
     int32_t* tilecnt;         // [nseg] histogram tiles of a large segment, 0 otherwise
     int32_t* tilepre;         // [nseg + 1] exclusive prefix of tilecnt
@@ -42,7 +42,8 @@ struct Work {
     int32_t* mcc;  // merge chunks of the bucket
     int32_t* msp;  // [10 * nseg + 1] prefix
 
-    int32_t* split;  // co-rank at the start of each merge chunk of the current round
+    int32_t* split;   // co-rank at the start of each merge chunk of the current round
+    int32_t* rounds;  // largest number of merge rounds any bucket needs
     uint32_t* err;   // device-side validation flag (bad offsets)
 
     int32_t tile;       // keys per local-sort tile (T)
