@@ -119,7 +119,7 @@ int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 struct Layout {
     // byte offsets into scratch
     size_t err, own_off, skeys, svals, tmin, tmax, rounds, plans, tilecnt, tilepre, bounds, counts, pos, bstart, bsize, tsc,
-        tsp, mcc, msp, split, part32, part64, total;
+        tsp, mcc, msp, tiles, sdesc, mdesc, part32, part64, total;
     // item bounds
     int64_t large_bound, tiles_bound, buckets, ts_bound, chunks_bound;
 };
@@ -162,7 +162,9 @@ Layout make_layout(int kind, int64_t n, int64_t nseg, const Config& c) {
     L.tsp = take(4 * (L.buckets + 1));
     L.mcc = take(4 * L.buckets);
     L.msp = take(4 * (L.buckets + 1));
-    L.split = take(4 * (L.chunks_bound + 1));
+    L.tiles = take(sizeof(TileDesc) * L.tiles_bound);
+    L.sdesc = take(sizeof(SortDesc) * L.ts_bound);
+    L.mdesc = take(sizeof(MergeDesc) * L.chunks_bound);
     const int64_t p32 = std::max(scan_partial_count(nseg), scan_partial_count(L.buckets));
     L.part32 = take(4 * p32);
     L.part64 = take(8 * scan_partial_count(10 * L.tiles_bound));
@@ -196,7 +198,9 @@ Work<K> make_work(const Layout& L, char* scr, K* keys, uint32_t* vals, const int
     w.tsp = (int32_t*)(scr + L.tsp);
     w.mcc = (int32_t*)(scr + L.mcc);
     w.msp = (int32_t*)(scr + L.msp);
-    w.split = (int32_t*)(scr + L.split);
+    w.tiles = (TileDesc*)(scr + L.tiles);
+    w.sdesc = (SortDesc*)(scr + L.sdesc);
+    w.mdesc = (MergeDesc*)(scr + L.mdesc);
     w.err = (uint32_t*)(scr + L.err);
     w.tile = (int32_t)c.tile;
     w.nv = (int32_t)c.merge_nv;
@@ -236,8 +240,8 @@ hipError_t small_by_shape(int64_t cap, const Work<K>& w, int64_t lo, int64_t hi,
 }
 
 template <typename K, bool PAIRS>
-hipError_t merge_by_shape(int64_t nv, const Work<K>& w, int pass, int64_t chunks, hipStream_t st) {
-    if (nv == 4096) return launch_merge<K, PAIRS, 256, 16>(w, pass, chunks, st);
+hipError_t merge_by_shape(int64_t nv, const Work<K>& w, int64_t chunks, hipStream_t st) {
+    if (nv == 4096) return launch_merge<K, PAIRS, 256, 16>(w, chunks, st);
     return hipErrorInvalidValue;
 }
 
@@ -298,6 +302,10 @@ int run(int kind, K* keys, uint32_t* vals, int64_t n, const int64_t* off, int64_
     }
     if (any_large) {
         {
+            Timer t(st, "tiles", 0);
+            HS_TRY(launch_tiles<K>(w, L.tiles_bound, st));
+        }
+        {
             Timer t(st, "range", sizeof(K) * (double)n);
             HS_TRY(launch_range<K>(w, L.tiles_bound, st));
             HS_TRY(launch_plans<K>(w, st));
@@ -316,6 +324,10 @@ int run(int kind, K* keys, uint32_t* vals, int64_t n, const int64_t* off, int64_
             HS_TRY(launch_btab<K>(w, st));
             HS_TRY(launch_scan_i32(ScanSpec{nullptr, 0, L.buckets}, L.buckets, w.tsc, w.tsp, (int32_t*)(scr + L.part32), st));
             HS_TRY(launch_scan_i32(ScanSpec{nullptr, 0, L.buckets}, L.buckets, w.mcc, w.msp, (int32_t*)(scr + L.part32), st));
+        }
+        {
+            Timer t(st, "sdesc", 0);
+            HS_TRY(launch_sdesc<K>(w, L.ts_bound, st));
         }
         {
             Timer t(st, "scatter", 2 * kb * n);
@@ -344,7 +356,7 @@ int run(int kind, K* keys, uint32_t* vals, int64_t n, const int64_t* off, int64_
             {
                 Timer t(st, "merge", 0);
                 t.per_active_key(w.bsize, L.buckets, c.tile, p, 2 * kb);
-                HS_TRY((merge_by_shape<K, PAIRS>(c.merge_nv, w, p, L.chunks_bound, st)));
+                HS_TRY((merge_by_shape<K, PAIRS>(c.merge_nv, w, L.chunks_bound, st)));
             }
         }
     }

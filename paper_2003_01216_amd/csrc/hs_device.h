@@ -176,6 +176,27 @@ __device__ __forceinline__ int merge_path(int diag, int na, int nb, FA A, FB B) 
     return lo;
 }
 
+// Branch-free co-rank with log2(STEP0)+1 unrolled probes; STEP0 is a power
+// of two not below the largest possible hi - lo.  Probes outside [lo, hi)
+// read index 0 of each array instead (always a valid address for callers)
+// and are ignored.
+template <int STEP0, typename FA, typename FB>
+__device__ __forceinline__ int merge_path_fixed(int diag, int na, int nb, FA A, FB B) {
+    const int lo = diag > nb ? diag - nb : 0;
+    const int hi = diag < na ? diag : na;
+    int pos = lo;
+#pragma unroll
+    for (int step = STEP0; step > 0; step >>= 1) {
+        const int m = pos + step - 1;
+        const bool inr = m < hi;
+        const int ma = inr ? m : 0;
+        const int mb = inr ? diag - 1 - m : 0;
+        const bool take = inr && !(B(mb) < A(ma));
+        pos = take ? pos + step : pos;
+    }
+    return pos;
+}
+
 // 64-bit variant for global-memory co-ranks over long runs.
 template <typename FA, typename FB>
 __device__ __forceinline__ int64_t merge_path64(int64_t diag, int64_t na, int64_t nb, FA A, FB B) {

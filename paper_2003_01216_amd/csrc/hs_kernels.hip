@@ -11,9 +11,12 @@
 //   k_tilesort                     LDS sort of each T-key partition of a bucket
 //   k_partition + k_merge          bottom-up merge rounds (Figure 1b), per round
 //   k_small                        segments that fit a tile: one LDS sort each
-// All flat-list kernels are persistent (grid-stride over a device-side item
-// count), so the launch sequence and its grid sizes depend only on host-side
-// sizes and can be captured in a graph.
+// The flat work lists (histogram tiles, local-sort partitions, merge chunks)
+// live on the device as descriptor arrays written by small kernels (k_tiles,
+// k_sdesc, k_partition); every heavy kernel runs one workgroup per list slot
+// and reads one descriptor before its data.  Grids are sized by host-side
+// upper bounds (unused slots exit at once), so the launch sequence depends
+// only on host-side sizes and can be captured in a graph.
 #include <hip/hip_runtime.h>
 
 #include "hs_device.h"
@@ -158,35 +161,62 @@ __device__ __forceinline__ void gather_merge(const W* words, int a0, int b0, int
     bitonic_merge<W, VT>(v);
 }
 
-// Sorts words[0..NT*VT) (padded layout) ascending in LDS: a register sorting
-// network per thread, then log2(NT) merge levels.  Result in blocked layout.
-template <typename W, int NT, int VT>
-__device__ __forceinline__ void block_sort(W* words, int* sp) {
-    constexpr int NV = NT * VT;
-    const int tid = threadIdx.x;
-    W v[VT];
+// Full-chunk gather: x outputs from A starting at words[a_first], the rest
+// from B ending at words[b_last], arranged ascending-then-descending.
+template <typename W, int VT>
+__device__ __forceinline__ void gather_merge_full(const W* words, int a_first, int b_last, int x, W (&v)[VT]) {
 #pragma unroll
-    for (int i = 0; i < VT; i++) v[i] = words[lds_pad<W>(tid * VT + i)];
-    register_sort<W, VT>(v);
-#pragma unroll 1
-    for (int L = VT; L < NV; L <<= 1) {
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < VT; i++) words[lds_pad<W>(tid * VT + i)] = v[i];
-        __syncthreads();
-        const int gb = (tid * VT) & ~(2 * L - 1);
-        const int diag = tid * VT - gb;
-        auto A = [&](int i) { return words[lds_pad<W>(gb + i)]; };
-        auto B = [&](int i) { return words[lds_pad<W>(gb + L + i)]; };
-        const int ai = merge_path<W>(diag, L, L, A, B);
-        sp[tid] = ai;
-        __syncthreads();
-        const int an = (diag + VT == 2 * L) ? L : sp[tid + 1];
-        gather_merge<W, VT>(words, gb, gb + L, ai, diag - ai, an - ai, VT, v);
+    for (int i = 0; i < VT; i++) {
+        const int idx = i < x ? a_first + i : b_last - i;
+        v[i] = words[lds_pad<W>(idx)];
     }
+    bitonic_merge<W, VT>(v);
+}
+
+// One LDS merge level of the block sort: runs of L (one per VT/L... threads)
+// merged pairwise; each thread produces VT outputs.  `base` is the padded
+// start of this thread's VT-run (runs never straddle a pad word).
+template <typename W, int NT, int VT, int L>
+__device__ __forceinline__ void block_sort_level(W* words, int* sp, W (&v)[VT], int tid, int base) {
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < VT; i++) words[lds_pad<W>(tid * VT + i)] = v[i];
+    for (int i = 0; i < VT; i++) words[base + i] = v[i];
+    __syncthreads();
+    const int gb = (tid * VT) & ~(2 * L - 1);
+    const int diag = tid * VT - gb;
+    auto A = [&](int i) { return words[lds_pad<W>(gb + i)]; };
+    auto B = [&](int i) { return words[lds_pad<W>(gb + L + i)]; };
+    const int ai = merge_path_fixed<L>(diag, L, L, A, B);
+    sp[tid] = ai;
+    __syncthreads();
+    const int an = (diag + VT == 2 * L) ? L : sp[tid + 1];
+    gather_merge_full<W, VT>(words, gb + ai, gb + L + (diag - ai) + VT - 1, an - ai, v);
+}
+
+template <typename W, int NT, int VT, int L>
+__device__ __forceinline__ void block_sort_levels(W* words, int* sp, W (&v)[VT], int tid, int base) {
+    if constexpr (L < NT * VT) {
+        block_sort_level<W, NT, VT, L>(words, sp, v, tid, base);
+        block_sort_levels<W, NT, VT, 2 * L>(words, sp, v, tid, base);
+    }
+}
+
+// Sorts words[0..NT*VT) (padded layout) ascending in LDS: a register sorting
+// network per thread, then log2(NT) merge levels, fully unrolled.  Result in
+// blocked layout (thread t holds outputs t*VT .. t*VT+VT-1, also in LDS).
+template <typename W, int NT, int VT>
+__device__ __forceinline__ void block_sort(W* words, int* sp) {
+    static_assert((128 / (int)sizeof(W)) % VT == 0, "a VT-run must not straddle a pad word");
+    const int tid = threadIdx.x;
+    const int base = lds_pad<W>(tid * VT);
+    W v[VT];
+#pragma unroll
+    for (int i = 0; i < VT; i++) v[i] = words[base + i];
+    register_sort<W, VT>(v);
+    block_sort_levels<W, NT, VT, VT>(words, sp, v, tid, base);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < VT; i++) words[base + i] = v[i];
     __syncthreads();
 }
 
@@ -217,6 +247,30 @@ __global__ void k_classify(Work<K> w) {
     }
 }
 
+// Materialises the flat histogram-tile list (one thread per tile slot).
+template <typename K>
+__global__ void k_tiles(Work<K> w, int64_t tiles_bound) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= tiles_bound) return;
+    const int total = w.tilepre[w.nseg];
+    TileDesc d;
+    if (*w.err || t >= total) {
+        d = TileDesc{0, 0, 0, 0, 0, 0};
+    } else {
+        const int s = owner_of(w.tilepre, w.nseg, (int)t);
+        const int i = (int)t - w.tilepre[s];
+        const int64_t a = w.off[s];
+        const int64_t base = a + (int64_t)i * kHistTile;
+        d.base = base;
+        d.seg_base = a;
+        d.cnt = (int)min((int64_t)kHistTile, w.off[s + 1] - base);
+        d.seg = s;
+        d.idx = i;
+        d.nt = w.tilecnt[s];
+    }
+    w.tiles[t] = d;
+}
+
 // min/max of every histogram tile (one workgroup per tile).
 template <typename T, int NT>
 __device__ __forceinline__ void block_minmax(T& mn, T& mx, T* rmn, T* rmx) {
@@ -241,12 +295,11 @@ template <typename K>
 __global__ __launch_bounds__(kHistNT) void k_range(Work<K> w) {
     __shared__ K rmn[kHistNT / kWave], rmx[kHistNT / kWave];
     const int t = blockIdx.x;
-    if (*w.err || t >= w.tilepre[w.nseg]) return;
+    const TileDesc td = w.tiles[t];
+    if (td.cnt == 0) return;
     const int tid = threadIdx.x;
-    const int s = owner_of(w.tilepre, w.nseg, t);
-    const int64_t base = w.off[s] + (int64_t)(t - w.tilepre[s]) * kHistTile;
-    const int cnt = (int)min((int64_t)kHistTile, w.off[s + 1] - base);
-    const K* src = w.keys + base;
+    const int cnt = td.cnt;
+    const K* src = w.keys + td.base;
     K mn = Traits<K>::kMax, mx = Traits<K>::kMin;
 #pragma unroll
     for (int j = 0; j < kHistVT; j++) {
@@ -293,14 +346,12 @@ template <typename K>
 __global__ __launch_bounds__(kHistNT) void k_hist(Work<K> w) {
     __shared__ uint32_t red[kHistNT / kWave][5];
     const int t = blockIdx.x;
-    if (*w.err || t >= w.tilepre[w.nseg]) return;
+    const TileDesc td = w.tiles[t];
+    if (td.cnt == 0) return;
     const int tid = threadIdx.x;
-    const int s = owner_of(w.tilepre, w.nseg, t);
-    const int i = t - w.tilepre[s];
-    const int64_t base = w.off[s] + (int64_t)i * kHistTile;
-    const int cnt = (int)min((int64_t)kHistTile, w.off[s + 1] - base);
-    const DigitPlan<K> pl = w.plans[s];
-    const K* src = w.keys + base;
+    const int cnt = td.cnt;
+    const DigitPlan<K> pl = w.plans[td.seg];
+    const K* src = w.keys + td.base;
     uint64_t c = 0;
 #pragma unroll
     for (int j = 0; j < kHistVT; j++) {
@@ -310,7 +361,7 @@ __global__ __launch_bounds__(kHistNT) void k_hist(Work<K> w) {
     uint32_t wd[5];
     unpack5(c, wd);
     block_sum5<kHistNT>(wd, red);
-    if (tid < 10) w.counts[10 * w.tilepre[s] + tid * w.tilecnt[s] + i] = field16(wd, tid);
+    if (tid < 10) w.counts[10 * (int64_t)(t - td.idx) + tid * td.nt + td.idx] = field16(wd, tid);
 }
 
 // Bucket table: start and size of each of the ten buckets of every segment,
@@ -362,14 +413,14 @@ __global__ __launch_bounds__(kHistNT) void k_scatter(Work<K> w) {
     __shared__ uint32_t red[NT / kWave][5];
     __shared__ int64_t dbase[10];
     const int t = blockIdx.x;
-    if (*w.err || t >= w.tilepre[w.nseg]) return;
+    const TileDesc td = w.tiles[t];
+    if (td.cnt == 0) return;
     const int tid = threadIdx.x;
-    const int s = owner_of(w.tilepre, w.nseg, t);
-    const int i = t - w.tilepre[s];
-    const int nt = w.tilecnt[s];
-    const int64_t base = w.off[s] + (int64_t)i * HT;
-    const int cnt = (int)min((int64_t)HT, w.off[s + 1] - base);
-    const DigitPlan<K> pl = w.plans[s];
+    const int i = td.idx;
+    const int nt = td.nt;
+    const int64_t base = td.base;
+    const int cnt = td.cnt;
+    const DigitPlan<K> pl = w.plans[td.seg];
     // 1. coalesced load, natural order
 #pragma unroll
     for (int j = 0; j < VT; j++) {
@@ -380,8 +431,8 @@ __global__ __launch_bounds__(kHistNT) void k_scatter(Work<K> w) {
         }
     }
     if (tid < 10) {
-        const int64_t pbase = 10 * (int64_t)w.tilepre[s];
-        dbase[tid] = w.off[s] + w.pos[pbase + (int64_t)tid * nt + i] - w.pos[pbase];
+        const int64_t pbase = 10 * (int64_t)(t - i);
+        dbase[tid] = td.seg_base + w.pos[pbase + (int64_t)tid * nt + i] - w.pos[pbase];
     }
     __syncthreads();
     // 2. blocked: digit and rank among this thread's own keys, packed as
@@ -447,6 +498,24 @@ __global__ __launch_bounds__(kHistNT) void k_scatter(Work<K> w) {
     }
 }
 
+// Materialises the flat list of local-sort partitions (one thread per slot).
+template <typename K>
+__global__ void k_sdesc(Work<K> w, int64_t bound) {
+    const int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (item >= bound) return;
+    const int nb = 10 * w.nseg;
+    SortDesc d{0, 0, 0};
+    if (!*w.err && item < w.tsp[nb]) {
+        const int j = owner_of(w.tsp, nb, (int)item);
+        const int64_t i = item - w.tsp[j];
+        const int64_t size = w.bsize[j];
+        d.start = w.bstart[j] + i * w.tile;
+        d.cnt = (int)min((int64_t)w.tile, size - i * w.tile);
+        d.odd = merge_rounds(size, w.tile) & 1;
+    }
+    w.sdesc[item] = d;
+}
+
 // -------------------------------------------------------------- tile sort
 // Local sort of each T-key partition of every bucket (Section 3.4: each
 // thread of a node sorts its partition; here one workgroup per partition, in
@@ -461,38 +530,54 @@ __global__ __launch_bounds__(NT) void k_tilesort(Work<K> w) {
     __shared__ W words[lds_padded_size<W>(NV)];
     __shared__ uint32_t sv[PAIRS ? NV : 1];
     __shared__ int sp[NT + 1];
-    const int nb = 10 * w.nseg;
-    const int item = blockIdx.x;
-    if (*w.err || item >= w.tsp[nb]) return;
+    const SortDesc sd = w.sdesc[blockIdx.x];
+    if (sd.cnt == 0) return;
     const int tid = threadIdx.x;
     {
-        const int j = owner_of(w.tsp, nb, item);
-        const int i = item - w.tsp[j];
-        const int64_t size = w.bsize[j];
-        const int64_t start = w.bstart[j] + (int64_t)i * NV;
-        const int cnt = (int)min((int64_t)NV, size - (int64_t)i * NV);
-        const int P = merge_rounds(size, NV);
-        K* dk = (P & 1) ? w.skeys : w.keys;
-        uint32_t* dv = (P & 1) ? w.svals : w.vals;
+        const int64_t start = sd.start;
+        const int cnt = sd.cnt;
+        K* dk = (sd.odd ? w.skeys : w.keys) + start;
+        uint32_t* dv = PAIRS ? (sd.odd ? w.svals : w.vals) + start : nullptr;
+        const K* srck = w.skeys + start;
+        const uint32_t* srcv = PAIRS ? w.svals + start : nullptr;
+        if (cnt == NV) {
 #pragma unroll
-        for (int jj = 0; jj < VT; jj++) {
-            const int q = jj * NT + tid;
-            W word = WordMax<W>::v;
-            if (q < cnt) {
-                word = make_word<K, PAIRS>(w.skeys[start + q], q);
-                if constexpr (PAIRS) sv[q] = w.svals[start + q];
+            for (int jj = 0; jj < VT; jj++) {
+                const unsigned q = jj * NT + tid;
+                words[lds_pad<W>(q)] = make_word<K, PAIRS>(srck[q], q);
+                if constexpr (PAIRS) sv[q] = srcv[q];
             }
-            words[lds_pad<W>(q)] = word;
+        } else {
+#pragma unroll
+            for (int jj = 0; jj < VT; jj++) {
+                const unsigned q = jj * NT + tid;
+                W word = WordMax<W>::v;
+                if (q < (unsigned)cnt) {
+                    word = make_word<K, PAIRS>(srck[q], q);
+                    if constexpr (PAIRS) sv[q] = srcv[q];
+                }
+                words[lds_pad<W>(q)] = word;
+            }
         }
         __syncthreads();
         block_sort<W, NT, VT>(words, sp);
+        if (cnt == NV) {
 #pragma unroll
-        for (int jj = 0; jj < VT; jj++) {
-            const int q = jj * NT + tid;
-            if (q < cnt) {
+            for (int jj = 0; jj < VT; jj++) {
+                const unsigned q = jj * NT + tid;
                 const W word = words[lds_pad<W>(q)];
-                dk[start + q] = word_key<K, PAIRS>(word);
-                if constexpr (PAIRS) dv[start + q] = sv[pair_pos(word)];
+                dk[q] = word_key<K, PAIRS>(word);
+                if constexpr (PAIRS) dv[q] = sv[pair_pos(word)];
+            }
+        } else {
+#pragma unroll
+            for (int jj = 0; jj < VT; jj++) {
+                const unsigned q = jj * NT + tid;
+                if (q < (unsigned)cnt) {
+                    const W word = words[lds_pad<W>(q)];
+                    dk[q] = word_key<K, PAIRS>(word);
+                    if constexpr (PAIRS) dv[q] = sv[pair_pos(word)];
+                }
             }
         }
     }
@@ -505,105 +590,149 @@ __global__ __launch_bounds__(NT) void k_tilesort(Work<K> w) {
 // output of each pair is cut into chunks of NV keys; one workgroup per chunk.
 // k_partition finds, for every chunk start, how many of its preceding
 // outputs come from the left run (co-rank, ties to the left run = stable).
+// Round `pass` of the non-recursive merge (Figure 1b; Section 3.2 merge
+// rounds): inside every bucket still holding more than one run, runs of
+// L = T*2^pass keys are merged pairwise (an odd last run is carried).  The
+// output of each pair is cut into chunks of NV keys, one workgroup each.
+// k_partition (one thread per chunk) finds the co-rank of the chunk's first
+// output -- how many of the outputs before it come from the left run, ties
+// going to the left run (stable) -- and writes the chunk's descriptor.
 template <typename K>
-__global__ void k_partition(Work<K> w, int pass) {
-    if (*w.err || pass >= *w.rounds) return;
+__global__ __launch_bounds__(256) void k_partition(Work<K> w, int pass, int64_t bound) {
+    const int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (item >= bound) return;
     const int nb = 10 * w.nseg;
-    const int total = w.msp[nb];
-    const int64_t T = w.tile, NV = w.nv;
-    const int64_t L = T << pass;
-    for (int item = blockIdx.x * blockDim.x + threadIdx.x; item < total; item += gridDim.x * blockDim.x) {
-        const int j = owner_of(w.msp, nb, item);
+    MergeDesc d{0, 0, 0, 0, 0, 0, 0};
+    if (!*w.err && pass < *w.rounds && item < w.msp[nb]) {
+        const int j = owner_of(w.msp, nb, (int)item);
         const int64_t i = item - w.msp[j];
         const int64_t size = w.bsize[j];
+        const int64_t T = w.tile, NV = w.nv;
         const int P = merge_rounds(size, T);
-        if (P <= pass) continue;
-        const int64_t o = i * NV;
-        const int64_t ps = (o / (2 * L)) * (2 * L);
-        const int64_t a_len = min(L, size - ps);
-        const int64_t b_len = max((int64_t)0, min(L, size - ps - L));
-        const K* src = ((P - pass) & 1) ? w.skeys : w.keys;
-        const K* A = src + w.bstart[j] + ps;
-        const K* B = A + L;
-        const int64_t co =
-            merge_path64(o - ps, a_len, b_len, [&](int64_t x) { return A[x]; }, [&](int64_t x) { return B[x]; });
-        w.split[item] = (int32_t)co;
+        if (P > pass) {
+            const int64_t L = T << pass;
+            const int64_t o = i * NV;
+            const int64_t ps = (o / (2 * L)) * (2 * L);
+            const int64_t a_len = min(L, size - ps);
+            const int64_t b_len = max((int64_t)0, min(L, size - ps - L));
+            const bool odd = (P - pass) & 1;
+            const K* src = odd ? w.skeys : w.keys;
+            const int64_t base = w.bstart[j] + ps;
+            const K* A = src + base;
+            const K* B = A + L;
+            const int64_t diag = o - ps;
+            const int64_t cs =
+                merge_path64(diag, a_len, b_len, [&](int64_t x) { return A[x]; }, [&](int64_t x) { return B[x]; });
+            d.a = base + cs;
+            d.b = base + L + (diag - cs);
+            d.out = w.bstart[j] + o;
+            d.flags = kActive | (odd ? kFromScratch : 0);
+            if (o + NV >= min(ps + 2 * L, size)) {
+                d.flags |= kLastChunk;
+                d.a_end = base + a_len;
+                d.b_end = base + L + b_len;
+            }
+        }
     }
+    w.mdesc[item] = d;
 }
 
 template <typename K, bool PAIRS, int NT, int VT>
-__global__ __launch_bounds__(NT) void k_merge(Work<K> w, int pass) {
+__global__ __launch_bounds__(NT) void k_merge(Work<K> w, int64_t bound) {
     using W = typename WordOf<K, PAIRS>::type;
     constexpr int NV = NT * VT;
     __shared__ W words[lds_padded_size<W>(NV)];
     __shared__ uint32_t sv[PAIRS ? NV : 1];
     __shared__ int sp[NT + 1];
-    const int nb = 10 * w.nseg;
-    const int item = blockIdx.x;
-    if (*w.err || pass >= *w.rounds || item >= w.msp[nb]) return;
-    const int64_t T = w.tile;
-    const int64_t L = T << pass;
+    const int64_t item = blockIdx.x;
+    const MergeDesc md = w.mdesc[item];
+    const MergeDesc nx = w.mdesc[item + 1 < bound ? item + 1 : item];
+    if (!(md.flags & kActive)) return;
     const int tid = threadIdx.x;
-    {
-        const int j = owner_of(w.msp, nb, item);
-        const int64_t i = item - w.msp[j];
-        const int64_t size = w.bsize[j];
-        const int P = merge_rounds(size, T);
-        if (P <= pass) return;
-        const int64_t o = i * NV;
-        const int64_t ps = (o / (2 * L)) * (2 * L);
-        const int64_t a_len = min(L, size - ps);
-        const int64_t b_len = max((int64_t)0, min(L, size - ps - L));
-        const int64_t diag = o - ps;
-        const int64_t dend = min(o + NV, size) - ps;
-        const int64_t a_s = w.split[item];
-        const int64_t a_e = (dend == a_len + b_len) ? a_len : (int64_t)w.split[item + 1];
-        const int na = (int)(a_e - a_s);
-        const int tot = (int)(dend - diag);
-        const int64_t b_s = diag - a_s;
-        const bool odd = (P - pass) & 1;
-        const K* sk = odd ? w.skeys : w.keys;
-        const uint32_t* svv = odd ? w.svals : w.vals;
-        K* dk = odd ? w.keys : w.skeys;
-        uint32_t* dv = odd ? w.vals : w.svals;
-        const int64_t base = w.bstart[j] + ps;
-        const int64_t ga = base + a_s;
-        const int64_t gb = base + L + b_s;
+    const bool last = md.flags & kLastChunk;
+    const int na = (int)((last ? md.a_end : nx.a) - md.a);
+    const int tot = na + (int)((last ? md.b_end : nx.b) - md.b);
+    const bool odd = md.flags & kFromScratch;
+    const K* pa = (odd ? w.skeys : w.keys) + md.a;
+    const K* pb = (odd ? w.skeys : w.keys) + md.b;
+    const uint32_t* va = PAIRS ? (odd ? w.svals : w.vals) + md.a : nullptr;
+    const uint32_t* vb = PAIRS ? (odd ? w.svals : w.vals) + md.b : nullptr;
+    K* dk = (odd ? w.keys : w.skeys) + md.out;
+    uint32_t* dv = PAIRS ? (odd ? w.vals : w.svals) + md.out : nullptr;
+    auto A = [&](int x) { return words[lds_pad<W>(x)]; };
+    auto B = [&](int x) { return words[lds_pad<W>(na + x)]; };
+    W v[VT];
+    if (tot == NV) {
+        // rows of NT consecutive outputs come wholly from A, wholly from B, or
+        // (one row) from both: the choice is uniform per row
 #pragma unroll
         for (int jj = 0; jj < VT; jj++) {
             const int q = jj * NT + tid;
-            if (q < tot) {
-                const int64_t g = q < na ? ga + q : gb + (q - na);
-                words[lds_pad<W>(q)] = make_word<K, PAIRS>(sk[g], q);
-                if constexpr (PAIRS) sv[q] = svv[g];
+            K k;
+            uint32_t val = 0;
+            if (jj * NT + NT <= na) {
+                k = pa[q];
+                if constexpr (PAIRS) val = va[q];
+            } else if (jj * NT >= na) {
+                k = pb[q - na];
+                if constexpr (PAIRS) val = vb[q - na];
+            } else {
+                k = q < na ? pa[q] : pb[q - na];
+                if constexpr (PAIRS) val = q < na ? va[q] : vb[q - na];
             }
+            words[lds_pad<W>(q)] = make_word<K, PAIRS>(k, q);
+            if constexpr (PAIRS) sv[q] = val;
         }
         __syncthreads();
-        const int nbb = tot - na;
-        const int dt = min(tid * VT, tot);
-        auto A = [&](int x) { return words[lds_pad<W>(x)]; };
-        auto B = [&](int x) { return words[lds_pad<W>(na + x)]; };
-        const int ai = merge_path<W>(dt, na, nbb, A, B);
+        const int dt = tid * VT;
+        const int ai = merge_path_fixed<NV / 2>(dt, na, NV - na, A, B);
         sp[tid] = ai;
         __syncthreads();
         const int an = (tid == NT - 1) ? na : sp[tid + 1];
-        const int c = min(tid * VT + VT, tot) - dt;
-        W v[VT];
-        gather_merge<W, VT>(words, 0, na, ai, dt - ai, an - ai, c, v);
+        gather_merge_full<W, VT>(words, ai, na + (dt - ai) + VT - 1, an - ai, v);
         __syncthreads();
+        const int base = lds_pad<W>(tid * VT);
 #pragma unroll
-        for (int q = 0; q < VT; q++)
-            if (q < c) words[lds_pad<W>(tid * VT + q)] = v[q];
+        for (int q = 0; q < VT; q++) words[base + q] = v[q];
         __syncthreads();
-        const int64_t out = w.bstart[j] + o;
 #pragma unroll
         for (int jj = 0; jj < VT; jj++) {
-            const int q = jj * NT + tid;
-            if (q < tot) {
-                const W word = words[lds_pad<W>(q)];
-                dk[out + q] = word_key<K, PAIRS>(word);
-                if constexpr (PAIRS) dv[out + q] = sv[pair_pos(word)];
-            }
+            const unsigned q = jj * NT + tid;
+            const W word = words[lds_pad<W>(q)];
+            dk[q] = word_key<K, PAIRS>(word);
+            if constexpr (PAIRS) dv[q] = sv[pair_pos(word)];
+        }
+        return;
+    }
+    // a bucket's last, shorter chunk
+#pragma unroll
+    for (int jj = 0; jj < VT; jj++) {
+        const int q = jj * NT + tid;
+        if (q < tot) {
+            words[lds_pad<W>(q)] = make_word<K, PAIRS>(q < na ? pa[q] : pb[q - na], q);
+            if constexpr (PAIRS) sv[q] = q < na ? va[q] : vb[q - na];
+        }
+    }
+    __syncthreads();
+    const int dt = min(tid * VT, tot);
+    const int ai = merge_path_fixed<NV / 2>(dt, na, tot - na, A, B);
+    sp[tid] = ai;
+    __syncthreads();
+    const int an = (tid == NT - 1) ? na : sp[tid + 1];
+    const int c = min(tid * VT + VT, tot) - dt;
+    gather_merge<W, VT>(words, 0, na, ai, dt - ai, an - ai, c, v);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < VT; q++)
+        if (q < c) words[lds_pad<W>(tid * VT + q)] = v[q];
+    __syncthreads();
+#pragma unroll
+    for (int jj = 0; jj < VT; jj++) {
+        const int q = jj * NT + tid;
+        if (q < tot) {
+            const W word = words[lds_pad<W>(q)];
+            dk[q] = word_key<K, PAIRS>(word);
+            if constexpr (PAIRS) dv[q] = sv[pair_pos(word)];
         }
     }
 }
@@ -623,12 +752,13 @@ __global__ __launch_bounds__(NT) void k_small(Work<K> w, int64_t lo, int64_t hi)
     __shared__ uint32_t sv[PAIRS ? NV : 1];
     __shared__ int sp[NT + 1];
     __shared__ uint32_t red[NT / kWave][5];
-    if (*w.err) return;
+    const int s = blockIdx.x;
+    if (*w.err || s >= w.nseg) return;
     const int tid = threadIdx.x;
-    for (int s = blockIdx.x; s < w.nseg; s += gridDim.x) {
+    {
         const int64_t a = w.off[s];
         const int64_t m64 = w.off[s + 1] - a;
-        if (!(m64 > lo && m64 <= hi)) continue;
+        if (!(m64 > lo && m64 <= hi)) return;
         const int m = (int)m64;
         if (m > 1) {
 #pragma unroll
@@ -679,7 +809,6 @@ __global__ __launch_bounds__(NT) void k_small(Work<K> w, int64_t lo, int64_t hi)
             }
             w.bounds_out[11 * (int64_t)s + 10] = run;
         }
-        __syncthreads();
     }
 }
 
@@ -824,8 +953,6 @@ hipError_t launch_scan_u32_i64(const ScanSpec& sp, int64_t len_bound, const uint
 }
 int64_t scan_partial_count(int64_t len_bound) { return cdiv64(len_bound, kScanTile) + 1; }
 
-// Persistent grid: enough workgroups to fill every compute unit at the
-// kernel's occupancy, but no more than there are items.
 static int cu_count() {
     static int cus = 0;
     if (!cus) {
@@ -834,15 +961,6 @@ static int cu_count() {
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
     }
     return cus;
-}
-
-template <typename F>
-static int fill_grid(F kernel, int nt, int64_t items) {
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, nt, 0) != hipSuccess || per_cu <= 0) per_cu = 1;
-    int64_t g = (int64_t)cu_count() * per_cu;
-    if (items < g) g = items;
-    return g < 1 ? 1 : (int)g;
 }
 
 static int grid_of(int64_t items) { return (int)(items < 1 ? 1 : items); }
@@ -894,22 +1012,32 @@ hipError_t launch_tilesort(const Work<K>& w, int64_t items_bound, hipStream_t st
 }
 
 template <typename K>
+hipError_t launch_tiles(const Work<K>& w, int64_t tiles_bound, hipStream_t st) {
+    k_tiles<K><<<cdiv64(tiles_bound, 256), 256, 0, st>>>(w, tiles_bound);
+    return hipGetLastError();
+}
+
+template <typename K>
+hipError_t launch_sdesc(const Work<K>& w, int64_t items_bound, hipStream_t st) {
+    k_sdesc<K><<<cdiv64(items_bound, 256), 256, 0, st>>>(w, items_bound);
+    return hipGetLastError();
+}
+
+template <typename K>
 hipError_t launch_partition(const Work<K>& w, int pass, int64_t chunks_bound, hipStream_t st) {
-    const int64_t blocks = (chunks_bound + 255) / 256;
-    const int g = (int)min(blocks, (int64_t)8 * cu_count());
-    k_partition<K><<<g < 1 ? 1 : g, 256, 0, st>>>(w, pass);
+    k_partition<K><<<cdiv64(chunks_bound, 256), 256, 0, st>>>(w, pass, chunks_bound);
     return hipGetLastError();
 }
 
 template <typename K, bool PAIRS, int NT, int VT>
-hipError_t launch_merge(const Work<K>& w, int pass, int64_t chunks_bound, hipStream_t st) {
-    k_merge<K, PAIRS, NT, VT><<<grid_of(chunks_bound), NT, 0, st>>>(w, pass);
+hipError_t launch_merge(const Work<K>& w, int64_t chunks_bound, hipStream_t st) {
+    k_merge<K, PAIRS, NT, VT><<<grid_of(chunks_bound), NT, 0, st>>>(w, chunks_bound);
     return hipGetLastError();
 }
 
 template <typename K, bool PAIRS, int NT, int VT>
 hipError_t launch_small(const Work<K>& w, int64_t lo, int64_t hi, int64_t segs_bound, hipStream_t st) {
-    k_small<K, PAIRS, NT, VT><<<fill_grid(k_small<K, PAIRS, NT, VT>, NT, segs_bound), NT, 0, st>>>(w, lo, hi);
+    k_small<K, PAIRS, NT, VT><<<grid_of(segs_bound), NT, 0, st>>>(w, lo, hi);
     return hipGetLastError();
 }
 
@@ -934,6 +1062,8 @@ hipError_t launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t st
     template hipError_t launch_hist<K>(const Work<K>&, int64_t, hipStream_t);            \
     template hipError_t launch_btab<K>(const Work<K>&, hipStream_t);                     \
     template hipError_t launch_partition<K>(const Work<K>&, int, int64_t, hipStream_t);  \
+    template hipError_t launch_tiles<K>(const Work<K>&, int64_t, hipStream_t);           \
+    template hipError_t launch_sdesc<K>(const Work<K>&, int64_t, hipStream_t);           \
     template hipError_t launch_collect<K>(const Work<K>&, int, hipStream_t);
 HS_INST_K(int32_t)
 HS_INST_K(int64_t)
@@ -947,7 +1077,7 @@ template hipError_t launch_scatter<int64_t, false>(const Work<int64_t>&, int64_t
     template hipError_t launch_small<K, PAIRS, NT, VT>(const Work<K>&, int64_t, int64_t, int64_t, hipStream_t);
 HS_TILE_VARIANTS(HS_INST_TILE)
 #define HS_INST_MERGE(K, PAIRS, NT, VT) \
-    template hipError_t launch_merge<K, PAIRS, NT, VT>(const Work<K>&, int, int64_t, hipStream_t);
+    template hipError_t launch_merge<K, PAIRS, NT, VT>(const Work<K>&, int64_t, hipStream_t);
 HS_MERGE_VARIANTS(HS_INST_MERGE)
 
 }  // namespace hs

@@ -44,7 +44,11 @@ hipError_t launch_tilesort(const Work<K>& w, int64_t items_bound, hipStream_t st
 template <typename K>
 hipError_t launch_partition(const Work<K>& w, int pass, int64_t chunks_bound, hipStream_t st);
 template <typename K, bool PAIRS, int NT, int VT>
-hipError_t launch_merge(const Work<K>& w, int pass, int64_t chunks_bound, hipStream_t st);
+hipError_t launch_merge(const Work<K>& w, int64_t chunks_bound, hipStream_t st);
+template <typename K>
+hipError_t launch_tiles(const Work<K>& w, int64_t tiles_bound, hipStream_t st);
+template <typename K>
+hipError_t launch_sdesc(const Work<K>& w, int64_t items_bound, hipStream_t st);
 template <typename K, bool PAIRS, int NT, int VT>
 hipError_t launch_small(const Work<K>& w, int64_t lo, int64_t hi, int64_t segs_bound, hipStream_t st);
 template <typename K>

@@ -12,6 +12,36 @@ constexpr int kHistNT = 256;
 constexpr int kHistVT = 16;
 constexpr int kHistTile = kHistNT * kHistVT;
 
+// One histogram tile of a large segment (range, histogram and scatter read it).
+struct TileDesc {
+    int64_t base;      // first key of the tile
+    int64_t seg_base;  // first key of its segment
+    int32_t cnt;       // keys in the tile
+    int32_t seg;       // segment index
+    int32_t idx;       // tile index inside the segment
+    int32_t nt;        // tiles of the segment
+};
+
+// One local-sort partition of a bucket.
+struct SortDesc {
+    int64_t start;  // first key
+    int32_t cnt;    // keys (0: no work)
+    int32_t odd;    // 1: write to the scratch copy (odd number of merge rounds)
+};
+
+// One merge workgroup of one round: it merges A[a .. a_end) and
+// B[b .. b_end) into out[out ..).  The window ends are the next chunk's
+// starts, except for the last chunk of a pair, which carries them itself.
+struct MergeDesc {
+    int64_t a, b, out;
+    int64_t a_end, b_end;  // valid when flags & kLastChunk
+    int32_t flags;
+    int32_t pad;
+};
+constexpr int32_t kActive = 1;     // the chunk has work this round
+constexpr int32_t kFromScratch = 2;  // source is the scratch copy
+constexpr int32_t kLastChunk = 4;  // last chunk of its pair of runs
+
 template <typename K>
 struct Work {
     K* keys;          // the caller's keys (sorted in place)
@@ -42,7 +72,9 @@ struct Work {
     int32_t* mcc;  // merge chunks of the bucket
     int32_t* msp;  // [10 * nseg + 1] prefix
 
-    int32_t* split;   // co-rank at the start of each merge chunk of the current round
+    TileDesc* tiles;   // [tiles bound]
+    SortDesc* sdesc;   // [local-sort partitions bound]
+    MergeDesc* mdesc;  // [merge chunks bound] of the current round
     int32_t* rounds;  // largest number of merge rounds any bucket needs
     uint32_t* err;   // device-side validation flag (bad offsets)
 
