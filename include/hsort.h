@@ -103,13 +103,16 @@ int hsort_check(const void* scratch, void* stream);
 const char* hsort_last_error(void);
 
 /* ---------------------------------------------------------------- tuning
- * The shape of the local sort and of the merge, per key kind.  tile = keys
- * per local-sort partition (T); merge_nv = outputs per merge workgroup;
- * small_max = segments up to this size are sorted wholly in LDS.  Only the
- * compiled shapes are accepted (HSORT_ERR_UNSUPPORTED otherwise); the
- * current values are returned by hsort_get_config. */
-int hsort_set_config(int kind, int64_t tile, int64_t merge_nv, int64_t small_max);
-int hsort_get_config(int kind, int64_t* tile, int64_t* merge_nv, int64_t* small_max);
+ * The shape of the local sort and of the merge, per key kind: tile = keys
+ * per local-sort partition (T), tile_vt = keys per thread of that sort
+ * (T / tile_vt threads per workgroup); merge_nv = outputs per merge
+ * workgroup, merge_vt = outputs per thread; small_max = segments (and plain
+ * arrays) up to this size are sorted wholly in LDS.  merge_nv must divide
+ * tile.  Only compiled shapes are accepted (HSORT_ERR_UNSUPPORTED
+ * otherwise).  The setting is process-wide; scratch sizes depend on it. */
+int hsort_set_config(int kind, int64_t tile, int64_t tile_vt, int64_t merge_nv, int64_t merge_vt, int64_t small_max);
+int hsort_get_config(int kind, int64_t* tile, int64_t* tile_vt, int64_t* merge_nv, int64_t* merge_vt,
+                     int64_t* small_max);
 
 /* ----------------------------------------------------- test observability
  * Runs the plain-sort pipeline (kinds HSORT_KEYS_I32, HSORT_KEYS_I64,

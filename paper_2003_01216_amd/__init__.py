@@ -80,8 +80,8 @@ def load_library(path: str = LIB_PATH):
         "hsort_bounds_offset": ([I, I64, I64], SZ),
         "hsort_check": ([P, P], I),
         "hsort_last_error": ([], ctypes.c_char_p),
-        "hsort_set_config": ([I, I64, I64, I64], I),
-        "hsort_get_config": ([I, P, P, P], I),
+        "hsort_set_config": ([I, I64, I64, I64, I64, I64], I),
+        "hsort_get_config": ([I, P, P, P, P, P], I),
         "hsort_debug_stage": ([I, P, P, I64, I, P, SZ, P], I),
         "hsort_timing_enable": ([I], I),
         "hsort_timing_read": ([P, I64], I64),
@@ -196,14 +196,15 @@ def read_bounds(scratch: torch.Tensor, kind: int, n: int, nseg: int = 1) -> torc
     return scratch[off: off + 8 * 11 * nseg].view(torch.int64).view(nseg, 11)
 
 
-def hsort_set_config(kind: int, tile: int, merge_nv: int, small_max: int) -> None:
-    _check(load_library().hsort_set_config(kind, tile, merge_nv, small_max))
+def hsort_set_config(kind: int, tile: int, tile_vt: int, merge_nv: int, merge_vt: int, small_max: int) -> None:
+    _check(load_library().hsort_set_config(kind, tile, tile_vt, merge_nv, merge_vt, small_max))
 
 
 def hsort_get_config(kind: int):
-    t, m, s = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
-    _check(load_library().hsort_get_config(kind, ctypes.byref(t), ctypes.byref(m), ctypes.byref(s)))
-    return t.value, m.value, s.value
+    """(tile, tile_vt, merge_nv, merge_vt, small_max) of a key kind."""
+    vals = [ctypes.c_int64() for _ in range(5)]
+    _check(load_library().hsort_get_config(kind, *[ctypes.byref(v) for v in vals]))
+    return tuple(v.value for v in vals)
 
 
 def hsort_debug_stage(keys: torch.Tensor, stage: int, vals: torch.Tensor | None = None,

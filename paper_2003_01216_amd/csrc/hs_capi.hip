@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <mutex>
+#include <type_traits>
 #include <string>
 #include <vector>
 
@@ -26,13 +27,15 @@ int fail(int code, const std::string& msg) {
 // ------------------------------------------------------------- configuration
 struct Config {
     int64_t tile;       // local-sort tile (T)
+    int64_t tile_vt;    // keys per thread of the local sort
     int64_t merge_nv;   // outputs per merge workgroup
+    int64_t merge_vt;   // outputs per thread of the merge
     int64_t small_max;  // segments up to this size never leave LDS
 };
 
 std::mutex g_mu;
 // index: 0 = int32 keys, 1 = int64 keys, 2 = int32 pairs
-Config g_cfg[3] = {{8192, 4096, 8192}, {4096, 4096, 4096}, {4096, 4096, 4096}};
+Config g_cfg[3] = {{16384, 32, 4096, 16, 8192}, {4096, 16, 4096, 16, 4096}, {4096, 16, 4096, 16, 4096}};
 
 int cfg_index(int kind) {
     switch (kind) {
@@ -53,9 +56,40 @@ Config get_cfg(int kind) {
     return g_cfg[cfg_index(kind)];
 }
 
-bool tile_shape_ok(int ci, int64_t t) {
-    if (ci == 1 || ci == 2) return t == 8192 || t == 4096 || t == 2048 || t == 256;
-    return t == 8192 || t == 4096 || t == 2048 || t == 256;
+template <typename K, bool PAIRS>
+bool tile_shape_ok(int64_t nt, int64_t vt) {
+#define X(KK, P, NT_, VT_) \
+    if constexpr (std::is_same_v<K, KK> && PAIRS == P) \
+        if (nt == NT_ && vt == VT_) return true;
+    HS_TILE_VARIANTS(X)
+#undef X
+    return false;
+}
+
+template <typename K, bool PAIRS>
+bool merge_shape_ok(int64_t nt, int64_t vt) {
+#define X(KK, P, NT_, VT_) \
+    if constexpr (std::is_same_v<K, KK> && PAIRS == P) \
+        if (nt == NT_ && vt == VT_) return true;
+    HS_MERGE_VARIANTS(X)
+#undef X
+    return false;
+}
+
+bool config_ok(int ci, const Config& c) {
+    if (c.tile_vt <= 0 || c.merge_vt <= 0 || c.tile % c.tile_vt || c.merge_nv % c.merge_vt) return false;
+    if (c.tile % c.merge_nv) return false;  // merge chunks must tile a run
+    if (c.small_max < 0 || c.small_max > 8192) return false;
+    const int64_t tn = c.tile / c.tile_vt, mn = c.merge_nv / c.merge_vt;
+    switch (ci) {
+        case 0:
+            return tile_shape_ok<int32_t, false>(tn, c.tile_vt) && merge_shape_ok<int32_t, false>(mn, c.merge_vt);
+        case 1:
+            return tile_shape_ok<int64_t, false>(tn, c.tile_vt) && merge_shape_ok<int64_t, false>(mn, c.merge_vt);
+        case 2:
+            return tile_shape_ok<int32_t, true>(tn, c.tile_vt) && merge_shape_ok<int32_t, true>(mn, c.merge_vt);
+    }
+    return false;
 }
 
 // --------------------------------------------------------------- timing
@@ -210,17 +244,24 @@ Work<K> make_work(const Layout& L, char* scr, K* keys, uint32_t* vals, const int
 
 // ------------------------------------------------------------- dispatchers
 template <typename K, bool PAIRS>
-hipError_t tilesort_by_shape(int64_t tile, const Work<K>& w, int64_t items, hipStream_t st) {
-    switch (tile) {
-        case 8192:
-            return launch_tilesort<K, PAIRS, 512, 16>(w, items, st);
-        case 4096:
-            return launch_tilesort<K, PAIRS, 256, 16>(w, items, st);
-        case 2048:
-            return launch_tilesort<K, PAIRS, 256, 8>(w, items, st);
-        case 256:
-            return launch_tilesort<K, PAIRS, 64, 4>(w, items, st);
-    }
+hipError_t tilesort_by_shape(const Config& c, const Work<K>& w, int64_t items, hipStream_t st) {
+    const int64_t nt = c.tile / c.tile_vt, vt = c.tile_vt;
+#define X(KK, P, NT_, VT_) \
+    if constexpr (std::is_same_v<K, KK> && PAIRS == P) \
+        if (nt == NT_ && vt == VT_) return launch_tilesort<KK, P, NT_, VT_>(w, items, st);
+    HS_TILE_VARIANTS(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+template <typename K, bool PAIRS>
+hipError_t merge_by_shape(const Config& c, const Work<K>& w, int64_t chunks, hipStream_t st) {
+    const int64_t nt = c.merge_nv / c.merge_vt, vt = c.merge_vt;
+#define X(KK, P, NT_, VT_) \
+    if constexpr (std::is_same_v<K, KK> && PAIRS == P) \
+        if (nt == NT_ && vt == VT_) return launch_merge<KK, P, NT_, VT_>(w, chunks, st);
+    HS_MERGE_VARIANTS(X)
+#undef X
     return hipErrorInvalidValue;
 }
 
@@ -236,12 +277,6 @@ hipError_t small_by_shape(int64_t cap, const Work<K>& w, int64_t lo, int64_t hi,
         case 256:
             return launch_small<K, PAIRS, 64, 4>(w, lo, hi, segs, st);
     }
-    return hipErrorInvalidValue;
-}
-
-template <typename K, bool PAIRS>
-hipError_t merge_by_shape(int64_t nv, const Work<K>& w, int64_t chunks, hipStream_t st) {
-    if (nv == 4096) return launch_merge<K, PAIRS, 256, 16>(w, chunks, st);
     return hipErrorInvalidValue;
 }
 
@@ -339,7 +374,7 @@ int run(int kind, K* keys, uint32_t* vals, int64_t n, const int64_t* off, int64_
         }
         {
             Timer t(st, "tilesort", 2 * kb * n);
-            HS_TRY((tilesort_by_shape<K, PAIRS>(c.tile, w, L.ts_bound, st)));
+            HS_TRY((tilesort_by_shape<K, PAIRS>(c, w, L.ts_bound, st)));
         }
         if (stage == 2) {
             HS_TRY(launch_collect<K>(w, 2, st));
@@ -356,7 +391,7 @@ int run(int kind, K* keys, uint32_t* vals, int64_t n, const int64_t* off, int64_
             {
                 Timer t(st, "merge", 0);
                 t.per_active_key(w.bsize, L.buckets, c.tile, p, 2 * kb);
-                HS_TRY((merge_by_shape<K, PAIRS>(c.merge_nv, w, L.chunks_bound, st)));
+                HS_TRY((merge_by_shape<K, PAIRS>(c, w, L.chunks_bound, st)));
             }
         }
     }
@@ -455,24 +490,28 @@ int hsort_check(const void* scratch, void* stream) {
 
 const char* hsort_last_error(void) { return g_err.c_str(); }
 
-int hsort_set_config(int kind, int64_t tile, int64_t merge_nv, int64_t small_max) {
+int hsort_set_config(int kind, int64_t tile, int64_t tile_vt, int64_t merge_nv, int64_t merge_vt,
+                     int64_t small_max) {
     g_err.clear();
     const int ci = cfg_index(kind);
     if (ci < 0) return fail(HSORT_ERR_INVALID, "unknown kind");
-    if (!tile_shape_ok(ci, tile) || merge_nv != 4096 || tile % merge_nv != 0)
-        return fail(HSORT_ERR_UNSUPPORTED, "tile/merge shape not compiled");
-    if (small_max < 0 || small_max > 8192) return fail(HSORT_ERR_UNSUPPORTED, "small_max must be in [0, 8192]");
+    const Config c{tile, tile_vt, merge_nv, merge_vt, small_max};
+    if (!config_ok(ci, c)) return fail(HSORT_ERR_UNSUPPORTED, "tile/merge shape not compiled");
     std::lock_guard<std::mutex> lk(g_mu);
-    g_cfg[ci] = Config{tile, merge_nv, small_max};
+    g_cfg[ci] = c;
     return HSORT_OK;
 }
 
-int hsort_get_config(int kind, int64_t* tile, int64_t* merge_nv, int64_t* small_max) {
+int hsort_get_config(int kind, int64_t* tile, int64_t* tile_vt, int64_t* merge_nv, int64_t* merge_vt,
+                     int64_t* small_max) {
     const int ci = cfg_index(kind);
-    if (ci < 0 || !tile || !merge_nv || !small_max) return fail(HSORT_ERR_INVALID, "bad arguments");
+    if (ci < 0 || !tile || !tile_vt || !merge_nv || !merge_vt || !small_max)
+        return fail(HSORT_ERR_INVALID, "bad arguments");
     Config c = get_cfg(kind);
     *tile = c.tile;
+    *tile_vt = c.tile_vt;
     *merge_nv = c.merge_nv;
+    *merge_vt = c.merge_vt;
     *small_max = c.small_max;
     return HSORT_OK;
 }

@@ -65,10 +65,13 @@ __device__ __forceinline__ void unpack5(uint64_t c, uint32_t (&wd)[5]) {
         wd[m] = lo | (hi << 16);
     }
 }
+// Field d of the packed words, by mask arithmetic (an indexed select would be
+// lowered to a scratch-memory table).
 __device__ __forceinline__ uint32_t field16(const uint32_t (&wd)[5], int d) {
-    uint32_t w = wd[0];
-#pragma unroll
-    for (int m = 1; m < 5; m++) w = ((d >> 1) == m) ? wd[m] : w;
+    const int h = d >> 1;
+    const uint32_t w = (wd[0] & (0u - (uint32_t)(h == 0))) | (wd[1] & (0u - (uint32_t)(h == 1))) |
+                       (wd[2] & (0u - (uint32_t)(h == 2))) | (wd[3] & (0u - (uint32_t)(h == 3))) |
+                       (wd[4] & (0u - (uint32_t)(h == 4)));
     return (w >> ((d & 1) * 16)) & 0xFFFFu;
 }
 
@@ -1072,10 +1075,12 @@ template hipError_t launch_scatter<int32_t, false>(const Work<int32_t>&, int64_t
 template hipError_t launch_scatter<int32_t, true>(const Work<int32_t>&, int64_t, hipStream_t);
 template hipError_t launch_scatter<int64_t, false>(const Work<int64_t>&, int64_t, hipStream_t);
 
-#define HS_INST_TILE(K, PAIRS, NT, VT)                                                       \
-    template hipError_t launch_tilesort<K, PAIRS, NT, VT>(const Work<K>&, int64_t, hipStream_t); \
-    template hipError_t launch_small<K, PAIRS, NT, VT>(const Work<K>&, int64_t, int64_t, int64_t, hipStream_t);
+#define HS_INST_TILE(K, PAIRS, NT, VT) \
+    template hipError_t launch_tilesort<K, PAIRS, NT, VT>(const Work<K>&, int64_t, hipStream_t);
 HS_TILE_VARIANTS(HS_INST_TILE)
+#define HS_INST_SMALL(K, PAIRS, NT, VT) \
+    template hipError_t launch_small<K, PAIRS, NT, VT>(const Work<K>&, int64_t, int64_t, int64_t, hipStream_t);
+HS_SMALL_VARIANTS(HS_INST_SMALL)
 #define HS_INST_MERGE(K, PAIRS, NT, VT) \
     template hipError_t launch_merge<K, PAIRS, NT, VT>(const Work<K>&, int64_t, hipStream_t);
 HS_MERGE_VARIANTS(HS_INST_MERGE)

@@ -17,13 +17,19 @@ struct ScanSpec {
 // Compiled (key, stable pairs, threads, keys per thread) shapes of the LDS
 // sort (local-sort tiles and whole small segments) and of the merge.
 #define HS_TILE_VARIANTS(X)                                                                  \
-    X(int32_t, false, 512, 16)                                                               \
+    X(int32_t, false, 512, 32) X(int32_t, false, 256, 32) X(int32_t, false, 512, 16)         \
     X(int32_t, false, 256, 16) X(int32_t, false, 256, 8) X(int32_t, false, 64, 4)            \
     X(int64_t, false, 512, 16)                                                               \
     X(int64_t, false, 256, 16) X(int64_t, false, 256, 8) X(int64_t, false, 64, 4)            \
     X(int32_t, true, 512, 16) X(int32_t, true, 256, 16) X(int32_t, true, 256, 8) X(int32_t, true, 64, 4)
-#define HS_MERGE_VARIANTS(X) \
-    X(int32_t, false, 256, 16) X(int64_t, false, 256, 16) X(int32_t, true, 256, 16)
+#define HS_MERGE_VARIANTS(X)                                                                 \
+    X(int32_t, false, 256, 16) X(int32_t, false, 256, 32) X(int32_t, false, 512, 16)         \
+    X(int64_t, false, 256, 16) X(int32_t, true, 256, 16)
+// Shapes usable by the whole-segment LDS sort (5-bit digit counters: VT <= 16).
+#define HS_SMALL_VARIANTS(X)                                                                 \
+    X(int32_t, false, 512, 16) X(int32_t, false, 256, 16) X(int32_t, false, 256, 8) X(int32_t, false, 64, 4) \
+    X(int64_t, false, 512, 16) X(int64_t, false, 256, 16) X(int64_t, false, 256, 8) X(int64_t, false, 64, 4) \
+    X(int32_t, true, 512, 16) X(int32_t, true, 256, 16) X(int32_t, true, 256, 8) X(int32_t, true, 64, 4)
 
 // Each launcher sizes its own (persistent) grid from an upper bound on the
 // number of work items it can be handed.

@@ -71,9 +71,12 @@ def test_argument_errors_are_synchronous(lib):
 def test_config_roundtrip(lib):
     import paper_2003_01216_amd as hs
 
-    t, m, s = hs.hsort_get_config(hs.KEYS_I32)
-    assert t % m == 0 and s <= 8192
+    cfg = hs.hsort_get_config(hs.KEYS_I32)
+    t, tvt, m, mvt, s = cfg
+    assert t % m == 0 and s <= 8192 and t % tvt == 0 and m % mvt == 0
     with pytest.raises(hs.HsortError):
-        hs.hsort_set_config(hs.KEYS_I32, 1000, 4096, 100)
-    hs.hsort_set_config(hs.KEYS_I32, t, m, s)
-    assert hs.hsort_get_config(hs.KEYS_I32) == (t, m, s)
+        hs.hsort_set_config(hs.KEYS_I32, 1000, 16, 4096, 16, 100)
+    with pytest.raises(hs.HsortError):  # merge chunk does not divide the tile
+        hs.hsort_set_config(hs.KEYS_I32, 4096, 16, 8192, 32, 100)
+    hs.hsort_set_config(hs.KEYS_I32, *cfg)
+    assert hs.hsort_get_config(hs.KEYS_I32) == cfg
