@@ -113,41 +113,77 @@ def bench_keys(hs, torch, k, steps, warmup):
     return k.size * steps / (ms * 1e-3) / 1e9, kernel_table(rec, steps)
 
 
+def timed_refill(torch, base, run_one, steps, warmup):
+    """Per-call event times of `run_one(work)`, refilling `work` from `base`
+    outside the timed window each time (same buffers on every call)."""
+    work = base.clone()
+    total = 0.0
+    for i in range(warmup + steps):
+        work.copy_(base)
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        run_one(work)
+        b.record()
+        torch.cuda.synchronize()
+        if i >= warmup:
+            total += a.elapsed_time(b)
+    return total / steps, work
+
+
 def bench_segmented(hs, torch, steps, warmup):
     """16384 arrays, log-uniform sizes in [1, 2^16]: one batched call vs a loop of plain calls."""
     keys, off = W.segments_i32(16384, 2**16, 0)
     n = keys.size
-    base = torch.from_numpy(keys).cuda()
-    doff = torch.from_numpy(off).cuda()
     max_len = int(np.diff(off).max())
-    scratch = torch.empty(hs.scratch_bytes(hs.SEG_I32, n, 16384), dtype=torch.uint8, device="cuda")
-    ms, rec, copies = timed_sorts(hs, torch, lambda m: [base.clone() for _ in range(m)],
-                                  lambda t: hs.hsort_segmented(t, doff, max_seg_len=max_len, scratch=scratch),
-                                  steps, warmup)
-    batched = n * steps / (ms * 1e-3) / 1e9
-    del copies
-    # per-array loop of the plain method on sub-views, same stream, same scratch
-    loop_scratch = torch.empty(hs.scratch_bytes(hs.KEYS_I32, max_len), dtype=torch.uint8, device="cuda")
-    offs = off.tolist()
-    work = base.clone()
+    side = torch.cuda.Stream()
+    out = {"workload": "16384 int32 arrays, sizes log-uniform [1, 2^16], keys uniform [0, 2^31-1)", "keys": int(n)}
+    with torch.cuda.stream(side):
+        base = torch.from_numpy(keys).cuda()
+        doff = torch.from_numpy(off).cuda()
+        scratch = torch.empty(hs.scratch_bytes(hs.SEG_I32, n, 16384), dtype=torch.uint8, device="cuda")
 
-    def loop(t):
-        for i in range(16384):
-            a, b = offs[i], offs[i + 1]
-            if b > a:
-                hs.hsort_keys(t[a:b], loop_scratch)
+        def batched(t):
+            hs.hsort_segmented(t, doff, max_seg_len=max_len, scratch=scratch)
 
-    loop(base.clone())  # warm-up
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    loop(work)
-    torch.cuda.synchronize()
-    loop_s = time.perf_counter() - t0
-    per_loop = n / loop_s / 1e9
+        ms_eager, _ = timed_refill(torch, base, batched, steps, warmup)
+        hs.hsort_graph_mode(True)
+        try:
+            hs.hsort_timing_read()
+            ms_graph, work = timed_refill(torch, base, batched, steps, warmup)
+        finally:
+            hs.hsort_graph_mode(False)
+        # the kernels of one batched call, timed separately (eager, per-kernel events)
+        hs.hsort_timing_enable(True)
+        w2 = base.clone()
+        batched(w2)
+        torch.cuda.synchronize()
+        hs.hsort_timing_enable(False)
+        kernels = kernel_table(hs.hsort_timing_read(), 1)
+        # per-array loop of the plain method on sub-views, same stream, one scratch
+        loop_scratch = torch.empty(hs.scratch_bytes(hs.KEYS_I32, max_len), dtype=torch.uint8, device="cuda")
+        offs = off.tolist()
+
+        def loop(t):
+            for i in range(16384):
+                a, b = offs[i], offs[i + 1]
+                if b > a:
+                    hs.hsort_keys(t[a:b], loop_scratch)
+
+        loop(base.clone())  # warm-up
+        torch.cuda.synchronize()
+        lw = base.clone()
+        t0 = time.perf_counter()
+        loop(lw)
+        torch.cuda.synchronize()
+        loop_s = time.perf_counter() - t0
+        same = bool(torch.equal(lw, work))  # loop and batched agree
     torch.cuda.empty_cache()
-    return {"workload": "16384 int32 arrays, sizes log-uniform [1, 2^16], keys uniform [0, 2^31-1)",
-            "keys": int(n), "batched_Gkeys_s": round(batched, 3), "per_array_loop_Gkeys_s": round(per_loop, 4),
-            "speedup": round(batched / per_loop, 1), "batched_kernels": kernel_table(rec, steps)}
+    out.update({"batched_graph_Gkeys_s": round(n / ms_graph / 1e6, 3), "batched_eager_Gkeys_s": round(n / ms_eager / 1e6, 3),
+                "batched_graph_ms": round(ms_graph, 4), "per_array_loop_Gkeys_s": round(n / loop_s / 1e9, 4),
+                "per_array_loop_ms": round(loop_s * 1e3, 2), "speedup_graph_vs_loop": round(loop_s * 1e3 / ms_graph, 1),
+                "loop_equals_batched": same, "batched_kernels": kernels})
+    return out
 
 
 def cpu_baseline(samples=4, n=2**24):

@@ -103,16 +103,28 @@ int hsort_check(const void* scratch, void* stream);
 const char* hsort_last_error(void);
 
 /* ---------------------------------------------------------------- tuning
- * The shape of the local sort and of the merge, per key kind: tile = keys
- * per local-sort partition (T), tile_vt = keys per thread of that sort
- * (T / tile_vt threads per workgroup); merge_nv = outputs per merge
- * workgroup, merge_vt = outputs per thread; small_max = segments (and plain
- * arrays) up to this size are sorted wholly in LDS.  merge_nv must divide
- * tile.  Only compiled shapes are accepted (HSORT_ERR_UNSUPPORTED
- * otherwise).  The setting is process-wide; scratch sizes depend on it. */
-int hsort_set_config(int kind, int64_t tile, int64_t tile_vt, int64_t merge_nv, int64_t merge_vt, int64_t small_max);
-int hsort_get_config(int kind, int64_t* tile, int64_t* tile_vt, int64_t* merge_nv, int64_t* merge_vt,
+ * The shape of the local sort and of the merge, per key kind and size
+ * class: tile = keys per local-sort partition (T), tile_vt = keys per thread
+ * of that sort (T / tile_vt threads per workgroup); merge_nv = outputs per
+ * merge workgroup, merge_vt = outputs per thread; small_max = segments (and
+ * plain arrays) up to this size are sorted wholly in LDS.  merge_nv must
+ * divide tile.  Only compiled shapes are accepted (HSORT_ERR_UNSUPPORTED
+ * otherwise).  kind: any hsort_kind (the two segmented kinds share the
+ * table of their key type).  Size classes 0..3 hold calls whose deciding
+ * size -- n, or max_seg_len of a segmented call when given -- is at most
+ * 2^18, 2^22, 2^26, or larger (hsort_size_class(n) maps a size to its
+ * class); size_cls = -1 sets every class.  The table is process-wide, and
+ * scratch sizes depend on it: size scratch after changing it. */
+int hsort_set_config(int kind, int size_cls, int64_t tile, int64_t tile_vt, int64_t merge_nv, int64_t merge_vt,
+                     int64_t small_max);
+int hsort_get_config(int kind, int size_cls, int64_t* tile, int64_t* tile_vt, int64_t* merge_nv, int64_t* merge_vt,
                      int64_t* small_max);
+int hsort_size_class(int64_t n);
+
+/* Applies a tuning table written by the autotuner: text lines
+ * "kind size_class tile tile_vt merge_nv merge_vt small_max" ('#' starts a
+ * comment line).  Stops at the first bad line and returns its error. */
+int hsort_load_tuning(const char* path);
 
 /* ----------------------------------------------------- test observability
  * Runs the plain-sort pipeline (kinds HSORT_KEYS_I32, HSORT_KEYS_I64,
@@ -124,6 +136,22 @@ int hsort_get_config(int kind, int64_t* tile, int64_t* tile_vt, int64_t* merge_n
  * except for pairs. */
 int hsort_debug_stage(int kind, void* keys, uint32_t* vals, int64_t n, int stage, void* scratch,
                       size_t scratch_bytes, void* stream);
+
+/* ----------------------------------------------------------- hipGraphs
+ * With graph mode on, each distinct call -- same entry point, sizes,
+ * pointers, shapes and stream -- is captured once into a hipGraph (on the
+ * first such call) and replayed on later calls, which removes the per-kernel
+ * launch cost of the pass sequence.  The graphs read every data-dependent
+ * quantity (segment sizes, bucket sizes, work lists) on the device, so a
+ * replay with new key values or new offsets values is exact.  Calls on the
+ * null stream, and calls on a stream the caller is already capturing, are
+ * launched directly.  At most 64 graphs are cached (least recently used is
+ * dropped); hsort_graph_clear() destroys them all (call it before freeing
+ * buffers a cached graph refers to, if their addresses may be reused for
+ * calls of other sizes). */
+int hsort_graph_mode(int on);
+int hsort_graph_clear(void);
+int64_t hsort_graph_count(void);
 
 /* Per-kernel timing.  While enabled, every kernel launch of the library is
  * bracketed by HIP events recorded on the call's stream.  hsort_timing_read

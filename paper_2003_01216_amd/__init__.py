@@ -19,6 +19,8 @@ import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhsort.so")
+# table written by `python -m paper_2003_01216_amd.autotune`; applied at load
+TUNING_PATH = os.path.join(_HERE, "tuning.txt")
 
 HSORT_OK = 0
 HSORT_ERR_INVALID = 1
@@ -45,7 +47,12 @@ EXPORTS = [
     "hsort_last_error",
     "hsort_set_config",
     "hsort_get_config",
+    "hsort_size_class",
+    "hsort_load_tuning",
     "hsort_debug_stage",
+    "hsort_graph_mode",
+    "hsort_graph_clear",
+    "hsort_graph_count",
     "hsort_timing_enable",
     "hsort_timing_read",
     "hsort_copy",
@@ -80,9 +87,14 @@ def load_library(path: str = LIB_PATH):
         "hsort_bounds_offset": ([I, I64, I64], SZ),
         "hsort_check": ([P, P], I),
         "hsort_last_error": ([], ctypes.c_char_p),
-        "hsort_set_config": ([I, I64, I64, I64, I64, I64], I),
-        "hsort_get_config": ([I, P, P, P, P, P], I),
+        "hsort_set_config": ([I, I, I64, I64, I64, I64, I64], I),
+        "hsort_get_config": ([I, I, P, P, P, P, P], I),
+        "hsort_size_class": ([I64], I),
+        "hsort_load_tuning": ([ctypes.c_char_p], I),
         "hsort_debug_stage": ([I, P, P, I64, I, P, SZ, P], I),
+        "hsort_graph_mode": ([I], I),
+        "hsort_graph_clear": ([], I),
+        "hsort_graph_count": ([], I64),
         "hsort_timing_enable": ([I], I),
         "hsort_timing_read": ([P, I64], I64),
         "hsort_copy": ([P, P, I64, P], I),
@@ -92,6 +104,9 @@ def load_library(path: str = LIB_PATH):
         fn.argtypes = args
         fn.restype = res
     _lib = lib
+    tune = os.environ.get("HSORT_TUNE_FILE", TUNING_PATH)
+    if tune and os.path.exists(tune):
+        _check(lib.hsort_load_tuning(tune.encode()))
     return lib
 
 
@@ -196,15 +211,27 @@ def read_bounds(scratch: torch.Tensor, kind: int, n: int, nseg: int = 1) -> torc
     return scratch[off: off + 8 * 11 * nseg].view(torch.int64).view(nseg, 11)
 
 
-def hsort_set_config(kind: int, tile: int, tile_vt: int, merge_nv: int, merge_vt: int, small_max: int) -> None:
-    _check(load_library().hsort_set_config(kind, tile, tile_vt, merge_nv, merge_vt, small_max))
+def hsort_set_config(kind: int, tile: int, tile_vt: int, merge_nv: int, merge_vt: int, small_max: int,
+                     size_class: int = -1) -> None:
+    _check(load_library().hsort_set_config(kind, size_class, tile, tile_vt, merge_nv, merge_vt, small_max))
 
 
-def hsort_get_config(kind: int):
-    """(tile, tile_vt, merge_nv, merge_vt, small_max) of a key kind."""
+def hsort_get_config(kind: int, size_class: int | None = None, n: int | None = None):
+    """(tile, tile_vt, merge_nv, merge_vt, small_max) of a kind, for a size class or for n keys (default: 2^28)."""
+    lib = load_library()
+    if size_class is None:
+        size_class = lib.hsort_size_class(n if n is not None else 1 << 28)
     vals = [ctypes.c_int64() for _ in range(5)]
-    _check(load_library().hsort_get_config(kind, *[ctypes.byref(v) for v in vals]))
+    _check(lib.hsort_get_config(kind, size_class, *[ctypes.byref(v) for v in vals]))
     return tuple(v.value for v in vals)
+
+
+def hsort_size_class(n: int) -> int:
+    return int(load_library().hsort_size_class(n))
+
+
+def hsort_load_tuning(path: str) -> None:
+    _check(load_library().hsort_load_tuning(path.encode()))
 
 
 def hsort_debug_stage(keys: torch.Tensor, stage: int, vals: torch.Tensor | None = None,
@@ -220,6 +247,19 @@ def hsort_debug_stage(keys: torch.Tensor, stage: int, vals: torch.Tensor | None 
     _check(load_library().hsort_debug_stage(kind, _ptr(keys), _ptr(vals), n, stage, _ptr(s), s.numel(),
                                             _stream(keys)))
     return keys
+
+
+def hsort_graph_mode(on: bool) -> None:
+    """Capture each distinct call into a hipGraph once and replay it afterwards."""
+    load_library().hsort_graph_mode(1 if on else 0)
+
+
+def hsort_graph_clear() -> None:
+    load_library().hsort_graph_clear()
+
+
+def hsort_graph_count() -> int:
+    return int(load_library().hsort_graph_count())
 
 
 def hsort_timing_enable(on: bool) -> None:

@@ -34,26 +34,42 @@ struct Config {
 };
 
 std::mutex g_mu;
-// index: 0 = int32 keys, 1 = int64 keys, 2 = int32 pairs
-Config g_cfg[3] = {{16384, 32, 4096, 16, 8192}, {4096, 16, 4096, 16, 4096}, {4096, 16, 4096, 16, 4096}};
+// [kind][size class], kind as hsort_kind (0 int32 keys, 1 int64 keys,
+// 2 int32 pairs, 3 segmented int32, 4 segmented int64); size class by the
+// number of keys that decides the merge depth (n for a plain sort, the
+// longest segment for a segmented one when the caller gives it).
+constexpr int kKinds = 5;
+constexpr int kClasses = 4;
+constexpr int64_t kClassTop[kClasses - 1] = {1 << 18, 1 << 22, 1 << 26};
+Config g_cfg[kKinds][kClasses] = {
+    {{8192, 16, 4096, 16, 8192}, {8192, 16, 4096, 16, 8192}, {16384, 32, 4096, 16, 8192}, {16384, 32, 4096, 16, 8192}},
+    {{4096, 16, 4096, 16, 4096}, {4096, 16, 4096, 16, 4096}, {4096, 16, 4096, 16, 4096}, {4096, 16, 4096, 16, 4096}},
+    {{4096, 16, 4096, 16, 4096}, {4096, 16, 4096, 16, 4096}, {4096, 16, 4096, 16, 4096}, {4096, 16, 4096, 16, 4096}},
+    {{8192, 16, 4096, 16, 8192}, {8192, 16, 4096, 16, 8192}, {16384, 32, 4096, 16, 8192}, {16384, 32, 4096, 16, 8192}},
+    {{4096, 16, 4096, 16, 4096}, {4096, 16, 4096, 16, 4096}, {4096, 16, 4096, 16, 4096}, {4096, 16, 4096, 16, 4096}},
+};
 
-int cfg_index(int kind) {
-    switch (kind) {
-        case HSORT_KEYS_I32:
-        case HSORT_SEG_I32:
-            return 0;
-        case HSORT_KEYS_I64:
-        case HSORT_SEG_I64:
-            return 1;
-        case HSORT_PAIRS_I32_U32:
-            return 2;
-    }
-    return -1;
+int cfg_index(int kind) { return (kind >= 0 && kind < kKinds) ? kind : -1; }
+
+// key type of a kind: 0 int32 keys, 1 int64 keys, 2 int32 pairs
+int key_type(int kind) { return kind == HSORT_KEYS_I64 || kind == HSORT_SEG_I64 ? 1 : kind == HSORT_PAIRS_I32_U32 ? 2 : 0; }
+
+int size_class(int64_t n) {
+    int c = 0;
+    while (c < kClasses - 1 && n > kClassTop[c]) c++;
+    return c;
 }
 
-Config get_cfg(int kind) {
+// Size that selects the class: n, or for a segmented call the longest
+// segment when the caller knows it.
+int64_t class_size(int kind, int64_t n, int64_t max_seg_len) {
+    const bool seg = kind == HSORT_SEG_I32 || kind == HSORT_SEG_I64;
+    return (seg && max_seg_len > 0 && max_seg_len < n) ? max_seg_len : n;
+}
+
+Config get_cfg(int kind, int64_t size) {
     std::lock_guard<std::mutex> lk(g_mu);
-    return g_cfg[cfg_index(kind)];
+    return g_cfg[cfg_index(kind)][size_class(size)];
 }
 
 template <typename K, bool PAIRS>
@@ -106,6 +122,7 @@ struct Rec {
 };
 bool g_timing = false;
 std::vector<Rec> g_recs;
+thread_local bool g_capturing = false;  // no event records inside a captured graph
 
 struct Timer {
     hipStream_t st;
@@ -117,7 +134,7 @@ struct Timer {
     Timer(hipStream_t s, const char* n, double by) : st(s), name(n), bytes(by) {
         {
             std::lock_guard<std::mutex> lk(g_mu);
-            on = g_timing;
+            on = g_timing && !g_capturing;
         }
         if (on) {
             hipEventCreate(&a);
@@ -302,11 +319,14 @@ std::vector<SmallClass> small_classes(int64_t small_max) {
         if (e_ != hipSuccess) return fail(HSORT_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
-// One call: plain (off == nullptr, one segment) or segmented.
+// The launch sequence of one call: plain (off == nullptr, one segment) or
+// segmented.  Every host-side decision depends only on the arguments' sizes
+// and the configuration, never on device data, so the sequence can be
+// captured into a graph and replayed.
 template <typename K, bool PAIRS>
-int run(int kind, K* keys, uint32_t* vals, int64_t n, const int64_t* off, int64_t nseg, int64_t max_seg_len,
+int enqueue(int kind, K* keys, uint32_t* vals, int64_t n, const int64_t* off, int64_t nseg, int64_t max_seg_len,
         void* scratch, size_t scratch_bytes, hipStream_t st, int stage, int64_t small_override) {
-    const Config c = get_cfg(kind);
+    const Config c = get_cfg(kind, class_size(kind, n, max_seg_len));
     const bool seg = off != nullptr;
     if (!seg) nseg = 1;
     const Layout L = make_layout(kind, n, nseg, c);
@@ -404,6 +424,105 @@ int run(int kind, K* keys, uint32_t* vals, int64_t n, const int64_t* off, int64_
     return HSORT_OK;
 }
 
+// ------------------------------------------------------------ graph cache
+// With graph mode on, each distinct call (kind, sizes, pointers, shapes,
+// stream) is captured once into a hipGraph and replayed afterwards; the
+// kernels read all data-dependent quantities on the device.
+struct GraphKey {
+    int kind, stage;
+    int64_t n, nseg, max_seg_len, small_override;
+    const void *keys, *vals, *off, *scratch;
+    hipStream_t st;
+    Config c;
+};
+struct GraphEntry {
+    GraphKey key;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    uint64_t last_use;
+};
+bool g_graph_mode = false;
+std::vector<GraphEntry> g_graphs;
+uint64_t g_tick = 0;
+constexpr size_t kMaxGraphs = 64;
+
+void destroy_entry(GraphEntry& e) {
+    (void)hipStreamSynchronize(e.key.st);  // a replay may still be in flight
+    (void)hipGraphExecDestroy(e.exec);
+    (void)hipGraphDestroy(e.graph);
+}
+
+template <typename K, bool PAIRS>
+int run(int kind, K* keys, uint32_t* vals, int64_t n, const int64_t* off, int64_t nseg, int64_t max_seg_len,
+        void* scratch, size_t scratch_bytes, hipStream_t st, int stage, int64_t small_override) {
+    bool graphs;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        graphs = g_graph_mode;
+    }
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (graphs && st) (void)hipStreamIsCapturing(st, &cap);
+    if (!graphs || !st || cap != hipStreamCaptureStatusNone)
+        return enqueue<K, PAIRS>(kind, keys, vals, n, off, nseg, max_seg_len, scratch, scratch_bytes, st, stage,
+                                 small_override);
+    GraphKey key;
+    memset(&key, 0, sizeof key);
+    key.kind = kind;
+    key.stage = stage;
+    key.n = n;
+    key.nseg = nseg;
+    key.max_seg_len = max_seg_len;
+    key.small_override = small_override;
+    key.keys = keys;
+    key.vals = vals;
+    key.off = off;
+    key.scratch = scratch;
+    key.st = st;
+    key.c = get_cfg(kind, class_size(kind, n, max_seg_len));
+    hipGraphExec_t exec = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        for (GraphEntry& e : g_graphs)
+            if (!memcmp(&e.key, &key, sizeof key)) {
+                e.last_use = ++g_tick;
+                exec = e.exec;
+                break;
+            }
+    }
+    if (!exec) {
+        const Layout L = make_layout(kind, n, off ? nseg : 1, key.c);
+        if (scratch_bytes < L.total)
+            return fail(HSORT_ERR_SCRATCH, "scratch too small: need " + std::to_string(L.total) + " bytes");
+        HS_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        g_capturing = true;
+        const int rc = enqueue<K, PAIRS>(kind, keys, vals, n, off, nseg, max_seg_len, scratch, scratch_bytes, st,
+                                         stage, small_override);
+        g_capturing = false;
+        hipGraph_t graph = nullptr;
+        const hipError_t e = hipStreamEndCapture(st, &graph);
+        if (rc != HSORT_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        if (e != hipSuccess) return fail(HSORT_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+        const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (ei != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            return fail(HSORT_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+        }
+        std::lock_guard<std::mutex> lk(g_mu);
+        if (g_graphs.size() >= kMaxGraphs) {
+            auto lru = std::min_element(g_graphs.begin(), g_graphs.end(),
+                                        [](const GraphEntry& a, const GraphEntry& b) { return a.last_use < b.last_use; });
+            destroy_entry(*lru);
+            g_graphs.erase(lru);
+        }
+        g_graphs.push_back({key, graph, exec, ++g_tick});
+    }
+    HS_TRY(hipGraphLaunch(exec, st));
+    return HSORT_OK;
+}
+
 int check_common(const void* keys, int64_t n, const void* scratch) {
     if (n < 0) return fail(HSORT_ERR_INVALID, "n < 0");
     if (n > HSORT_MAX_KEYS) return fail(HSORT_ERR_UNSUPPORTED, "n above HSORT_MAX_KEYS");
@@ -418,13 +537,27 @@ extern "C" {
 
 size_t hsort_scratch_bytes(int kind, int64_t n, int64_t nseg) {
     if (cfg_index(kind) < 0 || n < 0 || nseg < 0) return 0;
-    return make_layout(kind, n, nseg, get_cfg(kind)).total;
+    // the largest need over the classes a segmented call of n keys may pick
+    size_t need = 0;
+    const bool seg = kind == HSORT_SEG_I32 || kind == HSORT_SEG_I64;
+    for (int c = 0; c < kClasses; c++) {
+        if (!seg && c != size_class(n)) continue;
+        Config cf;
+        {
+            std::lock_guard<std::mutex> lk(g_mu);
+            cf = g_cfg[cfg_index(kind)][c];
+        }
+        need = std::max(need, make_layout(kind, n, nseg, cf).total);
+    }
+    return need;
 }
 
 size_t hsort_bounds_offset(int kind, int64_t n, int64_t nseg) {
     if (cfg_index(kind) < 0) return 0;
-    return make_layout(kind, n, nseg, get_cfg(kind)).bounds;
+    return make_layout(kind, n, nseg, get_cfg(kind, n)).bounds;  // does not depend on the shapes
 }
+
+int hsort_size_class(int64_t n) { return size_class(n); }
 
 int hsort_keys_i32(int32_t* keys, int64_t n, void* scratch, size_t scratch_bytes, void* stream) {
     g_err.clear();
@@ -490,30 +623,58 @@ int hsort_check(const void* scratch, void* stream) {
 
 const char* hsort_last_error(void) { return g_err.c_str(); }
 
-int hsort_set_config(int kind, int64_t tile, int64_t tile_vt, int64_t merge_nv, int64_t merge_vt,
+int hsort_set_config(int kind, int size_cls, int64_t tile, int64_t tile_vt, int64_t merge_nv, int64_t merge_vt,
                      int64_t small_max) {
     g_err.clear();
     const int ci = cfg_index(kind);
     if (ci < 0) return fail(HSORT_ERR_INVALID, "unknown kind");
+    if (size_cls < -1 || size_cls >= kClasses) return fail(HSORT_ERR_INVALID, "size class out of range");
     const Config c{tile, tile_vt, merge_nv, merge_vt, small_max};
-    if (!config_ok(ci, c)) return fail(HSORT_ERR_UNSUPPORTED, "tile/merge shape not compiled");
+    if (!config_ok(key_type(kind), c)) return fail(HSORT_ERR_UNSUPPORTED, "tile/merge shape not compiled");
     std::lock_guard<std::mutex> lk(g_mu);
-    g_cfg[ci] = c;
+    for (int k = 0; k < kClasses; k++)
+        if (size_cls < 0 || k == size_cls) g_cfg[ci][k] = c;
     return HSORT_OK;
 }
 
-int hsort_get_config(int kind, int64_t* tile, int64_t* tile_vt, int64_t* merge_nv, int64_t* merge_vt,
+int hsort_get_config(int kind, int size_cls, int64_t* tile, int64_t* tile_vt, int64_t* merge_nv, int64_t* merge_vt,
                      int64_t* small_max) {
     const int ci = cfg_index(kind);
-    if (ci < 0 || !tile || !tile_vt || !merge_nv || !merge_vt || !small_max)
+    if (ci < 0 || size_cls < 0 || size_cls >= kClasses || !tile || !tile_vt || !merge_nv || !merge_vt || !small_max)
         return fail(HSORT_ERR_INVALID, "bad arguments");
-    Config c = get_cfg(kind);
+    Config c;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        c = g_cfg[ci][size_cls];
+    }
     *tile = c.tile;
     *tile_vt = c.tile_vt;
     *merge_nv = c.merge_nv;
     *merge_vt = c.merge_vt;
     *small_max = c.small_max;
     return HSORT_OK;
+}
+
+int hsort_load_tuning(const char* path) {
+    g_err.clear();
+    if (!path) return fail(HSORT_ERR_INVALID, "null path");
+    FILE* f = fopen(path, "r");
+    if (!f) return fail(HSORT_ERR_INVALID, std::string("cannot open ") + path);
+    char line[512];
+    int lineno = 0, rc = HSORT_OK;
+    while (fgets(line, sizeof line, f)) {
+        lineno++;
+        if (line[0] == '#' || line[0] == '\n') continue;
+        int kind = 0, cls = 0;
+        long long t, tv, m, mv, sm;
+        if (sscanf(line, "%d %d %lld %lld %lld %lld %lld", &kind, &cls, &t, &tv, &m, &mv, &sm) != 7) {
+            rc = fail(HSORT_ERR_INVALID, std::string(path) + ": bad line " + std::to_string(lineno));
+            break;
+        }
+        if ((rc = hsort_set_config(kind, cls, t, tv, m, mv, sm)) != HSORT_OK) break;
+    }
+    fclose(f);
+    return rc;
 }
 
 int hsort_debug_stage(int kind, void* keys, uint32_t* vals, int64_t n, int stage, void* scratch,
@@ -536,6 +697,24 @@ int hsort_debug_stage(int kind, void* keys, uint32_t* vals, int64_t n, int stage
                                       stage, 0);
     }
     return fail(HSORT_ERR_INVALID, "kind must be a plain kind");
+}
+
+int hsort_graph_mode(int on) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_graph_mode = on != 0;
+    return HSORT_OK;
+}
+
+int hsort_graph_clear(void) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (GraphEntry& e : g_graphs) destroy_entry(e);
+    g_graphs.clear();
+    return HSORT_OK;
+}
+
+int64_t hsort_graph_count(void) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    return (int64_t)g_graphs.size();
 }
 
 int hsort_timing_enable(int on) {

@@ -71,12 +71,29 @@ def test_argument_errors_are_synchronous(lib):
 def test_config_roundtrip(lib):
     import paper_2003_01216_amd as hs
 
-    cfg = hs.hsort_get_config(hs.KEYS_I32)
+    assert [hs.hsort_size_class(n) for n in (1, 1 << 18, (1 << 18) + 1, 1 << 22, 1 << 26, 1 << 28)] == [0, 0, 1, 1, 2, 3]
+    cfg = hs.hsort_get_config(hs.KEYS_I32, size_class=3)
     t, tvt, m, mvt, s = cfg
     assert t % m == 0 and s <= 8192 and t % tvt == 0 and m % mvt == 0
     with pytest.raises(hs.HsortError):
         hs.hsort_set_config(hs.KEYS_I32, 1000, 16, 4096, 16, 100)
     with pytest.raises(hs.HsortError):  # merge chunk does not divide the tile
         hs.hsort_set_config(hs.KEYS_I32, 4096, 16, 8192, 32, 100)
-    hs.hsort_set_config(hs.KEYS_I32, *cfg)
-    assert hs.hsort_get_config(hs.KEYS_I32) == cfg
+    hs.hsort_set_config(hs.KEYS_I32, *cfg, size_class=3)
+    assert hs.hsort_get_config(hs.KEYS_I32, size_class=3) == cfg
+
+
+def test_tuning_file(lib, tmp_path):
+    import paper_2003_01216_amd as hs
+
+    before = [hs.hsort_get_config(hs.KEYS_I64, size_class=c) for c in range(4)]
+    f = tmp_path / "t.txt"
+    f.write_text("# kind class tile tile_vt merge_nv merge_vt small_max\n1 2 8192 16 4096 16 2048\n")
+    hs.hsort_load_tuning(str(f))
+    assert hs.hsort_get_config(hs.KEYS_I64, size_class=2) == (8192, 16, 4096, 16, 2048)
+    assert hs.hsort_get_config(hs.KEYS_I64, size_class=1) == before[1]
+    f.write_text("1 2 999 16 4096 16 2048\n")
+    with pytest.raises(hs.HsortError):
+        hs.hsort_load_tuning(str(f))
+    for c, cfg in enumerate(before):
+        hs.hsort_set_config(hs.KEYS_I64, *cfg, size_class=c)

@@ -161,7 +161,7 @@ def test_stage_scatter_matches_oracle(hs, orc, name):
 @pytest.mark.parametrize("name", sorted(_stage_inputs().keys()))
 def test_stage_local_sorts_match_oracle(hs, orc, name):
     k = _stage_inputs()[name]
-    tile = hs.hsort_get_config(hs.KEYS_I32)[0]
+    tile = hs.hsort_get_config(hs.KEYS_I32, n=k.size)[0]
     say(f"stage tiles {name} tile={tile}")
     t = dev(k)
     hs.hsort_debug_stage(t, 2)
@@ -171,7 +171,7 @@ def test_stage_local_sorts_match_oracle(hs, orc, name):
 
 def test_stage_pairs_scatter_and_tiles(hs, orc):
     k, v = W.dup_pairs_i32(200_003, 31)
-    tile = hs.hsort_get_config(hs.PAIRS_I32_U32)[0]
+    tile = hs.hsort_get_config(hs.PAIRS_I32_U32, n=k.size)[0]
     for stage in (1, 2):
         say(f"pairs stage {stage}")
         tk, tv = dev(k), dev(v.view(np.int32))
@@ -186,7 +186,7 @@ def test_stage_pairs_scatter_and_tiles(hs, orc):
 
 def test_stage_int64(hs, orc):
     k = _i64_cases()["full_n100003"]
-    tile = hs.hsort_get_config(hs.KEYS_I64)[0]
+    tile = hs.hsort_get_config(hs.KEYS_I64, n=k.size)[0]
     for stage in (1, 2):
         say(f"int64 stage {stage}")
         t = dev(k)
