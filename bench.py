@@ -36,6 +36,28 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+HERE = os.path.dirname(os.path.abspath(__file__))
+TRAFFIC_RECORD = os.path.join(HERE, "profiles", "sort_i32_2e28_hbm_bytes.md")
+KERNEL_SOURCE = os.path.join(HERE, "paper_2003_01216_amd", "csrc", "hs_kernels.hip")
+
+
+def measured_traffic():
+    """HBM bytes per dispatch of the dominant kernel from the committed FETCH_SIZE/WRITE_SIZE record,
+    or None when the kernel source changed since the counters were taken."""
+    import hashlib
+    import re
+
+    try:
+        text = open(TRAFFIC_RECORD).read()
+        rec = json.loads(re.search(r"```json\n(.*?)\n```", text, re.S).group(1))
+        sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    except (OSError, AttributeError, ValueError):
+        return None
+    if rec.get("kernels_source_sha256") != sha:
+        return None
+    return rec["fetch_bytes_per_dispatch"] + rec["write_bytes_per_dispatch"]
+
+
 def kernel_table(rec, steps):
     """{name: {launches, ms_per_launch, GB/s, frac}} from hsort_timing_read()."""
     out = {}
@@ -186,6 +208,51 @@ def bench_segmented(hs, torch, steps, warmup):
     return out
 
 
+def bench_serving(count=300, budget=64 << 30, streams=3, load=0.7):
+    """Poisson stream of int64 sort requests (sizes log-uniform in [2^10, 2^24], keys over the full int64
+    range) through the continuous-batching server with a 64 GiB HBM budget.  The arrival rate is `load` times
+    the saturation rate measured first with every request submitted at once."""
+    import threading
+
+    import paper_2003_01216_amd.serve as serve
+
+    sizes = W.request_sizes(count, 2**10, 2**24, seed=0)
+    info = np.iinfo(np.int64)
+    reqs = [np.random.default_rng((0, i)).integers(info.min, info.max, int(s), dtype=np.int64, endpoint=True)
+            for i, s in enumerate(sizes)]
+    with serve.SortServer(hbm_budget=budget, streams=streams) as srv:  # warm-up
+        for f in [srv.submit(r) for r in reqs[:8]]:
+            f.result()
+    with serve.SortServer(hbm_budget=budget, streams=streams) as srv:
+        futs = [srv.submit(r) for r in reqs]
+        for f in futs:
+            f.result()
+        sat = srv.stats()
+    rate = load * count / sat["wall_s"]
+    gaps = np.random.default_rng(1).exponential(1.0 / rate, count)
+    with serve.SortServer(hbm_budget=budget, streams=streams) as srv:
+        futs = []
+
+        def client():
+            for r, g in zip(reqs, gaps):
+                time.sleep(g)
+                futs.append(srv.submit(r))
+
+        th = threading.Thread(target=client)
+        th.start()
+        th.join()
+        outs = [f.result() for f in futs]
+        st = srv.stats()
+    ok = all(bool(np.all(o[1:] >= o[:-1])) for o in outs[:: max(1, count // 20)])
+    return {"workload": f"{count} int64 requests, sizes log-uniform [2^10, 2^24], keys full int64 range, Poisson arrivals",
+            "budget_bytes": budget, "streams": streams, "saturation_Gkeys_s": round(sat["Gkeys_s"], 3),
+            "saturation_requests_s": round(count / sat["wall_s"], 1), "rate_requests_s": round(rate, 1),
+            "Gkeys_s": round(st["Gkeys_s"], 3), "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
+            "mean_batch_requests": round(st["mean_batch_requests"], 2), "batches": st["batches"],
+            "overlap_s": round(st["overlap_s"], 3), "peak_in_flight_bytes": st["peak_in_flight_bytes"],
+            "sorted_check": ok, "note": "end to end: host arrays in, host arrays out (PCIe copies included)"}
+
+
 def cpu_baseline(samples=4, n=2**24):
     """The oracle (single-threaded C) on `samples` arrays of n keys of the metric's distribution."""
     import oracle
@@ -228,6 +295,21 @@ def main():
     if not ok:
         log("[bench] ERROR: output of the last step is not sorted")
         sys.exit(1)
+    # plain copy through the library's copy kernel: the practical streaming ceiling, and the
+    # reference a byte-counter profile of this same command is scaled by
+    cb = 1 << 30
+    src = torch.empty(cb, dtype=torch.uint8, device="cuda")
+    dst = torch.empty(cb, dtype=torch.uint8, device="cuda")
+    hs.hsort_copy(src, dst)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(5):
+        hs.hsort_copy(src, dst)
+    b.record()
+    torch.cuda.synchronize()
+    copy_gbps = 5 * 2 * cb / (a.elapsed_time(b) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
     ms_step = ms / args.steps
     value = n / (ms_step * 1e-3) / 1e9
     table = kernel_table(rec, args.steps)
@@ -235,10 +317,15 @@ def main():
     for name, d in table.items():
         log(f"[bench]   {name:10s} {d['ms_per_step']:.3f} ms/step  {d.get('GBps', '-')} GB/s")
     dom = max((kv for kv in table.items() if "GBps" in kv[1]), key=lambda kv: kv[1]["ms_per_step"])
+    traffic = measured_traffic() if dom[0] == "merge" else None
     roof = {"bound": "hbm", "kernel": dom[0], "achieved": dom[1]["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(dom[1]["GBps"] / HBM_PEAK_GBS, 4), "traffic": None}
+            "frac": round(dom[1]["GBps"] / HBM_PEAK_GBS, 4),
+            "traffic": round(traffic / 1e9, 4) if traffic else None,
+            "traffic_unit": "GB per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "algorithmic_GB_per_launch": round(dom[1]["bytes_per_launch"] / 1e9, 4)}
     total_bytes = sum(d.get("bytes_per_launch", 0) * d["launches_per_step"] for d in table.values())
-    extra = {"kernels": table, "algorithmic_bytes_per_key": round(total_bytes / n, 2),
+    extra = {"kernels": table, "copy_kernel_GBps": round(copy_gbps, 1),
+             "algorithmic_bytes_per_key": round(total_bytes / n, 2),
              "whole_sort_frac_hbm_peak": round(total_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
     if not args.no_extras:
@@ -250,6 +337,8 @@ def main():
         extra["int64_full_range_2e26_Gkeys_s"] = round(bench_keys(hs, torch, W.uniform_i64(2**26, 0), 10, 2)[0], 3)
         log("[bench] batched segmented vs per-array loop")
         extra["segmented"] = bench_segmented(hs, torch, 10, 2)
+        log("[bench] serving loop")
+        extra["serving"] = bench_serving()
 
     cpu = None
     if not args.no_cpu:

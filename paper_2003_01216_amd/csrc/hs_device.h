@@ -197,6 +197,22 @@ __device__ __forceinline__ int merge_path_fixed(int diag, int na, int nb, FA A, 
     return pos;
 }
 
+// Global-memory co-rank by absolute power-of-two steps (top = a power of two
+// not below hi - lo).  Probes of nearby diagonals fall on the same few
+// positions in the early steps (lo is a multiple of the chunk size), so
+// neighbouring searches share cache lines instead of each pulling its own.
+template <typename FA, typename FB>
+__device__ __forceinline__ int64_t merge_path_steps64(int64_t diag, int64_t na, int64_t nb, int64_t top, FA A, FB B) {
+    const int64_t lo = diag > nb ? diag - nb : 0;
+    const int64_t hi = diag < na ? diag : na;
+    int64_t pos = lo;
+    for (int64_t step = top; step > 0; step >>= 1) {
+        const int64_t m = pos + step - 1;
+        if (m < hi && !(B(diag - 1 - m) < A(m))) pos += step;
+    }
+    return pos;
+}
+
 // 64-bit variant for global-memory co-ranks over long runs.
 template <typename FA, typename FB>
 __device__ __forceinline__ int64_t merge_path64(int64_t diag, int64_t na, int64_t nb, FA A, FB B) {

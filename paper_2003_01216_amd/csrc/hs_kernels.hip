@@ -322,20 +322,21 @@ __global__ __launch_bounds__(kHistNT) void k_range(Work<K> w) {
 
 // Per large segment: min/max over its tiles, then the decimal digit plan.
 template <typename K>
-__global__ __launch_bounds__(256) void k_plans(Work<K> w) {
-    __shared__ K rmn[256 / kWave], rmx[256 / kWave];
+__global__ __launch_bounds__(1024) void k_plans(Work<K> w) {
+    __shared__ K rmn[1024 / kWave], rmx[1024 / kWave];
     if (*w.err) return;
     for (int s = blockIdx.x; s < w.nseg; s += gridDim.x) {
         const int nt = w.tilecnt[s];
         if (nt == 0) continue;
         const int t0 = w.tilepre[s];
         K mn = Traits<K>::kMax, mx = Traits<K>::kMin;
-        for (int t = threadIdx.x; t < nt; t += 256) {
+#pragma unroll 8
+        for (int t = threadIdx.x; t < nt; t += 1024) {
             const K a = w.tmin[t0 + t], b = w.tmax[t0 + t];
             mn = a < mn ? a : mn;
             mx = b > mx ? b : mx;
         }
-        block_minmax<K, 256>(mn, mx, rmn, rmx);
+        block_minmax<K, 1024>(mn, mx, rmn, rmx);
         if (threadIdx.x == 0) w.plans[s] = make_digit_plan<K>(mn, mx);
     }
 }
@@ -624,8 +625,8 @@ __global__ __launch_bounds__(256) void k_partition(Work<K> w, int pass, int64_t 
             const K* A = src + base;
             const K* B = A + L;
             const int64_t diag = o - ps;
-            const int64_t cs =
-                merge_path64(diag, a_len, b_len, [&](int64_t x) { return A[x]; }, [&](int64_t x) { return B[x]; });
+            const int64_t cs = merge_path_steps64(
+                diag, a_len, b_len, L, [&](int64_t x) { return A[x]; }, [&](int64_t x) { return B[x]; });
             d.a = base + cs;
             d.b = base + L + (diag - cs);
             d.out = w.bstart[j] + o;
@@ -985,7 +986,7 @@ hipError_t launch_range(const Work<K>& w, int64_t tiles_bound, hipStream_t st) {
 template <typename K>
 hipError_t launch_plans(const Work<K>& w, hipStream_t st) {
     const int g = (int)min((int64_t)4096, (int64_t)w.nseg);
-    k_plans<K><<<g < 1 ? 1 : g, 256, 0, st>>>(w);
+    k_plans<K><<<g < 1 ? 1 : g, 1024, 0, st>>>(w);
     return hipGetLastError();
 }
 
