@@ -1,0 +1,135 @@
+// hs_io.h -- moving runs of keys between HBM and a workgroup with 16-byte
+// accesses.  On gfx950 a wavefront's 4-byte loads stream at about two thirds
+// of the rate of 16-byte loads, so a run [p, p + cnt) is split into a
+// scalar head up to the first 16-byte boundary, a body of aligned 16-byte
+// vectors, and a scalar tail.  No vector access is ever misaligned.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hs {
+
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<int32_t> {
+    using type = int4;
+    static constexpr int n = 4;
+    static __device__ __forceinline__ int32_t get(const int4& v, int e) {
+        return e == 0 ? v.x : e == 1 ? v.y : e == 2 ? v.z : v.w;
+    }
+    static __device__ __forceinline__ int4 make(int32_t a, int32_t b, int32_t c, int32_t d) {
+        return int4{a, b, c, d};
+    }
+};
+template <>
+struct Vec16<uint32_t> {
+    using type = uint4;
+    static constexpr int n = 4;
+    static __device__ __forceinline__ uint32_t get(const uint4& v, int e) {
+        return e == 0 ? v.x : e == 1 ? v.y : e == 2 ? v.z : v.w;
+    }
+    static __device__ __forceinline__ uint4 make(uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
+        return uint4{a, b, c, d};
+    }
+};
+template <>
+struct Vec16<int64_t> {
+    using type = longlong2;
+    static constexpr int n = 2;
+    static __device__ __forceinline__ int64_t get(const longlong2& v, int e) { return e == 0 ? v.x : v.y; }
+};
+
+// Elements of [0, cnt) before the first 16-byte boundary of src.
+template <typename T>
+__device__ __forceinline__ int head_len(const T* src, int cnt) {
+    constexpr int E = Vec16<T>::n;
+    const int mis = (int)(((uintptr_t)src & 15) / sizeof(T));
+    const int h = mis ? E - mis : 0;
+    return h < cnt ? h : cnt;
+}
+
+// Calls put(q, src[q]) for every q in [0, cnt), cnt <= MAXCNT, reading the
+// aligned body with 16-byte loads (all of them issued before any put).
+template <typename T, int NT, int MAXCNT, typename F>
+__device__ __forceinline__ void load_run(const T* src, int cnt, F&& put) {
+    constexpr int E = Vec16<T>::n;
+    using V = typename Vec16<T>::type;
+    constexpr int PER = (MAXCNT / E + NT - 1) / NT;
+    const int tid = threadIdx.x;
+    const int head = head_len(src, cnt);
+    const int body = (cnt - head) / E;
+    const int tail = head + body * E;
+    const V* vs = reinterpret_cast<const V*>(src + head);
+    V x[PER];
+#pragma unroll
+    for (int j = 0; j < PER; j++) {
+        const int v = j * NT + tid;
+        if (v < body) x[j] = vs[v];
+    }
+    if (tid < head) put(tid, src[tid]);
+    if (tid < cnt - tail) put(tail + tid, src[tail + tid]);
+#pragma unroll
+    for (int j = 0; j < PER; j++) {
+        const int v = j * NT + tid;
+        if (v < body) {
+#pragma unroll
+            for (int e = 0; e < E; e++) put(head + v * E + e, Vec16<T>::get(x[j], e));
+        }
+    }
+}
+
+// Writes dst[q] = get(q) for every q in [0, cnt), cnt <= MAXCNT, with 16-byte
+// stores for the aligned body (4-byte elements only).
+template <typename T, int NT, int MAXCNT, typename G>
+__device__ __forceinline__ void store_run(T* dst, int cnt, G&& get) {
+    static_assert(Vec16<T>::n == 4, "store_run handles 4-byte elements");
+    using V = typename Vec16<T>::type;
+    constexpr int PER = (MAXCNT / 4 + NT - 1) / NT;
+    const int tid = threadIdx.x;
+    const int head = head_len(dst, cnt);
+    const int body = (cnt - head) / 4;
+    const int tail = head + body * 4;
+    if (tid < head) dst[tid] = get(tid);
+    if (tid < cnt - tail) dst[tail + tid] = get(tail + tid);
+    V* vd = reinterpret_cast<V*>(dst + head);
+#pragma unroll
+    for (int j = 0; j < PER; j++) {
+        const int v = j * NT + tid;
+        if (v < body) {
+            const int q = head + v * 4;
+            vd[v] = Vec16<T>::make(get(q), get(q + 1), get(q + 2), get(q + 3));
+        }
+    }
+}
+
+// 8-byte elements: pairs of 16 bytes.
+template <int NT, int MAXCNT, typename G>
+__device__ __forceinline__ void store_run64(int64_t* dst, int cnt, G&& get) {
+    constexpr int PER = (MAXCNT / 2 + NT - 1) / NT;
+    const int tid = threadIdx.x;
+    const int head = head_len(dst, cnt);
+    const int body = (cnt - head) / 2;
+    const int tail = head + body * 2;
+    if (tid < head) dst[tid] = get(tid);
+    if (tid < cnt - tail) dst[tail + tid] = get(tail + tid);
+    longlong2* vd = reinterpret_cast<longlong2*>(dst + head);
+#pragma unroll
+    for (int j = 0; j < PER; j++) {
+        const int v = j * NT + tid;
+        if (v < body) {
+            const int q = head + v * 2;
+            vd[v] = longlong2{get(q), get(q + 1)};
+        }
+    }
+}
+
+template <typename K, int NT, int MAXCNT, typename G>
+__device__ __forceinline__ void store_keys(K* dst, int cnt, G&& get) {
+    if constexpr (sizeof(K) == 8)
+        store_run64<NT, MAXCNT>(dst, cnt, get);
+    else
+        store_run<K, NT, MAXCNT>(dst, cnt, get);
+}
+
+}  // namespace hs

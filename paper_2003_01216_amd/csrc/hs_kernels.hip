@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include "hs_device.h"
+#include "hs_io.h"
 #include "hs_launch.h"
 #include "hs_work.h"
 
@@ -302,17 +303,11 @@ __global__ __launch_bounds__(kHistNT) void k_range(Work<K> w) {
     if (td.cnt == 0) return;
     const int tid = threadIdx.x;
     const int cnt = td.cnt;
-    const K* src = w.keys + td.base;
     K mn = Traits<K>::kMax, mx = Traits<K>::kMin;
-#pragma unroll
-    for (int j = 0; j < kHistVT; j++) {
-        const int q = j * kHistNT + tid;
-        if (q < cnt) {
-            K k = src[q];
-            mn = k < mn ? k : mn;
-            mx = k > mx ? k : mx;
-        }
-    }
+    load_run<K, kHistNT, kHistTile>(w.keys + td.base, cnt, [&](int, K k) {
+        mn = k < mn ? k : mn;
+        mx = k > mx ? k : mx;
+    });
     block_minmax<K, kHistNT>(mn, mx, rmn, rmx);
     if (tid == 0) {
         w.tmin[t] = mn;
@@ -355,13 +350,9 @@ __global__ __launch_bounds__(kHistNT) void k_hist(Work<K> w) {
     const int tid = threadIdx.x;
     const int cnt = td.cnt;
     const DigitPlan<K> pl = w.plans[td.seg];
-    const K* src = w.keys + td.base;
-    uint64_t c = 0;
-#pragma unroll
-    for (int j = 0; j < kHistVT; j++) {
-        const int q = j * kHistNT + tid;
-        if (q < cnt) c += 1ull << (5 * digit_of(pl, src[q]));
-    }
+    uint64_t c = 0;  // a thread sees at most 16 + 3 + 3 keys: fits the 5-bit fields
+    load_run<K, kHistNT, kHistTile>(w.keys + td.base, cnt,
+                                    [&](int, K k) { c += 1ull << (5 * digit_of(pl, k)); });
     uint32_t wd[5];
     unpack5(c, wd);
     block_sum5<kHistNT>(wd, red);
@@ -425,15 +416,9 @@ __global__ __launch_bounds__(kHistNT) void k_scatter(Work<K> w) {
     const int64_t base = td.base;
     const int cnt = td.cnt;
     const DigitPlan<K> pl = w.plans[td.seg];
-    // 1. coalesced load, natural order
-#pragma unroll
-    for (int j = 0; j < VT; j++) {
-        const int q = j * NT + tid;
-        if (q < cnt) {
-            sk[lds_pad<K>(q)] = w.keys[base + q];
-            if constexpr (PAIRS) sv[q] = w.vals[base + q];
-        }
-    }
+    // 1. load in natural order (16-byte body)
+    load_run<K, NT, HT>(w.keys + base, cnt, [&](int q, K k) { sk[lds_pad<K>(q)] = k; });
+    if constexpr (PAIRS) load_run<uint32_t, NT, HT>(w.vals + base, cnt, [&](int q, uint32_t v) { sv[q] = v; });
     if (tid < 10) {
         const int64_t pbase = 10 * (int64_t)(t - i);
         dbase[tid] = td.seg_base + w.pos[pbase + (int64_t)tid * nt + i] - w.pos[pbase];
@@ -544,46 +529,16 @@ __global__ __launch_bounds__(NT) void k_tilesort(Work<K> w) {
         uint32_t* dv = PAIRS ? (sd.odd ? w.svals : w.vals) + start : nullptr;
         const K* srck = w.skeys + start;
         const uint32_t* srcv = PAIRS ? w.svals + start : nullptr;
-        if (cnt == NV) {
-#pragma unroll
-            for (int jj = 0; jj < VT; jj++) {
-                const unsigned q = jj * NT + tid;
-                words[lds_pad<W>(q)] = make_word<K, PAIRS>(srck[q], q);
-                if constexpr (PAIRS) sv[q] = srcv[q];
-            }
-        } else {
-#pragma unroll
-            for (int jj = 0; jj < VT; jj++) {
-                const unsigned q = jj * NT + tid;
-                W word = WordMax<W>::v;
-                if (q < (unsigned)cnt) {
-                    word = make_word<K, PAIRS>(srck[q], q);
-                    if constexpr (PAIRS) sv[q] = srcv[q];
-                }
-                words[lds_pad<W>(q)] = word;
-            }
+        load_run<K, NT, NV>(srck, cnt, [&](int q, K k) { words[lds_pad<W>(q)] = make_word<K, PAIRS>(k, q); });
+        if constexpr (PAIRS) load_run<uint32_t, NT, NV>(srcv, cnt, [&](int q, uint32_t v) { sv[q] = v; });
+        if (cnt < NV) {  // a bucket's last, shorter partition: pad with the largest word
+            for (int q = cnt + tid; q < NV; q += NT) words[lds_pad<W>(q)] = WordMax<W>::v;
         }
         __syncthreads();
         block_sort<W, NT, VT>(words, sp);
-        if (cnt == NV) {
-#pragma unroll
-            for (int jj = 0; jj < VT; jj++) {
-                const unsigned q = jj * NT + tid;
-                const W word = words[lds_pad<W>(q)];
-                dk[q] = word_key<K, PAIRS>(word);
-                if constexpr (PAIRS) dv[q] = sv[pair_pos(word)];
-            }
-        } else {
-#pragma unroll
-            for (int jj = 0; jj < VT; jj++) {
-                const unsigned q = jj * NT + tid;
-                if (q < (unsigned)cnt) {
-                    const W word = words[lds_pad<W>(q)];
-                    dk[q] = word_key<K, PAIRS>(word);
-                    if constexpr (PAIRS) dv[q] = sv[pair_pos(word)];
-                }
-            }
-        }
+        store_keys<K, NT, NV>(dk, cnt, [&](int q) { return word_key<K, PAIRS>(words[lds_pad<W>(q)]); });
+        if constexpr (PAIRS)
+            store_run<uint32_t, NT, NV>(dv, cnt, [&](int q) { return sv[pair_pos(words[lds_pad<W>(q)])]; });
     }
 }
 
@@ -665,29 +620,17 @@ __global__ __launch_bounds__(NT) void k_merge(Work<K> w, int64_t bound) {
     uint32_t* dv = PAIRS ? (odd ? w.vals : w.svals) + md.out : nullptr;
     auto A = [&](int x) { return words[lds_pad<W>(x)]; };
     auto B = [&](int x) { return words[lds_pad<W>(na + x)]; };
+    // the two input windows, side by side in LDS (16-byte bodies)
+    const int nb_ = tot - na;
+    load_run<K, NT, NV>(pa, na, [&](int q, K k) { words[lds_pad<W>(q)] = make_word<K, PAIRS>(k, q); });
+    load_run<K, NT, NV>(pb, nb_, [&](int q, K k) { words[lds_pad<W>(na + q)] = make_word<K, PAIRS>(k, na + q); });
+    if constexpr (PAIRS) {
+        load_run<uint32_t, NT, NV>(va, na, [&](int q, uint32_t x) { sv[q] = x; });
+        load_run<uint32_t, NT, NV>(vb, nb_, [&](int q, uint32_t x) { sv[na + q] = x; });
+    }
+    __syncthreads();
     W v[VT];
     if (tot == NV) {
-        // rows of NT consecutive outputs come wholly from A, wholly from B, or
-        // (one row) from both: the choice is uniform per row
-#pragma unroll
-        for (int jj = 0; jj < VT; jj++) {
-            const int q = jj * NT + tid;
-            K k;
-            uint32_t val = 0;
-            if (jj * NT + NT <= na) {
-                k = pa[q];
-                if constexpr (PAIRS) val = va[q];
-            } else if (jj * NT >= na) {
-                k = pb[q - na];
-                if constexpr (PAIRS) val = vb[q - na];
-            } else {
-                k = q < na ? pa[q] : pb[q - na];
-                if constexpr (PAIRS) val = q < na ? va[q] : vb[q - na];
-            }
-            words[lds_pad<W>(q)] = make_word<K, PAIRS>(k, q);
-            if constexpr (PAIRS) sv[q] = val;
-        }
-        __syncthreads();
         const int dt = tid * VT;
         const int ai = merge_path_fixed<NV / 2>(dt, na, NV - na, A, B);
         sp[tid] = ai;
@@ -698,47 +641,23 @@ __global__ __launch_bounds__(NT) void k_merge(Work<K> w, int64_t bound) {
         const int base = lds_pad<W>(tid * VT);
 #pragma unroll
         for (int q = 0; q < VT; q++) words[base + q] = v[q];
+    } else {  // a bucket's last, shorter chunk
+        const int dt = min(tid * VT, tot);
+        const int ai = merge_path_fixed<NV / 2>(dt, na, tot - na, A, B);
+        sp[tid] = ai;
+        __syncthreads();
+        const int an = (tid == NT - 1) ? na : sp[tid + 1];
+        const int c = min(tid * VT + VT, tot) - dt;
+        gather_merge<W, VT>(words, 0, na, ai, dt - ai, an - ai, c, v);
         __syncthreads();
 #pragma unroll
-        for (int jj = 0; jj < VT; jj++) {
-            const unsigned q = jj * NT + tid;
-            const W word = words[lds_pad<W>(q)];
-            dk[q] = word_key<K, PAIRS>(word);
-            if constexpr (PAIRS) dv[q] = sv[pair_pos(word)];
-        }
-        return;
-    }
-    // a bucket's last, shorter chunk
-#pragma unroll
-    for (int jj = 0; jj < VT; jj++) {
-        const int q = jj * NT + tid;
-        if (q < tot) {
-            words[lds_pad<W>(q)] = make_word<K, PAIRS>(q < na ? pa[q] : pb[q - na], q);
-            if constexpr (PAIRS) sv[q] = q < na ? va[q] : vb[q - na];
-        }
+        for (int q = 0; q < VT; q++)
+            if (q < c) words[lds_pad<W>(tid * VT + q)] = v[q];
     }
     __syncthreads();
-    const int dt = min(tid * VT, tot);
-    const int ai = merge_path_fixed<NV / 2>(dt, na, tot - na, A, B);
-    sp[tid] = ai;
-    __syncthreads();
-    const int an = (tid == NT - 1) ? na : sp[tid + 1];
-    const int c = min(tid * VT + VT, tot) - dt;
-    gather_merge<W, VT>(words, 0, na, ai, dt - ai, an - ai, c, v);
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < VT; q++)
-        if (q < c) words[lds_pad<W>(tid * VT + q)] = v[q];
-    __syncthreads();
-#pragma unroll
-    for (int jj = 0; jj < VT; jj++) {
-        const int q = jj * NT + tid;
-        if (q < tot) {
-            const W word = words[lds_pad<W>(q)];
-            dk[q] = word_key<K, PAIRS>(word);
-            if constexpr (PAIRS) dv[q] = sv[pair_pos(word)];
-        }
-    }
+    store_keys<K, NT, NV>(dk, tot, [&](int q) { return word_key<K, PAIRS>(words[lds_pad<W>(q)]); });
+    if constexpr (PAIRS)
+        store_run<uint32_t, NT, NV>(dv, tot, [&](int q) { return sv[pair_pos(words[lds_pad<W>(q)])]; });
 }
 
 // --------------------------------------------------------- small segments
@@ -765,27 +684,14 @@ __global__ __launch_bounds__(NT) void k_small(Work<K> w, int64_t lo, int64_t hi)
         if (!(m64 > lo && m64 <= hi)) return;
         const int m = (int)m64;
         if (m > 1) {
-#pragma unroll
-            for (int jj = 0; jj < VT; jj++) {
-                const int q = jj * NT + tid;
-                W word = WordMax<W>::v;
-                if (q < m) {
-                    word = make_word<K, PAIRS>(w.keys[a + q], q);
-                    if constexpr (PAIRS) sv[q] = w.vals[a + q];
-                }
-                words[lds_pad<W>(q)] = word;
-            }
+            load_run<K, NT, NV>(w.keys + a, m, [&](int q, K k) { words[lds_pad<W>(q)] = make_word<K, PAIRS>(k, q); });
+            if constexpr (PAIRS) load_run<uint32_t, NT, NV>(w.vals + a, m, [&](int q, uint32_t x) { sv[q] = x; });
+            for (int q = m + tid; q < NV; q += NT) words[lds_pad<W>(q)] = WordMax<W>::v;
             __syncthreads();
             block_sort<W, NT, VT>(words, sp);
-#pragma unroll
-            for (int jj = 0; jj < VT; jj++) {
-                const int q = jj * NT + tid;
-                if (q < m) {
-                    const W word = words[lds_pad<W>(q)];
-                    w.keys[a + q] = word_key<K, PAIRS>(word);
-                    if constexpr (PAIRS) w.vals[a + q] = sv[pair_pos(word)];
-                }
-            }
+            store_keys<K, NT, NV>(w.keys + a, m, [&](int q) { return word_key<K, PAIRS>(words[lds_pad<W>(q)]); });
+            if constexpr (PAIRS)
+                store_run<uint32_t, NT, NV>(w.vals + a, m, [&](int q) { return sv[pair_pos(words[lds_pad<W>(q)])]; });
         } else {
             if (tid == 0 && m == 1) words[lds_pad<W>(0)] = make_word<K, PAIRS>(w.keys[a], 0);
             __syncthreads();
