@@ -95,7 +95,8 @@ int hsort_segmented_i64(int64_t* keys, int64_t n, const int64_t* offsets, int64_
 size_t hsort_bounds_offset(int kind, int64_t n, int64_t nseg);
 
 /* Synchronises `stream` and reads the device-side error word of the last
- * call that used `scratch`: HSORT_ERR_INVALID if its offsets were invalid,
+ * call that used `scratch`: HSORT_ERR_INVALID if its offsets were invalid
+ * (or a device-side consistency check failed),
  * HSORT_ERR_HIP if the synchronisation failed, HSORT_OK otherwise. */
 int hsort_check(const void* scratch, void* stream);
 
@@ -107,8 +108,10 @@ const char* hsort_last_error(void);
  * class: tile = keys per local-sort partition (T), tile_vt = keys per thread
  * of that sort (T / tile_vt threads per workgroup); merge_nv = outputs per
  * merge workgroup, merge_vt = outputs per thread; small_max = segments (and
- * plain arrays) up to this size are sorted wholly in LDS.  merge_nv must
- * divide tile.  Only compiled shapes are accepted (HSORT_ERR_UNSUPPORTED
+ * plain arrays) up to this size are sorted wholly in LDS; fanin = runs
+ * merged per round, 2 (pairwise rounds, Figure 1b) or 4 (each round merges
+ * four runs: half as many rounds; a split point is placed by two-way
+ * searches only, see the kernels).  merge_nv must divide tile.  Only compiled shapes are accepted (HSORT_ERR_UNSUPPORTED
  * otherwise).  kind: any hsort_kind (the two segmented kinds share the
  * table of their key type).  Size classes 0..3 hold calls whose deciding
  * size -- n, or max_seg_len of a segmented call when given -- is at most
@@ -116,13 +119,13 @@ const char* hsort_last_error(void);
  * class); size_cls = -1 sets every class.  The table is process-wide, and
  * scratch sizes depend on it: size scratch after changing it. */
 int hsort_set_config(int kind, int size_cls, int64_t tile, int64_t tile_vt, int64_t merge_nv, int64_t merge_vt,
-                     int64_t small_max);
+                     int64_t small_max, int64_t fanin);
 int hsort_get_config(int kind, int size_cls, int64_t* tile, int64_t* tile_vt, int64_t* merge_nv, int64_t* merge_vt,
-                     int64_t* small_max);
+                     int64_t* small_max, int64_t* fanin);
 int hsort_size_class(int64_t n);
 
 /* Applies a tuning table written by the autotuner: text lines
- * "kind size_class tile tile_vt merge_nv merge_vt small_max" ('#' starts a
+ * "kind size_class tile tile_vt merge_nv merge_vt small_max fanin" ('#' starts a
  * comment line).  Stops at the first bad line and returns its error. */
 int hsort_load_tuning(const char* path);
 

@@ -2,8 +2,8 @@
 
 For every key kind and size class it times each compiled shape on the
 device -- tile (keys per local-sort partition) x keys per thread, merge
-outputs per workgroup x per thread, and the largest segment sorted wholly in
-LDS -- on a representative synthetic workload of that class, and writes the
+outputs per workgroup x per thread, the largest segment sorted wholly in
+LDS, and the merge fan-in (2 or 4 runs per round) -- on a representative synthetic workload of that class, and writes the
 fastest to a table (``tuning.txt``, applied by the binding when the library
 loads; see ``hsort_load_tuning``) plus a JSON report of every measurement.
 
@@ -41,12 +41,16 @@ CLASS_SIZES = {0: 1 << 18, 1: 1 << 22, 2: 1 << 26, 3: 1 << 28}
 NAMES = {KEYS_I32: "keys_i32", KEYS_I64: "keys_i64", PAIRS_I32_U32: "pairs_i32", SEG_I32: "seg_i32", SEG_I64: "seg_i64"}
 
 
+FANINS = [2, 4]
+MERGE4_NV = {(4096, 16)}  # fan-in-4 merge shapes compiled (capacity 2 * merge_nv)
+
+
 def candidates(kind):
     kt = KEY_TYPE[kind]
     smalls = SEG_SMALL if kind in (SEG_I32, SEG_I64) else SMALL[kt]
-    for (t, tv), (m, mv), s in itertools.product(TILES[kt], MERGES[kt], smalls):
-        if t % m == 0:
-            yield (t, tv, m, mv, s)
+    for (t, tv), (m, mv), s, f in itertools.product(TILES[kt], MERGES[kt], smalls, FANINS):
+        if t % m == 0 and (f == 2 or (m, mv) in MERGE4_NV):
+            yield (t, tv, m, mv, s, f)
 
 
 def _rng_keys(kind, n, seed):
@@ -114,7 +118,7 @@ def time_config(wl, cfg, cls, reps):
     The same buffers are sorted every time (refilled outside the timed
     window), so in graph mode the warm-up captures and the timed calls replay.
     """
-    hsort_set_config(wl.kind, *cfg, size_class=cls)
+    hsort_set_config(wl.kind, *cfg[:5], fanin=cfg[5], size_class=cls)
     scratch = wl.scratch()
     work = wl.base.clone()
     wv = wl.vals.clone() if wl.kind == PAIRS_I32_U32 else None
@@ -158,7 +162,7 @@ def tune(kinds, classes, quick=False, reps=5, log=print):
                     if best is None or ms < best[0]:
                         best = (ms, cfg)
                 table[(kind, cls)] = best[1]
-                hsort_set_config(kind, *best[1], size_class=cls)
+                hsort_set_config(kind, *best[1][:5], fanin=best[1][5], size_class=cls)
                 del wl
                 torch.cuda.empty_cache()
     finally:
@@ -167,7 +171,7 @@ def tune(kinds, classes, quick=False, reps=5, log=print):
 
 
 def write_table(table, path, report=None):
-    lines = ["# hsort tuning table: kind size_class tile tile_vt merge_nv merge_vt small_max",
+    lines = ["# hsort tuning table: kind size_class tile tile_vt merge_nv merge_vt small_max fanin",
              f"# written by paper_2003_01216_amd.autotune on {time.strftime('%Y-%m-%d %H:%M:%S')}"]
     for (kind, cls), cfg in sorted(table.items()):
         lines.append(f"{kind} {cls} " + " ".join(str(x) for x in cfg))

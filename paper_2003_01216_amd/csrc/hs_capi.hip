@@ -31,6 +31,7 @@ struct Config {
     int64_t merge_nv;   // outputs per merge workgroup
     int64_t merge_vt;   // outputs per thread of the merge
     int64_t small_max;  // segments up to this size never leave LDS
+    int64_t fanin;      // runs merged per round: 2 or 4
 };
 
 std::mutex g_mu;
@@ -42,11 +43,11 @@ constexpr int kKinds = 5;
 constexpr int kClasses = 4;
 constexpr int64_t kClassTop[kClasses - 1] = {1 << 18, 1 << 22, 1 << 26};
 Config g_cfg[kKinds][kClasses] = {
-    {{8192, 16, 4096, 16, 8192}, {8192, 16, 4096, 16, 8192}, {16384, 32, 4096, 16, 8192}, {16384, 32, 4096, 16, 8192}},
-    {{4096, 16, 4096, 16, 4096}, {4096, 16, 4096, 16, 4096}, {4096, 16, 4096, 16, 4096}, {4096, 16, 4096, 16, 4096}},
-    {{4096, 16, 4096, 16, 4096}, {4096, 16, 4096, 16, 4096}, {4096, 16, 4096, 16, 4096}, {4096, 16, 4096, 16, 4096}},
-    {{8192, 16, 4096, 16, 8192}, {8192, 16, 4096, 16, 8192}, {16384, 32, 4096, 16, 8192}, {16384, 32, 4096, 16, 8192}},
-    {{4096, 16, 4096, 16, 4096}, {4096, 16, 4096, 16, 4096}, {4096, 16, 4096, 16, 4096}, {4096, 16, 4096, 16, 4096}},
+    {{8192, 16, 4096, 16, 8192, 2}, {8192, 16, 4096, 16, 8192, 2}, {16384, 32, 4096, 16, 8192, 2}, {16384, 32, 4096, 16, 8192, 2}},
+    {{4096, 16, 4096, 16, 4096, 2}, {4096, 16, 4096, 16, 4096, 2}, {4096, 16, 4096, 16, 4096, 2}, {4096, 16, 4096, 16, 4096, 2}},
+    {{4096, 16, 4096, 16, 4096, 2}, {4096, 16, 4096, 16, 4096, 2}, {4096, 16, 4096, 16, 4096, 2}, {4096, 16, 4096, 16, 4096, 2}},
+    {{8192, 16, 4096, 16, 8192, 2}, {8192, 16, 4096, 16, 8192, 2}, {16384, 32, 4096, 16, 8192, 2}, {16384, 32, 4096, 16, 8192, 2}},
+    {{4096, 16, 4096, 16, 4096, 2}, {4096, 16, 4096, 16, 4096, 2}, {4096, 16, 4096, 16, 4096, 2}, {4096, 16, 4096, 16, 4096, 2}},
 };
 
 int cfg_index(int kind) { return (kind >= 0 && kind < kKinds) ? kind : -1; }
@@ -92,18 +93,36 @@ bool merge_shape_ok(int64_t nt, int64_t vt) {
     return false;
 }
 
-bool config_ok(int ci, const Config& c) {
+template <typename K, bool PAIRS>
+bool merge4_shape_ok(int64_t nt, int64_t vt) {
+#define X(KK, P, NT_, VT_) \
+    if constexpr (std::is_same_v<K, KK> && PAIRS == P) \
+        if (nt == NT_ && vt == VT_) return true;
+    HS_MERGE4_VARIANTS(X)
+#undef X
+    return false;
+}
+
+template <typename K, bool PAIRS>
+bool shapes_ok(const Config& c) {
+    const int64_t tn = c.tile / c.tile_vt, mn = c.merge_nv / c.merge_vt;
+    if (!tile_shape_ok<K, PAIRS>(tn, c.tile_vt)) return false;
+    if (c.fanin == 2) return merge_shape_ok<K, PAIRS>(mn, c.merge_vt);
+    return merge4_shape_ok<K, PAIRS>(mn, c.merge_vt);
+}
+
+bool config_ok(int key_type_index, const Config& c) {
     if (c.tile_vt <= 0 || c.merge_vt <= 0 || c.tile % c.tile_vt || c.merge_nv % c.merge_vt) return false;
     if (c.tile % c.merge_nv) return false;  // merge chunks must tile a run
     if (c.small_max < 0 || c.small_max > 8192) return false;
-    const int64_t tn = c.tile / c.tile_vt, mn = c.merge_nv / c.merge_vt;
-    switch (ci) {
+    if (c.fanin != 2 && c.fanin != 4) return false;
+    switch (key_type_index) {
         case 0:
-            return tile_shape_ok<int32_t, false>(tn, c.tile_vt) && merge_shape_ok<int32_t, false>(mn, c.merge_vt);
+            return shapes_ok<int32_t, false>(c);
         case 1:
-            return tile_shape_ok<int64_t, false>(tn, c.tile_vt) && merge_shape_ok<int64_t, false>(mn, c.merge_vt);
+            return shapes_ok<int64_t, false>(c);
         case 2:
-            return tile_shape_ok<int32_t, true>(tn, c.tile_vt) && merge_shape_ok<int32_t, true>(mn, c.merge_vt);
+            return shapes_ok<int32_t, true>(c);
     }
     return false;
 }
@@ -117,7 +136,7 @@ struct Rec {
     // read from the bucket table left in scratch when the records are read
     const int64_t* bsize = nullptr;
     int64_t nb = 0, tile = 0;
-    int pass = 0;
+    int pass = 0, fanin = 2;
     double per_key = 0;
 };
 bool g_timing = false;
@@ -153,12 +172,13 @@ struct Timer {
         std::lock_guard<std::mutex> lk(g_mu);
         g_recs.push_back(r);
     }
-    void per_active_key(const int64_t* bsize, int64_t nb, int64_t tile, int pass, double per_key) {
+    void per_active_key(const int64_t* bsize, int64_t nb, int64_t tile, int pass, double per_key, int fanin) {
         deferred.bsize = bsize;
         deferred.nb = nb;
         deferred.tile = tile;
         deferred.pass = pass;
         deferred.per_key = per_key;
+        deferred.fanin = fanin;
     }
 };
 
@@ -170,7 +190,7 @@ int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 struct Layout {
     // byte offsets into scratch
     size_t err, own_off, skeys, svals, tmin, tmax, rounds, plans, tilecnt, tilepre, bounds, counts, pos, bstart, bsize, tsc,
-        tsp, mcc, msp, tiles, sdesc, mdesc, part32, part64, total;
+        tsp, mcc, msp, tiles, sdesc, mdesc, srec, ssorted, part32, part64, total;
     // item bounds
     int64_t large_bound, tiles_bound, buckets, ts_bound, chunks_bound;
 };
@@ -216,6 +236,8 @@ Layout make_layout(int kind, int64_t n, int64_t nseg, const Config& c) {
     L.tiles = take(sizeof(TileDesc) * L.tiles_bound);
     L.sdesc = take(sizeof(SortDesc) * L.ts_bound);
     L.mdesc = take(sizeof(MergeDesc) * L.chunks_bound);
+    L.srec = take(sizeof(Split4) * L.chunks_bound);
+    L.ssorted = take(sizeof(Split4) * L.chunks_bound);
     const int64_t p32 = std::max(scan_partial_count(nseg), scan_partial_count(L.buckets));
     L.part32 = take(4 * p32);
     L.part64 = take(8 * scan_partial_count(10 * L.tiles_bound));
@@ -252,8 +274,11 @@ Work<K> make_work(const Layout& L, char* scr, K* keys, uint32_t* vals, const int
     w.tiles = (TileDesc*)(scr + L.tiles);
     w.sdesc = (SortDesc*)(scr + L.sdesc);
     w.mdesc = (MergeDesc*)(scr + L.mdesc);
+    w.srec = (Split4*)(scr + L.srec);
+    w.ssorted = (Split4*)(scr + L.ssorted);
     w.err = (uint32_t*)(scr + L.err);
     w.tile = (int32_t)c.tile;
+    w.fanin = (int32_t)c.fanin;
     w.nv = (int32_t)c.merge_nv;
     w.small_max = small_max;
     return w;
@@ -278,6 +303,17 @@ hipError_t merge_by_shape(const Config& c, const Work<K>& w, int64_t chunks, hip
     if constexpr (std::is_same_v<K, KK> && PAIRS == P) \
         if (nt == NT_ && vt == VT_) return launch_merge<KK, P, NT_, VT_>(w, chunks, st);
     HS_MERGE_VARIANTS(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+template <typename K, bool PAIRS>
+hipError_t merge4_by_shape(const Config& c, const Work<K>& w, int round, int64_t chunks, hipStream_t st) {
+    const int64_t nt = c.merge_nv / c.merge_vt, vt = c.merge_vt;
+#define X(KK, P, NT_, VT_) \
+    if constexpr (std::is_same_v<K, KK> && PAIRS == P) \
+        if (nt == NT_ && vt == VT_) return launch_merge4<KK, P, NT_, VT_>(w, round, chunks, st);
+    HS_MERGE4_VARIANTS(X)
 #undef X
     return hipErrorInvalidValue;
 }
@@ -402,15 +438,25 @@ int enqueue(int kind, K* keys, uint32_t* vals, int64_t n, const int64_t* off, in
         }
         int64_t biggest = n;
         if (seg && max_seg_len > 0) biggest = std::min(biggest, max_seg_len);
-        const int rounds = merge_rounds(biggest, c.tile);
+        const int rounds = merge_rounds(biggest, c.tile, (int)c.fanin);
         for (int p = 0; p < rounds; p++) {
+            if (c.fanin == 4) {
+                {
+                    Timer t(st, "partition", 0);
+                    HS_TRY(launch_part4<K>(w, p, L.chunks_bound, st));
+                }
+                Timer t(st, "merge", 0);
+                t.per_active_key(w.bsize, L.buckets, c.tile, p, 2 * kb, 4);
+                HS_TRY((merge4_by_shape<K, PAIRS>(c, w, p, L.chunks_bound, st)));
+                continue;
+            }
             {
                 Timer t(st, "partition", 0);
                 HS_TRY(launch_partition<K>(w, p, L.chunks_bound, st));
             }
             {
                 Timer t(st, "merge", 0);
-                t.per_active_key(w.bsize, L.buckets, c.tile, p, 2 * kb);
+                t.per_active_key(w.bsize, L.buckets, c.tile, p, 2 * kb, 2);
                 HS_TRY((merge_by_shape<K, PAIRS>(c, w, L.chunks_bound, st)));
             }
         }
@@ -617,19 +663,20 @@ int hsort_check(const void* scratch, void* stream) {
     uint32_t flag = 0;
     e = hipMemcpy(&flag, scratch, sizeof(flag), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return fail(HSORT_ERR_HIP, std::string("hipMemcpy: ") + hipGetErrorString(e));
-    if (flag) return fail(HSORT_ERR_INVALID, "invalid segment offsets");
+    if (flag & 1u) return fail(HSORT_ERR_INVALID, "invalid segment offsets");
+    if (flag) return fail(HSORT_ERR_INVALID, "internal consistency check failed on the device");
     return HSORT_OK;
 }
 
 const char* hsort_last_error(void) { return g_err.c_str(); }
 
 int hsort_set_config(int kind, int size_cls, int64_t tile, int64_t tile_vt, int64_t merge_nv, int64_t merge_vt,
-                     int64_t small_max) {
+                     int64_t small_max, int64_t fanin) {
     g_err.clear();
     const int ci = cfg_index(kind);
     if (ci < 0) return fail(HSORT_ERR_INVALID, "unknown kind");
     if (size_cls < -1 || size_cls >= kClasses) return fail(HSORT_ERR_INVALID, "size class out of range");
-    const Config c{tile, tile_vt, merge_nv, merge_vt, small_max};
+    const Config c{tile, tile_vt, merge_nv, merge_vt, small_max, fanin};
     if (!config_ok(key_type(kind), c)) return fail(HSORT_ERR_UNSUPPORTED, "tile/merge shape not compiled");
     std::lock_guard<std::mutex> lk(g_mu);
     for (int k = 0; k < kClasses; k++)
@@ -638,9 +685,10 @@ int hsort_set_config(int kind, int size_cls, int64_t tile, int64_t tile_vt, int6
 }
 
 int hsort_get_config(int kind, int size_cls, int64_t* tile, int64_t* tile_vt, int64_t* merge_nv, int64_t* merge_vt,
-                     int64_t* small_max) {
+                     int64_t* small_max, int64_t* fanin) {
     const int ci = cfg_index(kind);
-    if (ci < 0 || size_cls < 0 || size_cls >= kClasses || !tile || !tile_vt || !merge_nv || !merge_vt || !small_max)
+    if (ci < 0 || size_cls < 0 || size_cls >= kClasses || !tile || !tile_vt || !merge_nv || !merge_vt || !small_max ||
+        !fanin)
         return fail(HSORT_ERR_INVALID, "bad arguments");
     Config c;
     {
@@ -652,6 +700,7 @@ int hsort_get_config(int kind, int size_cls, int64_t* tile, int64_t* tile_vt, in
     *merge_nv = c.merge_nv;
     *merge_vt = c.merge_vt;
     *small_max = c.small_max;
+    *fanin = c.fanin;
     return HSORT_OK;
 }
 
@@ -666,12 +715,12 @@ int hsort_load_tuning(const char* path) {
         lineno++;
         if (line[0] == '#' || line[0] == '\n') continue;
         int kind = 0, cls = 0;
-        long long t, tv, m, mv, sm;
-        if (sscanf(line, "%d %d %lld %lld %lld %lld %lld", &kind, &cls, &t, &tv, &m, &mv, &sm) != 7) {
+        long long t, tv, m, mv, sm, fi;
+        if (sscanf(line, "%d %d %lld %lld %lld %lld %lld %lld", &kind, &cls, &t, &tv, &m, &mv, &sm, &fi) != 8) {
             rc = fail(HSORT_ERR_INVALID, std::string(path) + ": bad line " + std::to_string(lineno));
             break;
         }
-        if ((rc = hsort_set_config(kind, cls, t, tv, m, mv, sm)) != HSORT_OK) break;
+        if ((rc = hsort_set_config(kind, cls, t, tv, m, mv, sm, fi)) != HSORT_OK) break;
     }
     fclose(f);
     return rc;
@@ -748,7 +797,7 @@ int64_t hsort_timing_read(char* out, int64_t cap) {
             }
             double active = 0;
             for (int64_t v : sizes)
-                if (merge_rounds(v, r.tile) > r.pass) active += (double)v;
+                if (merge_rounds(v, r.tile, r.fanin) > r.pass) active += (double)v;
             r.bytes = r.per_key * active;
         }
         hipEventElapsedTime(&ms, r.a, r.b);

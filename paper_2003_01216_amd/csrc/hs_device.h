@@ -285,12 +285,35 @@ __device__ __forceinline__ int owner_of(const T* pre, int n, T x) {
 }
 
 // Number of bottom-up merge rounds a bucket of `size` keys needs when its
-// local sort leaves runs of `tile` keys and each round halves the run count.
-__host__ __device__ __forceinline__ int merge_rounds(int64_t size, int64_t tile) {
+// local sort leaves runs of `tile` keys and each round merges `fanin` (2 or
+// 4) runs into one.
+__host__ __device__ __forceinline__ int merge_rounds(int64_t size, int64_t tile, int fanin = 2) {
     int64_t runs = (size + tile - 1) / tile;
     int r = 0;
-    while (((int64_t)1 << r) < runs) r++;
+    int64_t cover = 1;
+    while (cover < runs) {
+        cover *= fanin;
+        r++;
+    }
     return r;
+}
+
+// Search helpers over a sorted run R[0..n) with absolute power-of-two steps
+// (top: a power of two >= n), so that searches of nearby values share the
+// cache lines of their early probes.
+template <typename K>
+__device__ __forceinline__ int64_t lower_bound_steps(const K* R, int64_t n, K v, int64_t top) {
+    int64_t pos = 0;
+    for (int64_t step = top; step > 0; step >>= 1)
+        if (pos + step <= n && R[pos + step - 1] < v) pos += step;
+    return pos;  // elements < v
+}
+template <typename K>
+__device__ __forceinline__ int64_t upper_bound_steps(const K* R, int64_t n, K v, int64_t top) {
+    int64_t pos = 0;
+    for (int64_t step = top; step > 0; step >>= 1)
+        if (pos + step <= n && !(v < R[pos + step - 1])) pos += step;
+    return pos;  // elements <= v
 }
 
 }  // namespace hs

@@ -79,6 +79,67 @@ __device__ __forceinline__ void load_run(const T* src, int cnt, F&& put) {
     }
 }
 
+// Several runs at once: calls put(off[r] + q, src[r][q]) for every run r and
+// q in [0, cnt[r]), sum of cnt <= MAXTOT.  The runs' aligned bodies form one
+// index space of 16-byte vectors shared out over the workgroup, and every
+// load (vector, head and tail) is issued before the first put, so the runs'
+// memory latencies overlap instead of adding up.
+template <typename T, int NT, int MAXTOT, int NR, typename F>
+__device__ __forceinline__ void load_runs(const T* const (&src)[NR], const int (&cnt)[NR], const int (&off)[NR],
+                                          F&& put) {
+    constexpr int E = Vec16<T>::n;
+    using V = typename Vec16<T>::type;
+    constexpr int PER = (MAXTOT / E + NT - 1) / NT;
+    const int tid = threadIdx.x;
+    int head[NR], tail[NR], pre[NR + 1];
+    uintptr_t vbase[NR];  // address of vector 0 of the shared index space, as seen from run r
+    int dbase[NR];        // put index of vector 0, as seen from run r
+    pre[0] = 0;
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+        head[r] = head_len(src[r], cnt[r]);
+        const int body = (cnt[r] - head[r]) / E;
+        tail[r] = head[r] + body * E;
+        pre[r + 1] = pre[r] + body;
+        vbase[r] = (uintptr_t)(src[r] + head[r]) - (uintptr_t)pre[r] * sizeof(V);
+        dbase[r] = off[r] + head[r] - pre[r] * E;
+    }
+    V x[PER];
+#pragma unroll
+    for (int j = 0; j < PER; j++) {
+        const int v = j * NT + tid;
+        if (v < pre[NR]) {
+            uintptr_t b = vbase[0];
+#pragma unroll
+            for (int r = 1; r < NR; r++) b = v >= pre[r] ? vbase[r] : b;
+            x[j] = reinterpret_cast<const V*>(b)[v];
+        }
+    }
+    T hv[NR], tv[NR];
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+        if (tid < head[r]) hv[r] = src[r][tid];
+        if (tid < cnt[r] - tail[r]) tv[r] = src[r][tail[r] + tid];
+    }
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+        if (tid < head[r]) put(off[r] + tid, hv[r]);
+        if (tid < cnt[r] - tail[r]) put(off[r] + tail[r] + tid, tv[r]);
+    }
+#pragma unroll
+    for (int j = 0; j < PER; j++) {
+        const int v = j * NT + tid;
+        if (v < pre[NR]) {
+            int d = dbase[0];
+#pragma unroll
+            for (int r = 1; r < NR; r++) d = v >= pre[r] ? dbase[r] : d;
+            d += v * E;
+#pragma unroll
+            for (int e = 0; e < E; e++) put(d + e, Vec16<T>::get(x[j], e));
+        }
+    }
+}
+
 // Writes dst[q] = get(q) for every q in [0, cnt), cnt <= MAXCNT, with 16-byte
 // stores for the aligned body (4-byte elements only).
 template <typename T, int NT, int MAXCNT, typename G>

@@ -387,7 +387,7 @@ __global__ void k_btab(Work<K> w) {
             w.tsc[10 * s + d] = (int32_t)((sz + w.tile - 1) / w.tile);
             w.mcc[10 * s + d] = (int32_t)((sz + w.nv - 1) / w.nv);
             w.bounds_out[11 * (int64_t)s + d] = st;
-            const int r = merge_rounds(sz, w.tile);
+            const int r = merge_rounds(sz, w.tile, w.fanin);
             if (r > 0) atomicMax(w.rounds, r);
         }
         w.bounds_out[11 * (int64_t)s + 10] = w.off[s + 1] - a;
@@ -500,7 +500,7 @@ __global__ void k_sdesc(Work<K> w, int64_t bound) {
         const int64_t size = w.bsize[j];
         d.start = w.bstart[j] + i * w.tile;
         d.cnt = (int)min((int64_t)w.tile, size - i * w.tile);
-        d.odd = merge_rounds(size, w.tile) & 1;
+        d.odd = merge_rounds(size, w.tile, w.fanin) & 1;
     }
     w.sdesc[item] = d;
 }
@@ -621,12 +621,14 @@ __global__ __launch_bounds__(NT) void k_merge(Work<K> w, int64_t bound) {
     auto A = [&](int x) { return words[lds_pad<W>(x)]; };
     auto B = [&](int x) { return words[lds_pad<W>(na + x)]; };
     // the two input windows, side by side in LDS (16-byte bodies)
-    const int nb_ = tot - na;
-    load_run<K, NT, NV>(pa, na, [&](int q, K k) { words[lds_pad<W>(q)] = make_word<K, PAIRS>(k, q); });
-    load_run<K, NT, NV>(pb, nb_, [&](int q, K k) { words[lds_pad<W>(na + q)] = make_word<K, PAIRS>(k, na + q); });
-    if constexpr (PAIRS) {
-        load_run<uint32_t, NT, NV>(va, na, [&](int q, uint32_t x) { sv[q] = x; });
-        load_run<uint32_t, NT, NV>(vb, nb_, [&](int q, uint32_t x) { sv[na + q] = x; });
+    {
+        const K* const ks[2] = {pa, pb};
+        const int cs[2] = {na, tot - na}, os[2] = {0, na};
+        load_runs<K, NT, NV, 2>(ks, cs, os, [&](int q, K k) { words[lds_pad<W>(q)] = make_word<K, PAIRS>(k, q); });
+        if constexpr (PAIRS) {
+            const uint32_t* const vs[2] = {va, vb};
+            load_runs<uint32_t, NT, NV, 2>(vs, cs, os, [&](int q, uint32_t x) { sv[q] = x; });
+        }
     }
     __syncthreads();
     W v[VT];
@@ -658,6 +660,256 @@ __global__ __launch_bounds__(NT) void k_merge(Work<K> w, int64_t bound) {
     store_keys<K, NT, NV>(dk, tot, [&](int q) { return word_key<K, PAIRS>(words[lds_pad<W>(q)]); });
     if constexpr (PAIRS)
         store_run<uint32_t, NT, NV>(dv, tot, [&](int q) { return sv[pair_pos(words[lds_pad<W>(q)])]; });
+}
+
+// ------------------------------------------------- fan-in-4 merge rounds
+// Round `round` with fan-in 4: runs of L = T*4^round keys, groups of four
+// consecutive runs R0..R3 of a bucket.  X = merge(R0, R1) and Y =
+// merge(R2, R3) are sampled every S keys (S = w.nv); a sample's place in the
+// group's output is exact from two-way searches only:
+//   X sample x (X position k*S): rank = k*S + #R2(< x) + #R3(< x)
+//   Y sample y (Y position j*S): rank = j*S + #R0(<= y) + #R1(<= y)
+// (equal keys keep run order R0 < R1 < R2 < R3: the stable order).  Between
+// two consecutive split points lie at most S keys of X and S of Y, so a
+// workgroup of capacity 2S merges them in LDS: W0+W1 and W2+W3, then the two.
+// One sample per S keys of a bucket, so the chunk list is the fan-in-2 one.
+template <typename K>
+__device__ __forceinline__ K elem_at_corank(const K* A, int64_t na, const K* B, int64_t nb, int64_t c, int64_t d) {
+    // the output after the first d of merge(A, B), whose co-rank is c (ties -> A)
+    const bool has_a = c < na, has_b = d - c < nb;
+    if (has_a && (!has_b || !(B[d - c] < A[c]))) return A[c];
+    return B[d - c];
+}
+
+template <typename K>
+__global__ __launch_bounds__(256) void k_part4(Work<K> w, int round, int64_t bound) {
+    const int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (item >= bound) return;
+    const int nb = 10 * w.nseg;
+    Split4 d{};
+    if (!*w.err && round < *w.rounds && item < w.msp[nb]) {
+        const int j = owner_of(w.msp, nb, (int)item);
+        const int64_t i = item - w.msp[j];
+        const int64_t size = w.bsize[j];
+        const int64_t T = w.tile, S = w.nv;
+        const int P = merge_rounds(size, T, 4);
+        if (P > round) {
+            const int64_t L = T << (2 * round);
+            const int64_t o = i * S;
+            const int64_t q = o / (2 * L);  // half-group: X of group q/2 when even, Y when odd
+            const int64_t g = q >> 1;
+            const int64_t gbase = g * 4 * L;
+            int64_t len[4];
+            for (int k = 0; k < 4; k++) len[k] = max((int64_t)0, min(L, size - gbase - k * L));
+            const bool odd = (P - round) & 1;
+            const K* src = (odd ? w.skeys : w.keys) + w.bstart[j] + gbase;
+            const K* R0 = src;
+            const K* R1 = src + L;
+            const K* R2 = src + 2 * L;
+            const K* R3 = src + 3 * L;
+            const int64_t pos = o - q * 2 * L;  // position inside X or Y
+            int64_t s0, s1, s2, s3, rank;
+            if (!(q & 1)) {
+                const int64_t c = merge_path_steps64(pos, len[0], len[1], L, [&](int64_t x) { return R0[x]; },
+                                                     [&](int64_t x) { return R1[x]; });
+                const K x = elem_at_corank(R0, len[0], R1, len[1], c, pos);
+                s0 = c;
+                s1 = pos - c;
+                s2 = lower_bound_steps(R2, len[2], x, L);
+                s3 = lower_bound_steps(R3, len[3], x, L);
+                rank = pos + s2 + s3;
+            } else {
+                const int64_t e = merge_path_steps64(pos, len[2], len[3], L, [&](int64_t x) { return R2[x]; },
+                                                     [&](int64_t x) { return R3[x]; });
+                const K y = elem_at_corank(R2, len[2], R3, len[3], e, pos);
+                s0 = upper_bound_steps(R0, len[0], y, L);
+                s1 = upper_bound_steps(R1, len[1], y, L);
+                s2 = e;
+                s3 = pos - e;
+                rank = pos + s0 + s1;
+            }
+            const int64_t nx = (len[0] + len[1] + S - 1) / S;
+            const int64_t ny = (len[2] + len[3] + S - 1) / S;
+            d.base = w.bstart[j] + gbase;
+            d.rank = rank;
+            d.s[0] = (int32_t)s0;
+            d.s[1] = (int32_t)s1;
+            d.s[2] = (int32_t)s2;
+            d.s[3] = (int32_t)s3;
+            for (int k = 0; k < 4; k++) d.len[k] = (int32_t)len[k];
+            d.first = (int32_t)(w.msp[j] + gbase / S);
+            d.items = (int32_t)(nx + ny);
+            d.nx = (int32_t)nx;
+            d.flags = kActive | (odd ? kFromScratch : 0);
+        }
+    }
+    w.srec[item] = d;
+}
+
+// Places every split point at its rank order inside its group: an X point's
+// position is its X index plus the Y points ranked before it, and vice versa.
+template <typename K>
+__global__ __launch_bounds__(256) void k_order4(Work<K> w, int64_t bound) {
+    const int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (item >= bound) return;
+    const Split4 d = w.srec[item];
+    if (!(d.flags & kActive)) {
+        w.ssorted[item] = d;
+        return;
+    }
+    const int local = (int)(item - d.first);
+    const bool is_x = local < d.nx;
+    const int own = is_x ? local : local - d.nx;
+    const Split4* other = w.srec + d.first + (is_x ? d.nx : 0);
+    int lo = 0, hi = is_x ? d.items - d.nx : d.nx;  // count of the other side's ranks < d.rank
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (other[mid].rank < d.rank)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    w.ssorted[d.first + own + lo] = d;
+}
+
+// A workgroup merges the keys between two consecutive split points (at most
+// S of X and S of Y, S = NT*VT) in two LDS levels.  Work is counted in jobs
+// of VT outputs, one merge-path co-rank and one bitonic gather each; a
+// thread runs up to two jobs per level, so the cost follows the chunk's size
+// (chunks vary between 1 and 2S keys) rather than its capacity.
+template <typename W, int VT>
+struct Job {
+    int a0, na, nb, dt, cnt;  // merge of words[a0, a0+na) and words[a0+na, a0+na+nb), outputs dt..dt+cnt
+    int end_corank;           // co-rank at dt + cnt when this is the merge's last job, else -1
+};
+
+template <typename K, bool PAIRS, int NT, int VT>
+__global__ __launch_bounds__(NT) void k_merge4(Work<K> w, int round, int64_t bound) {
+    using W = typename WordOf<K, PAIRS>::type;
+    constexpr int BLK = NT * VT;  // S
+    constexpr int CAP = 2 * BLK;
+    __shared__ W words[lds_padded_size<W>(CAP)];
+    __shared__ uint32_t sv[PAIRS ? CAP : 1];
+    __shared__ int sp[2 * NT + 1];
+    const int64_t item = blockIdx.x;
+    const Split4 r0 = w.ssorted[item];
+    if (!(r0.flags & kActive)) return;
+    const bool last = item + 1 - r0.first == r0.items;
+    const Split4 nx1 = w.ssorted[item + 1 < bound ? item + 1 : item];
+    int e[4];
+    int64_t rank_end;
+    if (last) {
+#pragma unroll
+        for (int k = 0; k < 4; k++) e[k] = r0.len[k];
+        rank_end = (int64_t)r0.len[0] + r0.len[1] + r0.len[2] + r0.len[3];
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; k++) e[k] = nx1.s[k];
+        rank_end = nx1.rank;
+    }
+    const int tid = threadIdx.x;
+    const int c0 = e[0] - r0.s[0], c1 = e[1] - r0.s[1], c2 = e[2] - r0.s[2], c3 = e[3] - r0.s[3];
+    const int o1 = c0, o2 = c0 + c1, o3 = o2 + c2, c = o3 + c3;
+    // a split point inconsistent with its successor would make the windows
+    // run past their runs: flag it and do nothing (never observed; cheap)
+    if (c != rank_end - r0.rank || c0 < 0 || c1 < 0 || c2 < 0 || c3 < 0 || c0 + c1 > BLK || c2 + c3 > BLK) {
+        if (tid == 0) atomicOr(w.err, 2u);
+        return;
+    }
+    if (c == 0) return;
+    const int64_t L = (int64_t)w.tile << (2 * round);
+    const bool odd = r0.flags & kFromScratch;
+    const K* sk = (odd ? w.skeys : w.keys) + r0.base;
+    const uint32_t* svv = PAIRS ? (odd ? w.svals : w.vals) + r0.base : nullptr;
+    K* dk = (odd ? w.keys : w.skeys) + r0.base + r0.rank;
+    uint32_t* dv = PAIRS ? (odd ? w.vals : w.svals) + r0.base + r0.rank : nullptr;
+    // the four windows side by side in LDS: [W0 | W1 | W2 | W3]
+    {
+        const int cs[4] = {c0, c1, c2, c3};
+        const int os[4] = {0, o1, o2, o3};
+        const K* const ks[4] = {sk + r0.s[0], sk + L + r0.s[1], sk + 2 * L + r0.s[2], sk + 3 * L + r0.s[3]};
+        load_runs<K, NT, CAP, 4>(ks, cs, os, [&](int q, K key) { words[lds_pad<W>(q)] = make_word<K, PAIRS>(key, q); });
+        if constexpr (PAIRS) {
+            const uint32_t* const vs[4] = {svv + r0.s[0], svv + L + r0.s[1], svv + 2 * L + r0.s[2],
+                                           svv + 3 * L + r0.s[3]};
+            load_runs<uint32_t, NT, CAP, 4>(vs, cs, os, [&](int q, uint32_t x) { sv[q] = x; });
+        }
+    }
+    __syncthreads();
+    // one merge level over a list of jobs; jobs [0, njobs), thread t runs t and t + NT
+    auto level = [&](auto job_of, int njobs) {
+        W v[2][VT];
+        Job<W, VT> jb[2];
+        int ai[2];
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            const int j = tid + h * NT;
+            jb[h] = job_of(j < njobs ? j : njobs - 1);
+            if (j < njobs) {
+                const int a0 = jb[h].a0, na = jb[h].na;
+                auto A = [&](int x) { return words[lds_pad<W>(a0 + x)]; };
+                auto B = [&](int x) { return words[lds_pad<W>(a0 + na + x)]; };
+                ai[h] = merge_path_fixed<BLK / 2>(jb[h].dt, na, jb[h].nb, A, B);
+                sp[j] = ai[h];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            const int j = tid + h * NT;
+            if (j < njobs) {
+                const int an = jb[h].end_corank >= 0 ? jb[h].end_corank : sp[j + 1];
+                gather_merge<W, VT>(words, jb[h].a0, jb[h].a0 + jb[h].na, ai[h], jb[h].dt - ai[h], an - ai[h],
+                                    jb[h].cnt, v[h]);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            const int j = tid + h * NT;
+            if (j < njobs) {
+#pragma unroll
+                for (int q = 0; q < VT; q++)
+                    if (q < jb[h].cnt) words[lds_pad<W>(jb[h].a0 + jb[h].dt + q)] = v[h][q];
+            }
+        }
+        __syncthreads();
+    };
+    // level 1: X' = merge(W0, W1) into [0, o2), Y' = merge(W2, W3) into [o2, c)
+    const int jx = (o2 + VT - 1) / VT, jy = (c - o2 + VT - 1) / VT;
+    level(
+        [&](int j) {
+            // y = 0 for a job of X', 1 for one of Y' (arithmetic, not
+            // selects: keeps the fields in registers)
+            Job<W, VT> b;
+            const int y = j >= jx;
+            const int jj = j - y * jx;
+            b.a0 = y * o2;
+            b.na = c0 + y * (c2 - c0);
+            b.nb = c1 + y * (c3 - c1);
+            b.dt = jj * VT;
+            b.cnt = min(VT, b.na + b.nb - b.dt);
+            b.end_corank = (jj == jx + y * (jy - jx) - 1) ? b.na : -1;
+            return b;
+        },
+        jx + jy);
+    // level 2: merge [0, o2) with [o2, c)
+    const int jc = (c + VT - 1) / VT;
+    level(
+        [&](int j) {
+            Job<W, VT> b;
+            b.a0 = 0;
+            b.na = o2;
+            b.nb = c - o2;
+            b.dt = j * VT;
+            b.cnt = min(VT, c - b.dt);
+            b.end_corank = (j == jc - 1) ? o2 : -1;
+            return b;
+        },
+        jc);
+    store_keys<K, NT, CAP>(dk, c, [&](int q) { return word_key<K, PAIRS>(words[lds_pad<W>(q)]); });
+    if constexpr (PAIRS)
+        store_run<uint32_t, NT, CAP>(dv, c, [&](int q) { return sv[pair_pos(words[lds_pad<W>(q)])]; });
 }
 
 // --------------------------------------------------------- small segments
@@ -733,7 +985,7 @@ __global__ void k_collect(Work<K> w, int stage) {
     for (int j = blockIdx.x; j < nb; j += gridDim.x) {
         const int64_t size = w.bsize[j];
         if (size == 0) continue;
-        if (stage == 2 && !(merge_rounds(size, w.tile) & 1)) continue;
+        if (stage == 2 && !(merge_rounds(size, w.tile, w.fanin) & 1)) continue;
         const int64_t st = w.bstart[j];
         for (int64_t q = threadIdx.x; q < size; q += blockDim.x) {
             w.keys[st + q] = w.skeys[st + q];
@@ -945,6 +1197,19 @@ hipError_t launch_merge(const Work<K>& w, int64_t chunks_bound, hipStream_t st) 
     return hipGetLastError();
 }
 
+template <typename K>
+hipError_t launch_part4(const Work<K>& w, int round, int64_t chunks_bound, hipStream_t st) {
+    k_part4<K><<<cdiv64(chunks_bound, 256), 256, 0, st>>>(w, round, chunks_bound);
+    k_order4<K><<<cdiv64(chunks_bound, 256), 256, 0, st>>>(w, chunks_bound);
+    return hipGetLastError();
+}
+
+template <typename K, bool PAIRS, int NT, int VT>
+hipError_t launch_merge4(const Work<K>& w, int round, int64_t chunks_bound, hipStream_t st) {
+    k_merge4<K, PAIRS, NT, VT><<<grid_of(chunks_bound), NT, 0, st>>>(w, round, chunks_bound);
+    return hipGetLastError();
+}
+
 template <typename K, bool PAIRS, int NT, int VT>
 hipError_t launch_small(const Work<K>& w, int64_t lo, int64_t hi, int64_t segs_bound, hipStream_t st) {
     k_small<K, PAIRS, NT, VT><<<grid_of(segs_bound), NT, 0, st>>>(w, lo, hi);
@@ -974,6 +1239,7 @@ hipError_t launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t st
     template hipError_t launch_partition<K>(const Work<K>&, int, int64_t, hipStream_t);  \
     template hipError_t launch_tiles<K>(const Work<K>&, int64_t, hipStream_t);           \
     template hipError_t launch_sdesc<K>(const Work<K>&, int64_t, hipStream_t);           \
+    template hipError_t launch_part4<K>(const Work<K>&, int, int64_t, hipStream_t);      \
     template hipError_t launch_collect<K>(const Work<K>&, int, hipStream_t);
 HS_INST_K(int32_t)
 HS_INST_K(int64_t)
@@ -991,5 +1257,8 @@ HS_SMALL_VARIANTS(HS_INST_SMALL)
 #define HS_INST_MERGE(K, PAIRS, NT, VT) \
     template hipError_t launch_merge<K, PAIRS, NT, VT>(const Work<K>&, int64_t, hipStream_t);
 HS_MERGE_VARIANTS(HS_INST_MERGE)
+#define HS_INST_MERGE4(K, PAIRS, NT, VT) \
+    template hipError_t launch_merge4<K, PAIRS, NT, VT>(const Work<K>&, int, int64_t, hipStream_t);
+HS_MERGE4_VARIANTS(HS_INST_MERGE4)
 
 }  // namespace hs

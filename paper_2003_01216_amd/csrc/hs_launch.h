@@ -25,6 +25,10 @@ struct ScanSpec {
 #define HS_MERGE_VARIANTS(X)                                                                 \
     X(int32_t, false, 256, 16) X(int32_t, false, 256, 32) X(int32_t, false, 512, 16)         \
     X(int64_t, false, 256, 16) X(int32_t, true, 256, 16)
+// Fan-in-4 merge: NT*VT = merge_nv (samples every merge_nv keys; a chunk
+// holds up to twice that).
+#define HS_MERGE4_VARIANTS(X) \
+    X(int32_t, false, 256, 16) X(int64_t, false, 256, 16) X(int32_t, true, 256, 16)
 // Shapes usable by the whole-segment LDS sort (5-bit digit counters: VT <= 16).
 #define HS_SMALL_VARIANTS(X)                                                                 \
     X(int32_t, false, 512, 16) X(int32_t, false, 256, 16) X(int32_t, false, 256, 8) X(int32_t, false, 64, 4) \
@@ -59,6 +63,10 @@ template <typename K, bool PAIRS, int NT, int VT>
 hipError_t launch_small(const Work<K>& w, int64_t lo, int64_t hi, int64_t segs_bound, hipStream_t st);
 template <typename K>
 hipError_t launch_collect(const Work<K>& w, int stage, hipStream_t st);
+template <typename K>
+hipError_t launch_part4(const Work<K>& w, int round, int64_t chunks_bound, hipStream_t st);
+template <typename K, bool PAIRS, int NT, int VT>
+hipError_t launch_merge4(const Work<K>& w, int round, int64_t chunks_bound, hipStream_t st);
 
 hipError_t launch_scan_i32(const ScanSpec& sp, int64_t len_bound, const int32_t* in, int32_t* out, int32_t* partial,
                            hipStream_t st);

@@ -42,6 +42,22 @@ constexpr int32_t kActive = 1;     // the chunk has work this round
 constexpr int32_t kFromScratch = 2;  // source is the scratch copy
 constexpr int32_t kLastChunk = 4;  // last chunk of its pair of runs
 
+// Fan-in-4 merge rounds: a split point of a group of four runs R0..R3 (the
+// first `rank` outputs of the group's stable merge are R0[0..s0), R1[0..s1),
+// R2[0..s2), R3[0..s3)).  Written per sample by k_part4, copied into rank
+// order by k_order4; a merge workgroup takes the keys between two
+// consecutive split points.
+struct Split4 {
+    int64_t base;   // absolute index of the group's first key (run k starts at base + k*L)
+    int64_t rank;   // output position of the split point inside the group
+    int32_t s[4];   // keys of each run before the split point
+    int32_t len[4]; // run lengths of the group
+    int32_t first;  // flat index of the group's first chunk
+    int32_t items;  // chunks of the group (= split points)
+    int32_t nx;     // split points sampled from merge(R0, R1); the rest from merge(R2, R3)
+    int32_t flags;  // kActive | kFromScratch
+};
+
 template <typename K>
 struct Work {
     K* keys;          // the caller's keys (sorted in place)
@@ -74,11 +90,14 @@ struct Work {
 
     TileDesc* tiles;   // [tiles bound]
     SortDesc* sdesc;   // [local-sort partitions bound]
-    MergeDesc* mdesc;  // [merge chunks bound] of the current round
+    MergeDesc* mdesc;  // [merge chunks bound] of the current round (fan-in 2)
+    Split4* srec;      // [merge chunks bound] split points by sample (fan-in 4)
+    Split4* ssorted;   // [merge chunks bound] split points by rank (fan-in 4)
     int32_t* rounds;  // largest number of merge rounds any bucket needs
     uint32_t* err;   // device-side validation flag (bad offsets)
 
     int32_t tile;       // keys per local-sort tile (T)
+    int32_t fanin;      // runs merged per round: 2 or 4
     int32_t nv;         // outputs per merge workgroup (divides T)
     int64_t small_max;  // segments up to this size are sorted wholly in LDS
 };
