@@ -29,11 +29,17 @@ from . import (KEYS_I32, KEYS_I64, PAIRS_I32_U32, SEG_I32, SEG_I64, TUNING_PATH,
                hsort_keys, hsort_pairs, hsort_segmented, hsort_set_config, load_library, scratch_bytes)
 
 TILES = {
-    KEYS_I32: [(4096, 16), (8192, 16), (8192, 32), (16384, 32)],
+    KEYS_I32: [(8192, 16), (8192, 32), (16384, 32)],
     KEYS_I64: [(4096, 16), (8192, 16)],
     PAIRS_I32_U32: [(4096, 16), (8192, 16)],
 }
-MERGES = {KEYS_I32: [(4096, 16), (8192, 16)], KEYS_I64: [(4096, 16)], PAIRS_I32_U32: [(4096, 16)]}
+# merge shapes (outputs per workgroup, per thread) by fan-in; for fan-in 4
+# the first number is also the sampling stride S (a workgroup holds <= 2S)
+MERGES = {
+    2: {KEYS_I32: [(4096, 16), (8192, 16), (8192, 32)], KEYS_I64: [(4096, 16)], PAIRS_I32_U32: [(4096, 16)]},
+    4: {KEYS_I32: [(4096, 16), (2048, 16), (2048, 8)], KEYS_I64: [(4096, 16), (2048, 16), (2048, 8)],
+        PAIRS_I32_U32: [(4096, 16), (2048, 16), (2048, 8)]},
+}
 SMALL = {KEYS_I32: [8192], KEYS_I64: [4096], PAIRS_I32_U32: [4096]}
 SEG_SMALL = [2048, 4096, 8192]
 KEY_TYPE = {KEYS_I32: KEYS_I32, SEG_I32: KEYS_I32, KEYS_I64: KEYS_I64, SEG_I64: KEYS_I64, PAIRS_I32_U32: PAIRS_I32_U32}
@@ -42,15 +48,15 @@ NAMES = {KEYS_I32: "keys_i32", KEYS_I64: "keys_i64", PAIRS_I32_U32: "pairs_i32",
 
 
 FANINS = [2, 4]
-MERGE4_NV = {(4096, 16)}  # fan-in-4 merge shapes compiled (capacity 2 * merge_nv)
 
 
 def candidates(kind):
     kt = KEY_TYPE[kind]
     smalls = SEG_SMALL if kind in (SEG_I32, SEG_I64) else SMALL[kt]
-    for (t, tv), (m, mv), s, f in itertools.product(TILES[kt], MERGES[kt], smalls, FANINS):
-        if t % m == 0 and (f == 2 or (m, mv) in MERGE4_NV):
-            yield (t, tv, m, mv, s, f)
+    for f in FANINS:
+        for (t, tv), (m, mv), s in itertools.product(TILES[kt], MERGES[f][kt], smalls):
+            if t % m == 0:
+                yield (t, tv, m, mv, s, f)
 
 
 def _rng_keys(kind, n, seed):

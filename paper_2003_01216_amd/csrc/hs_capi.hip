@@ -190,7 +190,7 @@ int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 struct Layout {
     // byte offsets into scratch
     size_t err, own_off, skeys, svals, tmin, tmax, rounds, plans, tilecnt, tilepre, bounds, counts, pos, bstart, bsize, tsc,
-        tsp, mcc, msp, tiles, sdesc, mdesc, srec, ssorted, part32, part64, total;
+        tsp, mcc, msp, tiles, sdesc, mdesc, ssorted, part32, part64, total;
     // item bounds
     int64_t large_bound, tiles_bound, buckets, ts_bound, chunks_bound;
 };
@@ -236,7 +236,6 @@ Layout make_layout(int kind, int64_t n, int64_t nseg, const Config& c) {
     L.tiles = take(sizeof(TileDesc) * L.tiles_bound);
     L.sdesc = take(sizeof(SortDesc) * L.ts_bound);
     L.mdesc = take(sizeof(MergeDesc) * L.chunks_bound);
-    L.srec = take(sizeof(Split4) * L.chunks_bound);
     L.ssorted = take(sizeof(Split4) * L.chunks_bound);
     const int64_t p32 = std::max(scan_partial_count(nseg), scan_partial_count(L.buckets));
     L.part32 = take(4 * p32);
@@ -274,7 +273,6 @@ Work<K> make_work(const Layout& L, char* scr, K* keys, uint32_t* vals, const int
     w.tiles = (TileDesc*)(scr + L.tiles);
     w.sdesc = (SortDesc*)(scr + L.sdesc);
     w.mdesc = (MergeDesc*)(scr + L.mdesc);
-    w.srec = (Split4*)(scr + L.srec);
     w.ssorted = (Split4*)(scr + L.ssorted);
     w.err = (uint32_t*)(scr + L.err);
     w.tile = (int32_t)c.tile;

@@ -116,8 +116,10 @@ __device__ __forceinline__ void cas_up(W& a, W& b) {  // a <- min, b <- max
 // VT-strided positions spread over the banks.
 template <typename W>
 __device__ __forceinline__ int lds_pad(int i) {
-    constexpr int per = 128 / (int)sizeof(W);
-    return i + i / per;
+    // i >= 0 always: the unsigned shift is one instruction where a signed
+    // division takes four
+    constexpr unsigned per = 128 / sizeof(W);
+    return i + (int)((unsigned)i / per);
 }
 template <typename W>
 constexpr int lds_padded_size(int n) {
@@ -197,35 +199,58 @@ __device__ __forceinline__ int merge_path_fixed(int diag, int na, int nb, FA A, 
     return pos;
 }
 
-// Global-memory co-rank by absolute power-of-two steps (top = a power of two
-// not below hi - lo).  Probes of nearby diagonals fall on the same few
-// positions in the early steps (lo is a multiple of the chunk size), so
-// neighbouring searches share cache lines instead of each pulling its own.
-template <typename FA, typename FB>
-__device__ __forceinline__ int64_t merge_path_steps64(int64_t diag, int64_t na, int64_t nb, int64_t top, FA A, FB B) {
-    const int64_t lo = diag > nb ? diag - nb : 0;
-    const int64_t hi = diag < na ? diag : na;
-    int64_t pos = lo;
-    for (int64_t step = top; step > 0; step >>= 1) {
-        const int64_t m = pos + step - 1;
-        if (m < hi && !(B(diag - 1 - m) < A(m))) pos += step;
+// Co-rank over padded LDS runs (logical positions; physical lds_pad) A at
+// [sa, sa+na) and B at [sb, sb+nb): how many of the first `diag` merged
+// outputs come from A (ties to A).  log2(STEP0)+1 probes, STEP0 a power of
+// two with 2*STEP0 > hi - lo.  Probe indices are clamped into the runs (B
+// may be read one word before sb, or at nb, the first word after it), so
+// every read is in bounds and no probe needs a branch.
+template <typename W, int STEP0>
+__device__ __forceinline__ int lds_corank(const W* lds, int sa, int sb, int diag, int na, int nb) {
+    const int lo = diag > nb ? diag - nb : 0;
+    const int hi = diag < na ? diag : na;
+    const int hic = hi > 0 ? hi - 1 : 0;
+    const int kb = sb + diag - 1;  // B[diag - 1 - m] sits at kb - m
+    int pos = lo;
+#pragma unroll
+    for (int step = STEP0; step > 0; step >>= 1) {
+        const int m = pos + step - 1;
+        const int mc = m < hic ? m : hic;
+        const W a = lds[lds_pad<W>(sa + mc)];
+        const W b = lds[lds_pad<W>(kb - mc)];
+        pos = (m < hi && !(b < a)) ? pos + step : pos;
     }
     return pos;
 }
 
-// 64-bit variant for global-memory co-ranks over long runs.
-template <typename FA, typename FB>
-__device__ __forceinline__ int64_t merge_path64(int64_t diag, int64_t na, int64_t nb, FA A, FB B) {
-    int64_t lo = diag > nb ? diag - nb : 0;
-    int64_t hi = diag < na ? diag : na;
-    while (lo < hi) {
-        int64_t mid = (lo + hi) >> 1;
-        if (!(B(diag - 1 - mid) < A(mid)))
-            lo = mid + 1;
-        else
-            hi = mid;
-    }
-    return lo;
+// VT consecutive words from logical position p0 of a padded LDS array
+// (VT <= one pad period, so the run crosses at most one pad word): VT+1
+// reads at constant offsets, then one select per word.
+template <typename W, int VT>
+__device__ __forceinline__ void lds_read_padded(const W* lds, int p0, W (&r)[VT]) {
+    constexpr int per = 128 / (int)sizeof(W);
+    static_assert(VT <= per, "a window crosses at most one pad word");
+    const W* base = lds + lds_pad<W>(p0);
+    const int cut = per - (p0 & (per - 1));  // words i >= cut lie one further
+    W x[VT + 1];
+#pragma unroll
+    for (int i = 0; i <= VT; i++) x[i] = base[i];
+#pragma unroll
+    for (int i = 0; i < VT; i++) r[i] = i >= cut ? x[i + 1] : x[i];
+}
+
+// The VT outputs that follow co-rank (ai, bi) of a merge: the VT smallest
+// of A[ai..ai+VT) and B[bi..bi+VT) (both runs followed by at least VT
+// largest-word sentinels).  min(a[i], b[VT-1-i]) is the bitonic sequence of
+// those VT words; one bitonic merge sorts it.
+template <typename W, int VT>
+__device__ __forceinline__ void lds_merge_window(const W* lds, int pa, int pb, W (&v)[VT]) {
+    W b[VT];
+    lds_read_padded<W, VT>(lds, pa, v);
+    lds_read_padded<W, VT>(lds, pb, b);
+#pragma unroll
+    for (int i = 0; i < VT; i++) v[i] = b[VT - 1 - i] < v[i] ? b[VT - 1 - i] : v[i];
+    bitonic_merge<W, VT>(v);
 }
 
 // --------------------------------------------------------- wave/block helpers
@@ -298,22 +323,41 @@ __host__ __device__ __forceinline__ int merge_rounds(int64_t size, int64_t tile,
     return r;
 }
 
-// Search helpers over a sorted run R[0..n) with absolute power-of-two steps
-// (top: a power of two >= n), so that searches of nearby values share the
-// cache lines of their early probes.
-template <typename K>
-__device__ __forceinline__ int64_t lower_bound_steps(const K* R, int64_t n, K v, int64_t top) {
-    int64_t pos = 0;
-    for (int64_t step = top; step > 0; step >>= 1)
-        if (pos + step <= n && R[pos + step - 1] < v) pos += step;
-    return pos;  // elements < v
+// Global-memory searches over long runs by absolute power-of-two steps (top:
+// a power of two not below the search range), so that searches of nearby
+// values share the cache lines of their early probes.  These searches are
+// bound by the cache lines they pull (every deep probe of a search touches
+// its own line), not by latency: a 4-ary search, with three probes per
+// level, pulls more lines and is slower.
+
+// Co-rank: how many of the first diag outputs of merge(A, B) come from A
+// (ties to A).
+template <typename FA, typename FB>
+__device__ __forceinline__ int64_t merge_path_steps64(int64_t diag, int64_t na, int64_t nb, int64_t top, FA A, FB B) {
+    const int64_t lo = diag > nb ? diag - nb : 0;
+    const int64_t hi = diag < na ? diag : na;
+    int64_t pos = lo;
+    for (int64_t step = top; step > 0; step >>= 1) {
+        const int64_t m = pos + step - 1;
+        if (m < hi && !(B(diag - 1 - m) < A(m))) pos += step;
+    }
+    return pos;
 }
-template <typename K>
-__device__ __forceinline__ int64_t upper_bound_steps(const K* R, int64_t n, K v, int64_t top) {
-    int64_t pos = 0;
-    for (int64_t step = top; step > 0; step >>= 1)
-        if (pos + step <= n && !(v < R[pos + step - 1])) pos += step;
-    return pos;  // elements <= v
+
+// Bounds of v in two sorted runs R[0..nr) and Q[0..nq) (elements < v when
+// UPPER is false, <= v when true), the two searches stepping together.
+template <bool UPPER, typename K>
+__device__ __forceinline__ void bound2_steps(const K* R, int64_t nr, const K* Q, int64_t nq, K v, int64_t top,
+                                             int64_t& pr, int64_t& pq) {
+    pr = 0;
+    pq = 0;
+    for (int64_t step = top; step > 0; step >>= 1) {
+        const bool ir = pr + step <= nr, iq = pq + step <= nq;
+        const K r = ir ? R[pr + step - 1] : v;  // no read outside a run (it may be empty)
+        const K q = iq ? Q[pq + step - 1] : v;
+        if (ir && (UPPER ? !(v < r) : r < v)) pr += step;
+        if (iq && (UPPER ? !(v < q) : q < v)) pq += step;
+    }
 }
 
 }  // namespace hs

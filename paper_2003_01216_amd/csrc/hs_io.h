@@ -7,6 +7,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "hs_device.h"
+
 namespace hs {
 
 template <typename T>
@@ -136,6 +138,75 @@ __device__ __forceinline__ void load_runs(const T* const (&src)[NR], const int (
             d += v * E;
 #pragma unroll
             for (int e = 0; e < E; e++) put(d + e, Vec16<T>::get(x[j], e));
+        }
+    }
+}
+
+// Runs into a padded LDS array (one pad word per 128 bytes): element q of
+// run r goes to logical position at[r] + q as xf(off[r] + q, src[r][q])
+// (off: the element's index in the concatenation of the runs).  The caller
+// places each run so that its 16-byte body vectors start on logical
+// multiples of 4, (at[r] + head_len(src[r], cnt[r])) % 4 == 0; a vector's
+// words then share one pad period and sit at constant offsets from one
+// address.  All global loads are issued before the first LDS write.
+template <typename K, typename W, int NT, int MAXTOT, int NR, typename XF>
+__device__ __forceinline__ void load_runs_lds(const K* const (&src)[NR], const int (&cnt)[NR], const int (&at)[NR],
+                                              const int (&off)[NR], W* words, XF&& xf) {
+    constexpr int E = Vec16<K>::n;
+    using V = typename Vec16<K>::type;
+    constexpr int PER = (MAXTOT / E + NT - 1) / NT;
+    const int tid = threadIdx.x;
+    int head[NR], tail[NR], pre[NR + 1];
+    uintptr_t vbase[NR];
+    int wbase[NR], obase[NR];  // logical LDS position / concatenated index of vector 0, as seen from run r
+    pre[0] = 0;
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+        head[r] = head_len(src[r], cnt[r]);
+        const int body = (cnt[r] - head[r]) / E;
+        tail[r] = head[r] + body * E;
+        pre[r + 1] = pre[r] + body;
+        vbase[r] = (uintptr_t)(src[r] + head[r]) - (uintptr_t)pre[r] * sizeof(V);
+        wbase[r] = at[r] + head[r] - pre[r] * E;
+        obase[r] = off[r] + head[r] - pre[r] * E;
+    }
+    V x[PER];
+#pragma unroll
+    for (int j = 0; j < PER; j++) {
+        const int v = j * NT + tid;
+        if (v < pre[NR]) {
+            uintptr_t b = vbase[0];
+#pragma unroll
+            for (int r = 1; r < NR; r++) b = v >= pre[r] ? vbase[r] : b;
+            x[j] = reinterpret_cast<const V*>(b)[v];
+        }
+    }
+    K hv[NR], tv[NR];
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+        if (tid < head[r]) hv[r] = src[r][tid];
+        if (tid < cnt[r] - tail[r]) tv[r] = src[r][tail[r] + tid];
+    }
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+        if (tid < head[r]) words[lds_pad<W>(at[r] + tid)] = xf(off[r] + tid, hv[r]);
+        if (tid < cnt[r] - tail[r]) words[lds_pad<W>(at[r] + tail[r] + tid)] = xf(off[r] + tail[r] + tid, tv[r]);
+    }
+#pragma unroll
+    for (int j = 0; j < PER; j++) {
+        const int v = j * NT + tid;
+        if (v < pre[NR]) {
+            int d = wbase[0], o = obase[0];
+#pragma unroll
+            for (int r = 1; r < NR; r++) {
+                d = v >= pre[r] ? wbase[r] : d;
+                o = v >= pre[r] ? obase[r] : o;
+            }
+            d += v * E;
+            o += v * E;
+            W* dst = words + lds_pad<W>(d);
+#pragma unroll
+            for (int e = 0; e < E; e++) dst[e] = xf(o + e, Vec16<K>::get(x[j], e));
         }
     }
 }

@@ -673,6 +673,9 @@ __global__ __launch_bounds__(NT) void k_merge(Work<K> w, int64_t bound) {
 // two consecutive split points lie at most S keys of X and S of Y, so a
 // workgroup of capacity 2S merges them in LDS: W0+W1 and W2+W3, then the two.
 // One sample per S keys of a bucket, so the chunk list is the fan-in-2 one.
+// A sample's place among all samples of its group, in rank order, follows
+// from the same counts: the Y samples before x are those at Y positions
+// below #R2(< x) + #R3(< x), ceil of that over S; likewise for y.
 template <typename K>
 __device__ __forceinline__ K elem_at_corank(const K* A, int64_t na, const K* B, int64_t nb, int64_t c, int64_t d) {
     // the output after the first d of merge(A, B), whose co-rank is c (ties -> A)
@@ -708,25 +711,25 @@ __global__ __launch_bounds__(256) void k_part4(Work<K> w, int round, int64_t bou
             const K* R2 = src + 2 * L;
             const K* R3 = src + 3 * L;
             const int64_t pos = o - q * 2 * L;  // position inside X or Y
-            int64_t s0, s1, s2, s3, rank;
+            int64_t s0, s1, s2, s3, rank, before;  // before: samples of the other half ranked earlier
             if (!(q & 1)) {
                 const int64_t c = merge_path_steps64(pos, len[0], len[1], L, [&](int64_t x) { return R0[x]; },
                                                      [&](int64_t x) { return R1[x]; });
                 const K x = elem_at_corank(R0, len[0], R1, len[1], c, pos);
                 s0 = c;
                 s1 = pos - c;
-                s2 = lower_bound_steps(R2, len[2], x, L);
-                s3 = lower_bound_steps(R3, len[3], x, L);
+                bound2_steps<false>(R2, len[2], R3, len[3], x, L, s2, s3);
                 rank = pos + s2 + s3;
+                before = (s2 + s3 + S - 1) / S;
             } else {
                 const int64_t e = merge_path_steps64(pos, len[2], len[3], L, [&](int64_t x) { return R2[x]; },
                                                      [&](int64_t x) { return R3[x]; });
                 const K y = elem_at_corank(R2, len[2], R3, len[3], e, pos);
-                s0 = upper_bound_steps(R0, len[0], y, L);
-                s1 = upper_bound_steps(R1, len[1], y, L);
+                bound2_steps<true>(R0, len[0], R1, len[1], y, L, s0, s1);
                 s2 = e;
                 s3 = pos - e;
                 rank = pos + s0 + s1;
+                before = (s0 + s1 + S - 1) / S;
             }
             const int64_t nx = (len[0] + len[1] + S - 1) / S;
             const int64_t ny = (len[2] + len[3] + S - 1) / S;
@@ -741,56 +744,34 @@ __global__ __launch_bounds__(256) void k_part4(Work<K> w, int round, int64_t bou
             d.items = (int32_t)(nx + ny);
             d.nx = (int32_t)nx;
             d.flags = kActive | (odd ? kFromScratch : 0);
+            w.ssorted[d.first + pos / S + before] = d;
+            return;
         }
     }
-    w.srec[item] = d;
-}
-
-// Places every split point at its rank order inside its group: an X point's
-// position is its X index plus the Y points ranked before it, and vice versa.
-template <typename K>
-__global__ __launch_bounds__(256) void k_order4(Work<K> w, int64_t bound) {
-    const int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (item >= bound) return;
-    const Split4 d = w.srec[item];
-    if (!(d.flags & kActive)) {
-        w.ssorted[item] = d;
-        return;
-    }
-    const int local = (int)(item - d.first);
-    const bool is_x = local < d.nx;
-    const int own = is_x ? local : local - d.nx;
-    const Split4* other = w.srec + d.first + (is_x ? d.nx : 0);
-    int lo = 0, hi = is_x ? d.items - d.nx : d.nx;  // count of the other side's ranks < d.rank
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (other[mid].rank < d.rank)
-            lo = mid + 1;
-        else
-            hi = mid;
-    }
-    w.ssorted[d.first + own + lo] = d;
+    w.ssorted[item] = d;
 }
 
 // A workgroup merges the keys between two consecutive split points (at most
-// S of X and S of Y, S = NT*VT) in two LDS levels.  Work is counted in jobs
-// of VT outputs, one merge-path co-rank and one bitonic gather each; a
-// thread runs up to two jobs per level, so the cost follows the chunk's size
-// (chunks vary between 1 and 2S keys) rather than its capacity.
-template <typename W, int VT>
-struct Job {
-    int a0, na, nb, dt, cnt;  // merge of words[a0, a0+na) and words[a0+na, a0+na+nb), outputs dt..dt+cnt
-    int end_corank;           // co-rank at dt + cnt when this is the merge's last job, else -1
-};
-
+// S of X and S of Y, S = NT*VT) in two LDS levels: W0+W1 -> X' and W2+W3 ->
+// Y', then X'+Y'.  Work is counted in jobs of VT outputs (one co-rank and
+// one window merge each); a thread runs up to two jobs per level, so the
+// cost follows the chunk's size (1 to 2S keys), not its capacity.
+//
+// LDS is padded (one word per 128 bytes: neighbouring threads' co-ranks lie
+// about VT/2 words apart, and the pad spreads them over the banks).  Every
+// run is followed by VT largest-word sentinels, so lds_merge_window reads
+// VT words past a co-rank without bounds checks.  Level outputs start on
+// multiples of VT, so a thread's VT outputs share one pad period and are
+// written at constant offsets.
 template <typename K, bool PAIRS, int NT, int VT>
 __global__ __launch_bounds__(NT) void k_merge4(Work<K> w, int round, int64_t bound) {
     using W = typename WordOf<K, PAIRS>::type;
-    constexpr int BLK = NT * VT;  // S
-    constexpr int CAP = 2 * BLK;
-    __shared__ W words[lds_padded_size<W>(CAP)];
+    constexpr int S = NT * VT;
+    constexpr int CAP = 2 * S;
+    constexpr int LOGICAL = CAP + 8 * VT + 32;  // four windows, sentinels, spacing, alignment
+    static_assert((128 / sizeof(W)) % VT == 0, "a VT block fits one pad period");
+    __shared__ W words[lds_padded_size<W>(LOGICAL)];
     __shared__ uint32_t sv[PAIRS ? CAP : 1];
-    __shared__ int sp[2 * NT + 1];
     const int64_t item = blockIdx.x;
     const Split4 r0 = w.ssorted[item];
     if (!(r0.flags & kActive)) return;
@@ -812,7 +793,7 @@ __global__ __launch_bounds__(NT) void k_merge4(Work<K> w, int round, int64_t bou
     const int o1 = c0, o2 = c0 + c1, o3 = o2 + c2, c = o3 + c3;
     // a split point inconsistent with its successor would make the windows
     // run past their runs: flag it and do nothing (never observed; cheap)
-    if (c != rank_end - r0.rank || c0 < 0 || c1 < 0 || c2 < 0 || c3 < 0 || c0 + c1 > BLK || c2 + c3 > BLK) {
+    if (c != rank_end - r0.rank || c0 < 0 || c1 < 0 || c2 < 0 || c3 < 0 || c0 + c1 > S || c2 + c3 > S) {
         if (tid == 0) atomicOr(w.err, 2u);
         return;
     }
@@ -823,90 +804,97 @@ __global__ __launch_bounds__(NT) void k_merge4(Work<K> w, int round, int64_t bou
     const uint32_t* svv = PAIRS ? (odd ? w.svals : w.vals) + r0.base : nullptr;
     K* dk = (odd ? w.keys : w.skeys) + r0.base + r0.rank;
     uint32_t* dv = PAIRS ? (odd ? w.vals : w.svals) + r0.base + r0.rank : nullptr;
-    // the four windows side by side in LDS: [W0 | W1 | W2 | W3]
+    const W wmax = WordMax<W>::v;
+    const K* const ks[4] = {sk + r0.s[0], sk + L + r0.s[1], sk + 2 * L + r0.s[2], sk + 3 * L + r0.s[3]};
+    const int cs[4] = {c0, c1, c2, c3};
+    const int os[4] = {0, o1, o2, o3};
+    // window r at logical at[r] (>= 1; body vectors on multiples of 4), then
+    // VT sentinels and VT + 4 spare words (room for X' and Y' rounded down
+    // to multiples of VT)
+    int at[4];
     {
-        const int cs[4] = {c0, c1, c2, c3};
-        const int os[4] = {0, o1, o2, o3};
-        const K* const ks[4] = {sk + r0.s[0], sk + L + r0.s[1], sk + 2 * L + r0.s[2], sk + 3 * L + r0.s[3]};
-        load_runs<K, NT, CAP, 4>(ks, cs, os, [&](int q, K key) { words[lds_pad<W>(q)] = make_word<K, PAIRS>(key, q); });
-        if constexpr (PAIRS) {
-            const uint32_t* const vs[4] = {svv + r0.s[0], svv + L + r0.s[1], svv + 2 * L + r0.s[2],
-                                           svv + 3 * L + r0.s[3]};
-            load_runs<uint32_t, NT, CAP, 4>(vs, cs, os, [&](int q, uint32_t x) { sv[q] = x; });
+        int cur = 4;
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            const int h = head_len(ks[r], cs[r]);
+            at[r] = ((cur + h + 3) & ~3) - h;
+            cur = at[r] + cs[r] + 2 * VT + 4;
         }
     }
+    load_runs_lds<K, W, NT, CAP, 4>(ks, cs, at, os, words, [](int q, K k) { return make_word<K, PAIRS>(k, q); });
+    if constexpr (PAIRS) {
+        const uint32_t* const vs[4] = {svv + r0.s[0], svv + L + r0.s[1], svv + 2 * L + r0.s[2],
+                                       svv + 3 * L + r0.s[3]};
+        load_runs<uint32_t, NT, CAP, 4>(vs, cs, os, [&](int q, uint32_t x) { sv[q] = x; });
+    }
+    if (tid < 4 * VT) {
+        const int r = tid / VT;
+        int p = at[0] + c0;
+        p = r == 1 ? at[1] + c1 : p;
+        p = r == 2 ? at[2] + c2 : p;
+        p = r == 3 ? at[3] + c3 : p;
+        words[lds_pad<W>(p + tid % VT)] = wmax;
+    }
     __syncthreads();
-    // one merge level over a list of jobs; jobs [0, njobs), thread t runs t and t + NT
-    auto level = [&](auto job_of, int njobs) {
-        W v[2][VT];
-        Job<W, VT> jb[2];
-        int ai[2];
-#pragma unroll
-        for (int h = 0; h < 2; h++) {
-            const int j = tid + h * NT;
-            jb[h] = job_of(j < njobs ? j : njobs - 1);
-            if (j < njobs) {
-                const int a0 = jb[h].a0, na = jb[h].na;
-                auto A = [&](int x) { return words[lds_pad<W>(a0 + x)]; };
-                auto B = [&](int x) { return words[lds_pad<W>(a0 + na + x)]; };
-                ai[h] = merge_path_fixed<BLK / 2>(jb[h].dt, na, jb[h].nb, A, B);
-                sp[j] = ai[h];
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int h = 0; h < 2; h++) {
-            const int j = tid + h * NT;
-            if (j < njobs) {
-                const int an = jb[h].end_corank >= 0 ? jb[h].end_corank : sp[j + 1];
-                gather_merge<W, VT>(words, jb[h].a0, jb[h].a0 + jb[h].na, ai[h], jb[h].dt - ai[h], an - ai[h],
-                                    jb[h].cnt, v[h]);
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int h = 0; h < 2; h++) {
-            const int j = tid + h * NT;
-            if (j < njobs) {
-#pragma unroll
-                for (int q = 0; q < VT; q++)
-                    if (q < jb[h].cnt) words[lds_pad<W>(jb[h].a0 + jb[h].dt + q)] = v[h][q];
-            }
-        }
-        __syncthreads();
-    };
-    // level 1: X' = merge(W0, W1) into [0, o2), Y' = merge(W2, W3) into [o2, c)
+    // level 1: X' = merge(W0, W1) at x0, Y' = merge(W2, W3) at y0, in place
+    // of the windows (all reads end at the barrier before the writes)
+    const int x0 = at[0] & ~(VT - 1), y0 = at[2] & ~(VT - 1);
     const int jx = (o2 + VT - 1) / VT, jy = (c - o2 + VT - 1) / VT;
-    level(
-        [&](int j) {
-            // y = 0 for a job of X', 1 for one of Y' (arithmetic, not
-            // selects: keeps the fields in registers)
-            Job<W, VT> b;
-            const int y = j >= jx;
-            const int jj = j - y * jx;
-            b.a0 = y * o2;
-            b.na = c0 + y * (c2 - c0);
-            b.nb = c1 + y * (c3 - c1);
-            b.dt = jj * VT;
-            b.cnt = min(VT, b.na + b.nb - b.dt);
-            b.end_corank = (jj == jx + y * (jy - jx) - 1) ? b.na : -1;
-            return b;
-        },
-        jx + jy);
-    // level 2: merge [0, o2) with [o2, c)
-    const int jc = (c + VT - 1) / VT;
-    level(
-        [&](int j) {
-            Job<W, VT> b;
-            b.a0 = 0;
-            b.na = o2;
-            b.nb = c - o2;
-            b.dt = j * VT;
-            b.cnt = min(VT, c - b.dt);
-            b.end_corank = (j == jc - 1) ? o2 : -1;
-            return b;
-        },
-        jc);
+    {
+        W v[2][VT];
+        int dst[2];
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            const int j = tid + h * NT;
+            if (j < jx + jy) {
+                const int y = j >= jx;  // arithmetic selects keep these in registers
+                const int dt = (j - y * jx) * VT;
+                const int sa = at[0] + y * (at[2] - at[0]), sb = at[1] + y * (at[3] - at[1]);
+                const int na = c0 + y * (c2 - c0), nb = c1 + y * (c3 - c1);
+                const int ai = lds_corank<W, S / 2>(words, sa, sb, dt, na, nb);
+                lds_merge_window<W, VT>(words, sa + ai, sb + dt - ai, v[h]);
+                dst[h] = lds_pad<W>(x0 + y * (y0 - x0) + dt);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            const int j = tid + h * NT;
+            if (j < jx + jy) {
+#pragma unroll
+                for (int q = 0; q < VT; q++) words[dst[h] + q] = v[h][q];
+            }
+        }
+        // sentinels past the last VT group of X' and of Y' (the groups end in
+        // sentinels already: their outputs past the end are the windows')
+        if (tid < 2 * VT) words[lds_pad<W>((tid < VT ? x0 + jx * VT : y0 + jy * VT - VT) + tid)] = wmax;
+        __syncthreads();
+    }
+    // level 2: merge X' (o2 words) with Y' (c - o2) into logical [0, c)
+    {
+        const int jc = (c + VT - 1) / VT;
+        W v[2][VT];
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            const int j = tid + h * NT;
+            if (j < jc) {
+                const int dt = j * VT;
+                const int ai = lds_corank<W, S>(words, x0, y0, dt, o2, c - o2);
+                lds_merge_window<W, VT>(words, x0 + ai, y0 + dt - ai, v[h]);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            const int j = tid + h * NT;
+            if (j < jc) {
+                W* dst = words + lds_pad<W>(j * VT);
+#pragma unroll
+                for (int q = 0; q < VT; q++) dst[q] = v[h][q];
+            }
+        }
+        __syncthreads();
+    }
     store_keys<K, NT, CAP>(dk, c, [&](int q) { return word_key<K, PAIRS>(words[lds_pad<W>(q)]); });
     if constexpr (PAIRS)
         store_run<uint32_t, NT, CAP>(dv, c, [&](int q) { return sv[pair_pos(words[lds_pad<W>(q)])]; });
@@ -1200,7 +1188,6 @@ hipError_t launch_merge(const Work<K>& w, int64_t chunks_bound, hipStream_t st) 
 template <typename K>
 hipError_t launch_part4(const Work<K>& w, int round, int64_t chunks_bound, hipStream_t st) {
     k_part4<K><<<cdiv64(chunks_bound, 256), 256, 0, st>>>(w, round, chunks_bound);
-    k_order4<K><<<cdiv64(chunks_bound, 256), 256, 0, st>>>(w, chunks_bound);
     return hipGetLastError();
 }
 

@@ -28,7 +28,9 @@ struct ScanSpec {
 // Fan-in-4 merge: NT*VT = merge_nv (samples every merge_nv keys; a chunk
 // holds up to twice that).
 #define HS_MERGE4_VARIANTS(X) \
-    X(int32_t, false, 256, 16) X(int64_t, false, 256, 16) X(int32_t, true, 256, 16)
+    X(int32_t, false, 256, 16) X(int64_t, false, 256, 16) X(int32_t, true, 256, 16) \
+    X(int32_t, false, 512, 8) X(int32_t, false, 256, 8) X(int32_t, false, 128, 16) X(int32_t, true, 128, 16) \
+    X(int32_t, true, 256, 8) X(int64_t, false, 128, 16) X(int64_t, false, 256, 8)
 // Shapes usable by the whole-segment LDS sort (5-bit digit counters: VT <= 16).
 #define HS_SMALL_VARIANTS(X)                                                                 \
     X(int32_t, false, 512, 16) X(int32_t, false, 256, 16) X(int32_t, false, 256, 8) X(int32_t, false, 64, 4) \

@@ -91,7 +91,6 @@ struct Work {
     TileDesc* tiles;   // [tiles bound]
     SortDesc* sdesc;   // [local-sort partitions bound]
     MergeDesc* mdesc;  // [merge chunks bound] of the current round (fan-in 2)
-    Split4* srec;      // [merge chunks bound] split points by sample (fan-in 4)
     Split4* ssorted;   // [merge chunks bound] split points by rank (fan-in 4)
     int32_t* rounds;  // largest number of merge rounds any bucket needs
     uint32_t* err;   // device-side validation flag (bad offsets)
