@@ -142,74 +142,108 @@ __device__ __forceinline__ void load_runs(const T* const (&src)[NR], const int (
     }
 }
 
-// Runs into a padded LDS array (one pad word per 128 bytes): element q of
-// run r goes to logical position at[r] + q as xf(off[r] + q, src[r][q])
-// (off: the element's index in the concatenation of the runs).  The caller
-// places each run so that its 16-byte body vectors start on logical
-// multiples of 4, (at[r] + head_len(src[r], cnt[r])) % 4 == 0; a vector's
-// words then share one pad period and sit at constant offsets from one
-// address.  All global loads are issued before the first LDS write.
-template <typename K, typename W, int NT, int MAXTOT, int NR, typename XF>
-__device__ __forceinline__ void load_runs_lds(const K* const (&src)[NR], const int (&cnt)[NR], const int (&at)[NR],
-                                              const int (&off)[NR], W* words, XF&& xf) {
-    constexpr int E = Vec16<K>::n;
+// Runs into LDS in two halves: issue() starts every global load of the runs
+// (16-byte body vectors shared out over the workgroup, scalar heads and
+// tails) into registers, all before any LDS write; commit() writes them to
+// LDS.  commit_padded puts element q of run r into a padded array at logical
+// position at[r] + q as xf(off[r] + q, src[r][q]) (off: the element's index
+// in the concatenation of the runs).  The caller places each run so that its
+// body vectors start on logical multiples of 4, (at[r] + head_len(src[r],
+// cnt[r])) % 4 == 0; a vector's words then share one pad period and sit at
+// constant offsets from one address.
+template <typename K, int NT, int MAXTOT, int NR>
+struct RunsToLds {
+    static constexpr int E = Vec16<K>::n;
     using V = typename Vec16<K>::type;
-    constexpr int PER = (MAXTOT / E + NT - 1) / NT;
-    const int tid = threadIdx.x;
-    int head[NR], tail[NR], pre[NR + 1];
-    uintptr_t vbase[NR];
-    int wbase[NR], obase[NR];  // logical LDS position / concatenated index of vector 0, as seen from run r
-    pre[0] = 0;
-#pragma unroll
-    for (int r = 0; r < NR; r++) {
-        head[r] = head_len(src[r], cnt[r]);
-        const int body = (cnt[r] - head[r]) / E;
-        tail[r] = head[r] + body * E;
-        pre[r + 1] = pre[r] + body;
-        vbase[r] = (uintptr_t)(src[r] + head[r]) - (uintptr_t)pre[r] * sizeof(V);
-        wbase[r] = at[r] + head[r] - pre[r] * E;
-        obase[r] = off[r] + head[r] - pre[r] * E;
-    }
+    static constexpr int PER = (MAXTOT / E + NT - 1) / NT;
     V x[PER];
-#pragma unroll
-    for (int j = 0; j < PER; j++) {
-        const int v = j * NT + tid;
-        if (v < pre[NR]) {
-            uintptr_t b = vbase[0];
-#pragma unroll
-            for (int r = 1; r < NR; r++) b = v >= pre[r] ? vbase[r] : b;
-            x[j] = reinterpret_cast<const V*>(b)[v];
-        }
-    }
     K hv[NR], tv[NR];
+    int head[NR], tail[NR], cnt[NR], at[NR], off[NR], pre[NR + 1], wbase[NR], obase[NR];
+
+    __device__ __forceinline__ void issue(const K* const (&src)[NR], const int (&cnt_)[NR], const int (&at_)[NR],
+                                          const int (&off_)[NR]) {
+        const int tid = threadIdx.x;
+        uintptr_t vbase[NR];
+        pre[0] = 0;
 #pragma unroll
-    for (int r = 0; r < NR; r++) {
-        if (tid < head[r]) hv[r] = src[r][tid];
-        if (tid < cnt[r] - tail[r]) tv[r] = src[r][tail[r] + tid];
-    }
+        for (int r = 0; r < NR; r++) {
+            cnt[r] = cnt_[r];
+            at[r] = at_[r];
+            off[r] = off_[r];
+            head[r] = head_len(src[r], cnt[r]);
+            const int body = (cnt[r] - head[r]) / E;
+            tail[r] = head[r] + body * E;
+            pre[r + 1] = pre[r] + body;
+            vbase[r] = (uintptr_t)(src[r] + head[r]) - (uintptr_t)pre[r] * sizeof(V);
+            wbase[r] = at[r] + head[r] - pre[r] * E;  // logical LDS position of vector 0, seen from run r
+            obase[r] = off[r] + head[r] - pre[r] * E;  // concatenated index of vector 0, seen from run r
+        }
 #pragma unroll
-    for (int r = 0; r < NR; r++) {
-        if (tid < head[r]) words[lds_pad<W>(at[r] + tid)] = xf(off[r] + tid, hv[r]);
-        if (tid < cnt[r] - tail[r]) words[lds_pad<W>(at[r] + tail[r] + tid)] = xf(off[r] + tail[r] + tid, tv[r]);
-    }
+        for (int j = 0; j < PER; j++) {
+            const int v = j * NT + tid;
+            if (v < pre[NR]) {
+                uintptr_t b = vbase[0];
 #pragma unroll
-    for (int j = 0; j < PER; j++) {
-        const int v = j * NT + tid;
-        if (v < pre[NR]) {
-            int d = wbase[0], o = obase[0];
-#pragma unroll
-            for (int r = 1; r < NR; r++) {
-                d = v >= pre[r] ? wbase[r] : d;
-                o = v >= pre[r] ? obase[r] : o;
+                for (int r = 1; r < NR; r++) b = v >= pre[r] ? vbase[r] : b;
+                x[j] = reinterpret_cast<const V*>(b)[v];
             }
-            d += v * E;
-            o += v * E;
-            W* dst = words + lds_pad<W>(d);
+        }
 #pragma unroll
-            for (int e = 0; e < E; e++) dst[e] = xf(o + e, Vec16<K>::get(x[j], e));
+        for (int r = 0; r < NR; r++) {
+            if (tid < head[r]) hv[r] = src[r][tid];
+            if (tid < cnt[r] - tail[r]) tv[r] = src[r][tail[r] + tid];
         }
     }
-}
+
+    // put1(pos, idx, key) for single elements, putv(pos, idx, keys[E]) for a
+    // body vector (pos = logical position at[r] + q, a multiple of 4 for
+    // vectors; idx = off[r] + q).
+    template <typename P1, typename PV>
+    __device__ __forceinline__ void commit(P1&& put1, PV&& putv) const {
+        const int tid = threadIdx.x;
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            if (tid < head[r]) put1(at[r] + tid, off[r] + tid, hv[r]);
+            if (tid < cnt[r] - tail[r]) put1(at[r] + tail[r] + tid, off[r] + tail[r] + tid, tv[r]);
+        }
+#pragma unroll
+        for (int j = 0; j < PER; j++) {
+            const int v = j * NT + tid;
+            if (v < pre[NR]) {
+                int d = wbase[0], o = obase[0];
+#pragma unroll
+                for (int r = 1; r < NR; r++) {
+                    d = v >= pre[r] ? wbase[r] : d;
+                    o = v >= pre[r] ? obase[r] : o;
+                }
+                K k[E];
+#pragma unroll
+                for (int e = 0; e < E; e++) k[e] = Vec16<K>::get(x[j], e);
+                putv(d + v * E, o + v * E, k);
+            }
+        }
+    }
+
+    // Keys as words of a padded LDS array: words[lds_pad(pos)] = xf(idx, key).
+    template <typename W, typename XF>
+    __device__ __forceinline__ void commit_padded(W* words, XF&& xf) const {
+        commit([&](int pos, int idx, K k) { words[lds_pad<W>(pos)] = xf(idx, k); },
+               [&](int pos, int idx, const K (&k)[E]) {
+                   W* dst = words + lds_pad<W>(pos);
+#pragma unroll
+                   for (int e = 0; e < E; e++) dst[e] = xf(idx + e, k[e]);
+               });
+    }
+
+    // Dense by concatenated index: dst[idx] = key.
+    __device__ __forceinline__ void commit_dense(K* dst) const {
+        commit([&](int, int idx, K k) { dst[idx] = k; },
+               [&](int, int idx, const K (&k)[E]) {
+#pragma unroll
+                   for (int e = 0; e < E; e++) dst[idx + e] = k[e];
+               });
+    }
+};
 
 // Writes dst[q] = get(q) for every q in [0, cnt), cnt <= MAXCNT, with 16-byte
 // stores for the aligned body (4-byte elements only).

@@ -475,7 +475,8 @@ __global__ __launch_bounds__(kHistNT) void k_scatter(Work<K> w) {
         dbase[tid] -= (int64_t)st;
     }
     __syncthreads();
-    // 6. coalesced runs out to the buckets
+    // 6. coalesced runs out to the buckets (a per-bucket loop of 16-byte
+    //    stores measured no faster for keys and slower for pairs)
 #pragma unroll
     for (int j = 0; j < VT; j++) {
         const int q = j * NT + tid;
@@ -763,82 +764,124 @@ __global__ __launch_bounds__(256) void k_part4(Work<K> w, int round, int64_t bou
 // VT words past a co-rank without bounds checks.  Level outputs start on
 // multiples of VT, so a thread's VT outputs share one pad period and are
 // written at constant offsets.
-template <typename K, bool PAIRS, int NT, int VT>
-__global__ __launch_bounds__(NT) void k_merge4(Work<K> w, int round, int64_t bound) {
-    using W = typename WordOf<K, PAIRS>::type;
-    constexpr int S = NT * VT;
-    constexpr int CAP = 2 * S;
-    constexpr int LOGICAL = CAP + 8 * VT + 32;  // four windows, sentinels, spacing, alignment
-    static_assert((128 / sizeof(W)) % VT == 0, "a VT block fits one pad period");
-    __shared__ W words[lds_padded_size<W>(LOGICAL)];
-    __shared__ uint32_t sv[PAIRS ? CAP : 1];
-    const int64_t item = blockIdx.x;
+
+// One chunk of a fan-in-4 round: its four input windows and its output.
+template <typename K>
+struct Chunk4 {
+    bool active;  // false: nothing to do (inactive item, empty chunk or a flagged inconsistency)
+    int c[4];     // window lengths
+    int at[4];    // logical LDS position of each window
+    const K* ks[4];
+    const uint32_t* vs[4];
+    K* dk;
+    uint32_t* dv;
+};
+
+template <typename K, bool PAIRS, int S, int VT>
+__device__ __forceinline__ Chunk4<K> chunk4_of(const Work<K>& w, int round, int64_t item, int64_t bound) {
+    Chunk4<K> g;
+    g.active = false;
     const Split4 r0 = w.ssorted[item];
-    if (!(r0.flags & kActive)) return;
+    if (!(r0.flags & kActive)) return g;
     const bool last = item + 1 - r0.first == r0.items;
     const Split4 nx1 = w.ssorted[item + 1 < bound ? item + 1 : item];
-    int e[4];
-    int64_t rank_end;
-    if (last) {
+    int64_t rank_end = 0;
 #pragma unroll
-        for (int k = 0; k < 4; k++) e[k] = r0.len[k];
-        rank_end = (int64_t)r0.len[0] + r0.len[1] + r0.len[2] + r0.len[3];
-    } else {
-#pragma unroll
-        for (int k = 0; k < 4; k++) e[k] = nx1.s[k];
-        rank_end = nx1.rank;
+    for (int k = 0; k < 4; k++) {
+        const int e = last ? r0.len[k] : nx1.s[k];
+        g.c[k] = e - r0.s[k];
+        rank_end += last ? r0.len[k] : 0;
     }
-    const int tid = threadIdx.x;
-    const int c0 = e[0] - r0.s[0], c1 = e[1] - r0.s[1], c2 = e[2] - r0.s[2], c3 = e[3] - r0.s[3];
-    const int o1 = c0, o2 = c0 + c1, o3 = o2 + c2, c = o3 + c3;
+    if (!last) rank_end = nx1.rank;
+    const int c = g.c[0] + g.c[1] + g.c[2] + g.c[3];
     // a split point inconsistent with its successor would make the windows
     // run past their runs: flag it and do nothing (never observed; cheap)
-    if (c != rank_end - r0.rank || c0 < 0 || c1 < 0 || c2 < 0 || c3 < 0 || c0 + c1 > S || c2 + c3 > S) {
-        if (tid == 0) atomicOr(w.err, 2u);
-        return;
+    if (c != rank_end - r0.rank || g.c[0] < 0 || g.c[1] < 0 || g.c[2] < 0 || g.c[3] < 0 || g.c[0] + g.c[1] > S ||
+        g.c[2] + g.c[3] > S) {
+        if (threadIdx.x == 0) atomicOr(w.err, 2u);
+        return g;
     }
-    if (c == 0) return;
+    if (c == 0) return g;
     const int64_t L = (int64_t)w.tile << (2 * round);
     const bool odd = r0.flags & kFromScratch;
     const K* sk = (odd ? w.skeys : w.keys) + r0.base;
     const uint32_t* svv = PAIRS ? (odd ? w.svals : w.vals) + r0.base : nullptr;
-    K* dk = (odd ? w.keys : w.skeys) + r0.base + r0.rank;
-    uint32_t* dv = PAIRS ? (odd ? w.vals : w.svals) + r0.base + r0.rank : nullptr;
-    const W wmax = WordMax<W>::v;
-    const K* const ks[4] = {sk + r0.s[0], sk + L + r0.s[1], sk + 2 * L + r0.s[2], sk + 3 * L + r0.s[3]};
-    const int cs[4] = {c0, c1, c2, c3};
-    const int os[4] = {0, o1, o2, o3};
+    g.dk = (odd ? w.keys : w.skeys) + r0.base + r0.rank;
+    g.dv = PAIRS ? (odd ? w.vals : w.svals) + r0.base + r0.rank : nullptr;
     // window r at logical at[r] (>= 1; body vectors on multiples of 4), then
     // VT sentinels and VT + 4 spare words (room for X' and Y' rounded down
     // to multiples of VT)
-    int at[4];
-    {
-        int cur = 4;
+    int cur = 4;
 #pragma unroll
-        for (int r = 0; r < 4; r++) {
-            const int h = head_len(ks[r], cs[r]);
-            at[r] = ((cur + h + 3) & ~3) - h;
-            cur = at[r] + cs[r] + 2 * VT + 4;
-        }
+    for (int r = 0; r < 4; r++) {
+        g.ks[r] = sk + r * L + r0.s[r];
+        g.vs[r] = PAIRS ? svv + r * L + r0.s[r] : nullptr;
+        const int h = head_len(g.ks[r], g.c[r]);
+        g.at[r] = ((cur + h + 3) & ~3) - h;
+        cur = g.at[r] + g.c[r] + 2 * VT + 4;
     }
-    load_runs_lds<K, W, NT, CAP, 4>(ks, cs, at, os, words, [](int q, K k) { return make_word<K, PAIRS>(k, q); });
-    if constexpr (PAIRS) {
-        const uint32_t* const vs[4] = {svv + r0.s[0], svv + L + r0.s[1], svv + 2 * L + r0.s[2],
-                                       svv + 3 * L + r0.s[3]};
-        load_runs<uint32_t, NT, CAP, 4>(vs, cs, os, [&](int q, uint32_t x) { sv[q] = x; });
+    g.active = true;
+    return g;
+}
+
+template <typename K, bool PAIRS, int NT, int VT>
+struct Merge4Lds {
+    using W = typename WordOf<K, PAIRS>::type;
+    static constexpr int S = NT * VT;
+    static constexpr int CAP = 2 * S;
+    static constexpr int LOGICAL = CAP + 8 * VT + 32;  // four windows, sentinels, spacing, alignment
+    static_assert((128 / sizeof(W)) % VT == 0, "a VT block fits one pad period");
+    W words[lds_padded_size<W>(LOGICAL)];
+    uint32_t sv[PAIRS ? CAP : 1];
+};
+
+template <typename K, bool PAIRS, int NT, int VT>
+struct Merge4Loads {
+    static constexpr int CAP = 2 * NT * VT;
+    RunsToLds<K, NT, CAP, 4> keys;
+    RunsToLds<uint32_t, NT, PAIRS ? CAP : 4, 4> vals;
+
+    __device__ __forceinline__ void issue(const Chunk4<K>& g) {
+        const int os[4] = {0, g.c[0], g.c[0] + g.c[1], g.c[0] + g.c[1] + g.c[2]};
+        keys.issue(g.ks, g.c, g.at, os);
+        if constexpr (PAIRS) vals.issue(g.vs, g.c, os, os);
     }
+};
+
+// Windows to LDS (from loads issued earlier) plus their sentinels.
+template <typename K, bool PAIRS, int NT, int VT>
+__device__ __forceinline__ void stage4(Merge4Lds<K, PAIRS, NT, VT>& sm, const Merge4Loads<K, PAIRS, NT, VT>& ld,
+                                       const Chunk4<K>& g) {
+    using W = typename WordOf<K, PAIRS>::type;
+    const int tid = threadIdx.x;
+    ld.keys.commit_padded(sm.words, [](int q, K k) { return make_word<K, PAIRS>(k, q); });
+    if constexpr (PAIRS) ld.vals.commit_dense(sm.sv);
     if (tid < 4 * VT) {
         const int r = tid / VT;
-        int p = at[0] + c0;
-        p = r == 1 ? at[1] + c1 : p;
-        p = r == 2 ? at[2] + c2 : p;
-        p = r == 3 ? at[3] + c3 : p;
-        words[lds_pad<W>(p + tid % VT)] = wmax;
+        int p = g.at[0] + g.c[0];
+        p = r == 1 ? g.at[1] + g.c[1] : p;
+        p = r == 2 ? g.at[2] + g.c[2] : p;
+        p = r == 3 ? g.at[3] + g.c[3] : p;
+        sm.words[lds_pad<W>(p + tid % VT)] = WordMax<W>::v;
     }
-    __syncthreads();
+}
+
+// The two merge levels and the store, on windows staged in LDS (the caller
+// has synchronised after stage4).  Ends with the LDS free for reuse only
+// after the caller's next barrier.
+template <typename K, bool PAIRS, int NT, int VT>
+__device__ __forceinline__ void merge4_chunk(Merge4Lds<K, PAIRS, NT, VT>& sm, const Chunk4<K>& g) {
+    using W = typename WordOf<K, PAIRS>::type;
+    constexpr int S = NT * VT;
+    constexpr int CAP = 2 * S;
+    W* words = sm.words;
+    const W wmax = WordMax<W>::v;
+    const int tid = threadIdx.x;
+    const int c0 = g.c[0], c1 = g.c[1], c2 = g.c[2], c3 = g.c[3];
+    const int o2 = c0 + c1, c = o2 + c2 + c3;
     // level 1: X' = merge(W0, W1) at x0, Y' = merge(W2, W3) at y0, in place
     // of the windows (all reads end at the barrier before the writes)
-    const int x0 = at[0] & ~(VT - 1), y0 = at[2] & ~(VT - 1);
+    const int x0 = g.at[0] & ~(VT - 1), y0 = g.at[2] & ~(VT - 1);
     const int jx = (o2 + VT - 1) / VT, jy = (c - o2 + VT - 1) / VT;
     {
         W v[2][VT];
@@ -849,7 +892,7 @@ __global__ __launch_bounds__(NT) void k_merge4(Work<K> w, int round, int64_t bou
             if (j < jx + jy) {
                 const int y = j >= jx;  // arithmetic selects keep these in registers
                 const int dt = (j - y * jx) * VT;
-                const int sa = at[0] + y * (at[2] - at[0]), sb = at[1] + y * (at[3] - at[1]);
+                const int sa = g.at[0] + y * (g.at[2] - g.at[0]), sb = g.at[1] + y * (g.at[3] - g.at[1]);
                 const int na = c0 + y * (c2 - c0), nb = c1 + y * (c3 - c1);
                 const int ai = lds_corank<W, S / 2>(words, sa, sb, dt, na, nb);
                 lds_merge_window<W, VT>(words, sa + ai, sb + dt - ai, v[h]);
@@ -869,6 +912,13 @@ __global__ __launch_bounds__(NT) void k_merge4(Work<K> w, int round, int64_t bou
         // sentinels already: their outputs past the end are the windows')
         if (tid < 2 * VT) words[lds_pad<W>((tid < VT ? x0 + jx * VT : y0 + jy * VT - VT) + tid)] = wmax;
         __syncthreads();
+    }
+    if (o2 == 0 || o2 == c) {  // one side empty (a group short of four runs): X' or Y' is the result
+        const int r = o2 == 0 ? y0 : x0;
+        store_keys<K, NT, CAP>(g.dk, c, [&](int q) { return word_key<K, PAIRS>(words[lds_pad<W>(r + q)]); });
+        if constexpr (PAIRS)
+            store_run<uint32_t, NT, CAP>(g.dv, c, [&](int q) { return sm.sv[pair_pos(words[lds_pad<W>(r + q)])]; });
+        return;
     }
     // level 2: merge X' (o2 words) with Y' (c - o2) into logical [0, c)
     {
@@ -895,9 +945,22 @@ __global__ __launch_bounds__(NT) void k_merge4(Work<K> w, int round, int64_t bou
         }
         __syncthreads();
     }
-    store_keys<K, NT, CAP>(dk, c, [&](int q) { return word_key<K, PAIRS>(words[lds_pad<W>(q)]); });
+    store_keys<K, NT, CAP>(g.dk, c, [&](int q) { return word_key<K, PAIRS>(words[lds_pad<W>(q)]); });
     if constexpr (PAIRS)
-        store_run<uint32_t, NT, CAP>(dv, c, [&](int q) { return sv[pair_pos(words[lds_pad<W>(q)])]; });
+        store_run<uint32_t, NT, CAP>(g.dv, c, [&](int q) { return sm.sv[pair_pos(words[lds_pad<W>(q)])]; });
+}
+
+// One workgroup per chunk.
+template <typename K, bool PAIRS, int NT, int VT>
+__global__ __launch_bounds__(NT) void k_merge4(Work<K> w, int round, int64_t bound) {
+    __shared__ Merge4Lds<K, PAIRS, NT, VT> sm;
+    const Chunk4<K> g = chunk4_of<K, PAIRS, NT * VT, VT>(w, round, blockIdx.x, bound);
+    if (!g.active) return;
+    Merge4Loads<K, PAIRS, NT, VT> ld;
+    ld.issue(g);
+    stage4(sm, ld, g);
+    __syncthreads();
+    merge4_chunk(sm, g);
 }
 
 // --------------------------------------------------------- small segments
