@@ -13,24 +13,31 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-@pytest.fixture(scope="module")
-def hs4():
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+# fan-in-4 merge shapes compiled for every key kind: (sampling stride S =
+# outputs per workgroup, outputs per thread); a workgroup holds up to 2S keys
+SHAPES = [(4096, 16), (2048, 16), (2048, 8)]
+
+
+@pytest.fixture(scope="module", params=SHAPES, ids=lambda s: f"S{s[0]}x{s[1]}")
+def hs4(request):
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     import paper_2003_01216_amd as hs
 
     hs.load_library()
+    nv, vt = request.param
     saved = {(k, c): hs.hsort_get_config(k, size_class=c) for k in range(5) for c in range(4)}
-    for (k, c), cfg in saved.items():  # fan-in 4 is compiled for 4096-key merge chunks
-        hs.hsort_set_config(k, cfg[0], cfg[1], 4096, 16, cfg[4], fanin=4, size_class=c)
+    for (k, c), cfg in saved.items():
+        hs.hsort_set_config(k, cfg[0], cfg[1], nv, vt, cfg[4], fanin=4, size_class=c)
+    say(f"fanin4 shape S={nv} VT={vt}")
     yield hs
     for (k, c), cfg in saved.items():
         hs.hsort_set_config(k, *cfg[:5], fanin=cfg[5], size_class=c)
-
-
-def say(msg):
-    print(msg, flush=True)
-    sys.stdout.flush()
 
 
 def dev(a):
