@@ -161,6 +161,61 @@ __device__ __forceinline__ void bitonic_merge(W (&v)[VT]) {
     }
 }
 
+// ------------------------------------------------ merges across lanes (DPP)
+// A register's value in the partner lane, through a DPP lane permutation
+// (CTRL: 0xB1 = lane ^ 1, 0x4E = lane ^ 2, 0x1B = lane ^ 3 within quads,
+// 0x141 = lane ^ 7 within half-rows of eight).
+template <int CTRL, typename W>
+__device__ __forceinline__ W dpp_partner(W x) {
+    if constexpr (sizeof(W) == 4) {
+        return (W)__builtin_amdgcn_mov_dpp((int)x, CTRL, 0xF, 0xF, false);
+    } else {
+        const uint64_t u = (uint64_t)x;
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)u, CTRL, 0xF, 0xF, false);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, false);
+        return (W)(((uint64_t)hi << 32) | lo);
+    }
+}
+
+// One compare-exchange stage between lanes: register i meets the partner
+// lane's register i (or VT-1-i when FLIP); the lane with `lower` set keeps
+// the smaller word.
+template <typename W, int VT, int CTRL, bool FLIP>
+__device__ __forceinline__ void lane_stage(W (&v)[VT], bool lower) {
+    W p[VT];
+#pragma unroll
+    for (int i = 0; i < VT; i++) p[i] = dpp_partner<CTRL>(v[FLIP ? VT - 1 - i : i]);
+#pragma unroll
+    for (int i = 0; i < VT; i++) {
+        const bool lt = p[i] < v[i];
+        const W lo = lt ? p[i] : v[i], hi = lt ? v[i] : p[i];
+        v[i] = lower ? lo : hi;
+    }
+}
+
+// Groups of G lanes (G = 2, 4, 8) each holding VT sorted words, the two
+// halves of a group sorted runs: merged into one run over the group, lane
+// blocked (the group's lane j ends with outputs j*VT .. j*VT+VT-1).  A
+// bitonic merge of the two runs: the first stage pairs element e with
+// element 2M-1-e (M = G/2*VT; the partner lane is lane ^ (G-1), register
+// VT-1-i), then half-cleaners at lane distances G/4 .. 1 and within the
+// registers.  No LDS, no barrier.
+template <typename W, int VT, int G>
+__device__ __forceinline__ void lane_merge(W (&v)[VT], int lane) {
+    static_assert(G == 2 || G == 4 || G == 8, "groups of 2, 4 or 8 lanes");
+    if constexpr (G == 2) {
+        lane_stage<W, VT, 0xB1, true>(v, !(lane & 1));
+    } else if constexpr (G == 4) {
+        lane_stage<W, VT, 0x1B, true>(v, !(lane & 2));
+        lane_stage<W, VT, 0xB1, false>(v, !(lane & 1));
+    } else {
+        lane_stage<W, VT, 0x141, true>(v, !(lane & 4));
+        lane_stage<W, VT, 0x4E, false>(v, !(lane & 2));
+        lane_stage<W, VT, 0xB1, false>(v, !(lane & 1));
+    }
+    bitonic_merge<W, VT>(v);
+}
+
 // Merge path (co-rank): of the first `diag` outputs of the stable merge of
 // sorted A[0..na) and B[0..nb), how many come from A.  Ties go to A.
 // Accessors read A[i] / B[j].

@@ -206,18 +206,24 @@ __device__ __forceinline__ void block_sort_levels(W* words, int* sp, W (&v)[VT],
 }
 
 // Sorts words[0..NT*VT) (padded layout) ascending in LDS: a register sorting
-// network per thread, then log2(NT) merge levels, fully unrolled.  Result in
-// blocked layout (thread t holds outputs t*VT .. t*VT+VT-1, also in LDS).
+// network per thread, three merge levels across groups of 2, 4 and 8 lanes
+// (DPP, in registers), then the remaining log2(NT) - 3 merge levels in LDS,
+// fully unrolled.  Result in blocked layout (thread t holds outputs
+// t*VT .. t*VT+VT-1, also in LDS).
 template <typename W, int NT, int VT>
 __device__ __forceinline__ void block_sort(W* words, int* sp) {
     static_assert((128 / (int)sizeof(W)) % VT == 0, "a VT-run must not straddle a pad word");
+    static_assert(NT >= 8, "lane merges need groups of eight threads");
     const int tid = threadIdx.x;
     const int base = lds_pad<W>(tid * VT);
     W v[VT];
 #pragma unroll
     for (int i = 0; i < VT; i++) v[i] = words[base + i];
     register_sort<W, VT>(v);
-    block_sort_levels<W, NT, VT, VT>(words, sp, v, tid, base);
+    lane_merge<W, VT, 2>(v, tid);
+    lane_merge<W, VT, 4>(v, tid);
+    lane_merge<W, VT, 8>(v, tid);
+    block_sort_levels<W, NT, VT, 8 * VT>(words, sp, v, tid, base);
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < VT; i++) words[base + i] = v[i];
