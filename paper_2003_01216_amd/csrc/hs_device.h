@@ -162,17 +162,30 @@ __device__ __forceinline__ void bitonic_merge(W (&v)[VT]) {
 }
 
 // ------------------------------------------------ merges across lanes (DPP)
-// A register's value in the partner lane, through a DPP lane permutation
-// (CTRL: 0xB1 = lane ^ 1, 0x4E = lane ^ 2, 0x1B = lane ^ 3 within quads,
-// 0x141 = lane ^ 7 within half-rows of eight).
-template <int CTRL, typename W>
-__device__ __forceinline__ W dpp_partner(W x) {
+// A 32-bit register's value in lane ^ MASK: a DPP lane permutation where
+// one exists (0xB1 = lane ^ 1, 0x4E = lane ^ 2, 0x1B = lane ^ 3 within
+// quads, 0x141 = lane ^ 7 within half-rows, 0x140 = lane ^ 15 within rows,
+// 0x128 = lane ^ 8 as a rotation by eight within rows), else a bit-mode
+// swizzle (xor mask within 32 lanes).
+template <int MASK>
+__device__ __forceinline__ int lane_xor32(int x) {
+    if constexpr (MASK == 1) return __builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, false);
+    else if constexpr (MASK == 2) return __builtin_amdgcn_mov_dpp(x, 0x4E, 0xF, 0xF, false);
+    else if constexpr (MASK == 3) return __builtin_amdgcn_mov_dpp(x, 0x1B, 0xF, 0xF, false);
+    else if constexpr (MASK == 7) return __builtin_amdgcn_mov_dpp(x, 0x141, 0xF, 0xF, false);
+    else if constexpr (MASK == 15) return __builtin_amdgcn_mov_dpp(x, 0x140, 0xF, 0xF, false);
+    else if constexpr (MASK == 8) return __builtin_amdgcn_mov_dpp(x, 0x128, 0xF, 0xF, false);
+    else return __builtin_amdgcn_ds_swizzle(x, 0x1F | (MASK << 10));
+}
+
+template <int MASK, typename W>
+__device__ __forceinline__ W lane_xor(W x) {
     if constexpr (sizeof(W) == 4) {
-        return (W)__builtin_amdgcn_mov_dpp((int)x, CTRL, 0xF, 0xF, false);
+        return (W)lane_xor32<MASK>((int)x);
     } else {
         const uint64_t u = (uint64_t)x;
-        const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)u, CTRL, 0xF, 0xF, false);
-        const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, false);
+        const uint32_t lo = (uint32_t)lane_xor32<MASK>((int)(uint32_t)u);
+        const uint32_t hi = (uint32_t)lane_xor32<MASK>((int)(uint32_t)(u >> 32));
         return (W)(((uint64_t)hi << 32) | lo);
     }
 }
@@ -180,11 +193,11 @@ __device__ __forceinline__ W dpp_partner(W x) {
 // One compare-exchange stage between lanes: register i meets the partner
 // lane's register i (or VT-1-i when FLIP); the lane with `lower` set keeps
 // the smaller word.
-template <typename W, int VT, int CTRL, bool FLIP>
+template <typename W, int VT, int MASK, bool FLIP>
 __device__ __forceinline__ void lane_stage(W (&v)[VT], bool lower) {
     W p[VT];
 #pragma unroll
-    for (int i = 0; i < VT; i++) p[i] = dpp_partner<CTRL>(v[FLIP ? VT - 1 - i : i]);
+    for (int i = 0; i < VT; i++) p[i] = lane_xor<MASK>(v[FLIP ? VT - 1 - i : i]);
 #pragma unroll
     for (int i = 0; i < VT; i++) {
         const bool lt = p[i] < v[i];
@@ -193,26 +206,26 @@ __device__ __forceinline__ void lane_stage(W (&v)[VT], bool lower) {
     }
 }
 
-// Groups of G lanes (G = 2, 4, 8) each holding VT sorted words, the two
+// Groups of G lanes (G = 2 .. 32) each holding VT sorted words, the two
 // halves of a group sorted runs: merged into one run over the group, lane
 // blocked (the group's lane j ends with outputs j*VT .. j*VT+VT-1).  A
 // bitonic merge of the two runs: the first stage pairs element e with
 // element 2M-1-e (M = G/2*VT; the partner lane is lane ^ (G-1), register
 // VT-1-i), then half-cleaners at lane distances G/4 .. 1 and within the
-// registers.  No LDS, no barrier.
+// registers.  No LDS memory, no barrier.
+template <typename W, int VT, int D>
+__device__ __forceinline__ void lane_half_cleaners(W (&v)[VT], int lane) {
+    if constexpr (D >= 1) {
+        lane_stage<W, VT, D, false>(v, !(lane & D));
+        lane_half_cleaners<W, VT, D / 2>(v, lane);
+    }
+}
+
 template <typename W, int VT, int G>
 __device__ __forceinline__ void lane_merge(W (&v)[VT], int lane) {
-    static_assert(G == 2 || G == 4 || G == 8, "groups of 2, 4 or 8 lanes");
-    if constexpr (G == 2) {
-        lane_stage<W, VT, 0xB1, true>(v, !(lane & 1));
-    } else if constexpr (G == 4) {
-        lane_stage<W, VT, 0x1B, true>(v, !(lane & 2));
-        lane_stage<W, VT, 0xB1, false>(v, !(lane & 1));
-    } else {
-        lane_stage<W, VT, 0x141, true>(v, !(lane & 4));
-        lane_stage<W, VT, 0x4E, false>(v, !(lane & 2));
-        lane_stage<W, VT, 0xB1, false>(v, !(lane & 1));
-    }
+    static_assert(G >= 2 && G <= 32 && (G & (G - 1)) == 0, "groups of 2 to 32 lanes");
+    lane_stage<W, VT, G - 1, true>(v, !(lane & (G / 2)));
+    lane_half_cleaners<W, VT, G / 4>(v, lane);
     bitonic_merge<W, VT>(v);
 }
 

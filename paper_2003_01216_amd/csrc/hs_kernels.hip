@@ -206,14 +206,14 @@ __device__ __forceinline__ void block_sort_levels(W* words, int* sp, W (&v)[VT],
 }
 
 // Sorts words[0..NT*VT) (padded layout) ascending in LDS: a register sorting
-// network per thread, three merge levels across groups of 2, 4 and 8 lanes
-// (DPP, in registers), then the remaining log2(NT) - 3 merge levels in LDS,
-// fully unrolled.  Result in blocked layout (thread t holds outputs
+// network per thread, four merge levels across groups of 2, 4, 8 and 16
+// lanes (lane permutations, in registers), then the remaining log2(NT) - 4
+// merge levels in LDS, fully unrolled.  Result in blocked layout (thread t holds outputs
 // t*VT .. t*VT+VT-1, also in LDS).
 template <typename W, int NT, int VT>
 __device__ __forceinline__ void block_sort(W* words, int* sp) {
     static_assert((128 / (int)sizeof(W)) % VT == 0, "a VT-run must not straddle a pad word");
-    static_assert(NT >= 8, "lane merges need groups of eight threads");
+    static_assert(NT >= 16, "lane merges need groups of sixteen threads");
     const int tid = threadIdx.x;
     const int base = lds_pad<W>(tid * VT);
     W v[VT];
@@ -223,7 +223,8 @@ __device__ __forceinline__ void block_sort(W* words, int* sp) {
     lane_merge<W, VT, 2>(v, tid);
     lane_merge<W, VT, 4>(v, tid);
     lane_merge<W, VT, 8>(v, tid);
-    block_sort_levels<W, NT, VT, 8 * VT>(words, sp, v, tid, base);
+    lane_merge<W, VT, 16>(v, tid);
+    block_sort_levels<W, NT, VT, 16 * VT>(words, sp, v, tid, base);
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < VT; i++) words[base + i] = v[i];
