@@ -94,10 +94,10 @@ bool merge_shape_ok(int64_t nt, int64_t vt) {
 }
 
 template <typename K, bool PAIRS>
-bool merge4_shape_ok(int64_t nt, int64_t vt) {
-#define X(KK, P, NT_, VT_) \
+bool merge4_shape_ok(int64_t nv, int64_t vt) {
+#define X(KK, P, NT_, VT_, J_) \
     if constexpr (std::is_same_v<K, KK> && PAIRS == P) \
-        if (nt == NT_ && vt == VT_) return true;
+        if (nv == NT_ * VT_ * J_ / 2 && vt == VT_) return true;
     HS_MERGE4_VARIANTS(X)
 #undef X
     return false;
@@ -108,7 +108,7 @@ bool shapes_ok(const Config& c) {
     const int64_t tn = c.tile / c.tile_vt, mn = c.merge_nv / c.merge_vt;
     if (!tile_shape_ok<K, PAIRS>(tn, c.tile_vt)) return false;
     if (c.fanin == 2) return merge_shape_ok<K, PAIRS>(mn, c.merge_vt);
-    return merge4_shape_ok<K, PAIRS>(mn, c.merge_vt);
+    return merge4_shape_ok<K, PAIRS>(c.merge_nv, c.merge_vt);
 }
 
 bool config_ok(int key_type_index, const Config& c) {
@@ -307,10 +307,10 @@ hipError_t merge_by_shape(const Config& c, const Work<K>& w, int64_t chunks, hip
 
 template <typename K, bool PAIRS>
 hipError_t merge4_by_shape(const Config& c, const Work<K>& w, int round, int64_t chunks, hipStream_t st) {
-    const int64_t nt = c.merge_nv / c.merge_vt, vt = c.merge_vt;
-#define X(KK, P, NT_, VT_) \
+    const int64_t nv = c.merge_nv, vt = c.merge_vt;
+#define X(KK, P, NT_, VT_, J_) \
     if constexpr (std::is_same_v<K, KK> && PAIRS == P) \
-        if (nt == NT_ && vt == VT_) return launch_merge4<KK, P, NT_, VT_>(w, round, chunks, st);
+        if (nv == NT_ * VT_ * J_ / 2 && vt == VT_) return launch_merge4<KK, P, NT_, VT_, J_>(w, round, chunks, st);
     HS_MERGE4_VARIANTS(X)
 #undef X
     return hipErrorInvalidValue;

@@ -831,10 +831,10 @@ __device__ __forceinline__ Chunk4<K> chunk4_of(const Work<K>& w, int round, int6
     return g;
 }
 
-template <typename K, bool PAIRS, int NT, int VT>
+template <typename K, bool PAIRS, int NT, int VT, int JOBS>
 struct Merge4Lds {
     using W = typename WordOf<K, PAIRS>::type;
-    static constexpr int S = NT * VT;
+    static constexpr int S = NT * VT * JOBS / 2;
     static constexpr int CAP = 2 * S;
     static constexpr int LOGICAL = CAP + 8 * VT + 32;  // four windows, sentinels, spacing, alignment
     static_assert((128 / sizeof(W)) % VT == 0, "a VT block fits one pad period");
@@ -842,9 +842,9 @@ struct Merge4Lds {
     uint32_t sv[PAIRS ? CAP : 1];
 };
 
-template <typename K, bool PAIRS, int NT, int VT>
+template <typename K, bool PAIRS, int NT, int VT, int JOBS>
 struct Merge4Loads {
-    static constexpr int CAP = 2 * NT * VT;
+    static constexpr int CAP = NT * VT * JOBS;
     RunsToLds<K, NT, CAP, 4> keys;
     RunsToLds<uint32_t, NT, PAIRS ? CAP : 4, 4> vals;
 
@@ -856,8 +856,8 @@ struct Merge4Loads {
 };
 
 // Windows to LDS (from loads issued earlier) plus their sentinels.
-template <typename K, bool PAIRS, int NT, int VT>
-__device__ __forceinline__ void stage4(Merge4Lds<K, PAIRS, NT, VT>& sm, const Merge4Loads<K, PAIRS, NT, VT>& ld,
+template <typename K, bool PAIRS, int NT, int VT, int JOBS>
+__device__ __forceinline__ void stage4(Merge4Lds<K, PAIRS, NT, VT, JOBS>& sm, const Merge4Loads<K, PAIRS, NT, VT, JOBS>& ld,
                                        const Chunk4<K>& g) {
     using W = typename WordOf<K, PAIRS>::type;
     const int tid = threadIdx.x;
@@ -876,10 +876,10 @@ __device__ __forceinline__ void stage4(Merge4Lds<K, PAIRS, NT, VT>& sm, const Me
 // The two merge levels and the store, on windows staged in LDS (the caller
 // has synchronised after stage4).  Ends with the LDS free for reuse only
 // after the caller's next barrier.
-template <typename K, bool PAIRS, int NT, int VT>
-__device__ __forceinline__ void merge4_chunk(Merge4Lds<K, PAIRS, NT, VT>& sm, const Chunk4<K>& g) {
+template <typename K, bool PAIRS, int NT, int VT, int JOBS>
+__device__ __forceinline__ void merge4_chunk(Merge4Lds<K, PAIRS, NT, VT, JOBS>& sm, const Chunk4<K>& g) {
     using W = typename WordOf<K, PAIRS>::type;
-    constexpr int S = NT * VT;
+    constexpr int S = NT * VT * JOBS / 2;
     constexpr int CAP = 2 * S;
     W* words = sm.words;
     const W wmax = WordMax<W>::v;
@@ -891,10 +891,10 @@ __device__ __forceinline__ void merge4_chunk(Merge4Lds<K, PAIRS, NT, VT>& sm, co
     const int x0 = g.at[0] & ~(VT - 1), y0 = g.at[2] & ~(VT - 1);
     const int jx = (o2 + VT - 1) / VT, jy = (c - o2 + VT - 1) / VT;
     {
-        W v[2][VT];
-        int dst[2];
+        W v[JOBS][VT];
+        int dst[JOBS];
 #pragma unroll
-        for (int h = 0; h < 2; h++) {
+        for (int h = 0; h < JOBS; h++) {
             const int j = tid + h * NT;
             if (j < jx + jy) {
                 const int y = j >= jx;  // arithmetic selects keep these in registers
@@ -908,7 +908,7 @@ __device__ __forceinline__ void merge4_chunk(Merge4Lds<K, PAIRS, NT, VT>& sm, co
         }
         __syncthreads();
 #pragma unroll
-        for (int h = 0; h < 2; h++) {
+        for (int h = 0; h < JOBS; h++) {
             const int j = tid + h * NT;
             if (j < jx + jy) {
 #pragma unroll
@@ -930,9 +930,9 @@ __device__ __forceinline__ void merge4_chunk(Merge4Lds<K, PAIRS, NT, VT>& sm, co
     // level 2: merge X' (o2 words) with Y' (c - o2) into logical [0, c)
     {
         const int jc = (c + VT - 1) / VT;
-        W v[2][VT];
+        W v[JOBS][VT];
 #pragma unroll
-        for (int h = 0; h < 2; h++) {
+        for (int h = 0; h < JOBS; h++) {
             const int j = tid + h * NT;
             if (j < jc) {
                 const int dt = j * VT;
@@ -942,7 +942,7 @@ __device__ __forceinline__ void merge4_chunk(Merge4Lds<K, PAIRS, NT, VT>& sm, co
         }
         __syncthreads();
 #pragma unroll
-        for (int h = 0; h < 2; h++) {
+        for (int h = 0; h < JOBS; h++) {
             const int j = tid + h * NT;
             if (j < jc) {
                 W* dst = words + lds_pad<W>(j * VT);
@@ -958,12 +958,12 @@ __device__ __forceinline__ void merge4_chunk(Merge4Lds<K, PAIRS, NT, VT>& sm, co
 }
 
 // One workgroup per chunk.
-template <typename K, bool PAIRS, int NT, int VT>
+template <typename K, bool PAIRS, int NT, int VT, int JOBS>
 __global__ __launch_bounds__(NT) void k_merge4(Work<K> w, int round, int64_t bound) {
-    __shared__ Merge4Lds<K, PAIRS, NT, VT> sm;
-    const Chunk4<K> g = chunk4_of<K, PAIRS, NT * VT, VT>(w, round, blockIdx.x, bound);
+    __shared__ Merge4Lds<K, PAIRS, NT, VT, JOBS> sm;
+    const Chunk4<K> g = chunk4_of<K, PAIRS, NT * VT * JOBS / 2, VT>(w, round, blockIdx.x, bound);
     if (!g.active) return;
-    Merge4Loads<K, PAIRS, NT, VT> ld;
+    Merge4Loads<K, PAIRS, NT, VT, JOBS> ld;
     ld.issue(g);
     stage4(sm, ld, g);
     __syncthreads();
@@ -1261,9 +1261,9 @@ hipError_t launch_part4(const Work<K>& w, int round, int64_t chunks_bound, hipSt
     return hipGetLastError();
 }
 
-template <typename K, bool PAIRS, int NT, int VT>
+template <typename K, bool PAIRS, int NT, int VT, int JOBS>
 hipError_t launch_merge4(const Work<K>& w, int round, int64_t chunks_bound, hipStream_t st) {
-    k_merge4<K, PAIRS, NT, VT><<<grid_of(chunks_bound), NT, 0, st>>>(w, round, chunks_bound);
+    k_merge4<K, PAIRS, NT, VT, JOBS><<<grid_of(chunks_bound), NT, 0, st>>>(w, round, chunks_bound);
     return hipGetLastError();
 }
 
@@ -1314,8 +1314,8 @@ HS_SMALL_VARIANTS(HS_INST_SMALL)
 #define HS_INST_MERGE(K, PAIRS, NT, VT) \
     template hipError_t launch_merge<K, PAIRS, NT, VT>(const Work<K>&, int64_t, hipStream_t);
 HS_MERGE_VARIANTS(HS_INST_MERGE)
-#define HS_INST_MERGE4(K, PAIRS, NT, VT) \
-    template hipError_t launch_merge4<K, PAIRS, NT, VT>(const Work<K>&, int, int64_t, hipStream_t);
+#define HS_INST_MERGE4(K, PAIRS, NT, VT, JOBS) \
+    template hipError_t launch_merge4<K, PAIRS, NT, VT, JOBS>(const Work<K>&, int, int64_t, hipStream_t);
 HS_MERGE4_VARIANTS(HS_INST_MERGE4)
 
 }  // namespace hs

@@ -25,12 +25,17 @@ struct ScanSpec {
 #define HS_MERGE_VARIANTS(X)                                                                 \
     X(int32_t, false, 256, 16) X(int32_t, false, 256, 32) X(int32_t, false, 512, 16)         \
     X(int64_t, false, 256, 16) X(int32_t, true, 256, 16)
-// Fan-in-4 merge: NT*VT = merge_nv (samples every merge_nv keys; a chunk
-// holds up to twice that).
-#define HS_MERGE4_VARIANTS(X) \
-    X(int32_t, false, 256, 16) X(int64_t, false, 256, 16) X(int32_t, true, 256, 16) \
-    X(int32_t, false, 512, 8) X(int32_t, false, 256, 8) X(int32_t, false, 128, 16) X(int32_t, true, 128, 16) \
-    X(int32_t, true, 256, 8) X(int64_t, false, 128, 16) X(int64_t, false, 256, 8)
+// Fan-in-4 merge: (key, pairs, threads NT, outputs per job VT, jobs per
+// thread and level JOBS); sampling stride S = NT*VT*JOBS/2 = merge_nv, a
+// workgroup holds up to 2S keys.  The first variant listed for a given
+// (S, VT) is the one used.
+#define HS_MERGE4_VARIANTS(X)                                                                \
+    X(int32_t, false, 512, 16, 1) X(int32_t, true, 256, 16, 1) X(int32_t, true, 512, 8, 1)   \
+    X(int64_t, false, 256, 16, 1) X(int64_t, false, 512, 8, 1)                               \
+    X(int32_t, false, 256, 16, 2) X(int64_t, false, 256, 16, 2) X(int32_t, true, 256, 16, 2) \
+    X(int32_t, false, 512, 8, 2) X(int32_t, false, 256, 8, 2) X(int32_t, false, 256, 16, 1)  \
+    X(int32_t, false, 128, 16, 2) X(int32_t, true, 128, 16, 2) X(int32_t, true, 256, 8, 2)   \
+    X(int64_t, false, 128, 16, 2) X(int64_t, false, 256, 8, 2)
 // Shapes usable by the whole-segment LDS sort (5-bit digit counters: VT <= 16).
 #define HS_SMALL_VARIANTS(X)                                                                 \
     X(int32_t, false, 512, 16) X(int32_t, false, 256, 16) X(int32_t, false, 256, 8) X(int32_t, false, 64, 4) \
@@ -67,7 +72,7 @@ template <typename K>
 hipError_t launch_collect(const Work<K>& w, int stage, hipStream_t st);
 template <typename K>
 hipError_t launch_part4(const Work<K>& w, int round, int64_t chunks_bound, hipStream_t st);
-template <typename K, bool PAIRS, int NT, int VT>
+template <typename K, bool PAIRS, int NT, int VT, int JOBS>
 hipError_t launch_merge4(const Work<K>& w, int round, int64_t chunks_bound, hipStream_t st);
 
 hipError_t launch_scan_i32(const ScanSpec& sp, int64_t len_bound, const int32_t* in, int32_t* out, int32_t* partial,
