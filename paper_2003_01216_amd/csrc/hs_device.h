@@ -121,6 +121,16 @@ __device__ __forceinline__ int lds_pad(int i) {
     constexpr unsigned per = 128 / sizeof(W);
     return i + (int)((unsigned)i / per);
 }
+// words[lds_pad(i)], with the byte offset formed as (i + (i >> p)) * size:
+// a shift and one add-shift instruction.
+template <typename W>
+__device__ __forceinline__ W lds_at_padded(const W* words, int i) {
+    constexpr unsigned per_log2 = sizeof(W) == 8 ? 4 : 5;  // 128-byte pad period
+    constexpr unsigned size_log2 = sizeof(W) == 8 ? 3 : 2;
+    const unsigned u = (unsigned)i;
+    const unsigned off = (u + (u >> per_log2)) << size_log2;
+    return *reinterpret_cast<const W*>(reinterpret_cast<const char*>(words) + off);
+}
 template <typename W>
 constexpr int lds_padded_size(int n) {
     return n + n / (128 / (int)sizeof(W)) + 1;
@@ -284,8 +294,12 @@ __device__ __forceinline__ int lds_corank(const W* lds, int sa, int sb, int diag
     for (int step = STEP0; step > 0; step >>= 1) {
         const int m = pos + step - 1;
         const int mc = m < hic ? m : hic;
-        const W a = lds[lds_pad<W>(sa + mc)];
-        const W b = lds[lds_pad<W>(kb - mc)];
+        W a = lds_at_padded(lds, sa + mc);
+        W b = lds_at_padded(lds, kb - mc);
+        // both reads are used unconditionally: otherwise the compiler moves
+        // them under a branch on m < hi, and every probe pays for the exec
+        // mask bookkeeping in scalar instructions
+        asm volatile("" : "+v"(a), "+v"(b));
         pos = (m < hi && !(b < a)) ? pos + step : pos;
     }
     return pos;

@@ -159,7 +159,7 @@ __device__ __forceinline__ void gather_merge(const W* words, int a0, int b0, int
         const bool sentinel = !from_a && i < x + gap;
         int idx = from_a ? (a0 + ai + i) : (b0 + bi + (VT - 1 - i));
         idx = sentinel ? a0 : idx;
-        W val = words[lds_pad<W>(idx)];
+        W val = lds_at_padded(words, idx);
         v[i] = sentinel ? WordMax<W>::v : val;
     }
     bitonic_merge<W, VT>(v);
@@ -172,7 +172,7 @@ __device__ __forceinline__ void gather_merge_full(const W* words, int a_first, i
 #pragma unroll
     for (int i = 0; i < VT; i++) {
         const int idx = i < x ? a_first + i : b_last - i;
-        v[i] = words[lds_pad<W>(idx)];
+        v[i] = lds_at_padded(words, idx);
     }
     bitonic_merge<W, VT>(v);
 }
@@ -188,8 +188,8 @@ __device__ __forceinline__ void block_sort_level(W* words, int* sp, W (&v)[VT], 
     __syncthreads();
     const int gb = (tid * VT) & ~(2 * L - 1);
     const int diag = tid * VT - gb;
-    auto A = [&](int i) { return words[lds_pad<W>(gb + i)]; };
-    auto B = [&](int i) { return words[lds_pad<W>(gb + L + i)]; };
+    auto A = [&](int i) { return lds_at_padded(words, gb + i); };
+    auto B = [&](int i) { return lds_at_padded(words, gb + L + i); };
     const int ai = merge_path_fixed<L>(diag, L, L, A, B);
     sp[tid] = ai;
     __syncthreads();
@@ -544,9 +544,9 @@ __global__ __launch_bounds__(NT) void k_tilesort(Work<K> w) {
         }
         __syncthreads();
         block_sort<W, NT, VT>(words, sp);
-        store_keys<K, NT, NV>(dk, cnt, [&](int q) { return word_key<K, PAIRS>(words[lds_pad<W>(q)]); });
+        store_keys<K, NT, NV>(dk, cnt, [&](int q) { return word_key<K, PAIRS>(lds_at_padded(words, q)); });
         if constexpr (PAIRS)
-            store_run<uint32_t, NT, NV>(dv, cnt, [&](int q) { return sv[pair_pos(words[lds_pad<W>(q)])]; });
+            store_run<uint32_t, NT, NV>(dv, cnt, [&](int q) { return sv[pair_pos(lds_at_padded(words, q))]; });
     }
 }
 
@@ -626,8 +626,8 @@ __global__ __launch_bounds__(NT) void k_merge(Work<K> w, int64_t bound) {
     const uint32_t* vb = PAIRS ? (odd ? w.svals : w.vals) + md.b : nullptr;
     K* dk = (odd ? w.keys : w.skeys) + md.out;
     uint32_t* dv = PAIRS ? (odd ? w.vals : w.svals) + md.out : nullptr;
-    auto A = [&](int x) { return words[lds_pad<W>(x)]; };
-    auto B = [&](int x) { return words[lds_pad<W>(na + x)]; };
+    auto A = [&](int x) { return lds_at_padded(words, x); };
+    auto B = [&](int x) { return lds_at_padded(words, na + x); };
     // the two input windows, side by side in LDS (16-byte bodies)
     {
         const K* const ks[2] = {pa, pb};
@@ -665,9 +665,9 @@ __global__ __launch_bounds__(NT) void k_merge(Work<K> w, int64_t bound) {
             if (q < c) words[lds_pad<W>(tid * VT + q)] = v[q];
     }
     __syncthreads();
-    store_keys<K, NT, NV>(dk, tot, [&](int q) { return word_key<K, PAIRS>(words[lds_pad<W>(q)]); });
+    store_keys<K, NT, NV>(dk, tot, [&](int q) { return word_key<K, PAIRS>(lds_at_padded(words, q)); });
     if constexpr (PAIRS)
-        store_run<uint32_t, NT, NV>(dv, tot, [&](int q) { return sv[pair_pos(words[lds_pad<W>(q)])]; });
+        store_run<uint32_t, NT, NV>(dv, tot, [&](int q) { return sv[pair_pos(lds_at_padded(words, q))]; });
 }
 
 // ------------------------------------------------- fan-in-4 merge rounds
@@ -922,9 +922,9 @@ __device__ __forceinline__ void merge4_chunk(Merge4Lds<K, PAIRS, NT, VT, JOBS>& 
     }
     if (o2 == 0 || o2 == c) {  // one side empty (a group short of four runs): X' or Y' is the result
         const int r = o2 == 0 ? y0 : x0;
-        store_keys<K, NT, CAP>(g.dk, c, [&](int q) { return word_key<K, PAIRS>(words[lds_pad<W>(r + q)]); });
+        store_keys<K, NT, CAP>(g.dk, c, [&](int q) { return word_key<K, PAIRS>(lds_at_padded(words, r + q)); });
         if constexpr (PAIRS)
-            store_run<uint32_t, NT, CAP>(g.dv, c, [&](int q) { return sm.sv[pair_pos(words[lds_pad<W>(r + q)])]; });
+            store_run<uint32_t, NT, CAP>(g.dv, c, [&](int q) { return sm.sv[pair_pos(lds_at_padded(words, r + q))]; });
         return;
     }
     // level 2: merge X' (o2 words) with Y' (c - o2) into logical [0, c)
@@ -952,9 +952,9 @@ __device__ __forceinline__ void merge4_chunk(Merge4Lds<K, PAIRS, NT, VT, JOBS>& 
         }
         __syncthreads();
     }
-    store_keys<K, NT, CAP>(g.dk, c, [&](int q) { return word_key<K, PAIRS>(words[lds_pad<W>(q)]); });
+    store_keys<K, NT, CAP>(g.dk, c, [&](int q) { return word_key<K, PAIRS>(lds_at_padded(words, q)); });
     if constexpr (PAIRS)
-        store_run<uint32_t, NT, CAP>(g.dv, c, [&](int q) { return sm.sv[pair_pos(words[lds_pad<W>(q)])]; });
+        store_run<uint32_t, NT, CAP>(g.dv, c, [&](int q) { return sm.sv[pair_pos(lds_at_padded(words, q))]; });
 }
 
 // One workgroup per chunk.
@@ -999,9 +999,9 @@ __global__ __launch_bounds__(NT) void k_small(Work<K> w, int64_t lo, int64_t hi)
             for (int q = m + tid; q < NV; q += NT) words[lds_pad<W>(q)] = WordMax<W>::v;
             __syncthreads();
             block_sort<W, NT, VT>(words, sp);
-            store_keys<K, NT, NV>(w.keys + a, m, [&](int q) { return word_key<K, PAIRS>(words[lds_pad<W>(q)]); });
+            store_keys<K, NT, NV>(w.keys + a, m, [&](int q) { return word_key<K, PAIRS>(lds_at_padded(words, q)); });
             if constexpr (PAIRS)
-                store_run<uint32_t, NT, NV>(w.vals + a, m, [&](int q) { return sv[pair_pos(words[lds_pad<W>(q)])]; });
+                store_run<uint32_t, NT, NV>(w.vals + a, m, [&](int q) { return sv[pair_pos(lds_at_padded(words, q))]; });
         } else {
             if (tid == 0 && m == 1) words[lds_pad<W>(0)] = make_word<K, PAIRS>(w.keys[a], 0);
             __syncthreads();
@@ -1009,13 +1009,13 @@ __global__ __launch_bounds__(NT) void k_small(Work<K> w, int64_t lo, int64_t hi)
         // bucket bounds of the segment, from its sorted keys
         uint64_t c = 0;
         if (m > 0) {
-            const K mn = word_key<K, PAIRS>(words[lds_pad<W>(0)]);
-            const K mx = word_key<K, PAIRS>(words[lds_pad<W>(m - 1)]);
+            const K mn = word_key<K, PAIRS>(lds_at_padded(words, 0));
+            const K mx = word_key<K, PAIRS>(lds_at_padded(words, m - 1));
             const DigitPlan<K> pl = make_digit_plan<K>(mn, mx);
 #pragma unroll
             for (int v = 0; v < VT; v++) {
                 const int q = tid * VT + v;
-                if (q < m) c += 1ull << (5 * digit_of(pl, word_key<K, PAIRS>(words[lds_pad<W>(q)])));
+                if (q < m) c += 1ull << (5 * digit_of(pl, word_key<K, PAIRS>(lds_at_padded(words, q))));
             }
         }
         uint32_t wd[5];
