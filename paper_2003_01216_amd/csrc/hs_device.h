@@ -46,8 +46,9 @@ struct Traits<int64_t> {
 template <typename K>
 struct DigitPlan {
     using U = typename Traits<K>::U;
-    U beta;    // (U)beta
-    U thr[9];  // b*p - 1, saturated
+    U beta;          // (U)beta
+    U thr[9];        // b*p - 1, saturated
+    uint64_t magic;  // 32-bit keys: ceil(2^64 / p) for p >= 10, 0 for p == 1
 };
 
 template <typename K>
@@ -64,17 +65,31 @@ __host__ __device__ inline DigitPlan<K> make_digit_plan(K mn, K mx) {
         // b*p - 1, or umax when b*p does not fit
         pl.thr[b - 1] = (p > umax / (U)b) ? umax : (U)((U)b * p - 1);
     }
+    // p = 10^k does not divide 2^64 for k >= 1, so floor((2^64-1)/p) + 1 is
+    // ceil(2^64/p)
+    pl.magic = p == 1 ? 0 : ~0ull / (uint64_t)p + 1;
     return pl;
 }
 
+// The key's decimal digit floor(u / p), u = k - beta.  32-bit keys: the high
+// word of u * ceil(2^64 / p), exact for every u < 2^32 since p < 2^32 (with
+// M = 2^64/p + e, 0 < e < 1, u*M/2^64 exceeds u/p by less than 2^-32 < 1/p,
+// too little to cross the next integer); two multiply instructions.  64-bit
+// keys: nine compares against the saturated thresholds b*p - 1.
 template <typename K>
 __device__ __forceinline__ int digit_of(const DigitPlan<K>& pl, K k) {
     using U = typename Traits<K>::U;
     U u = (U)k - pl.beta;
-    int d = 0;
+    if constexpr (sizeof(U) == 4) {
+        const uint64_t m = pl.magic;
+        const uint64_t mid = (uint64_t)u * (uint32_t)(m >> 32) + (uint32_t)(((uint64_t)u * (uint32_t)m) >> 32);
+        return m ? (int)(mid >> 32) : (int)u;
+    } else {
+        int d = 0;
 #pragma unroll
-    for (int b = 0; b < 9; b++) d += (u > pl.thr[b]) ? 1 : 0;
-    return d;
+        for (int b = 0; b < 9; b++) d += (u > pl.thr[b]) ? 1 : 0;
+        return d;
+    }
 }
 
 // ----------------------------------------------------------------- sort words
