@@ -413,7 +413,12 @@ __global__ __launch_bounds__(kHistNT) void k_scatter(Work<K> w) {
     __shared__ uint32_t sv[PAIRS ? HT : 1];
     __shared__ uint8_t sd[HT];
     __shared__ uint32_t red[NT / kWave][5];
-    __shared__ int64_t dbase[10];
+    // each thread's staging start per bucket, read back by digit: an indexed
+    // LDS read is cheaper than selecting among registers, but the 5 KB cost
+    // 64-bit keys and pairs a resident workgroup, so they select instead
+    constexpr bool kOffsLds = sizeof(K) == 4 && !PAIRS;
+    __shared__ int32_t dbase[10];  // element index (n < 2^31) of bucket d's run, minus its staging start
+    __shared__ uint16_t offs[kOffsLds ? 10 : 1][NT];
     const int t = blockIdx.x;
     const TileDesc td = w.tiles[t];
     if (td.cnt == 0) return;
@@ -428,7 +433,7 @@ __global__ __launch_bounds__(kHistNT) void k_scatter(Work<K> w) {
     if constexpr (PAIRS) load_run<uint32_t, NT, HT>(w.vals + base, cnt, [&](int q, uint32_t v) { sv[q] = v; });
     if (tid < 10) {
         const int64_t pbase = 10 * (int64_t)(t - i);
-        dbase[tid] = td.seg_base + w.pos[pbase + (int64_t)tid * nt + i] - w.pos[pbase];
+        dbase[tid] = (int32_t)(td.seg_base + w.pos[pbase + (int64_t)tid * nt + i] - w.pos[pbase]);
     }
     __syncthreads();
     // 2. blocked: digit and rank among this thread's own keys, packed as
@@ -462,11 +467,19 @@ __global__ __launch_bounds__(kHistNT) void k_scatter(Work<K> w) {
         wd[m] += lo | (hi << 16);
     }
     // 5. stage grouped by bucket
+    if constexpr (kOffsLds) {
+#pragma unroll
+        for (int m = 0; m < 5; m++) {
+            offs[2 * m][tid] = (uint16_t)(wd[m] & 0xFFFFu);
+            offs[2 * m + 1][tid] = (uint16_t)(wd[m] >> 16);
+        }
+    }
 #pragma unroll
     for (int v = 0; v < VT; v++) {
         const uint32_t d = pk[v] & 15u;
         if (d < 10) {
-            const int sp = (int)(field16(wd, (int)d) + (pk[v] >> 4));
+            const uint32_t start = kOffsLds ? (uint32_t)offs[kOffsLds ? d : 0][tid] : field16(wd, (int)d);
+            const int sp = (int)(start + (pk[v] >> 4));
             sk[lds_pad<K>(sp)] = key[v];
             sd[sp] = (uint8_t)d;
             if constexpr (PAIRS) sv[sp] = val[v];
@@ -479,7 +492,7 @@ __global__ __launch_bounds__(kHistNT) void k_scatter(Work<K> w) {
             st = (d == tid) ? r2 : st;
             r2 += (tot[d >> 1] >> ((d & 1) * 16)) & 0xFFFFu;
         }
-        dbase[tid] -= (int64_t)st;
+        dbase[tid] -= (int32_t)st;
     }
     __syncthreads();
     // 6. coalesced runs out to the buckets (a per-bucket loop of 16-byte
@@ -488,7 +501,7 @@ __global__ __launch_bounds__(kHistNT) void k_scatter(Work<K> w) {
     for (int j = 0; j < VT; j++) {
         const int q = j * NT + tid;
         if (q < cnt) {
-            const int64_t dst = dbase[sd[q]] + q;
+            const uint32_t dst = (uint32_t)(dbase[sd[q]] + q);
             w.skeys[dst] = sk[lds_pad<K>(q)];
             if constexpr (PAIRS) w.svals[dst] = sv[q];
         }
