@@ -151,22 +151,20 @@ constexpr int lds_padded_size(int n) {
     return n + n / (128 / (int)sizeof(W)) + 1;
 }
 
-// Bitonic sorting network over VT registers (VT a power of two), fully
-// unrolled: log2(VT)*(log2(VT)+1)/2 stages of VT/2 compare-exchanges.
+// Sorting network over VT registers (VT a power of two), fully unrolled:
+// Batcher's odd-even merge sort, every comparator ascending (191
+// compare-exchanges for 32 registers, where a bitonic sort takes 240).
 template <typename W, int VT>
 __device__ __forceinline__ void register_sort(W (&v)[VT]) {
 #pragma unroll
-    for (int k = 2; k <= VT; k <<= 1) {
+    for (int p = 1; p < VT; p <<= 1) {
 #pragma unroll
-        for (int j = k >> 1; j > 0; j >>= 1) {
+        for (int k = p; k >= 1; k >>= 1) {
 #pragma unroll
-            for (int i = 0; i < VT; i++) {
-                const int l = i ^ j;
-                if (l > i) {
-                    if ((i & k) == 0)
-                        cas_up(v[i], v[l]);
-                    else
-                        cas_up(v[l], v[i]);
+            for (int j = k % p; j + k < VT; j += 2 * k) {
+#pragma unroll
+                for (int i = 0; i < k; i++) {
+                    if (i < VT - j - k && (i + j) / (2 * p) == (i + j + k) / (2 * p)) cas_up(v[i + j], v[i + j + k]);
                 }
             }
         }
