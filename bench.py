@@ -40,19 +40,29 @@ def log(*a):
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 TRAFFIC_RECORD = os.path.join(HERE, "profiles", "sort_i32_2e28_hbm_bytes.md")
-KERNEL_SOURCE = os.path.join(HERE, "paper_2003_01216_amd", "csrc", "hs_kernels.hip")
+KERNEL_SOURCES = ["hs_kernels.hip", "hs_device.h", "hs_io.h", "hs_work.h", "hs_launch.h"]
+
+
+def kernel_sources_sha256():
+    """Hash of the device sources the kernels are compiled from."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(HERE, "paper_2003_01216_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def measured_traffic():
     """HBM bytes per dispatch of the dominant kernel from the committed FETCH_SIZE/WRITE_SIZE record,
     or None when the kernel source changed since the counters were taken."""
-    import hashlib
     import re
 
     try:
         text = open(TRAFFIC_RECORD).read()
         rec = json.loads(re.search(r"```json\n(.*?)\n```", text, re.S).group(1))
-        sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+        sha = kernel_sources_sha256()
     except (OSError, AttributeError, ValueError):
         return None
     if rec.get("kernels_source_sha256") != sha:
