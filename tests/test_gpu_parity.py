@@ -307,3 +307,27 @@ def test_2e28_stable_pairs_properties(hs):
     assert np.array_equal(k[gv], gk)  # every output pair is an input pair
     same = gk[1:] == gk[:-1]
     assert np.all(gv[1:][same] > gv[:-1][same])  # input order kept inside equal keys
+
+
+def test_max_keys_properties_and_samples(hs, orc):
+    """The largest array one call accepts (2^31 - 1 int32 keys, about a billion
+    per decimal bucket: eight fan-in-4 rounds with runs up to 2^30 keys).
+    Checked on the device (order, 64-bit sum, count of one value) and by
+    order statistics the oracle computes one by one."""
+    n = 2**31 - 1
+    k = W.uniform_i32(n, 9)
+    say("2^31 - 1 uniform keys")
+    t = dev(k)
+    s = torch.empty(hs.scratch_bytes(hs.KEYS_I32, n), dtype=torch.uint8, device="cuda")
+    hs.hsort_keys(t, scratch=s)
+    hs.hsort_check(s)
+    del s
+    assert bool(torch.all(t[1:] >= t[:-1]).item())
+    assert int(t.sum(dtype=torch.int64).item()) == int(k.sum(dtype=np.int64))
+    probe = int(k[12345])
+    assert int((t == probe).sum().item()) == int(np.count_nonzero(k == probe))
+    r = np.random.default_rng(9)
+    for j in np.concatenate([[0, n - 1], r.integers(0, n, 4)]):
+        x = int(t[int(j)].item())
+        lt, le = orc.count_lt_le(k, x)
+        assert lt <= j < le, (j, x, lt, le)
