@@ -102,20 +102,32 @@ def test_fifo_admission(orc):
     assert taken == sorted(taken) and sorted(taken) == list(range(40))
 
 
+def _wait_running(ex, k, timeout=10.0):
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < timeout:
+        with ex.lock:
+            if ex.running >= k:
+                return
+        time.sleep(0.001)
+    raise AssertionError(f"executor never reached {k} running batches")
+
+
 def test_arrivals_during_flight_overlap(orc):
     rng = np.random.default_rng(3)
-    ex = FakeExecutor(orc, delay=0.05)
+    ex = FakeExecutor(orc, delay=0.2)
     with serve.SortServer(hbm_budget=1 << 30, streams=2, executor=ex) as srv:
-        futs = []
-        for i in range(10):
-            futs.append(srv.submit(tagged(i, 500, rng)))
-            time.sleep(0.02)  # arrive while earlier batches are in flight
+        futs = [srv.submit(tagged(0, 500, rng))]
+        _wait_running(ex, 1)  # the first request is on one stream...
+        futs.append(srv.submit(tagged(1, 500, rng)))
+        _wait_running(ex, 2)  # ...the second on the other
+        # both streams busy: these four wait and leave together in one batch
+        futs += [srv.submit(tagged(i, 500, rng)) for i in range(2, 6)]
         for f in futs:
             f.result(timeout=60)
         st = srv.stats()
     assert ex.max_running == 2
     assert st["overlap_s"] > 0
-    assert max(len(b) for b in ex.batches) > 1  # later arrivals were batched together
+    assert [2, 3, 4, 5] in ex.batches  # arrivals during flight were batched together
 
 
 def test_close_drains_and_rejects_new(orc):
