@@ -773,10 +773,13 @@ __global__ __launch_bounds__(256) void k_part4(Work<K> w, int round, int64_t bou
 }
 
 // A workgroup merges the keys between two consecutive split points (at most
-// S of X and S of Y, S = NT*VT) in two LDS levels: W0+W1 -> X' and W2+W3 ->
-// Y', then X'+Y'.  Work is counted in jobs of VT outputs (one co-rank and
-// one window merge each); a thread runs up to two jobs per level, so the
-// cost follows the chunk's size (1 to 2S keys), not its capacity.
+// S of X and S of Y) in two LDS levels: W0+W1 -> X' and W2+W3 -> Y', then
+// X'+Y'.  Work is counted in jobs of VT outputs (one co-rank and one window
+// merge each); a thread runs up to JOBS jobs per level (S = NT*VT*JOBS/2, so
+// that NT*JOBS jobs cover the largest chunk, 2S keys), and the cost follows
+// the chunk's size (1 to 2S keys), not its capacity.  With one job per
+// thread the same LDS carries twice the threads: more waves to hide the LDS
+// round trips of the co-rank searches.
 //
 // LDS is padded (one word per 128 bytes: neighbouring threads' co-ranks lie
 // about VT/2 words apart, and the pad spreads them over the banks).  Every

@@ -27,15 +27,12 @@ struct ScanSpec {
     X(int64_t, false, 256, 16) X(int32_t, true, 256, 16)
 // Fan-in-4 merge: (key, pairs, threads NT, outputs per job VT, jobs per
 // thread and level JOBS); sampling stride S = NT*VT*JOBS/2 = merge_nv, a
-// workgroup holds up to 2S keys.  The first variant listed for a given
-// (S, VT) is the one used.
+// workgroup holds up to 2S keys.  One variant per (S, VT): 4096/16, 2048/16
+// and 2048/8 for every key kind.
 #define HS_MERGE4_VARIANTS(X)                                                                \
-    X(int32_t, false, 512, 16, 1) X(int32_t, true, 256, 16, 1) X(int32_t, true, 512, 8, 1)   \
-    X(int64_t, false, 256, 16, 1) X(int64_t, false, 512, 8, 1)                               \
-    X(int32_t, false, 256, 16, 2) X(int64_t, false, 256, 16, 2) X(int32_t, true, 256, 16, 2) \
-    X(int32_t, false, 512, 8, 2) X(int32_t, false, 256, 8, 2) X(int32_t, false, 256, 16, 1)  \
-    X(int32_t, false, 128, 16, 2) X(int32_t, true, 128, 16, 2) X(int32_t, true, 256, 8, 2)   \
-    X(int64_t, false, 128, 16, 2) X(int64_t, false, 256, 8, 2)
+    X(int32_t, false, 512, 16, 1) X(int32_t, false, 256, 16, 1) X(int32_t, false, 256, 8, 2)  \
+    X(int64_t, false, 256, 16, 2) X(int64_t, false, 256, 16, 1) X(int64_t, false, 512, 8, 1)  \
+    X(int32_t, true, 256, 16, 2) X(int32_t, true, 256, 16, 1) X(int32_t, true, 512, 8, 1)
 // Shapes usable by the whole-segment LDS sort (5-bit digit counters: VT <= 16).
 #define HS_SMALL_VARIANTS(X)                                                                 \
     X(int32_t, false, 512, 16) X(int32_t, false, 256, 16) X(int32_t, false, 256, 8) X(int32_t, false, 64, 4) \
