@@ -42,6 +42,14 @@ struct Vec16<int64_t> {
     static __device__ __forceinline__ int64_t get(const longlong2& v, int e) { return e == 0 ? v.x : v.y; }
 };
 
+// A computed address of global memory, typed so that loads through it are
+// global loads (an integer cast to a generic pointer gives flat loads, which
+// also count against the LDS wait counter).
+template <typename V>
+__device__ __forceinline__ const V* global_at(uintptr_t a) {
+    return (const V*)reinterpret_cast<const __attribute__((address_space(1))) V*>(a);
+}
+
 // Elements of [0, cnt) before the first 16-byte boundary of src.
 template <typename T>
 __device__ __forceinline__ int head_len(const T* src, int cnt) {
@@ -114,7 +122,7 @@ __device__ __forceinline__ void load_runs(const T* const (&src)[NR], const int (
             uintptr_t b = vbase[0];
 #pragma unroll
             for (int r = 1; r < NR; r++) b = v >= pre[r] ? vbase[r] : b;
-            x[j] = reinterpret_cast<const V*>(b)[v];
+            x[j] = global_at<V>(b)[v];
         }
     }
     T hv[NR], tv[NR];
@@ -185,7 +193,7 @@ struct RunsToLds {
                 uintptr_t b = vbase[0];
 #pragma unroll
                 for (int r = 1; r < NR; r++) b = v >= pre[r] ? vbase[r] : b;
-                x[j] = reinterpret_cast<const V*>(b)[v];
+                x[j] = global_at<V>(b)[v];
             }
         }
 #pragma unroll

@@ -802,33 +802,29 @@ struct Chunk4 {
 
 template <typename K, bool PAIRS, int S, int VT>
 __device__ __forceinline__ Chunk4<K> chunk4_of(const Work<K>& w, int round, int64_t item, int64_t bound) {
-    Chunk4<K> g;
-    g.active = false;
+    // Straight-line code: the split point, its successor and every kernel
+    // argument are read before the first decision, so the workgroup waits for
+    // one round trip to memory, not for a chain of them, before its loads.
     const Split4 r0 = w.ssorted[item];
-    if (!(r0.flags & kActive)) return g;
-    const bool last = item + 1 - r0.first == r0.items;
     const Split4 nx1 = w.ssorted[item + 1 < bound ? item + 1 : item];
-    int64_t rank_end = 0;
-#pragma unroll
-    for (int k = 0; k < 4; k++) {
-        const int e = last ? r0.len[k] : nx1.s[k];
-        g.c[k] = e - r0.s[k];
-        rank_end += last ? r0.len[k] : 0;
-    }
-    if (!last) rank_end = nx1.rank;
-    const int c = g.c[0] + g.c[1] + g.c[2] + g.c[3];
-    // a split point inconsistent with its successor would make the windows
-    // run past their runs: flag it and do nothing (never observed; cheap)
-    if (c != rank_end - r0.rank || g.c[0] < 0 || g.c[1] < 0 || g.c[2] < 0 || g.c[3] < 0 || g.c[0] + g.c[1] > S ||
-        g.c[2] + g.c[3] > S) {
-        if (threadIdx.x == 0) atomicOr(w.err, 2u);
-        return g;
-    }
-    if (c == 0) return g;
-    const int64_t L = (int64_t)w.tile << (2 * round);
     const bool odd = r0.flags & kFromScratch;
     const K* sk = (odd ? w.skeys : w.keys) + r0.base;
     const uint32_t* svv = PAIRS ? (odd ? w.svals : w.vals) + r0.base : nullptr;
+    const int64_t L = (int64_t)w.tile << (2 * round);
+    Chunk4<K> g;
+    const bool last = item + 1 - r0.first == r0.items;
+    int64_t rank_end = last ? 0 : nx1.rank;
+    bool neg = false;
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        g.c[k] = (last ? r0.len[k] : nx1.s[k]) - r0.s[k];
+        rank_end += last ? r0.len[k] : 0;
+        neg |= g.c[k] < 0;
+    }
+    const int c = g.c[0] + g.c[1] + g.c[2] + g.c[3];
+    // a split point inconsistent with its successor would make the windows
+    // run past their runs: flag it and do nothing (never observed; cheap)
+    const bool bad = c != rank_end - r0.rank || neg || g.c[0] + g.c[1] > S || g.c[2] + g.c[3] > S;
     g.dk = (odd ? w.keys : w.skeys) + r0.base + r0.rank;
     g.dv = PAIRS ? (odd ? w.vals : w.svals) + r0.base + r0.rank : nullptr;
     // window r at logical at[r] (>= 1; body vectors on multiples of 4), then
@@ -843,7 +839,13 @@ __device__ __forceinline__ Chunk4<K> chunk4_of(const Work<K>& w, int round, int6
         g.at[r] = ((cur + h + 3) & ~3) - h;
         cur = g.at[r] + g.c[r] + 2 * VT + 4;
     }
-    g.active = true;
+    // the addresses are needed only past the branch below, but forming them
+    // here keeps their argument reads in the first round trip
+    asm volatile("" ::"s"(g.ks[0]), "s"(g.ks[3]), "s"(g.dk));
+    if constexpr (PAIRS) asm volatile("" ::"s"(g.vs[0]), "s"(g.dv));
+    const bool act = r0.flags & kActive;
+    if (act && bad && threadIdx.x == 0) atomicOr(w.err, 2u);
+    g.active = act && !bad && c != 0;
     return g;
 }
 
