@@ -764,7 +764,7 @@ __global__ __launch_bounds__(256) void k_part4(Work<K> w, int round, int64_t bou
             d.first = (int32_t)(w.msp[j] + gbase / S);
             d.items = (int32_t)(nx + ny);
             d.nx = (int32_t)nx;
-            d.flags = kActive | (odd ? kFromScratch : 0);
+            d.flags = kActive | (odd ? kFromScratch : 0) | round_tag(round);
             w.ssorted[d.first + pos / S + before] = d;
             return;
         }
@@ -822,9 +822,14 @@ __device__ __forceinline__ Chunk4<K> chunk4_of(const Work<K>& w, int round, int6
         neg |= g.c[k] < 0;
     }
     const int c = g.c[0] + g.c[1] + g.c[2] + g.c[3];
-    // a split point inconsistent with its successor would make the windows
-    // run past their runs: flag it and do nothing (never observed; cheap)
-    const bool bad = c != rank_end - r0.rank || neg || g.c[0] + g.c[1] > S || g.c[2] + g.c[3] > S;
+    // a split point inconsistent with its successor, or either of them left
+    // over from an earlier round (sorted runs map every sample to its own
+    // slot, so neither happens), would make the windows run past their runs:
+    // flag it and do nothing
+    const int32_t tag = round_tag(round), tagmask = ~(int32_t)0xFF;
+    const bool stale = (r0.flags & tagmask) != tag || (!last && (nx1.flags & (tagmask | kActive)) != (tag | kActive));
+    const bool bad =
+        stale || c != rank_end - r0.rank || neg || g.c[0] + g.c[1] > S || g.c[2] + g.c[3] > S;
     g.dk = (odd ? w.keys : w.skeys) + r0.base + r0.rank;
     g.dv = PAIRS ? (odd ? w.vals : w.svals) + r0.base + r0.rank : nullptr;
     // window r at logical at[r] (>= 1; body vectors on multiples of 4), then

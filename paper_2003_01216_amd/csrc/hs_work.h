@@ -55,8 +55,11 @@ struct Split4 {
     int32_t first;  // flat index of the group's first chunk
     int32_t items;  // chunks of the group (= split points)
     int32_t nx;     // split points sampled from merge(R0, R1); the rest from merge(R2, R3)
-    int32_t flags;  // kActive | kFromScratch
+    int32_t flags;  // kActive | kFromScratch | round_tag(round)
 };
+// A split point records the round that wrote it (bits 8 and up), so that a
+// slot left over from an earlier round is recognised instead of trusted.
+__host__ __device__ constexpr int32_t round_tag(int round) { return (round + 1) << 8; }
 
 template <typename K>
 struct Work {
