@@ -302,24 +302,57 @@ __device__ __forceinline__ void block_minmax(T& mn, T& mx, T* rmn, T* rmx) {
     __syncthreads();
 }
 
+// Per tile: min and max, and the bucket counts under the tile's own digit
+// plan when the tile holds no negative key (beta 0, p the largest power of
+// ten not above the tile's max).  If the segment's plan has beta 0 as well,
+// it has the same p or a larger one, so the histogram pass only has to fix
+// the tiles whose p is smaller (every key then has digit 0) instead of
+// reading the keys again.  Keys are read strided (thread t: t, t + NT, ...),
+// coalesced per wave, and kept in registers for the count.
 template <typename K>
 __global__ __launch_bounds__(kHistNT) void k_range(Work<K> w) {
     __shared__ K rmn[kHistNT / kWave], rmx[kHistNT / kWave];
+    __shared__ uint32_t red[kHistNT / kWave][5];
     const int t = blockIdx.x;
     const TileDesc td = w.tiles[t];
     if (td.cnt == 0) return;
     const int tid = threadIdx.x;
     const int cnt = td.cnt;
-    K mn = Traits<K>::kMax, mx = Traits<K>::kMin;
-    load_run<K, kHistNT, kHistTile>(w.keys + td.base, cnt, [&](int, K k) {
-        mn = k < mn ? k : mn;
-        mx = k > mx ? k : mx;
-    });
+    const K* src = w.keys + td.base;
+    const K k0 = src[0];
+    K ks[kHistVT];
+#pragma unroll
+    for (int v = 0; v < kHistVT; v++) {
+        const int q = tid + v * kHistNT;
+        ks[v] = q < cnt ? src[q] : k0;  // k0 leaves the min and max unchanged
+    }
+    K mn = ks[0], mx = ks[0];
+#pragma unroll
+    for (int v = 1; v < kHistVT; v++) {
+        mn = ks[v] < mn ? ks[v] : mn;
+        mx = ks[v] > mx ? ks[v] : mx;
+    }
     block_minmax<K, kHistNT>(mn, mx, rmn, rmx);
     if (tid == 0) {
         w.tmin[t] = mn;
         w.tmax[t] = mx;
     }
+    if (mn < 0) {
+        if (tid == 0) w.tp[t] = 0;
+        return;
+    }
+    const DigitPlan<K> pl = make_digit_plan<K>(K(0), mx);
+    uint64_t c = 0;  // at most kHistVT = 16 keys per thread: fits the 5-bit fields
+#pragma unroll
+    for (int v = 0; v < kHistVT; v++) {
+        const int q = tid + v * kHistNT;
+        c += (uint64_t)(q < cnt) << (5 * digit_of(pl, ks[v]));
+    }
+    uint32_t wd[5];
+    unpack5(c, wd);
+    block_sum5<kHistNT>(wd, red);
+    if (tid < 10) w.counts[10 * (int64_t)(t - td.idx) + tid * td.nt + td.idx] = field16(wd, tid);
+    if (tid == 0) w.tp[t] = (uint64_t)pl.thr[0] + 1;
 }
 
 // Per large segment: min/max over its tiles, then the decimal digit plan.
@@ -349,21 +382,55 @@ __global__ __launch_bounds__(1024) void k_plans(Work<K> w) {
 // minor), so one exclusive scan of the whole array yields every tile's write
 // offset inside its bucket.
 template <typename K>
-__global__ __launch_bounds__(kHistNT) void k_hist(Work<K> w) {
+__global__ __launch_bounds__(kHistNT) void k_hist(Work<K> w, int64_t tiles_bound) {
     __shared__ uint32_t red[kHistNT / kWave][5];
-    const int t = blockIdx.x;
-    const TileDesc td = w.tiles[t];
-    if (td.cnt == 0) return;
+    __shared__ int64_t slow[kHistNT];
+    __shared__ int nslow;
     const int tid = threadIdx.x;
-    const int cnt = td.cnt;
-    const DigitPlan<K> pl = w.plans[td.seg];
-    uint64_t c = 0;  // a thread sees at most 16 + 3 + 3 keys: fits the 5-bit fields
-    load_run<K, kHistNT, kHistTile>(w.keys + td.base, cnt,
-                                    [&](int, K k) { c += 1ull << (5 * digit_of(pl, k)); });
-    uint32_t wd[5];
-    unpack5(c, wd);
-    block_sum5<kHistNT>(wd, red);
-    if (tid < 10) w.counts[10 * (int64_t)(t - td.idx) + tid * td.nt + td.idx] = field16(wd, tid);
+    const int64_t G = gridDim.x;
+    // A fixed grid strides over the tiles (most need no work here, and a
+    // workgroup per tile would cost a launch of every one of them).  This
+    // workgroup's tiles are blockIdx.x + i*G, checked NT at a time, one per
+    // thread; the ones whose keys must be counted are listed in LDS and
+    // counted by the whole workgroup, one after the other.
+    for (int64_t i0 = 0; blockIdx.x + i0 * G < tiles_bound; i0 += kHistNT) {
+        if (tid == 0) nslow = 0;
+        __syncthreads();
+        const int64_t t = blockIdx.x + (i0 + tid) * G;
+        if (t < tiles_bound) {
+            const TileDesc td = w.tiles[t];
+            if (td.cnt > 0) {
+                const DigitPlan<K> pl = w.plans[td.seg];
+                const uint64_t tp = w.tp[t];
+                if (pl.beta == 0 && tp != 0) {
+                    // counted by k_range under the tile's own plan: the
+                    // segment's plan, or one with a smaller p, and then every
+                    // key has digit 0
+                    if (tp != (uint64_t)pl.thr[0] + 1) {
+                        uint32_t* out = w.counts + 10 * (t - td.idx) + td.idx;
+                        out[0] = (uint32_t)td.cnt;
+                        for (int d = 1; d < 10; d++) out[d * td.nt] = 0;
+                    }
+                } else {
+                    slow[atomicAdd(&nslow, 1)] = t;
+                }
+            }
+        }
+        __syncthreads();
+        const int ns = nslow;
+        for (int k = 0; k < ns; k++) {
+            const TileDesc td = w.tiles[slow[k]];
+            const DigitPlan<K> pl = w.plans[td.seg];
+            uint64_t c = 0;  // a thread sees at most 16 + 3 + 3 keys: fits the 5-bit fields
+            load_run<K, kHistNT, kHistTile>(w.keys + td.base, td.cnt,
+                                            [&](int, K k) { c += 1ull << (5 * digit_of(pl, k)); });
+            uint32_t wd[5];
+            unpack5(c, wd);
+            block_sum5<kHistNT>(wd, red);
+            if (tid < 10) w.counts[10 * (slow[k] - td.idx) + tid * td.nt + td.idx] = field16(wd, tid);
+        }
+        __syncthreads();
+    }
 }
 
 // Bucket table: start and size of each of the ten buckets of every segment,
@@ -1231,7 +1298,7 @@ hipError_t launch_plans(const Work<K>& w, hipStream_t st) {
 
 template <typename K>
 hipError_t launch_hist(const Work<K>& w, int64_t tiles_bound, hipStream_t st) {
-    k_hist<K><<<grid_of(tiles_bound), kHistNT, 0, st>>>(w);
+    k_hist<K><<<grid_of(tiles_bound < kHistGrid ? tiles_bound : kHistGrid), kHistNT, 0, st>>>(w, tiles_bound);
     return hipGetLastError();
 }
 

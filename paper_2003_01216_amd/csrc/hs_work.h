@@ -11,6 +11,7 @@ namespace hs {
 constexpr int kHistNT = 256;
 constexpr int kHistVT = 16;
 constexpr int kHistTile = kHistNT * kHistVT;
+constexpr int64_t kHistGrid = 8192;  // workgroups of the histogram pass (it strides over the tiles)
 
 // One histogram tile of a large segment (range, histogram and scatter read it).
 struct TileDesc {
@@ -44,9 +45,9 @@ constexpr int32_t kLastChunk = 4;  // last chunk of its pair of runs
 
 // Fan-in-4 merge rounds: a split point of a group of four runs R0..R3 (the
 // first `rank` outputs of the group's stable merge are R0[0..s0), R1[0..s1),
-// R2[0..s2), R3[0..s3)).  Written per sample by k_part4, copied into rank
-// order by k_order4; a merge workgroup takes the keys between two
-// consecutive split points.
+// R2[0..s2), R3[0..s3)).  k_part4 computes one per sample and writes it
+// straight to its slot in rank order; a merge workgroup takes the keys
+// between two consecutive split points.
 struct Split4 {
     int64_t base;   // absolute index of the group's first key (run k starts at base + k*L)
     int64_t rank;   // output position of the split point inside the group
@@ -74,6 +75,7 @@ struct Work {
     // per histogram tile, then per segment
     K* tmin;                  // [tiles] min of each tile
     K* tmax;                  // [tiles] max of each tile
+    uint64_t* tp;             // [tiles] the tile's own p when it has no negative key (its counts are in), else 0
     DigitPlan<K>* plans;      // [nseg]
     int32_t* tilecnt;         // [nseg] histogram tiles of a large segment, 0 otherwise
     int32_t* tilepre;         // [nseg + 1] exclusive prefix of tilecnt
