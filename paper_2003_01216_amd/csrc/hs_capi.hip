@@ -402,7 +402,9 @@ int enqueue(int kind, K* keys, uint32_t* vals, int64_t n, const int64_t* off, in
             HS_TRY(launch_plans<K>(w, st));
         }
         {
-            Timer t(st, "hist", sizeof(K) * (double)n);
+            // reads keys again only for segments with a negative key (data
+            // dependent, so not counted as algorithmic bytes)
+            Timer t(st, "hist", 0);
             HS_TRY(launch_hist<K>(w, L.tiles_bound, st));
         }
         {
