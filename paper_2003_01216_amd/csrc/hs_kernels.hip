@@ -321,10 +321,26 @@ __global__ __launch_bounds__(kHistNT) void k_range(Work<K> w) {
     const K* src = w.keys + td.base;
     const K k0 = src[0];
     K ks[kHistVT];
+    // a full, 16-byte aligned tile is read in 16-byte vectors (consecutive
+    // threads on consecutive vectors), any other strided by element (then
+    // key v of a thread is element tid + v*NT; the counts need no order)
+    using V = typename Vec16<K>::type;
+    constexpr int E = Vec16<K>::n;
+    const bool vec = cnt == kHistTile && ((uintptr_t)src & 15) == 0;
+    if (vec) {
+        const V* sv = reinterpret_cast<const V*>(src);
 #pragma unroll
-    for (int v = 0; v < kHistVT; v++) {
-        const int q = tid + v * kHistNT;
-        ks[v] = q < cnt ? src[q] : k0;  // k0 leaves the min and max unchanged
+        for (int j = 0; j < kHistVT / E; j++) {
+            const V x = sv[tid + j * kHistNT];
+#pragma unroll
+            for (int e = 0; e < E; e++) ks[j * E + e] = (K)Vec16<K>::get(x, e);
+        }
+    } else {
+#pragma unroll
+        for (int v = 0; v < kHistVT; v++) {
+            const int q = tid + v * kHistNT;
+            ks[v] = q < cnt ? src[q] : k0;  // k0 leaves the min and max unchanged
+        }
     }
     K mn = ks[0], mx = ks[0];
 #pragma unroll
@@ -344,10 +360,7 @@ __global__ __launch_bounds__(kHistNT) void k_range(Work<K> w) {
     const DigitPlan<K> pl = make_digit_plan<K>(K(0), mx);
     uint64_t c = 0;  // at most kHistVT = 16 keys per thread: fits the 5-bit fields
 #pragma unroll
-    for (int v = 0; v < kHistVT; v++) {
-        const int q = tid + v * kHistNT;
-        c += (uint64_t)(q < cnt) << (5 * digit_of(pl, ks[v]));
-    }
+    for (int v = 0; v < kHistVT; v++) c += (uint64_t)(vec || tid + v * kHistNT < cnt) << (5 * digit_of(pl, ks[v]));
     uint32_t wd[5];
     unpack5(c, wd);
     block_sum5<kHistNT>(wd, red);
