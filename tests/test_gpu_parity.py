@@ -195,6 +195,57 @@ def test_stage_int64(hs, orc):
         assert np.array_equal(t.cpu().numpy(), ok)
 
 
+def _mixed_magnitudes(dtype, seed):
+    """Blocks of whole 4096-key histogram tiles whose maxima have 1, 3, 5, 8, 10 (and, for int64, 19)
+    digits, in random block order, so that the tiles' own powers of ten differ from the array's."""
+    r = np.random.default_rng(seed)
+    tops = [10, 1000, 10**5, 10**8, 2**31 - 1] + ([2**62] if dtype == np.int64 else [])
+    blocks = [r.integers(0, top, 4096 * int(r.integers(1, 4)), dtype=dtype) for top in tops for _ in range(2)]
+    order = r.permutation(len(blocks))
+    return np.concatenate([blocks[i] for i in order] + [r.integers(0, 1000, 777, dtype=dtype)])
+
+
+@pytest.mark.parametrize("dtype", [np.int32, np.int64])
+def test_tiles_with_smaller_digit_plans(hs, orc, dtype):
+    # the range pass counts each tile under the tile's own plan; tiles whose
+    # maxima have fewer digits than the array's must end up all in bucket 0
+    k = _mixed_magnitudes(dtype, 5)
+    kind = hs.KEYS_I32 if dtype == np.int32 else hs.KEYS_I64
+    say(f"mixed magnitudes {np.dtype(dtype).name} n={k.size}")
+    t = dev(k)
+    s = torch.empty(hs.scratch_bytes(kind, k.size), dtype=torch.uint8, device="cuda")
+    hs.hsort_keys(t, scratch=s)
+    hs.hsort_check(s)
+    assert np.array_equal(t.cpu().numpy(), orc.sort_keys(k))
+    assert np.array_equal(hs.read_bounds(s, kind, k.size).cpu().numpy()[0], orc.bounds(k))
+
+
+def test_segmented_mixed_signs_and_magnitudes(hs, orc):
+    # one call in which some large segments hold negative keys (their tiles
+    # are counted again from the keys) and others do not (counts from the
+    # range pass, some tiles with smaller digit plans than their segment)
+    r = np.random.default_rng(9)
+    parts = []
+    for i in range(12):
+        m = int(r.integers(20_000, 60_000))
+        if i % 3 == 0:
+            parts.append(r.integers(-(10**6), 10**6, m, dtype=np.int32))
+        elif i % 3 == 1:
+            parts.append(_mixed_magnitudes(np.int32, 100 + i)[:m])
+        else:
+            parts.append(r.integers(0, 10 ** int(r.integers(1, 10)), m, dtype=np.int32))
+    keys = np.concatenate(parts)
+    off = np.concatenate([[0], np.cumsum([p.size for p in parts])]).astype(np.int64)
+    say(f"segmented mixed signs n={keys.size}")
+    t, o = dev(keys), dev(off)
+    s = torch.empty(hs.scratch_bytes(hs.SEG_I32, keys.size, off.size - 1), dtype=torch.uint8, device="cuda")
+    hs.hsort_segmented(t, o, scratch=s)
+    hs.hsort_check(s)
+    ok, ob = orc.sort_segmented(keys, off)
+    assert np.array_equal(t.cpu().numpy(), ok)
+    assert np.array_equal(hs.read_bounds(s, hs.SEG_I32, keys.size, off.size - 1).cpu().numpy(), ob)
+
+
 # --------------------------------------------------------------- segmented
 def _segmented_case(dtype, nseg, max_len, seed):
     keys, off = W.segments_i32(nseg, max_len, seed)
