@@ -115,6 +115,10 @@ struct WordMax<int64_t> {
     static constexpr int64_t v = INT64_MAX;
 };
 template <>
+struct WordMax<uint32_t> {
+    static constexpr uint32_t v = ~0u;
+};
+template <>
 struct WordMax<uint64_t> {
     static constexpr uint64_t v = ~0ull;
 };

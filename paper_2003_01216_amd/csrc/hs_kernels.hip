@@ -594,7 +594,7 @@ __global__ void k_sdesc(Work<K> w, int64_t bound) {
     const int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (item >= bound) return;
     const int nb = 10 * w.nseg;
-    SortDesc d{0, 0, 0};
+    SortDesc d{0, 0, 0, 0, 0};
     if (!*w.err && item < w.tsp[nb]) {
         const int j = owner_of(w.tsp, nb, (int)item);
         const int64_t i = item - w.tsp[j];
@@ -602,6 +602,7 @@ __global__ void k_sdesc(Work<K> w, int64_t bound) {
         d.start = w.bstart[j] + i * w.tile;
         d.cnt = (int)min((int64_t)w.tile, size - i * w.tile);
         d.odd = merge_rounds(size, w.tile, w.fanin) & 1;
+        d.bucket = j;
     }
     w.sdesc[item] = d;
 }
@@ -630,6 +631,33 @@ __global__ __launch_bounds__(NT) void k_tilesort(Work<K> w) {
         uint32_t* dv = PAIRS ? (sd.odd ? w.svals : w.vals) + start : nullptr;
         const K* srck = w.skeys + start;
         const uint32_t* srcv = PAIRS ? w.svals + start : nullptr;
+        if constexpr (PAIRS && sizeof(K) == 4) {
+            // Every key of the partition has its bucket's digit d, so
+            // u - d*p (u = k - beta) lies in [0, p).  When p fits next to the
+            // key's index in 32 bits the sort runs on words
+            // (u - d*p) << POS | q: the same strict order as the 64-bit
+            // words, half the LDS traffic and cheaper compares.
+            using U = typename Traits<K>::U;
+            constexpr int POS = NV <= 4096 ? 12 : 13;
+            static_assert(NV <= (1 << POS), "indices fit the narrow word");
+            const DigitPlan<K> pl = w.plans[sd.bucket / 10];
+            const uint64_t p = (uint64_t)pl.thr[0] + 1;
+            if (p - 1 <= (uint64_t(1) << (32 - POS)) - 2) {
+                const U base = pl.beta + (U)(sd.bucket % 10) * (U)p;
+                uint32_t* w32 = reinterpret_cast<uint32_t*>(words);
+                load_run<K, NT, NV>(srck, cnt, [&](int q, K k) {
+                    w32[lds_pad<uint32_t>(q)] = ((uint32_t)((U)k - base) << POS) | (uint32_t)q;
+                });
+                load_run<uint32_t, NT, NV>(srcv, cnt, [&](int q, uint32_t v) { sv[q] = v; });
+                for (int q = cnt + tid; q < NV; q += NT) w32[lds_pad<uint32_t>(q)] = WordMax<uint32_t>::v;
+                __syncthreads();
+                block_sort<uint32_t, NT, VT>(w32, sp);
+                store_keys<K, NT, NV>(dk, cnt, [&](int q) { return (K)((U)(lds_at_padded(w32, q) >> POS) + base); });
+                store_run<uint32_t, NT, NV>(dv, cnt,
+                                            [&](int q) { return sv[lds_at_padded(w32, q) & ((1u << POS) - 1)]; });
+                return;
+            }
+        }
         load_run<K, NT, NV>(srck, cnt, [&](int q, K k) { words[lds_pad<W>(q)] = make_word<K, PAIRS>(k, q); });
         if constexpr (PAIRS) load_run<uint32_t, NT, NV>(srcv, cnt, [&](int q, uint32_t v) { sv[q] = v; });
         if (cnt < NV) {  // a bucket's last, shorter partition: pad with the largest word
@@ -958,33 +986,32 @@ struct Merge4Loads {
     }
 };
 
-// Windows to LDS (from loads issued earlier) plus their sentinels.
-template <typename K, bool PAIRS, int NT, int VT, int JOBS>
-__device__ __forceinline__ void stage4(Merge4Lds<K, PAIRS, NT, VT, JOBS>& sm, const Merge4Loads<K, PAIRS, NT, VT, JOBS>& ld,
-                                       const Chunk4<K>& g) {
-    using W = typename WordOf<K, PAIRS>::type;
+// Windows to LDS as words mk(q, key) (q: index in the concatenated windows),
+// from loads issued earlier, plus their sentinels.
+template <typename W, typename K, bool PAIRS, int NT, int VT, int JOBS, typename MK>
+__device__ __forceinline__ void stage4(W* words, uint32_t* sv, const Merge4Loads<K, PAIRS, NT, VT, JOBS>& ld,
+                                       const Chunk4<K>& g, MK&& mk) {
     const int tid = threadIdx.x;
-    ld.keys.commit_padded(sm.words, [](int q, K k) { return make_word<K, PAIRS>(k, q); });
-    if constexpr (PAIRS) ld.vals.commit_dense(sm.sv);
+    ld.keys.commit_padded(words, mk);
+    if constexpr (PAIRS) ld.vals.commit_dense(sv);
     if (tid < 4 * VT) {
         const int r = tid / VT;
         int p = g.at[0] + g.c[0];
         p = r == 1 ? g.at[1] + g.c[1] : p;
         p = r == 2 ? g.at[2] + g.c[2] : p;
         p = r == 3 ? g.at[3] + g.c[3] : p;
-        sm.words[lds_pad<W>(p + tid % VT)] = WordMax<W>::v;
+        words[lds_pad<W>(p + tid % VT)] = WordMax<W>::v;
     }
 }
 
 // The two merge levels and the store, on windows staged in LDS (the caller
 // has synchronised after stage4).  Ends with the LDS free for reuse only
 // after the caller's next barrier.
-template <typename K, bool PAIRS, int NT, int VT, int JOBS>
-__device__ __forceinline__ void merge4_chunk(Merge4Lds<K, PAIRS, NT, VT, JOBS>& sm, const Chunk4<K>& g) {
-    using W = typename WordOf<K, PAIRS>::type;
+template <typename W, typename K, bool PAIRS, int NT, int VT, int JOBS, typename KeyOf, typename PosOf>
+__device__ __forceinline__ void merge4_chunk(W* words, const uint32_t* sv, const Chunk4<K>& g, KeyOf&& key_of,
+                                             PosOf&& pos_of) {
     constexpr int S = NT * VT * JOBS / 2;
     constexpr int CAP = 2 * S;
-    W* words = sm.words;
     const W wmax = WordMax<W>::v;
     const int tid = threadIdx.x;
     const int c0 = g.c[0], c1 = g.c[1], c2 = g.c[2], c3 = g.c[3];
@@ -1025,9 +1052,9 @@ __device__ __forceinline__ void merge4_chunk(Merge4Lds<K, PAIRS, NT, VT, JOBS>& 
     }
     if (o2 == 0 || o2 == c) {  // one side empty (a group short of four runs): X' or Y' is the result
         const int r = o2 == 0 ? y0 : x0;
-        store_keys<K, NT, CAP>(g.dk, c, [&](int q) { return word_key<K, PAIRS>(lds_at_padded(words, r + q)); });
+        store_keys<K, NT, CAP>(g.dk, c, [&](int q) { return key_of(lds_at_padded(words, r + q)); });
         if constexpr (PAIRS)
-            store_run<uint32_t, NT, CAP>(g.dv, c, [&](int q) { return sm.sv[pair_pos(lds_at_padded(words, r + q))]; });
+            store_run<uint32_t, NT, CAP>(g.dv, c, [&](int q) { return sv[pos_of(lds_at_padded(words, r + q))]; });
         return;
     }
     // level 2: merge X' (o2 words) with Y' (c - o2) into logical [0, c)
@@ -1055,22 +1082,62 @@ __device__ __forceinline__ void merge4_chunk(Merge4Lds<K, PAIRS, NT, VT, JOBS>& 
         }
         __syncthreads();
     }
-    store_keys<K, NT, CAP>(g.dk, c, [&](int q) { return word_key<K, PAIRS>(lds_at_padded(words, q)); });
+    store_keys<K, NT, CAP>(g.dk, c, [&](int q) { return key_of(lds_at_padded(words, q)); });
     if constexpr (PAIRS)
-        store_run<uint32_t, NT, CAP>(g.dv, c, [&](int q) { return sm.sv[pair_pos(lds_at_padded(words, q))]; });
+        store_run<uint32_t, NT, CAP>(g.dv, c, [&](int q) { return sv[pos_of(lds_at_padded(words, q))]; });
+}
+
+// Stable pairs whose chunk spans fewer than 2^19 - 1 key values (the keys of
+// each window lie between its first and last; both are read by every lane)
+// merge 32-bit words ((key - kmin) << 13 | q) instead of 64-bit ones: the
+// same strict order (key, then index q < 2^13 in the concatenated windows),
+// half the LDS traffic and far fewer VALU operations per compare.  The
+// largest word stays below the all-ones sentinel.
+constexpr int kNarrowPosBits = 13;
+constexpr int64_t kNarrowSpan = (int64_t(1) << (32 - kNarrowPosBits)) - 2;
+template <typename K>
+__device__ __forceinline__ bool narrow_chunk(const Chunk4<K>& g, K& kmin) {
+    K lo = Traits<K>::kMax, hi = Traits<K>::kMin;
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+        if (g.c[r] > 0) {
+            const K a = g.ks[r][0], b = g.ks[r][g.c[r] - 1];
+            lo = a < lo ? a : lo;
+            hi = b > hi ? b : hi;
+        }
+    }
+    kmin = lo;
+    return (int64_t)hi - (int64_t)lo <= kNarrowSpan;
 }
 
 // One workgroup per chunk.
 template <typename K, bool PAIRS, int NT, int VT, int JOBS>
 __global__ __launch_bounds__(NT) void k_merge4(Work<K> w, int round, int64_t bound) {
+    using W = typename WordOf<K, PAIRS>::type;
     __shared__ Merge4Lds<K, PAIRS, NT, VT, JOBS> sm;
     const Chunk4<K> g = chunk4_of<K, PAIRS, NT * VT * JOBS / 2, VT>(w, round, blockIdx.x, bound);
     if (!g.active) return;
     Merge4Loads<K, PAIRS, NT, VT, JOBS> ld;
     ld.issue(g);
-    stage4(sm, ld, g);
+    if constexpr (PAIRS && sizeof(K) == 4) {
+        static_assert(NT * VT * JOBS <= (1 << kNarrowPosBits), "window indices fit the narrow word");
+        K kmin;
+        const bool narrow = narrow_chunk(g, kmin);  // the same on every lane
+        if (narrow) {
+            uint32_t* words = reinterpret_cast<uint32_t*>(sm.words);
+            stage4<uint32_t>(words, sm.sv, ld, g,
+                             [=](int q, K k) { return ((uint32_t)(k - kmin) << kNarrowPosBits) | (uint32_t)q; });
+            __syncthreads();
+            merge4_chunk<uint32_t, K, PAIRS, NT, VT, JOBS>(
+                words, sm.sv, g, [=](uint32_t x) { return (K)(kmin + (K)(x >> kNarrowPosBits)); },
+                [](uint32_t x) { return x & ((1u << kNarrowPosBits) - 1); });
+            return;
+        }
+    }
+    stage4<W>(sm.words, sm.sv, ld, g, [](int q, K k) { return make_word<K, PAIRS>(k, q); });
     __syncthreads();
-    merge4_chunk(sm, g);
+    merge4_chunk<W, K, PAIRS, NT, VT, JOBS>(sm.words, sm.sv, g, [](W x) { return word_key<K, PAIRS>(x); },
+                                           [](W x) { return pair_pos((uint64_t)x); });
 }
 
 // --------------------------------------------------------- small segments

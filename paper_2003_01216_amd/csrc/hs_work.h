@@ -25,9 +25,11 @@ struct TileDesc {
 
 // One local-sort partition of a bucket.
 struct SortDesc {
-    int64_t start;  // first key
-    int32_t cnt;    // keys (0: no work)
-    int32_t odd;    // 1: write to the scratch copy (odd number of merge rounds)
+    int64_t start;   // first key
+    int32_t cnt;     // keys (0: no work)
+    int32_t odd;     // 1: write to the scratch copy (odd number of merge rounds)
+    int32_t bucket;  // 10 * segment + digit
+    int32_t pad;
 };
 
 // One merge workgroup of one round: it merges A[a .. a_end) and
