@@ -91,6 +91,22 @@ def test_pairs_stable(hs4, orc, n):
     assert np.array_equal(gk, ok) and np.array_equal(gv, ov)
 
 
+@pytest.mark.parametrize("span", ["full_range", "near_narrow_limit", "small_negative"])
+def test_pairs_word_widths(hs4, orc, span):
+    # chunks spanning more or fewer than 2^19 - 1 key values merge on 64- or
+    # 32-bit words; these mixes exercise both, and the limit itself
+    n = 600_001
+    r = np.random.default_rng(len(span))
+    I = np.iinfo(np.int32)
+    lo, hi = {"full_range": (I.min, I.max), "near_narrow_limit": (0, 2**19), "small_negative": (-300_000, 200_000)}[span]
+    k = r.integers(lo, hi, n, dtype=np.int32, endpoint=True)
+    v = r.integers(0, 2**32, n, dtype=np.uint32)
+    say(f"fanin4 pairs word widths {span}")
+    gk, gv = sort_checked(hs4, k, v)
+    ok, ov = orc.sort_pairs(k, v)
+    assert np.array_equal(gk, ok) and np.array_equal(gv, ov)
+
+
 @pytest.mark.parametrize("dtype", [np.int32, np.int64])
 def test_segmented(hs4, orc, dtype):
     keys, off = W.segments_i32(400, 2**17, 12)
