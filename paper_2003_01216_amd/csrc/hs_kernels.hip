@@ -675,12 +675,6 @@ __global__ __launch_bounds__(NT) void k_tilesort(Work<K> w) {
 // Round `pass` of the non-recursive merge (Figure 1b; Section 3.2 merge
 // rounds): inside every bucket still holding more than one run, runs of
 // L = T*2^pass keys are merged pairwise (an odd last run is carried).  The
-// output of each pair is cut into chunks of NV keys; one workgroup per chunk.
-// k_partition finds, for every chunk start, how many of its preceding
-// outputs come from the left run (co-rank, ties to the left run = stable).
-// Round `pass` of the non-recursive merge (Figure 1b; Section 3.2 merge
-// rounds): inside every bucket still holding more than one run, runs of
-// L = T*2^pass keys are merged pairwise (an odd last run is carried).  The
 // output of each pair is cut into chunks of NV keys, one workgroup each.
 // k_partition (one thread per chunk) finds the co-rank of the chunk's first
 // output -- how many of the outputs before it come from the left run, ties
