@@ -105,6 +105,16 @@ __device__ __forceinline__ int32_t pair_key(uint64_t w) { return (int32_t)((uint
 __device__ __forceinline__ uint32_t pair_pos(uint64_t w) { return (uint32_t)w; }
 
 template <typename W>
+struct WordMin;
+template <>
+struct WordMin<int32_t> {
+    static constexpr int32_t v = INT32_MIN;
+};
+template <>
+struct WordMin<uint32_t> {
+    static constexpr uint32_t v = 0u;
+};
+template <typename W>
 struct WordMax;
 template <>
 struct WordMax<int32_t> {
@@ -217,19 +227,40 @@ __device__ __forceinline__ W lane_xor(W x) {
     }
 }
 
+// The median of three 32-bit words, one instruction.  With c the smallest
+// word it is min(a, b), with c the largest max(a, b): a lane keeps the
+// smaller or the larger of its word and its partner's by its own c.
+__device__ __forceinline__ int32_t med3_word(int32_t a, int32_t b, int32_t c) {
+    int32_t r;
+    asm("v_med3_i32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+__device__ __forceinline__ uint32_t med3_word(uint32_t a, uint32_t b, uint32_t c) {
+    uint32_t r;
+    asm("v_med3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
 // One compare-exchange stage between lanes: register i meets the partner
 // lane's register i (or VT-1-i when FLIP); the lane with `lower` set keeps
-// the smaller word.
+// the smaller word.  32-bit words: the partner's word and one median of
+// three per register; 64-bit words: compare and selects.
 template <typename W, int VT, int MASK, bool FLIP>
 __device__ __forceinline__ void lane_stage(W (&v)[VT], bool lower) {
     W p[VT];
 #pragma unroll
     for (int i = 0; i < VT; i++) p[i] = lane_xor<MASK>(v[FLIP ? VT - 1 - i : i]);
+    if constexpr (sizeof(W) == 4) {
+        const W c = lower ? WordMin<W>::v : WordMax<W>::v;
 #pragma unroll
-    for (int i = 0; i < VT; i++) {
-        const bool lt = p[i] < v[i];
-        const W lo = lt ? p[i] : v[i], hi = lt ? v[i] : p[i];
-        v[i] = lower ? lo : hi;
+        for (int i = 0; i < VT; i++) v[i] = med3_word(v[i], p[i], c);
+    } else {
+#pragma unroll
+        for (int i = 0; i < VT; i++) {
+            const bool lt = p[i] < v[i];
+            const W lo = lt ? p[i] : v[i], hi = lt ? v[i] : p[i];
+            v[i] = lower ? lo : hi;
+        }
     }
 }
 
