@@ -206,14 +206,14 @@ __device__ __forceinline__ void block_sort_levels(W* words, int* sp, W (&v)[VT],
 }
 
 // Sorts words[0..NT*VT) (padded layout) ascending in LDS: a register sorting
-// network per thread, four merge levels across groups of 2, 4, 8 and 16
-// lanes (lane permutations, in registers), then the remaining log2(NT) - 4
-// merge levels in LDS, fully unrolled.  Result in blocked layout (thread t holds outputs
-// t*VT .. t*VT+VT-1, also in LDS).
+// network per thread, merge levels across groups of 2, 4, 8, 16 (and, for
+// 32-bit words, 32) lanes (lane permutations, in registers), then the
+// remaining merge levels in LDS, fully unrolled.  Result in blocked layout
+// (thread t holds outputs t*VT .. t*VT+VT-1, also in LDS).
 template <typename W, int NT, int VT>
 __device__ __forceinline__ void block_sort(W* words, int* sp) {
     static_assert((128 / (int)sizeof(W)) % VT == 0, "a VT-run must not straddle a pad word");
-    static_assert(NT >= 16, "lane merges need groups of sixteen threads");
+    static_assert(NT >= 32, "lane merges need groups of 32 threads");
     const int tid = threadIdx.x;
     const int base = lds_pad<W>(tid * VT);
     W v[VT];
@@ -224,7 +224,15 @@ __device__ __forceinline__ void block_sort(W* words, int* sp) {
     lane_merge<W, VT, 4>(v, tid);
     lane_merge<W, VT, 8>(v, tid);
     lane_merge<W, VT, 16>(v, tid);
-    block_sort_levels<W, NT, VT, 16 * VT>(words, sp, v, tid, base);
+    if constexpr (sizeof(W) == 4) {
+        // 32-bit words: a fifth lane level (lane ^ 31 by a swizzle) is
+        // cheaper than the LDS level it replaces; 64-bit words need two
+        // exchanges and a compare-and-select per register, and it is not
+        lane_merge<W, VT, 32>(v, tid);
+        block_sort_levels<W, NT, VT, 32 * VT>(words, sp, v, tid, base);
+    } else {
+        block_sort_levels<W, NT, VT, 16 * VT>(words, sp, v, tid, base);
+    }
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < VT; i++) words[base + i] = v[i];
