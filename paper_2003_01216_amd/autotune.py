@@ -29,7 +29,7 @@ from . import (KEYS_I32, KEYS_I64, PAIRS_I32_U32, SEG_I32, SEG_I64, TUNING_PATH,
                hsort_keys, hsort_pairs, hsort_segmented, hsort_set_config, load_library, scratch_bytes)
 
 TILES = {
-    KEYS_I32: [(8192, 16), (8192, 32), (16384, 32)],
+    KEYS_I32: [(8192, 16), (8192, 32), (16384, 32), (32768, 32)],
     KEYS_I64: [(4096, 16), (8192, 16)],
     PAIRS_I32_U32: [(4096, 16), (8192, 16)],
 }

@@ -17,7 +17,8 @@ struct ScanSpec {
 // Compiled (key, stable pairs, threads, keys per thread) shapes of the LDS
 // sort (local-sort tiles and whole small segments) and of the merge.
 #define HS_TILE_VARIANTS(X)                                                                  \
-    X(int32_t, false, 512, 32) X(int32_t, false, 256, 32) X(int32_t, false, 512, 16)         \
+    X(int32_t, false, 1024, 32) X(int32_t, false, 512, 32) X(int32_t, false, 256, 32)        \
+    X(int32_t, false, 512, 16)                                                               \
     X(int32_t, false, 256, 16) X(int32_t, false, 256, 8) X(int32_t, false, 64, 4)            \
     X(int64_t, false, 512, 16)                                                               \
     X(int64_t, false, 256, 16) X(int64_t, false, 256, 8) X(int64_t, false, 64, 4)            \
