@@ -300,7 +300,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}, WORLD_SIZE {world}); "
-              "the sort has no multi-GPU path in this build", file=sys.stderr)
+              "the sort runs on one GPU (no multi-GPU path)", file=sys.stderr)
         sys.exit(2)
 
     import torch
