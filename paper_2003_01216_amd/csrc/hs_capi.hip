@@ -189,7 +189,7 @@ int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 struct Layout {
     // byte offsets into scratch
-    size_t err, own_off, skeys, svals, tmin, tmax, tp, rounds, plans, tilecnt, tilepre, bounds, counts, pos, bstart, bsize, tsc,
+    size_t err, own_off, skeys, svals, tmin, tmax, tp, smpf, smpl, rounds, plans, tilecnt, tilepre, bounds, counts, pos, bstart, bsize, tsc,
         tsp, mcc, msp, tiles, sdesc, mdesc, ssorted, part32, part64, total;
     // item bounds
     int64_t large_bound, tiles_bound, buckets, ts_bound, chunks_bound;
@@ -222,6 +222,8 @@ Layout make_layout(int kind, int64_t n, int64_t nseg, const Config& c) {
     L.tmin = take(ksz * L.tiles_bound);
     L.tmax = take(ksz * L.tiles_bound);
     L.tp = take(8 * L.tiles_bound);
+    L.smpf = take(ksz * (n / kSampleBlock + L.buckets + 2));
+    L.smpl = take(ksz * (n / kSampleBlock + L.buckets + 2));
     L.rounds = take(4);
     L.plans = take((ksz == 8 ? sizeof(DigitPlan<int64_t>) : sizeof(DigitPlan<int32_t>)) * nseg);
     L.tilecnt = take(4 * nseg);
@@ -259,6 +261,8 @@ Work<K> make_work(const Layout& L, char* scr, K* keys, uint32_t* vals, const int
     w.tmin = (K*)(scr + L.tmin);
     w.tmax = (K*)(scr + L.tmax);
     w.tp = (uint64_t*)(scr + L.tp);
+    w.smpf = (K*)(scr + L.smpf);
+    w.smpl = (K*)(scr + L.smpl);
     w.rounds = (int32_t*)(scr + L.rounds);
     w.plans = (DigitPlan<K>*)(scr + L.plans);
     w.tilecnt = (int32_t*)(scr + L.tilecnt);

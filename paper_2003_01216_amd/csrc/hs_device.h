@@ -474,6 +474,68 @@ __device__ __forceinline__ int64_t merge_path_steps64(int64_t diag, int64_t na, 
     return pos;
 }
 
+// Searches over runs that start on 32-key block boundaries and come with
+// block samples (first key F[b] = R[32b] of every block, last key
+// Lst[b] = R[32b + 31] of every full block): a binary search over the dense
+// samples, whose lines neighbouring searches share, then at most six probes
+// of the keys inside one block.
+__device__ __forceinline__ int64_t top_step(int64_t w) {  // largest power of two <= w, 0 for 0
+    return w > 0 ? (int64_t)1 << (63 - __builtin_clzll((unsigned long long)w)) : 0;
+}
+
+// Co-rank of diag (a multiple of 32) in the stable merge of A[0..na) and
+// B[0..nb): how many of the first diag outputs come from A (ties to A).
+// Coarse probes m = 32i + 31 compare A's block end la[i] with B's block start
+// fb[diag/32 - i - 1] = B[diag - 1 - m].
+template <typename K>
+__device__ __forceinline__ int64_t merge_path_sampled(int64_t diag, const K* A, int64_t na, const K* la, const K* B,
+                                                      int64_t nb, const K* fb) {
+    const int64_t lo = diag > nb ? diag - nb : 0;
+    const int64_t hi = diag < na ? diag : na;
+    const int64_t ilo = lo / 32, ihi = hi >= 32 ? (hi - 32) / 32 : -1;
+    int64_t t = 0;  // coarse probes from ilo on at which A's key comes first
+    for (int64_t step = top_step(ihi - ilo + 1); step > 0; step >>= 1) {
+        const int64_t i = ilo + t + step - 1;
+        if (i <= ihi && !(fb[diag / 32 - i - 1] < la[i])) t += step;
+    }
+    int64_t a = t > 0 ? 32 * (ilo + t) : lo;
+    int64_t b = ilo + t <= ihi ? 32 * (ilo + t) + 31 : hi;
+    a = a > lo ? a : lo;
+    b = b < hi ? b : hi;
+    int64_t pos = a;  // b - a < 64
+#pragma unroll
+    for (int64_t step = 32; step > 0; step >>= 1) {
+        const int64_t m = pos + step - 1;
+        if (m < b && !(B[diag - 1 - m] < A[m])) pos += step;
+    }
+    return pos;
+}
+
+// Counts of R[0..nr) and Q[0..nq) below v (UPPER: not above v), from their
+// block first keys fr and fq; the two searches step together.
+template <bool UPPER, typename K>
+__device__ __forceinline__ void bound2_sampled(const K* R, int64_t nr, const K* fr, const K* Q, int64_t nq, const K* fq,
+                                               K v, int64_t& pr, int64_t& pq) {
+    auto in = [&](K x) { return UPPER ? !(v < x) : x < v; };
+    const int64_t br = (nr + 31) / 32, bq = (nq + 31) / 32;
+    int64_t tr = 0, tq = 0;  // blocks whose first key is in
+    for (int64_t step = top_step(br > bq ? br : bq); step > 0; step >>= 1) {
+        const int64_t ir = tr + step - 1, iq = tq + step - 1;
+        if (ir < br && in(fr[ir])) tr += step;
+        if (iq < bq && in(fq[iq])) tq += step;
+    }
+    // the count lies in [32(t-1) + 1, min(32t, n)] (0 when t = 0)
+    pr = tr > 0 ? 32 * (tr - 1) + 1 : 0;
+    pq = tq > 0 ? 32 * (tq - 1) + 1 : 0;
+    const int64_t er = tr * 32 < nr ? tr * 32 : nr, eq = tq * 32 < nq ? tq * 32 : nq;
+#pragma unroll
+    for (int64_t step = 16; step > 0; step >>= 1) {
+        const int64_t mr = pr + step - 1, mq = pq + step - 1;
+        if (mr < er && in(R[mr])) pr += step;
+        if (mq < eq && in(Q[mq])) pq += step;
+    }
+}
+
 // Bounds of v in two sorted runs R[0..nr) and Q[0..nq) (elements < v when
 // UPPER is false, <= v when true), the two searches stepping together.
 template <bool UPPER, typename K>

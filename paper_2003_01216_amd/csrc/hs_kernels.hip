@@ -611,8 +611,20 @@ __global__ void k_sdesc(Work<K> w, int64_t bound) {
         d.cnt = (int)min((int64_t)w.tile, size - i * w.tile);
         d.odd = merge_rounds(size, w.tile, w.fanin) & 1;
         d.bucket = j;
+        d.sbase = (int32_t)(sample_base(w.bstart[j], j) + i * w.tile / kSampleBlock);
     }
     w.sdesc[item] = d;
+}
+
+// First and last key of every 32-key block of a sorted partition that starts
+// on a block boundary (the split-point searches of fan-in-4 rounds probe
+// these dense samples before the keys).
+template <typename K, int NT, typename KeyAt>
+__device__ __forceinline__ void store_block_samples(const Work<K>& w, int64_t sbase, int cnt, KeyAt&& key_at) {
+    for (int b = threadIdx.x; b * kSampleBlock < cnt; b += NT) {
+        w.smpf[sbase + b] = key_at(b * kSampleBlock);
+        if ((b + 1) * kSampleBlock <= cnt) w.smpl[sbase + b] = key_at(b * kSampleBlock + kSampleBlock - 1);
+    }
 }
 
 // -------------------------------------------------------------- tile sort
@@ -660,9 +672,11 @@ __global__ __launch_bounds__(NT) void k_tilesort(Work<K> w) {
                 for (int q = cnt + tid; q < NV; q += NT) w32[lds_pad<uint32_t>(q)] = WordMax<uint32_t>::v;
                 __syncthreads();
                 block_sort<uint32_t, NT, VT>(w32, sp);
-                store_keys<K, NT, NV>(dk, cnt, [&](int q) { return (K)((U)(lds_at_padded(w32, q) >> POS) + base); });
+                auto key_at = [&](int q) { return (K)((U)(lds_at_padded(w32, q) >> POS) + base); };
+                store_keys<K, NT, NV>(dk, cnt, key_at);
                 store_run<uint32_t, NT, NV>(dv, cnt,
                                             [&](int q) { return sv[lds_at_padded(w32, q) & ((1u << POS) - 1)]; });
+                if (w.fanin == 4) store_block_samples<K, NT>(w, sd.sbase, cnt, key_at);
                 return;
             }
         }
@@ -673,9 +687,11 @@ __global__ __launch_bounds__(NT) void k_tilesort(Work<K> w) {
         }
         __syncthreads();
         block_sort<W, NT, VT>(words, sp);
-        store_keys<K, NT, NV>(dk, cnt, [&](int q) { return word_key<K, PAIRS>(lds_at_padded(words, q)); });
+        auto key_at = [&](int q) { return word_key<K, PAIRS>(lds_at_padded(words, q)); };
+        store_keys<K, NT, NV>(dk, cnt, key_at);
         if constexpr (PAIRS)
             store_run<uint32_t, NT, NV>(dv, cnt, [&](int q) { return sv[pair_pos(lds_at_padded(words, q))]; });
+        if (w.fanin == 4) store_block_samples<K, NT>(w, sd.sbase, cnt, key_at);
     }
 }
 
@@ -843,20 +859,23 @@ __global__ __launch_bounds__(256) void k_part4(Work<K> w, int round, int64_t bou
             const K* R3 = src + 3 * L;
             const int64_t pos = o - q * 2 * L;  // position inside X or Y
             int64_t s0, s1, s2, s3, rank, before;  // before: samples of the other half ranked earlier
+            // run k's 32-key blocks: samples from gs + k*L/32 (written by the
+            // producer of the runs); searches probe them before the keys
+            const int64_t gs = sample_base(w.bstart[j], j) + gbase / kSampleBlock, lb = L / kSampleBlock;
+            const K* F = w.smpf + gs;
+            const K* Lst = w.smpl + gs;
             if (!(q & 1)) {
-                const int64_t c = merge_path_steps64(pos, len[0], len[1], L, [&](int64_t x) { return R0[x]; },
-                                                     [&](int64_t x) { return R1[x]; });
+                const int64_t c = merge_path_sampled(pos, R0, len[0], Lst, R1, len[1], F + lb);
                 const K x = elem_at_corank(R0, len[0], R1, len[1], c, pos);
                 s0 = c;
                 s1 = pos - c;
-                bound2_steps<false>(R2, len[2], R3, len[3], x, L, s2, s3);
+                bound2_sampled<false>(R2, len[2], F + 2 * lb, R3, len[3], F + 3 * lb, x, s2, s3);
                 rank = pos + s2 + s3;
                 before = (s2 + s3 + S - 1) / S;
             } else {
-                const int64_t e = merge_path_steps64(pos, len[2], len[3], L, [&](int64_t x) { return R2[x]; },
-                                                     [&](int64_t x) { return R3[x]; });
+                const int64_t e = merge_path_sampled(pos, R2, len[2], Lst + 2 * lb, R3, len[3], F + 3 * lb);
                 const K y = elem_at_corank(R2, len[2], R3, len[3], e, pos);
-                bound2_steps<true>(R0, len[0], R1, len[1], y, L, s0, s1);
+                bound2_sampled<true>(R0, len[0], F, R1, len[1], F + lb, y, s0, s1);
                 s2 = e;
                 s3 = pos - e;
                 rank = pos + s0 + s1;
@@ -873,8 +892,8 @@ __global__ __launch_bounds__(256) void k_part4(Work<K> w, int round, int64_t bou
             for (int k = 0; k < 4; k++) d.len[k] = (int32_t)len[k];
             d.first = (int32_t)(w.msp[j] + gbase / S);
             d.items = (int32_t)(nx + ny);
-            d.nx = (int32_t)nx;
-            d.flags = kActive | (odd ? kFromScratch : 0) | round_tag(round);
+            d.sbase = (int32_t)gs;
+            d.flags = kActive | (odd ? kFromScratch : 0) | (round + 1 == P ? kLastRound : 0) | round_tag(round);
             w.ssorted[d.first + pos / S + before] = d;
             return;
         }
@@ -908,6 +927,9 @@ struct Chunk4 {
     const uint32_t* vs[4];
     K* dk;
     uint32_t* dv;
+    K* sf;         // block samples of the group's output (first keys), or null in the bucket's last round
+    K* sl;         // last keys of full blocks
+    int64_t rank;  // group position of the chunk's first output (outputs start blocks where rank + q is a multiple of 32)
 };
 
 template <typename K, bool PAIRS, int S, int VT>
@@ -942,6 +964,9 @@ __device__ __forceinline__ Chunk4<K> chunk4_of(const Work<K>& w, int round, int6
         stale || c != rank_end - r0.rank || neg || g.c[0] + g.c[1] > S || g.c[2] + g.c[3] > S;
     g.dk = (odd ? w.keys : w.skeys) + r0.base + r0.rank;
     g.dv = PAIRS ? (odd ? w.vals : w.svals) + r0.base + r0.rank : nullptr;
+    g.rank = r0.rank;
+    g.sf = (r0.flags & kLastRound) ? nullptr : w.smpf + r0.sbase;
+    g.sl = w.smpl + r0.sbase;
     // window r at logical at[r] (>= 1; body vectors on multiples of 4), then
     // VT sentinels and VT + 4 spare words (room for X' and Y' rounded down
     // to multiples of VT)
@@ -1006,6 +1031,20 @@ __device__ __forceinline__ void stage4(W* words, uint32_t* sv, const Merge4Loads
     }
 }
 
+// Block samples of a chunk's outputs (for the next round's split points):
+// output q is group position rank + q; it starts a block when that is a
+// multiple of 32 and ends one when it is 31 past one.
+template <int NT, typename K, typename KeyAt>
+__device__ __forceinline__ void store_chunk_samples(const Chunk4<K>& g, int c, KeyAt&& key_at) {
+    if (g.sf == nullptr) return;
+    const int m = (int)(g.rank % kSampleBlock);
+    const int64_t b0 = g.rank / kSampleBlock;
+    const int qf = (kSampleBlock - m) % kSampleBlock;  // first output that starts a block
+    for (int q = qf + kSampleBlock * (int)threadIdx.x; q < c; q += kSampleBlock * NT) g.sf[b0 + (m + q) / kSampleBlock] = key_at(q);
+    const int ql = kSampleBlock - 1 - m;  // first output that ends a block
+    for (int q = ql + kSampleBlock * (int)threadIdx.x; q < c; q += kSampleBlock * NT) g.sl[b0 + (m + q) / kSampleBlock] = key_at(q);
+}
+
 // The two merge levels and the store, on windows staged in LDS (the caller
 // has synchronised after stage4).  Ends with the LDS free for reuse only
 // after the caller's next barrier.
@@ -1057,6 +1096,7 @@ __device__ __forceinline__ void merge4_chunk(W* words, const uint32_t* sv, const
         store_keys<K, NT, CAP>(g.dk, c, [&](int q) { return key_of(lds_at_padded(words, r + q)); });
         if constexpr (PAIRS)
             store_run<uint32_t, NT, CAP>(g.dv, c, [&](int q) { return sv[pos_of(lds_at_padded(words, r + q))]; });
+        store_chunk_samples<NT>(g, c, [&](int q) { return key_of(lds_at_padded(words, r + q)); });
         return;
     }
     // level 2: merge X' (o2 words) with Y' (c - o2) into logical [0, c)
@@ -1087,6 +1127,7 @@ __device__ __forceinline__ void merge4_chunk(W* words, const uint32_t* sv, const
     store_keys<K, NT, CAP>(g.dk, c, [&](int q) { return key_of(lds_at_padded(words, q)); });
     if constexpr (PAIRS)
         store_run<uint32_t, NT, CAP>(g.dv, c, [&](int q) { return sv[pos_of(lds_at_padded(words, q))]; });
+    store_chunk_samples<NT>(g, c, [&](int q) { return key_of(lds_at_padded(words, q)); });
 }
 
 // Stable pairs whose chunk spans fewer than 2^19 - 1 key values (the keys of

@@ -29,7 +29,7 @@ struct SortDesc {
     int32_t cnt;     // keys (0: no work)
     int32_t odd;     // 1: write to the scratch copy (odd number of merge rounds)
     int32_t bucket;  // 10 * segment + digit
-    int32_t pad;
+    int32_t sbase;   // sample index of the partition's first 32-key block
 };
 
 // One merge workgroup of one round: it merges A[a .. a_end) and
@@ -57,9 +57,20 @@ struct Split4 {
     int32_t len[4]; // run lengths of the group
     int32_t first;  // flat index of the group's first chunk
     int32_t items;  // chunks of the group (= split points)
-    int32_t nx;     // split points sampled from merge(R0, R1); the rest from merge(R2, R3)
-    int32_t flags;  // kActive | kFromScratch | round_tag(round)
+    int32_t sbase;  // sample index of the group's first 32-key block
+    int32_t flags;  // kActive | kFromScratch | kLastRound | round_tag(round)
 };
+constexpr int32_t kLastRound = 4;  // the bucket's last merge round: its output needs no samples
+
+// Block samples for the split-point searches of fan-in-4 rounds: the runs a
+// round reads are cut into 32-key blocks counted from their bucket's start,
+// and the producer of the runs (the local sort, or the previous round)
+// stores the first and the last key of every block.  Bucket j's block b
+// lives at index bstart/32 + j + b: the +j keeps the last block of a bucket
+// and the first of the next apart when a bucket ends inside an aligned
+// 32-key window.
+constexpr int kSampleBlock = 32;
+__host__ __device__ inline int64_t sample_base(int64_t bstart, int j) { return bstart / kSampleBlock + j; }
 // A split point records the round that wrote it (bits 8 and up), so that a
 // slot left over from an earlier round is recognised instead of trusted.
 __host__ __device__ constexpr int32_t round_tag(int round) { return (round + 1) << 8; }
@@ -78,6 +89,8 @@ struct Work {
     K* tmin;                  // [tiles] min of each tile
     K* tmax;                  // [tiles] max of each tile
     uint64_t* tp;             // [tiles] the tile's own p when it has no negative key (its counts are in), else 0
+    K* smpf;                  // [n/32 + buckets + 2] first key of each 32-key block (fan-in-4 rounds)
+    K* smpl;                  // [n/32 + buckets + 2] last key of each full 32-key block
     DigitPlan<K>* plans;      // [nseg]
     int32_t* tilecnt;         // [nseg] histogram tiles of a large segment, 0 otherwise
     int32_t* tilepre;         // [nseg + 1] exclusive prefix of tilecnt
