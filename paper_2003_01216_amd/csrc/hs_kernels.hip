@@ -609,7 +609,7 @@ __global__ void k_sdesc(Work<K> w, int64_t bound) {
         const int64_t size = w.bsize[j];
         d.start = w.bstart[j] + i * w.tile;
         d.cnt = (int)min((int64_t)w.tile, size - i * w.tile);
-        d.odd = merge_rounds(size, w.tile, w.fanin) & 1;
+        d.odd = (merge_rounds(size, w.tile, w.fanin) & 1) | (int)(i & 1) << 1;  // bit 1: an odd run of its group
         d.bucket = j;
         d.sbase = (int32_t)(sample_base(w.bstart[j], j) + i * w.tile / kSampleBlock);
     }
@@ -619,11 +619,14 @@ __global__ void k_sdesc(Work<K> w, int64_t bound) {
 // First and last key of every 32-key block of a sorted partition that starts
 // on a block boundary (the split-point searches of fan-in-4 rounds probe
 // these dense samples before the keys).
+// Block last keys are read only from runs 0 and 2 of a group (the A side of
+// its merge paths): `last` is false for the others.
 template <typename K, int NT, typename KeyAt>
-__device__ __forceinline__ void store_block_samples(const Work<K>& w, int64_t sbase, int cnt, KeyAt&& key_at) {
+__device__ __forceinline__ void store_block_samples(const Work<K>& w, int64_t sbase, int cnt, bool last,
+                                                    KeyAt&& key_at) {
     for (int b = threadIdx.x; b * kSampleBlock < cnt; b += NT) {
         w.smpf[sbase + b] = key_at(b * kSampleBlock);
-        if ((b + 1) * kSampleBlock <= cnt) w.smpl[sbase + b] = key_at(b * kSampleBlock + kSampleBlock - 1);
+        if (last && (b + 1) * kSampleBlock <= cnt) w.smpl[sbase + b] = key_at(b * kSampleBlock + kSampleBlock - 1);
     }
 }
 
@@ -647,8 +650,8 @@ __global__ __launch_bounds__(NT) void k_tilesort(Work<K> w) {
     {
         const int64_t start = sd.start;
         const int cnt = sd.cnt;
-        K* dk = (sd.odd ? w.skeys : w.keys) + start;
-        uint32_t* dv = PAIRS ? (sd.odd ? w.svals : w.vals) + start : nullptr;
+        K* dk = ((sd.odd & 1) ? w.skeys : w.keys) + start;
+        uint32_t* dv = PAIRS ? ((sd.odd & 1) ? w.svals : w.vals) + start : nullptr;
         const K* srck = w.skeys + start;
         const uint32_t* srcv = PAIRS ? w.svals + start : nullptr;
         if constexpr (PAIRS && sizeof(K) == 4) {
@@ -676,7 +679,7 @@ __global__ __launch_bounds__(NT) void k_tilesort(Work<K> w) {
                 store_keys<K, NT, NV>(dk, cnt, key_at);
                 store_run<uint32_t, NT, NV>(dv, cnt,
                                             [&](int q) { return sv[lds_at_padded(w32, q) & ((1u << POS) - 1)]; });
-                if (w.fanin == 4) store_block_samples<K, NT>(w, sd.sbase, cnt, key_at);
+                if (w.fanin == 4) store_block_samples<K, NT>(w, sd.sbase, cnt, !(sd.odd & 2), key_at);
                 return;
             }
         }
@@ -691,7 +694,7 @@ __global__ __launch_bounds__(NT) void k_tilesort(Work<K> w) {
         store_keys<K, NT, NV>(dk, cnt, key_at);
         if constexpr (PAIRS)
             store_run<uint32_t, NT, NV>(dv, cnt, [&](int q) { return sv[pair_pos(lds_at_padded(words, q))]; });
-        if (w.fanin == 4) store_block_samples<K, NT>(w, sd.sbase, cnt, key_at);
+        if (w.fanin == 4) store_block_samples<K, NT>(w, sd.sbase, cnt, !(sd.odd & 2), key_at);
     }
 }
 
@@ -893,7 +896,8 @@ __global__ __launch_bounds__(256) void k_part4(Work<K> w, int round, int64_t bou
             d.first = (int32_t)(w.msp[j] + gbase / S);
             d.items = (int32_t)(nx + ny);
             d.sbase = (int32_t)gs;
-            d.flags = kActive | (odd ? kFromScratch : 0) | (round + 1 == P ? kLastRound : 0) | round_tag(round);
+            d.flags = kActive | (odd ? kFromScratch : 0) | (round + 1 == P ? kLastRound : 0) |
+                      ((g & 1) ? kOddGroup : 0) | round_tag(round);
             w.ssorted[d.first + pos / S + before] = d;
             return;
         }
@@ -966,7 +970,7 @@ __device__ __forceinline__ Chunk4<K> chunk4_of(const Work<K>& w, int round, int6
     g.dv = PAIRS ? (odd ? w.vals : w.svals) + r0.base + r0.rank : nullptr;
     g.rank = r0.rank;
     g.sf = (r0.flags & kLastRound) ? nullptr : w.smpf + r0.sbase;
-    g.sl = w.smpl + r0.sbase;
+    g.sl = (r0.flags & kOddGroup) ? nullptr : w.smpl + r0.sbase;
     // window r at logical at[r] (>= 1; body vectors on multiples of 4), then
     // VT sentinels and VT + 4 spare words (room for X' and Y' rounded down
     // to multiples of VT)
@@ -1041,6 +1045,7 @@ __device__ __forceinline__ void store_chunk_samples(const Chunk4<K>& g, int c, K
     const int64_t b0 = g.rank / kSampleBlock;
     const int qf = (kSampleBlock - m) % kSampleBlock;  // first output that starts a block
     for (int q = qf + kSampleBlock * (int)threadIdx.x; q < c; q += kSampleBlock * NT) g.sf[b0 + (m + q) / kSampleBlock] = key_at(q);
+    if (g.sl == nullptr) return;
     const int ql = kSampleBlock - 1 - m;  // first output that ends a block
     for (int q = ql + kSampleBlock * (int)threadIdx.x; q < c; q += kSampleBlock * NT) g.sl[b0 + (m + q) / kSampleBlock] = key_at(q);
 }

@@ -27,7 +27,7 @@ struct TileDesc {
 struct SortDesc {
     int64_t start;   // first key
     int32_t cnt;     // keys (0: no work)
-    int32_t odd;     // 1: write to the scratch copy (odd number of merge rounds)
+    int32_t odd;     // bit 0: write to the scratch copy (odd number of merge rounds); bit 1: odd partition
     int32_t bucket;  // 10 * segment + digit
     int32_t sbase;   // sample index of the partition's first 32-key block
 };
@@ -61,6 +61,7 @@ struct Split4 {
     int32_t flags;  // kActive | kFromScratch | kLastRound | round_tag(round)
 };
 constexpr int32_t kLastRound = 4;  // the bucket's last merge round: its output needs no samples
+constexpr int32_t kOddGroup = 8;   // odd group: its output is run 1 or 3 of the next round's group (no last keys)
 
 // Block samples for the split-point searches of fan-in-4 rounds: the runs a
 // round reads are cut into 32-key blocks counted from their bucket's start,
