@@ -14,6 +14,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <limits>
+#include <type_traits>
+
 namespace hs {
 
 constexpr int kWave = 64;
@@ -386,42 +389,82 @@ __device__ __forceinline__ void lds_merge_window(const W* lds, int pa, int pb, W
 // --------------------------------------------------------- wave/block helpers
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 
-template <typename T>
-__device__ __forceinline__ T wave_incl_scan_add(T x) {
-    const int lane = lane_id();
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        T y = __shfl_up(x, d, kWave);
-        if (lane >= d) x += y;
-    }
+// 32-bit wave scans and reductions by DPP (no LDS traffic): shifts by 1, 2,
+// 4 and 8 lanes within each row of 16 (lanes shifted in from outside the
+// row take the identity), then rows 1 and 3 combine the last lane of the row
+// before them (row_bcast:15) and rows 2 and 3 the last lane of row 1
+// (row_bcast:31).  Lane 63 ends with the whole wave's result.
+template <int CTRL, int ROWS, typename T>
+__device__ __forceinline__ T dpp_from(T x, T id) {
+    return (T)__builtin_amdgcn_update_dpp((int)id, (int)x, CTRL, ROWS, 0xF, false);
+}
+template <typename T, typename Op>
+__device__ __forceinline__ T wave_incl_scan_dpp(T x, T id, Op op) {
+    static_assert(sizeof(T) == 4, "32-bit lanes");
+    x = op(x, dpp_from<0x111, 0xF>(x, id));  // row_shr:1
+    x = op(x, dpp_from<0x112, 0xF>(x, id));  // row_shr:2
+    x = op(x, dpp_from<0x114, 0xF>(x, id));  // row_shr:4
+    x = op(x, dpp_from<0x118, 0xF>(x, id));  // row_shr:8
+    x = op(x, dpp_from<0x142, 0xA>(x, id));  // row_bcast:15 into rows 1, 3
+    x = op(x, dpp_from<0x143, 0xC>(x, id));  // row_bcast:31 into rows 2, 3
     return x;
 }
 
 template <typename T>
-__device__ __forceinline__ T wave_reduce_add(T x) {
+__device__ __forceinline__ T wave_incl_scan_add(T x) {
+    if constexpr (sizeof(T) == 4) {
+        return wave_incl_scan_dpp<T>(x, T(0), [](T a, T b) { return a + b; });
+    } else {
+        const int lane = lane_id();
 #pragma unroll
-    for (int d = kWave / 2; d > 0; d >>= 1) x += __shfl_xor(x, d, kWave);
-    return x;
+        for (int d = 1; d < kWave; d <<= 1) {
+            T y = __shfl_up(x, d, kWave);
+            if (lane >= d) x += y;
+        }
+        return x;
+    }
+}
+
+// The wave's total in every lane.
+template <typename T>
+__device__ __forceinline__ T wave_reduce_add(T x) {
+    if constexpr (sizeof(T) == 4) {
+        return (T)__builtin_amdgcn_readlane((int)wave_incl_scan_add(x), kWave - 1);
+    } else {
+#pragma unroll
+        for (int d = kWave / 2; d > 0; d >>= 1) x += __shfl_xor(x, d, kWave);
+        return x;
+    }
 }
 
 template <typename T>
 __device__ __forceinline__ T wave_reduce_min(T x) {
+    if constexpr (sizeof(T) == 4) {
+        const T r = wave_incl_scan_dpp<T>(x, std::numeric_limits<T>::max(), [](T a, T b) { return b < a ? b : a; });
+        return (T)__builtin_amdgcn_readlane((int)r, kWave - 1);
+    } else {
 #pragma unroll
-    for (int d = kWave / 2; d > 0; d >>= 1) {
-        T y = __shfl_xor(x, d, kWave);
-        x = y < x ? y : x;
+        for (int d = kWave / 2; d > 0; d >>= 1) {
+            T y = __shfl_xor(x, d, kWave);
+            x = y < x ? y : x;
+        }
+        return x;
     }
-    return x;
 }
 
 template <typename T>
 __device__ __forceinline__ T wave_reduce_max(T x) {
+    if constexpr (sizeof(T) == 4) {
+        const T r = wave_incl_scan_dpp<T>(x, std::numeric_limits<T>::lowest(), [](T a, T b) { return b > a ? b : a; });
+        return (T)__builtin_amdgcn_readlane((int)r, kWave - 1);
+    } else {
 #pragma unroll
-    for (int d = kWave / 2; d > 0; d >>= 1) {
-        T y = __shfl_xor(x, d, kWave);
-        x = y > x ? y : x;
+        for (int d = kWave / 2; d > 0; d >>= 1) {
+            T y = __shfl_xor(x, d, kWave);
+            x = y > x ? y : x;
+        }
+        return x;
     }
-    return x;
 }
 
 // Index of the last entry of pre[0..n] (non-decreasing, pre[0] = 0) that is

@@ -530,16 +530,22 @@ __global__ __launch_bounds__(kHistNT) void k_scatter(Work<K> w) {
     uint32_t val[PAIRS ? VT : 1];
     uint32_t pk[VT];
     uint64_t c = 0;
+    auto rank_keys = [&](auto full) {  // full: every slot holds a key (no per-key bounds test)
 #pragma unroll
-    for (int v = 0; v < VT; v++) {
-        const int q = tid * VT + v;
-        const bool ok = q < cnt;
-        key[v] = sk[lds_pad<K>(ok ? q : 0)];
-        if constexpr (PAIRS) val[v] = sv[ok ? q : 0];
-        const int d = digit_of(pl, key[v]);
-        pk[v] = ok ? ((((uint32_t)(c >> (5 * d)) & 31u) << 4) | (uint32_t)d) : 15u;
-        c += ok ? (1ull << (5 * d)) : 0ull;
-    }
+        for (int v = 0; v < VT; v++) {
+            const int q = tid * VT + v;
+            const bool ok = decltype(full)::value || q < cnt;
+            key[v] = sk[lds_pad<K>(ok ? q : 0)];
+            if constexpr (PAIRS) val[v] = sv[ok ? q : 0];
+            const int d = digit_of(pl, key[v]);
+            pk[v] = ok ? ((((uint32_t)(c >> (5 * d)) & 31u) << 4) | (uint32_t)d) : 15u;
+            c += ok ? (1ull << (5 * d)) : 0ull;
+        }
+    };
+    if (cnt == HT)
+        rank_keys(std::true_type{});
+    else
+        rank_keys(std::false_type{});
     // 3. exclusive scan over threads, and the tile's bucket totals
     uint32_t wd[5], tot[5];
     unpack5(c, wd);
