@@ -222,8 +222,8 @@ Layout make_layout(int kind, int64_t n, int64_t nseg, const Config& c) {
     L.tmin = take(ksz * L.tiles_bound);
     L.tmax = take(ksz * L.tiles_bound);
     L.tp = take(8 * L.tiles_bound);
-    L.smpf = take(ksz * (n / kSampleBlock + L.buckets + 2));
-    L.smpl = take(ksz * (n / kSampleBlock + L.buckets + 2));
+    L.smpf = take(ksz * (n / kSampleBlock + L.chunks_bound + 2));
+    L.smpl = take(ksz * (n / kSampleBlock + L.chunks_bound + 2));
     L.rounds = take(4);
     L.plans = take((ksz == 8 ? sizeof(DigitPlan<int64_t>) : sizeof(DigitPlan<int32_t>)) * nseg);
     L.tilecnt = take(4 * nseg);

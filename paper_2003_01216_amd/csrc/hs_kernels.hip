@@ -617,7 +617,7 @@ __global__ void k_sdesc(Work<K> w, int64_t bound) {
         d.cnt = (int)min((int64_t)w.tile, size - i * w.tile);
         d.odd = (merge_rounds(size, w.tile, w.fanin) & 1) | (int)(i & 1) << 1;  // bit 1: an odd run of its group
         d.bucket = j;
-        d.sbase = (int32_t)(sample_base(w.bstart[j], j) + i * w.tile / kSampleBlock);
+        d.sbase = (int32_t)(sample_base(w.bstart[j], w.msp[j]) + i * w.tile / kSampleBlock);
     }
     w.sdesc[item] = d;
 }
@@ -870,7 +870,7 @@ __global__ __launch_bounds__(256) void k_part4(Work<K> w, int round, int64_t bou
             int64_t s0, s1, s2, s3, rank, before;  // before: samples of the other half ranked earlier
             // run k's 32-key blocks: samples from gs + k*L/32 (written by the
             // producer of the runs); searches probe them before the keys
-            const int64_t gs = sample_base(w.bstart[j], j) + gbase / kSampleBlock, lb = L / kSampleBlock;
+            const int64_t gs = sample_base(w.bstart[j], w.msp[j]) + gbase / kSampleBlock, lb = L / kSampleBlock;
             const K* F = w.smpf + gs;
             const K* Lst = w.smpl + gs;
             if (!(q & 1)) {

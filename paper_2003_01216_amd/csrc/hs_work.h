@@ -67,11 +67,15 @@ constexpr int32_t kOddGroup = 8;   // odd group: its output is run 1 or 3 of the
 // round reads are cut into 32-key blocks counted from their bucket's start,
 // and the producer of the runs (the local sort, or the previous round)
 // stores the first and the last key of every block.  Bucket j's block b
-// lives at index bstart/32 + j + b: the +j keeps the last block of a bucket
-// and the first of the next apart when a bucket ends inside an aligned
-// 32-key window.
+// lives at index bstart/32 + msp[j] + b, msp the prefix of merge chunks
+// per bucket: a bucket that merges has at least one chunk, so the term keeps
+// its last block and the next such bucket's first apart when a bucket ends
+// inside an aligned 32-key window; buckets of small segments have none, so
+// the indices stay below n/32 + (chunks bound).
 constexpr int kSampleBlock = 32;
-__host__ __device__ inline int64_t sample_base(int64_t bstart, int j) { return bstart / kSampleBlock + j; }
+__host__ __device__ inline int64_t sample_base(int64_t bstart, int32_t chunks_before) {
+    return bstart / kSampleBlock + chunks_before;
+}
 // A split point records the round that wrote it (bits 8 and up), so that a
 // slot left over from an earlier round is recognised instead of trusted.
 __host__ __device__ constexpr int32_t round_tag(int round) { return (round + 1) << 8; }
