@@ -172,8 +172,9 @@ def timed_refill(torch, base, run_one, steps, warmup):
     return total / steps, work
 
 
-def bench_segmented(hs, torch, steps, warmup):
-    """16384 arrays, log-uniform sizes in [1, 2^16]: one batched call vs a loop of plain calls."""
+def bench_segmented(hs, torch, steps, warmup, loop=True):
+    """16384 arrays, log-uniform sizes in [1, 2^16]: one batched call vs a loop of plain calls
+    (the loop is skipped when `loop` is false)."""
     keys, off = W.segments_i32(16384, 2**16, 0)
     n = keys.size
     max_len = int(np.diff(off).max())
@@ -201,6 +202,12 @@ def bench_segmented(hs, torch, steps, warmup):
         torch.cuda.synchronize()
         hs.hsort_timing_enable(False)
         kernels = kernel_table(hs.hsort_timing_read(), 1)
+        out.update({"batched_graph_Gkeys_s": round(n / ms_graph / 1e6, 3),
+                    "batched_eager_Gkeys_s": round(n / ms_eager / 1e6, 3), "batched_graph_ms": round(ms_graph, 4),
+                    "batched_kernels": kernels})
+        if not loop:
+            torch.cuda.empty_cache()
+            return out
         # per-array loop of the plain method on sub-views, same stream, one scratch
         loop_scratch = torch.empty(hs.scratch_bytes(hs.KEYS_I32, max_len), dtype=torch.uint8, device="cuda")
         offs = off.tolist()
@@ -220,10 +227,8 @@ def bench_segmented(hs, torch, steps, warmup):
         loop_s = time.perf_counter() - t0
         same = bool(torch.equal(lw, work))  # loop and batched agree
     torch.cuda.empty_cache()
-    out.update({"batched_graph_Gkeys_s": round(n / ms_graph / 1e6, 3), "batched_eager_Gkeys_s": round(n / ms_eager / 1e6, 3),
-                "batched_graph_ms": round(ms_graph, 4), "per_array_loop_Gkeys_s": round(n / loop_s / 1e9, 4),
-                "per_array_loop_ms": round(loop_s * 1e3, 2), "speedup_graph_vs_loop": round(loop_s * 1e3 / ms_graph, 1),
-                "loop_equals_batched": same, "batched_kernels": kernels})
+    out.update({"per_array_loop_Gkeys_s": round(n / loop_s / 1e9, 4), "per_array_loop_ms": round(loop_s * 1e3, 2),
+                "speedup_graph_vs_loop": round(loop_s * 1e3 / ms_graph, 1), "loop_equals_batched": same})
     return out
 
 
@@ -295,6 +300,9 @@ def main():
     ap.add_argument("--log2n", type=int, default=28, help="keys in the metric workload (2^log2n)")
     ap.add_argument("--no-extras", action="store_true", help="only the metric workload")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--extras", default="pairs,keys,segmented,serving",
+                    help="comma list of the extra workloads to run: pairs, keys, segmented, serving")
+    ap.add_argument("--no-loop", action="store_true", help="segmented: skip the per-array loop of plain calls")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -347,15 +355,23 @@ def main():
              "algorithmic_bytes_per_key": round(total_bytes / n, 2),
              "whole_sort_frac_hbm_peak": round(total_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
-    if not args.no_extras:
+    extras = set() if args.no_extras else {e.strip() for e in args.extras.split(",") if e.strip()}
+    unknown = extras - {"pairs", "keys", "segmented", "serving"}
+    if unknown:
+        log(f"[bench] ERROR: unknown extra workloads {sorted(unknown)}")
+        sys.exit(2)
+    if "pairs" in extras:
         log("[bench] stable pairs 2^28, keys in [0,1000), payload = index")
         extra["pairs_dup_2e28_Gkeys_s"], extra["pairs_kernels"] = bench_pairs(hs, torch, 2**28, 5, 1)
+    if "keys" in extras:
         log("[bench] 2^26 uniform / log-uniform / int64 full range")
         extra["uniform_2e26_Gkeys_s"] = round(bench_keys(hs, torch, W.uniform_i32(2**26, 0), 10, 2)[0], 3)
         extra["loguniform_2e26_Gkeys_s"] = round(bench_keys(hs, torch, W.loguniform_i32(2**26, 0), 10, 2)[0], 3)
         extra["int64_full_range_2e26_Gkeys_s"] = round(bench_keys(hs, torch, W.uniform_i64(2**26, 0), 10, 2)[0], 3)
-        log("[bench] batched segmented vs per-array loop")
-        extra["segmented"] = bench_segmented(hs, torch, 10, 2)
+    if "segmented" in extras:
+        log("[bench] batched segmented" + ("" if args.no_loop else " vs per-array loop"))
+        extra["segmented"] = bench_segmented(hs, torch, 10, 2, loop=not args.no_loop)
+    if "serving" in extras:
         log("[bench] serving loop")
         extra["serving"] = bench_serving()
 
