@@ -310,6 +310,12 @@ def main():
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}, WORLD_SIZE {world}); "
               "the sort runs on one GPU (no multi-GPU path)", file=sys.stderr)
         sys.exit(2)
+    extras = set() if args.no_extras else {e.strip() for e in args.extras.split(",") if e.strip()}
+    unknown = extras - {"pairs", "keys", "segmented", "serving"}
+    if unknown:
+        print(f"bench.py: unknown extra workloads {sorted(unknown)} "
+              "(choose from pairs, keys, segmented, serving)", file=sys.stderr)
+        sys.exit(2)
 
     import torch
 
@@ -355,11 +361,6 @@ def main():
              "algorithmic_bytes_per_key": round(total_bytes / n, 2),
              "whole_sort_frac_hbm_peak": round(total_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
-    extras = set() if args.no_extras else {e.strip() for e in args.extras.split(",") if e.strip()}
-    unknown = extras - {"pairs", "keys", "segmented", "serving"}
-    if unknown:
-        log(f"[bench] ERROR: unknown extra workloads {sorted(unknown)}")
-        sys.exit(2)
     if "pairs" in extras:
         log("[bench] stable pairs 2^28, keys in [0,1000), payload = index")
         extra["pairs_dup_2e28_Gkeys_s"], extra["pairs_kernels"] = bench_pairs(hs, torch, 2**28, 5, 1)
