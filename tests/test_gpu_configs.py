@@ -1,0 +1,134 @@
+"""Every configuration the autotuner can pick (local-sort tile shape, merge
+shape, fan-in 2 or 4, small-segment threshold) sorts bit-exactly like the
+oracle, so a tuning table can select none that is untested.  Inputs are sized
+so that the largest bucket holds more than four local-sort tiles (two fan-in-4
+rounds, three fan-in-2 rounds) and end in a ragged tile."""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import paper_2003_01216_amd as hsmod  # noqa: E402
+from paper_2003_01216_amd import autotune  # noqa: E402
+
+RAGGED = 1234
+I32, I64 = np.iinfo(np.int32), np.iinfo(np.int64)
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _cands(kind):
+    return [pytest.param(c, id="t{}x{}-m{}x{}-s{}-f{}".format(*c)) for c in autotune.candidates(kind)]
+
+
+@pytest.fixture(scope="module")
+def hs():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    hsmod.load_library()
+    saved = {(k, c): hsmod.hsort_get_config(k, size_class=c) for k in range(5) for c in range(4)}
+    yield hsmod
+    for (k, c), cfg in saved.items():
+        hsmod.hsort_set_config(k, *cfg[:5], fanin=cfg[5], size_class=c)
+
+
+def use(hs, kind, cfg):
+    for c in range(4):
+        hs.hsort_set_config(kind, *cfg[:5], fanin=cfg[5], size_class=c)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def scratch(hs, kind, n, nseg=1):
+    return torch.empty(hs.scratch_bytes(kind, n, nseg), dtype=torch.uint8, device="cuda")
+
+
+@pytest.mark.parametrize("cfg", _cands(hsmod.KEYS_I32))
+def test_keys_i32(hs, orc, cfg):
+    # full int32 range: buckets 0..4 of the shifted keys, the largest ~23 %
+    n = 18 * cfg[0] + RAGGED
+    k = np.random.default_rng(cfg[0] + cfg[2] + cfg[5]).integers(I32.min, I32.max, n, dtype=np.int32, endpoint=True)
+    say(f"config keys_i32 {cfg} n={n}")
+    use(hs, hs.KEYS_I32, cfg)
+    t = dev(k)
+    s = scratch(hs, hs.KEYS_I32, n)
+    hs.hsort_keys(t, scratch=s)
+    hs.hsort_check(s)
+    assert np.array_equal(t.cpu().numpy(), orc.sort_keys(k))
+
+
+@pytest.mark.parametrize("cfg", _cands(hsmod.KEYS_I64))
+def test_keys_i64(hs, orc, cfg):
+    # full int64 range: two buckets of the shifted keys, the larger ~55 %
+    n = 8 * cfg[0] + RAGGED
+    k = np.random.default_rng(cfg[0] + cfg[2] + cfg[5]).integers(I64.min, I64.max, n, dtype=np.int64, endpoint=True)
+    say(f"config keys_i64 {cfg} n={n}")
+    use(hs, hs.KEYS_I64, cfg)
+    t = dev(k)
+    s = scratch(hs, hs.KEYS_I64, n)
+    hs.hsort_keys(t, scratch=s)
+    hs.hsort_check(s)
+    assert np.array_equal(t.cpu().numpy(), orc.sort_keys(k))
+
+
+@pytest.mark.parametrize("span", ["dup", "full"])
+@pytest.mark.parametrize("cfg", _cands(hsmod.PAIRS_I32_U32))
+def test_pairs(hs, orc, cfg, span):
+    # "dup": keys in [0, 1000), ten buckets of ~10 %, narrow merge words;
+    # "full": the whole int32 range, wide merge words
+    if span == "dup":
+        n = 45 * cfg[0] + RAGGED
+        k, v = W.dup_pairs_i32(n, cfg[0] + cfg[2])
+    else:
+        n = 18 * cfg[0] + RAGGED
+        r = np.random.default_rng(cfg[0] + cfg[2] + 7)
+        k = r.integers(I32.min, I32.max, n, dtype=np.int32, endpoint=True)
+        v = r.integers(0, 2**32 - 1, n, dtype=np.uint32, endpoint=True)
+    say(f"config pairs {span} {cfg} n={n}")
+    use(hs, hs.PAIRS_I32_U32, cfg)
+    t, tv = dev(k), dev(v.view(np.int32))
+    s = scratch(hs, hs.PAIRS_I32_U32, n)
+    hs.hsort_pairs(t, tv, scratch=s)
+    hs.hsort_check(s)
+    ok, ov = orc.sort_pairs(k, v)
+    assert np.array_equal(t.cpu().numpy(), ok)
+    assert np.array_equal(tv.cpu().numpy().view(np.uint32), ov)
+
+
+def _segments(dtype, tile, seed):
+    """One segment of 18 tiles, then 59 of log-uniform sizes in [1, 2 tiles]
+    (whole-LDS and pipeline segments both), keys over the full range."""
+    r = np.random.default_rng(seed)
+    sizes = [18 * tile + 5] + np.exp(r.uniform(0, np.log(2 * tile), 59)).astype(np.int64).tolist()
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    info = np.iinfo(dtype)
+    keys = r.integers(info.min, info.max, int(off[-1]), dtype=dtype, endpoint=True)
+    return keys, off
+
+
+@pytest.mark.parametrize("dtype", [np.int32, np.int64])
+def test_segmented_every_config(hs, orc, dtype):
+    kind = hs.SEG_I32 if dtype == np.int32 else hs.SEG_I64
+    for cfg in autotune.candidates(kind):
+        keys, off = _segments(dtype, cfg[0], cfg[0] + cfg[4] + cfg[5])
+        nseg = off.size - 1
+        say(f"config seg {np.dtype(dtype).name} {cfg} n={keys.size}")
+        use(hs, kind, cfg)
+        t, o = dev(keys), dev(off)
+        s = scratch(hs, kind, keys.size, nseg)
+        hs.hsort_segmented(t, o, scratch=s)
+        hs.hsort_check(s)
+        ok, ob = orc.sort_segmented(keys, off)
+        assert np.array_equal(t.cpu().numpy(), ok), cfg
+        assert np.array_equal(hs.read_bounds(s, kind, keys.size, nseg).cpu().numpy(), ob), cfg
