@@ -386,28 +386,6 @@ __device__ __forceinline__ void lds_merge_window(const W* lds, int pa, int pb, W
     bitonic_merge<W, VT>(v);
 }
 
-// The same, also returning how many of the VT outputs come from A: the
-// number of i with a[i] <= b[VT-1-i] (the predicate falls from true to false
-// once along i, and its count is where the merge path crosses the window's
-// far diagonal).  Past the end of A its sentinels only tie with B's
-// sentinels or with a key equal to the sentinel, so the count can exceed
-// A's remaining length there and the caller clamps it.
-template <typename W, int VT>
-__device__ __forceinline__ int lds_merge_window_count(const W* lds, int pa, int pb, W (&v)[VT]) {
-    W b[VT];
-    lds_read_padded<W, VT>(lds, pa, v);
-    lds_read_padded<W, VT>(lds, pb, b);
-    int cnt = 0;
-#pragma unroll
-    for (int i = 0; i < VT; i++) {
-        const bool tb = b[VT - 1 - i] < v[i];
-        cnt += tb ? 0 : 1;
-        v[i] = tb ? b[VT - 1 - i] : v[i];
-    }
-    bitonic_merge<W, VT>(v);
-    return cnt;
-}
-
 // --------------------------------------------------------- wave/block helpers
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 

@@ -1069,40 +1069,29 @@ __device__ __forceinline__ void merge4_chunk(W* words, const uint32_t* sv, const
     const int c0 = g.c[0], c1 = g.c[1], c2 = g.c[2], c3 = g.c[3];
     const int o2 = c0 + c1, c = o2 + c2 + c3;
     // level 1: X' = merge(W0, W1) at x0, Y' = merge(W2, W3) at y0, in place
-    // of the windows (all reads end at the barrier before the writes).  A
-    // thread's jobs are consecutive: only its first one searches for its
-    // co-rank, each later one starts where the previous window's outputs
-    // end (or at 0, as the first job of Y').
+    // of the windows (all reads end at the barrier before the writes)
     const int x0 = g.at[0] & ~(VT - 1), y0 = g.at[2] & ~(VT - 1);
     const int jx = (o2 + VT - 1) / VT, jy = (c - o2 + VT - 1) / VT;
     {
         W v[JOBS][VT];
         int dst[JOBS];
-        int next = 0;  // co-rank after the previous job's outputs
 #pragma unroll
         for (int h = 0; h < JOBS; h++) {
-            const int j = tid * JOBS + h;
+            const int j = tid + h * NT;
             if (j < jx + jy) {
                 const int y = j >= jx;  // arithmetic selects keep these in registers
                 const int dt = (j - y * jx) * VT;
                 const int sa = g.at[0] + y * (g.at[2] - g.at[0]), sb = g.at[1] + y * (g.at[3] - g.at[1]);
                 const int na = c0 + y * (c2 - c0), nb = c1 + y * (c3 - c1);
-                int ai;
-                if (h == 0)
-                    ai = lds_corank<W, S / 2>(words, sa, sb, dt, na, nb);
-                else
-                    ai = dt == 0 ? 0 : min(next, na);
-                if (h + 1 < JOBS)
-                    next = ai + lds_merge_window_count<W, VT>(words, sa + ai, sb + dt - ai, v[h]);
-                else
-                    lds_merge_window<W, VT>(words, sa + ai, sb + dt - ai, v[h]);
+                const int ai = lds_corank<W, S / 2>(words, sa, sb, dt, na, nb);
+                lds_merge_window<W, VT>(words, sa + ai, sb + dt - ai, v[h]);
                 dst[h] = lds_pad<W>(x0 + y * (y0 - x0) + dt);
             }
         }
         __syncthreads();
 #pragma unroll
         for (int h = 0; h < JOBS; h++) {
-            const int j = tid * JOBS + h;
+            const int j = tid + h * NT;
             if (j < jx + jy) {
 #pragma unroll
                 for (int q = 0; q < VT; q++) words[dst[h] + q] = v[h][q];
@@ -1125,23 +1114,19 @@ __device__ __forceinline__ void merge4_chunk(W* words, const uint32_t* sv, const
     {
         const int jc = (c + VT - 1) / VT;
         W v[JOBS][VT];
-        int next = 0;
 #pragma unroll
         for (int h = 0; h < JOBS; h++) {
-            const int j = tid * JOBS + h;
+            const int j = tid + h * NT;
             if (j < jc) {
                 const int dt = j * VT;
-                const int ai = h == 0 ? lds_corank<W, S>(words, x0, y0, dt, o2, c - o2) : min(next, o2);
-                if (h + 1 < JOBS)
-                    next = ai + lds_merge_window_count<W, VT>(words, x0 + ai, y0 + dt - ai, v[h]);
-                else
-                    lds_merge_window<W, VT>(words, x0 + ai, y0 + dt - ai, v[h]);
+                const int ai = lds_corank<W, S>(words, x0, y0, dt, o2, c - o2);
+                lds_merge_window<W, VT>(words, x0 + ai, y0 + dt - ai, v[h]);
             }
         }
         __syncthreads();
 #pragma unroll
         for (int h = 0; h < JOBS; h++) {
-            const int j = tid * JOBS + h;
+            const int j = tid + h * NT;
             if (j < jc) {
                 W* dst = words + lds_pad<W>(j * VT);
 #pragma unroll
