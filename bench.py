@@ -13,11 +13,13 @@ Prints ONE JSON line on stdout:
              launch time (HIP events on the sorting stream, recorded in a
              separate run of up to five sorts so that the timed steps carry no
              per-kernel events) vs 8 TB/s HBM peak
-  cpu_baseline  the CPU oracle (single-threaded) on a bounded sample of the
-             same workload
-  extra      per-kernel table and the other workloads (stable pairs with
-             heavy duplicates, skewed keys, int64 keys, batched segmented vs
-             a per-array loop of the plain method)
+  cpu_baseline  the CPU oracle (single-threaded) on the metric's own input,
+             once; extra.cpu_openmp_hybrid is the paper's method with OpenMP
+             on all host cores, same input
+  extra      per-kernel table and the other workloads (2^20 keys eager and
+             graph-replayed, stable pairs with heavy duplicates, skewed keys,
+             int64 keys, batched segmented vs a per-array loop of the plain
+             method, eager and graph-captured, and the serving loop)
 """
 from __future__ import annotations
 
@@ -120,13 +122,14 @@ def bench_metric(hs, torch, n, steps, warmup):
     ms, _, copies = timed_sorts(hs, torch, make, lambda t: hs.hsort_keys(t, scratch), steps, warmup, timing=False)
     last = copies[-1]
     ok = bool(torch.all(last[1:] >= last[:-1]).item()) and int(last.to(torch.int64).sum()) == int(k.astype(np.int64).sum())
-    del copies
+    out = last.cpu().numpy()
+    del copies, last
     torch.cuda.empty_cache()
     rec_steps = min(steps, 5)
     _, rec, copies = timed_sorts(hs, torch, make, lambda t: hs.hsort_keys(t, scratch), rec_steps, 1)
     del copies
     torch.cuda.empty_cache()
-    return ms, rec, rec_steps, ok
+    return ms, rec, rec_steps, ok, k, out
 
 
 def bench_pairs(hs, torch, n, steps, warmup):
@@ -152,6 +155,26 @@ def bench_keys(hs, torch, k, steps, warmup):
     del copies
     torch.cuda.empty_cache()
     return k.size * steps / (ms * 1e-3) / 1e9, kernel_table(rec, steps)
+
+
+def bench_small_keys(hs, torch, n, steps=50, warmup=5):
+    """n uniform int32 keys (seed 0): per-call time of the plain sort, eager and replayed from a hipGraph,
+    refilling the same buffer from a resident copy outside the timed window before every call."""
+    base = torch.from_numpy(W.uniform_i32(n, 0)).cuda()
+    scratch = torch.empty(hs.scratch_bytes(hs.KEYS_I32, n), dtype=torch.uint8, device="cuda")
+    out = {"workload": f"sort 2^{int(np.log2(n))} int32 keys uniform in [0, 2^31-1), keys only, seed 0"}
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        ms_eager, _ = timed_refill(torch, base, lambda t: hs.hsort_keys(t, scratch), steps, warmup)
+        hs.hsort_graph_mode(True)
+        try:
+            ms_graph, _ = timed_refill(torch, base, lambda t: hs.hsort_keys(t, scratch), steps, warmup)
+        finally:
+            hs.hsort_graph_mode(False)
+            hs.hsort_graph_clear()
+    out.update({"eager_ms": round(ms_eager, 4), "eager_Gkeys_s": round(n / ms_eager / 1e6, 3),
+                "graph_ms": round(ms_graph, 4), "graph_Gkeys_s": round(n / ms_graph / 1e6, 3)})
+    return out
 
 
 def timed_refill(torch, base, run_one, steps, warmup):
@@ -226,16 +249,45 @@ def bench_segmented(hs, torch, steps, warmup, loop=True):
         torch.cuda.synchronize()
         loop_s = time.perf_counter() - t0
         same = bool(torch.equal(lw, work))  # loop and batched agree
+        # the same loop captured once into one graph on the side stream and
+        # replayed: no host launch cost per call, the fair comparison
+        lw.copy_(base)
+        side.synchronize()
+        g = torch.cuda.CUDAGraph()
+        t0 = time.perf_counter()
+        with torch.cuda.graph(g, stream=side):
+            loop(lw)
+        capture_s = time.perf_counter() - t0
+        loop_graph = []
+        for i in range(4):
+            lw.copy_(base)
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            g.replay()
+            b.record()
+            torch.cuda.synchronize()
+            if i:
+                loop_graph.append(a.elapsed_time(b))
+        same_graph = bool(torch.equal(lw, work))
+        del g
     torch.cuda.empty_cache()
+    loop_graph_ms = float(np.median(loop_graph))
     out.update({"per_array_loop_Gkeys_s": round(n / loop_s / 1e9, 4), "per_array_loop_ms": round(loop_s * 1e3, 2),
-                "speedup_graph_vs_loop": round(loop_s * 1e3 / ms_graph, 1), "loop_equals_batched": same})
+                "speedup_graph_vs_loop": round(loop_s * 1e3 / ms_graph, 1), "loop_equals_batched": same,
+                "per_array_loop_graph_Gkeys_s": round(n / loop_graph_ms / 1e6, 4),
+                "per_array_loop_graph_ms": round(loop_graph_ms, 3),
+                "per_array_loop_graph_capture_s": round(capture_s, 2),
+                "speedup_graph_vs_loop_graph": round(loop_graph_ms / ms_graph, 1),
+                "loop_graph_equals_batched": same_graph})
     return out
 
 
-def bench_serving(count=300, budget=64 << 30, streams=3, load=0.7):
+def bench_serving(count=1000, budget=64 << 30, small_budget=1 << 30, streams=3, load=0.7):
     """Poisson stream of int64 sort requests (sizes log-uniform in [2^10, 2^24], keys over the full int64
     range) through the continuous-batching server with a 64 GiB HBM budget.  The arrival rate is `load` times
-    the saturation rate measured first with every request submitted at once."""
+    the saturation rate measured first with every request submitted at once.  The same arrivals are then
+    replayed against a 1 GiB budget, under which admission has to wait for memory."""
     import threading
 
     import paper_2003_01216_amd.serve as serve
@@ -254,42 +306,73 @@ def bench_serving(count=300, budget=64 << 30, streams=3, load=0.7):
         sat = srv.stats()
     rate = load * count / sat["wall_s"]
     gaps = np.random.default_rng(1).exponential(1.0 / rate, count)
-    with serve.SortServer(hbm_budget=budget, streams=streams) as srv:
-        futs = []
 
-        def client():
-            for r, g in zip(reqs, gaps):
-                time.sleep(g)
-                futs.append(srv.submit(r))
+    def poisson_run(bud):
+        with serve.SortServer(hbm_budget=bud, streams=streams) as srv:
+            futs = []
 
-        th = threading.Thread(target=client)
-        th.start()
-        th.join()
-        outs = [f.result() for f in futs]
-        st = srv.stats()
-    ok = all(bool(np.all(o[1:] >= o[:-1])) for o in outs[:: max(1, count // 20)])
-    return {"workload": f"{count} int64 requests, sizes log-uniform [2^10, 2^24], keys full int64 range, Poisson arrivals",
-            "budget_bytes": budget, "streams": streams, "saturation_Gkeys_s": round(sat["Gkeys_s"], 3),
-            "saturation_requests_s": round(count / sat["wall_s"], 1), "rate_requests_s": round(rate, 1),
-            "Gkeys_s": round(st["Gkeys_s"], 3), "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
-            "mean_batch_requests": round(st["mean_batch_requests"], 2), "batches": st["batches"],
-            "overlap_s": round(st["overlap_s"], 3), "peak_in_flight_bytes": st["peak_in_flight_bytes"],
-            "sorted_check": ok, "note": "end to end: host arrays in, host arrays out (PCIe copies included)"}
+            def client():
+                for r, g in zip(reqs, gaps):
+                    time.sleep(g)
+                    futs.append(srv.submit(r))
+
+            th = threading.Thread(target=client)
+            th.start()
+            th.join()
+            outs = [f.result() for f in futs]
+            st = srv.stats()
+        ok = all(bool(np.all(o[1:] >= o[:-1])) for o in outs[:: max(1, count // 20)])
+        return {"budget_bytes": bud, "Gkeys_s": round(st["Gkeys_s"], 3), "p50_ms": round(st["p50_ms"], 3),
+                "p99_ms": round(st["p99_ms"], 3), "mean_batch_requests": round(st["mean_batch_requests"], 2),
+                "batches": st["batches"], "overlap_s": round(st["overlap_s"], 3),
+                "peak_in_flight_bytes": st["peak_in_flight_bytes"], "budget_waits": st["budget_waits"],
+                "sorted_check": ok}
+
+    full = poisson_run(budget)
+    small = poisson_run(small_budget)
+    out = {"workload": f"{count} int64 requests, sizes log-uniform [2^10, 2^24], keys full int64 range, "
+                       "Poisson arrivals", "streams": streams, "saturation_Gkeys_s": round(sat["Gkeys_s"], 3),
+           "saturation_requests_s": round(count / sat["wall_s"], 1), "rate_requests_s": round(rate, 1)}
+    out.update(full)
+    out["reduced_budget"] = small
+    out["note"] = "end to end: host arrays in, host arrays out (PCIe copies included)"
+    return out
 
 
-def cpu_baseline(samples=4, n=2**24):
-    """The oracle (single-threaded C) on `samples` arrays of n keys of the metric's distribution."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baselines(k, gpu_out):
+    """The oracle (single-threaded C) on the metric's own input, once, and the paper's method on all host
+    cores (OpenMP: one-step ten-bucket partition, per-thread quicksort, merge rounds) on the same input."""
     import oracle
 
-    total = 0.0
-    for s in range(samples):
-        k = W.uniform_i32(n, 100 + s)
-        t0 = time.perf_counter()
-        oracle.sort_keys(k)
-        total += time.perf_counter() - t0
-    return {"value": round(samples * n / total / 1e9, 5), "unit": "Gkeys/s", "cores": 1, "kind": "oracle",
-            "sample": f"{samples} arrays of 2^{int(np.log2(n))} int32 keys uniform in [0, 2^31-1) "
-                      f"(seeds 100..{99 + samples}), {total:.1f} s of CPU"}
+    n = k.size
+    host_cores = len(os.sched_getaffinity(0))
+    t0 = time.perf_counter()
+    ref = oracle.sort_keys(k)
+    dt = time.perf_counter() - t0
+    base = {"value": round(n / dt / 1e9, 5), "unit": "Gkeys/s", "cores": 1, "kind": "oracle",
+            "sample": f"the metric's input itself (2^{int(np.log2(n))} int32 keys uniform in [0, 2^31-1), seed 0), "
+                      f"sorted once in {dt:.1f} s",
+            "cpu_model": cpu_model(), "host_cores": host_cores,
+            "equals_gpu_output": bool(np.array_equal(ref, gpu_out)) if gpu_out is not None else None}
+    del ref
+    t0 = time.perf_counter()
+    out, used = oracle.omp_hybrid_sort(k, host_cores)
+    dt = time.perf_counter() - t0
+    omp = {"value": round(n / dt / 1e9, 5), "unit": "Gkeys/s", "cores": used,
+           "kind": "the paper's method on the host (OpenMP, Sections 3.2-3.4)",
+           "sample": f"the metric's input, sorted once in {dt:.2f} s", "cpu_model": base["cpu_model"],
+           "equals_gpu_output": bool(np.array_equal(out, gpu_out)) if gpu_out is not None else None}
+    return base, omp
 
 
 def main():
@@ -300,8 +383,8 @@ def main():
     ap.add_argument("--log2n", type=int, default=28, help="keys in the metric workload (2^log2n)")
     ap.add_argument("--no-extras", action="store_true", help="only the metric workload")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--extras", default="pairs,keys,segmented,serving",
-                    help="comma list of the extra workloads to run: pairs, keys, segmented, serving")
+    ap.add_argument("--extras", default="small,pairs,keys,segmented,serving",
+                    help="comma list of the extra workloads to run: small, pairs, keys, segmented, serving")
     ap.add_argument("--no-loop", action="store_true", help="segmented: skip the per-array loop of plain calls")
     args = ap.parse_args()
 
@@ -311,10 +394,10 @@ def main():
               "the sort runs on one GPU (no multi-GPU path)", file=sys.stderr)
         sys.exit(2)
     extras = set() if args.no_extras else {e.strip() for e in args.extras.split(",") if e.strip()}
-    unknown = extras - {"pairs", "keys", "segmented", "serving"}
+    unknown = extras - {"small", "pairs", "keys", "segmented", "serving"}
     if unknown:
         print(f"bench.py: unknown extra workloads {sorted(unknown)} "
-              "(choose from pairs, keys, segmented, serving)", file=sys.stderr)
+              "(choose from small, pairs, keys, segmented, serving)", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -324,7 +407,7 @@ def main():
     hs.load_library()
     n = 1 << args.log2n
     log(f"[bench] metric workload: 2^{args.log2n} int32 uniform keys, {args.steps} steps, {args.warmup} warm-up")
-    ms, rec, rec_steps, ok = bench_metric(hs, torch, n, args.steps, args.warmup)
+    ms, rec, rec_steps, ok, metric_in, metric_out = bench_metric(hs, torch, n, args.steps, args.warmup)
     if not ok:
         log("[bench] ERROR: output of the last step is not sorted")
         sys.exit(1)
@@ -361,6 +444,9 @@ def main():
              "algorithmic_bytes_per_key": round(total_bytes / n, 2),
              "whole_sort_frac_hbm_peak": round(total_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
+    if "small" in extras:
+        log("[bench] 2^20 uniform int32 (eager and graph replay)")
+        extra["uniform_2e20"] = bench_small_keys(hs, torch, 2**20)
     if "pairs" in extras:
         log("[bench] stable pairs 2^28, keys in [0,1000), payload = index")
         extra["pairs_dup_2e28_Gkeys_s"], extra["pairs_kernels"] = bench_pairs(hs, torch, 2**28, 5, 1)
@@ -378,8 +464,8 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        log("[bench] CPU oracle baseline")
-        cpu = cpu_baseline()
+        log("[bench] CPU baselines: the oracle on one core, the OpenMP hybrid on all cores")
+        cpu, extra["cpu_openmp_hybrid"] = cpu_baselines(metric_in, metric_out)
 
     line = {
         "metric": "Gkeys/s + % HBM peak, int32 n=2^28; batched segmented vs per-array plain",

@@ -8,8 +8,8 @@
  * into ten non-overlapping buckets, a local sort of each bucket's partitions,
  * then non-recursive (bottom-up) merge rounds of the sorted runs inside each
  * bucket.  The buckets' order equals the key order, so the concatenation of
- * the sorted buckets is the sorted array (Section 3.4: each sorted bucket goes
- * "to its place in the original array").
+ * the sorted buckets is the sorted array (Section 3.4: every sorted bucket
+ * returns to its own position in the array).
  *
  * Conventions for every entry point:
  *   - keys, vals, offsets and scratch are DEVICE pointers (hipMalloc'd or
@@ -20,14 +20,15 @@
  *     `scratch` buffer of at least hsort_scratch_bytes(...) bytes.  Scratch
  *     contents are undefined after a call, except the bucket bounds (see
  *     hsort_bounds_offset) and the error word read by hsort_check.
- *   - argument errors (null pointer with n > 0, negative sizes, n or a
- *     segment above HSORT_MAX_KEYS, scratch too small) are returned
- *     synchronously before anything is enqueued; n == 0 or nseg == 0 is a
- *     no-op returning HSORT_OK.  A failed launch returns HSORT_ERR_HIP with a
- *     message in hsort_last_error().  Invalid segment offsets are detected on
- *     the device: every kernel of the call then does nothing, and
- *     hsort_check() reports HSORT_ERR_INVALID.  No C++ exception crosses
- *     this boundary.
+ *   - argument errors (null pointer with n > 0, negative sizes, n above
+ *     HSORT_MAX_KEYS, nseg above HSORT_MAX_SEGMENTS, scratch too small) are
+ *     returned synchronously before anything is enqueued; n == 0 or
+ *     nseg == 0 is a no-op returning HSORT_OK.  A failed launch returns
+ *     HSORT_ERR_HIP with a message in hsort_last_error().  Invalid segment
+ *     offsets, and a segment longer than the caller's max_seg_len, are
+ *     detected on the device: every kernel of the call then does nothing
+ *     (the keys are left as they were), and hsort_check() reports
+ *     HSORT_ERR_INVALID.  No C++ exception crosses this boundary.
  *   - calls on distinct scratch buffers may run concurrently on distinct
  *     streams; the host-side state (configuration, timing records) is
  *     guarded by a mutex.
@@ -61,6 +62,9 @@ typedef enum {
 
 /* Largest number of keys in one call (and in one segment). */
 #define HSORT_MAX_KEYS ((int64_t)2147483647)
+/* Largest number of segments in one segmented call (the per-bucket tables
+ * index buckets of all segments with 32-bit integers). */
+#define HSORT_MAX_SEGMENTS ((int64_t)16777216)
 
 /* Bytes of scratch a call of `kind` over n keys in nseg segments needs
  * (nseg is ignored for the non-segmented kinds).  Pure host function. */
@@ -75,13 +79,22 @@ int hsort_keys_i64(int64_t* keys, int64_t n, void* scratch, size_t scratch_bytes
 int hsort_pairs(int32_t* keys, uint32_t* vals, int64_t n, void* scratch, size_t scratch_bytes, void* stream);
 
 /* Sorts each segment keys[offsets[i] .. offsets[i+1]) independently, for
- * i in [0, nseg).  offsets: nseg+1 device int64, non-decreasing, with
- * 0 <= offsets[0] and offsets[nseg] <= n (n = length of `keys`); keys
- * outside [offsets[0], offsets[nseg]) are untouched.  Every segment gets the
- * full method; the independent buckets of all segments are scheduled as one
- * flat work list.  max_seg_len: an upper bound on the largest segment that
- * the caller knows (it bounds the number of merge rounds launched), or 0 if
- * unknown. */
+ * i in [0, nseg) (Section 3.4: the buckets are independent units of work;
+ * here every segment gets its own ten buckets and all buckets of all
+ * segments form one flat work list).  Ascending, in place.
+ *   keys:        device array of n keys (n bounds the offsets; keys outside
+ *                [offsets[0], offsets[nseg]) are untouched).
+ *   offsets:     nseg+1 device int64, non-decreasing, with 0 <= offsets[0]
+ *                and offsets[nseg] <= n.  Read on the device only, so a
+ *                graph replay may change their values.
+ *   max_seg_len: 0, or an upper bound on every segment's length.  A bound
+ *                lets the call launch only the merge rounds such a segment
+ *                needs and selects the tuning class; it is checked on the
+ *                device, and a longer segment makes the whole call do
+ *                nothing and hsort_check() report HSORT_ERR_INVALID.
+ *                Negative: HSORT_ERR_INVALID at once.
+ *   nseg:        at most HSORT_MAX_SEGMENTS (else HSORT_ERR_UNSUPPORTED).
+ * The bucket bounds of every segment are left in scratch (hsort_bounds_offset). */
 int hsort_segmented(int32_t* keys, int64_t n, const int64_t* offsets, int64_t nseg, int64_t max_seg_len,
                     void* scratch, size_t scratch_bytes, void* stream);
 int hsort_segmented_i64(int64_t* keys, int64_t n, const int64_t* offsets, int64_t nseg, int64_t max_seg_len,
@@ -95,8 +108,9 @@ int hsort_segmented_i64(int64_t* keys, int64_t n, const int64_t* offsets, int64_
 size_t hsort_bounds_offset(int kind, int64_t n, int64_t nseg);
 
 /* Synchronises `stream` and reads the device-side error word of the last
- * call that used `scratch`: HSORT_ERR_INVALID if its offsets were invalid
- * (or a device-side consistency check failed),
+ * call that used `scratch`: HSORT_ERR_INVALID if its offsets were invalid,
+ * a segment was longer than its max_seg_len, or a device-side consistency
+ * check failed,
  * HSORT_ERR_HIP if the synchronisation failed, HSORT_OK otherwise. */
 int hsort_check(const void* scratch, void* stream);
 

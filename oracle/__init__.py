@@ -21,6 +21,10 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# the paper's method on the host's cores (OpenMP): a CPU comparison point for
+# the benchmark, not the oracle
+_OMP_SRC = os.path.join(_HERE, "omp_hybrid.c")
+_OMP_LIB = os.path.join(_HERE, "libomp_hybrid.so")
 
 
 def build(force: bool = False, src: str = _SRC, out: str = _LIB) -> str:
@@ -30,6 +34,35 @@ def build(force: bool = False, src: str = _SRC, out: str = _LIB) -> str:
         subprocess.check_call(["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-fPIC", "-shared", "-o", tmp, src])
         os.replace(tmp, out)
     return out
+
+
+def build_omp(force: bool = False) -> str:
+    """Compile omp_hybrid.c into libomp_hybrid.so (gcc -O2 -fopenmp)."""
+    if force or not os.path.exists(_OMP_LIB) or os.path.getmtime(_OMP_LIB) < os.path.getmtime(_OMP_SRC):
+        tmp = _OMP_LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-fopenmp", "-fPIC", "-shared", "-o", tmp,
+                               _OMP_SRC])
+        os.replace(tmp, _OMP_LIB)
+    return _OMP_LIB
+
+
+_omp = None
+
+
+def omp_hybrid_sort(keys, threads: int = 0):
+    """(sorted int32 keys, threads used): Section 3.4's one-step decimal MSD
+    partition and the shared-memory quicksort + merge-round hybrid of
+    Sections 3.2-3.3 on `threads` host threads (0: all OpenMP allows)."""
+    global _omp
+    if _omp is None:
+        _omp = ctypes.CDLL(build_omp())
+        _omp.omp_hybrid_sort_i32.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int]
+        _omp.omp_hybrid_sort_i32.restype = ctypes.c_int
+    k = np.ascontiguousarray(keys, dtype=np.int32).copy()
+    used = _omp.omp_hybrid_sort_i32(_ptr(k), k.size, int(threads))
+    if used < 0:
+        raise RuntimeError("omp_hybrid_sort: allocation failed")
+    return k, used
 
 
 def _bind(path):

@@ -144,9 +144,13 @@ def _scratch(kind, n, nseg, device, scratch):
     need = scratch_bytes(kind, n, nseg)
     if scratch is None:
         return torch.empty(max(need, 1), dtype=torch.uint8, device=device)
-    if scratch.numel() * scratch.element_size() < need:
+    if _nbytes(scratch) < need:
         raise HsortError(HSORT_ERR_SCRATCH, f"scratch needs {need} bytes")
     return scratch
+
+
+def _nbytes(t: torch.Tensor) -> int:
+    return t.numel() * t.element_size()
 
 
 def hsort_keys(keys: torch.Tensor, scratch: torch.Tensor | None = None) -> torch.Tensor:
@@ -156,7 +160,7 @@ def hsort_keys(keys: torch.Tensor, scratch: torch.Tensor | None = None) -> torch
     n = keys.numel()
     s = _scratch(kind, n, 1, keys.device, scratch)
     fn = load_library().hsort_keys_i32 if kind == KEYS_I32 else load_library().hsort_keys_i64
-    _check(fn(_ptr(keys), n, _ptr(s), s.numel() * s.element_size(), _stream(keys)))
+    _check(fn(_ptr(keys), n, _ptr(s), _nbytes(s), _stream(keys)))
     return keys
 
 
@@ -180,7 +184,7 @@ def hsort_pairs(keys: torch.Tensor, vals: torch.Tensor, scratch: torch.Tensor | 
         raise ValueError("keys and vals differ in length")
     n = keys.numel()
     s = _scratch(PAIRS_I32_U32, n, 1, keys.device, scratch)
-    _check(load_library().hsort_pairs(_ptr(keys), _ptr(vals), n, _ptr(s), s.numel(), _stream(keys)))
+    _check(load_library().hsort_pairs(_ptr(keys), _ptr(vals), n, _ptr(s), _nbytes(s), _stream(keys)))
     return keys, vals
 
 
@@ -196,7 +200,7 @@ def hsort_segmented(keys: torch.Tensor, offsets: torch.Tensor, max_seg_len: int 
     n = keys.numel()
     s = _scratch(kind, n, max(nseg, 0), keys.device, scratch)
     fn = load_library().hsort_segmented if kind == SEG_I32 else load_library().hsort_segmented_i64
-    _check(fn(_ptr(keys), n, _ptr(offsets), nseg, int(max_seg_len), _ptr(s), s.numel(), _stream(keys)))
+    _check(fn(_ptr(keys), n, _ptr(offsets), nseg, int(max_seg_len), _ptr(s), _nbytes(s), _stream(keys)))
     return keys
 
 
@@ -245,7 +249,7 @@ def hsort_debug_stage(keys: torch.Tensor, stage: int, vals: torch.Tensor | None 
         kind = KEYS_I32 if keys.dtype == torch.int32 else KEYS_I64
     n = keys.numel()
     s = _scratch(kind, n, 1, keys.device, scratch)
-    _check(load_library().hsort_debug_stage(kind, _ptr(keys), _ptr(vals), n, stage, _ptr(s), s.numel(),
+    _check(load_library().hsort_debug_stage(kind, _ptr(keys), _ptr(vals), n, stage, _ptr(s), _nbytes(s),
                                             _stream(keys)))
     return keys
 

@@ -5,7 +5,8 @@ device -- tile (keys per local-sort partition) x keys per thread, merge
 outputs per workgroup x per thread, the largest segment sorted wholly in
 LDS, and the merge fan-in (2 or 4 runs per round) -- on a representative synthetic workload of that class, and writes the
 fastest to a table (``tuning.txt``, applied by the binding when the library
-loads; see ``hsort_load_tuning``) plus a JSON report of every measurement.
+loads; see ``hsort_load_tuning``), and, with ``--report PATH``, a JSON log
+of every measurement (a log, kept out of the package).
 
     python -m paper_2003_01216_amd.autotune [--quick] [--out tuning.txt]
 
@@ -176,21 +177,23 @@ def tune(kinds, classes, quick=False, reps=5, log=print):
     return table, report
 
 
-def write_table(table, path, report=None):
+def write_table(table, path, report=None, report_path=None):
     lines = ["# hsort tuning table: kind size_class tile tile_vt merge_nv merge_vt small_max fanin",
              f"# written by paper_2003_01216_amd.autotune on {time.strftime('%Y-%m-%d %H:%M:%S')}"]
     for (kind, cls), cfg in sorted(table.items()):
         lines.append(f"{kind} {cls} " + " ".join(str(x) for x in cfg))
     with open(path, "w") as f:
         f.write("\n".join(lines) + "\n")
-    if report is not None:
-        with open(os.path.splitext(path)[0] + "_report.json", "w") as f:
+    if report is not None and report_path:
+        os.makedirs(os.path.dirname(os.path.abspath(report_path)), exist_ok=True)
+        with open(report_path, "w") as f:
             json.dump(report, f, indent=1)
 
 
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--out", default=TUNING_PATH)
+    ap.add_argument("--report", default="", help="write the JSON log of every measurement to this path")
     ap.add_argument("--quick", action="store_true", help="smaller workloads (sizes capped at 2^24)")
     ap.add_argument("--kinds", default="keys_i32,keys_i64,pairs_i32,seg_i32,seg_i64")
     ap.add_argument("--classes", default="0,1,2,3")
@@ -201,7 +204,7 @@ def main(argv=None):
     classes = [int(c) for c in args.classes.split(",")]
     t0 = time.time()
     table, report = tune(kinds, classes, args.quick, args.reps, log=lambda m: print(m, flush=True))
-    write_table(table, args.out, report)
+    write_table(table, args.out, report, args.report)
     print(f"wrote {args.out} ({len(table)} entries) in {time.time() - t0:.0f} s", flush=True)
     return 0
 

@@ -249,7 +249,7 @@ Layout make_layout(int kind, int64_t n, int64_t nseg, const Config& c) {
 
 template <typename K>
 Work<K> make_work(const Layout& L, char* scr, K* keys, uint32_t* vals, const int64_t* off, int64_t n, int64_t nseg,
-                  const Config& c, int64_t small_max) {
+                  const Config& c, int64_t small_max, int64_t max_seg_len) {
     Work<K> w{};
     w.keys = keys;
     w.vals = vals;
@@ -285,6 +285,7 @@ Work<K> make_work(const Layout& L, char* scr, K* keys, uint32_t* vals, const int
     w.fanin = (int32_t)c.fanin;
     w.nv = (int32_t)c.merge_nv;
     w.small_max = small_max;
+    w.max_seg_len = max_seg_len;
     return w;
 }
 
@@ -375,7 +376,7 @@ int enqueue(int kind, K* keys, uint32_t* vals, int64_t n, const int64_t* off, in
                                            std::to_string(scratch_bytes));
     const int64_t small_max = small_override >= 0 ? small_override : c.small_max;
     char* scr = (char*)scratch;
-    Work<K> w = make_work<K>(L, scr, keys, vals, off, n, nseg, c, small_max);
+    Work<K> w = make_work<K>(L, scr, keys, vals, off, n, nseg, c, small_max, seg ? max_seg_len : 0);
     const double kb = sizeof(K) + (PAIRS ? 4.0 : 0.0);
     {
         Timer t(st, "setup", 0);
@@ -636,9 +637,11 @@ int hsort_pairs(int32_t* keys, uint32_t* vals, int64_t n, void* scratch, size_t 
                               (hipStream_t)stream, 3, -1);
 }
 
-static int seg_args(const void* keys, int64_t n, const int64_t* offsets, int64_t nseg, const void* scratch) {
+static int seg_args(const void* keys, int64_t n, const int64_t* offsets, int64_t nseg, int64_t max_seg_len,
+                    const void* scratch) {
     if (nseg < 0) return fail(HSORT_ERR_INVALID, "nseg < 0");
-    if (nseg > HSORT_MAX_KEYS) return fail(HSORT_ERR_UNSUPPORTED, "nseg above HSORT_MAX_KEYS");
+    if (nseg > HSORT_MAX_SEGMENTS) return fail(HSORT_ERR_UNSUPPORTED, "nseg above HSORT_MAX_SEGMENTS");
+    if (max_seg_len < 0) return fail(HSORT_ERR_INVALID, "max_seg_len < 0");
     if (nseg > 0 && !offsets) return fail(HSORT_ERR_INVALID, "null offsets");
     return check_common(keys, n, scratch);
 }
@@ -646,7 +649,7 @@ static int seg_args(const void* keys, int64_t n, const int64_t* offsets, int64_t
 int hsort_segmented(int32_t* keys, int64_t n, const int64_t* offsets, int64_t nseg, int64_t max_seg_len,
                     void* scratch, size_t scratch_bytes, void* stream) {
     g_err.clear();
-    int rc = seg_args(keys, n, offsets, nseg, scratch);
+    int rc = seg_args(keys, n, offsets, nseg, max_seg_len, scratch);
     if (rc || n == 0 || nseg == 0) return rc;
     return run<int32_t, false>(HSORT_SEG_I32, keys, nullptr, n, offsets, nseg, max_seg_len, scratch, scratch_bytes,
                                (hipStream_t)stream, 3, -1);
@@ -655,7 +658,7 @@ int hsort_segmented(int32_t* keys, int64_t n, const int64_t* offsets, int64_t ns
 int hsort_segmented_i64(int64_t* keys, int64_t n, const int64_t* offsets, int64_t nseg, int64_t max_seg_len,
                         void* scratch, size_t scratch_bytes, void* stream) {
     g_err.clear();
-    int rc = seg_args(keys, n, offsets, nseg, scratch);
+    int rc = seg_args(keys, n, offsets, nseg, max_seg_len, scratch);
     if (rc || n == 0 || nseg == 0) return rc;
     return run<int64_t, false>(HSORT_SEG_I64, keys, nullptr, n, offsets, nseg, max_seg_len, scratch, scratch_bytes,
                                (hipStream_t)stream, 3, -1);
@@ -669,7 +672,8 @@ int hsort_check(const void* scratch, void* stream) {
     uint32_t flag = 0;
     e = hipMemcpy(&flag, scratch, sizeof(flag), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return fail(HSORT_ERR_HIP, std::string("hipMemcpy: ") + hipGetErrorString(e));
-    if (flag & 1u) return fail(HSORT_ERR_INVALID, "invalid segment offsets");
+    if (flag & kErrOffsets) return fail(HSORT_ERR_INVALID, "invalid segment offsets");
+    if (flag & kErrSegLen) return fail(HSORT_ERR_INVALID, "a segment is longer than max_seg_len");
     if (flag) return fail(HSORT_ERR_INVALID, "internal consistency check failed on the device");
     return HSORT_OK;
 }

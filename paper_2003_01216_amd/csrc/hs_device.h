@@ -290,23 +290,6 @@ __device__ __forceinline__ void lane_merge(W (&v)[VT], int lane) {
     bitonic_merge<W, VT>(v);
 }
 
-// Merge path (co-rank): of the first `diag` outputs of the stable merge of
-// sorted A[0..na) and B[0..nb), how many come from A.  Ties go to A.
-// Accessors read A[i] / B[j].
-template <typename W, typename FA, typename FB>
-__device__ __forceinline__ int merge_path(int diag, int na, int nb, FA A, FB B) {
-    int lo = diag > nb ? diag - nb : 0;
-    int hi = diag < na ? diag : na;
-    while (lo < hi) {
-        int mid = (lo + hi) >> 1;
-        if (!(B(diag - 1 - mid) < A(mid)))
-            lo = mid + 1;
-        else
-            hi = mid;
-    }
-    return lo;
-}
-
 // Branch-free co-rank with log2(STEP0)+1 unrolled probes; STEP0 is a power
 // of two not below the largest possible hi - lo.  Probes outside [lo, hi)
 // read index 0 of each array instead (always a valid address for callers)
@@ -576,22 +559,6 @@ __device__ __forceinline__ void bound2_sampled(const K* R, int64_t nr, const K* 
         const int64_t mr = pr + step - 1, mq = pq + step - 1;
         if (mr < er && in(R[mr])) pr += step;
         if (mq < eq && in(Q[mq])) pq += step;
-    }
-}
-
-// Bounds of v in two sorted runs R[0..nr) and Q[0..nq) (elements < v when
-// UPPER is false, <= v when true), the two searches stepping together.
-template <bool UPPER, typename K>
-__device__ __forceinline__ void bound2_steps(const K* R, int64_t nr, const K* Q, int64_t nq, K v, int64_t top,
-                                             int64_t& pr, int64_t& pq) {
-    pr = 0;
-    pq = 0;
-    for (int64_t step = top; step > 0; step >>= 1) {
-        const bool ir = pr + step <= nr, iq = pq + step <= nq;
-        const K r = ir ? R[pr + step - 1] : v;  // no read outside a run (it may be empty)
-        const K q = iq ? Q[pq + step - 1] : v;
-        if (ir && (UPPER ? !(v < r) : r < v)) pr += step;
-        if (iq && (UPPER ? !(v < q) : q < v)) pq += step;
     }
 }
 

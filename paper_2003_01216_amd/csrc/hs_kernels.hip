@@ -254,14 +254,18 @@ __global__ void k_init(Work<K> w, int64_t* own_off) {
 }
 
 // Size class of every segment, histogram-tile count of the large ones, and
-// validation of the offsets (non-decreasing, inside [0, n]).
+// validation of the offsets (non-decreasing, inside [0, n]) and of the
+// caller's bound on the segment length: the host launches only the merge
+// rounds that bound needs, so a longer segment would be left partly merged.
+// Either error makes every later kernel of the call do nothing.
 template <typename K>
 __global__ void k_classify(Work<K> w) {
     for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < w.nseg; s += gridDim.x * blockDim.x) {
         const int64_t a = w.off[s], b = w.off[s + 1];
         const bool bad = (b < a) || (s == 0 && a < 0) || (s == w.nseg - 1 && b > w.n);
-        if (bad) atomicOr(w.err, 1u);
+        if (bad) atomicOr(w.err, kErrOffsets);
         const int64_t m = b - a;
+        if (!bad && w.max_seg_len > 0 && m > w.max_seg_len) atomicOr(w.err, kErrSegLen);
         w.tilecnt[s] = (!bad && m > w.small_max) ? (int32_t)((m + kHistTile - 1) / kHistTile) : 0;
     }
 }
@@ -994,7 +998,7 @@ __device__ __forceinline__ Chunk4<K> chunk4_of(const Work<K>& w, int round, int6
     asm volatile("" ::"s"(g.ks[0]), "s"(g.ks[3]), "s"(g.dk));
     if constexpr (PAIRS) asm volatile("" ::"s"(g.vs[0]), "s"(g.dv));
     const bool act = r0.flags & kActive;
-    if (act && bad && threadIdx.x == 0) atomicOr(w.err, 2u);
+    if (act && bad && threadIdx.x == 0) atomicOr(w.err, kErrConsistency);
     g.active = act && !bad && c != 0;
     return g;
 }

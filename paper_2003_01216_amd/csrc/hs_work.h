@@ -124,6 +124,12 @@ struct Work {
     int32_t fanin;      // runs merged per round: 2 or 4
     int32_t nv;         // outputs per merge workgroup (divides T)
     int64_t small_max;  // segments up to this size are sorted wholly in LDS
+    int64_t max_seg_len;  // the caller's bound on the longest segment (merge rounds launched), 0 if none
 };
+
+// Bits of the device-side error word (read by hsort_check).
+constexpr uint32_t kErrOffsets = 1;      // offsets decreasing or outside [0, n]
+constexpr uint32_t kErrConsistency = 2;  // a merge chunk inconsistent with its split points
+constexpr uint32_t kErrSegLen = 4;       // a segment longer than the caller's max_seg_len
 
 }  // namespace hs

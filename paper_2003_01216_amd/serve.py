@@ -105,7 +105,8 @@ class GpuExecutor:
             doff.copy_(torch.from_numpy(off), non_blocking=False)
             _check(self.lib.hsort_segmented_i64(ctypes.c_void_p(keys.data_ptr()), n, ctypes.c_void_p(doff.data_ptr()),
                                                 sizes.size, int(sizes.max()), ctypes.c_void_p(scratch.data_ptr()),
-                                                scratch.numel(), ctypes.c_void_p(st.cuda_stream)))
+                                                scratch.numel() * scratch.element_size(),
+                                                ctypes.c_void_p(st.cuda_stream)))
             pin_out = self._pinned(slot, "pin_out", n)
             pin_out.copy_(keys, non_blocking=True)
             st.synchronize()
@@ -142,6 +143,7 @@ class SortServer:
         self._done = []
         self._batches = []  # (t_start, t_end, requests, keys) per batch
         self._keys_done = 0
+        self._budget_waits = 0  # times a free worker found requests waiting but too little budget free
         self._workers = []
         for i in range(streams):
             th = threading.Thread(target=self._worker, args=(self.executor.make_slot(),), daemon=True,
@@ -207,6 +209,7 @@ class SortServer:
                         batch, need = self._take_batch()
                         if batch:
                             break
+                        self._budget_waits += 1
                     elif self._closed:
                         return
                     self._cv.wait()
@@ -237,8 +240,9 @@ class SortServer:
             done = list(self._done)
             batches = list(self._batches)
             peak = self._peak_bytes
+            waits = self._budget_waits
         if not done:
-            return {"requests": 0}
+            return {"requests": 0, "budget_waits": waits}
         lat = np.array([(r.t_done - r.t_submit) * 1e3 for r in done])
         t0 = min(r.t_submit for r in done)
         t1 = max(r.t_done for r in done)
@@ -256,4 +260,4 @@ class SortServer:
                 "Gkeys_s": keys / (t1 - t0) / 1e9, "p50_ms": float(np.percentile(lat, 50)),
                 "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()), "batches": len(batches),
                 "mean_batch_requests": float(np.mean([b[2] for b in batches])) if batches else 0.0,
-                "peak_in_flight_bytes": int(peak), "overlap_s": overlap}
+                "peak_in_flight_bytes": int(peak), "overlap_s": overlap, "budget_waits": waits}

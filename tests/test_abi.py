@@ -68,6 +68,30 @@ def test_argument_errors_are_synchronous(lib):
     assert b"scratch" in lib.hsort_last_error()
 
 
+def test_segment_count_and_hint_limits(lib):
+    # more segments than the per-bucket tables can index: rejected before
+    # anything is enqueued (10 * nseg buckets must stay within 32 bits)
+    fake = ctypes.c_void_p(0x1000)
+    big = (1 << 24) + 1
+    assert lib.hsort_segmented(fake, 10, fake, big, 0, fake, 1 << 40, None) == 4
+    assert b"HSORT_MAX_SEGMENTS" in lib.hsort_last_error()
+    assert lib.hsort_segmented_i64(fake, 10, fake, (1 << 31) - 1, 0, fake, 1 << 40, None) == 4
+    assert lib.hsort_segmented(fake, 10, fake, 3, -5, fake, 1 << 40, None) == 1  # negative hint
+    assert b"max_seg_len" in lib.hsort_last_error()
+    assert 10 * (1 << 24) < 2**31 - 1
+
+
+def test_binding_passes_byte_counts(monkeypatch):
+    # a scratch tensor of a wider dtype is sized in bytes, not elements
+    import paper_2003_01216_amd as hs
+    import torch
+
+    t = torch.empty(7, dtype=torch.int64)
+    assert hs._nbytes(t) == 56
+    src = open(os.path.join(ROOT, "paper_2003_01216_amd", "__init__.py")).read()
+    assert "s.numel()," not in src and "scratch.numel()," not in src
+
+
 def test_config_roundtrip(lib):
     import paper_2003_01216_amd as hs
 

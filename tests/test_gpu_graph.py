@@ -97,6 +97,41 @@ def test_segmented_graph_new_offsets(hs, orc):
             hs.hsort_graph_mode(False)
 
 
+def test_graph_replay_with_segment_beyond_hint(hs, orc):
+    """A graph captured for max_seg_len = 4096 and replayed with offsets whose
+    segment is longer: the device check reports it and leaves the keys, and a
+    later replay with valid offsets sorts again."""
+    n, nseg = 40_000, 20
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        t = torch.empty(n, dtype=torch.int32, device="cuda")
+        o = torch.empty(nseg + 1, dtype=torch.int64, device="cuda")
+        s = torch.empty(hs.scratch_bytes(hs.SEG_I32, n, nseg), dtype=torch.uint8, device="cuda")
+        good = np.linspace(0, n, nseg + 1).astype(np.int64)  # 2000 keys each
+        bad = good.copy()
+        bad[5] = bad[4] + 1
+        bad[6] = bad[5] + 9000  # one segment of 9000 keys, beyond the 4096 hint
+        hs.hsort_graph_mode(True)
+        try:
+            for rep, off in enumerate([good, bad, good]):
+                k = np.random.default_rng(200 + rep).integers(0, 2**31 - 1, n, dtype=np.int32)
+                t.copy_(dev(k))
+                o.copy_(dev(off))
+                eager_noise()
+                say(f"graph replay against the hint {rep}")
+                hs.hsort_segmented(t, o, max_seg_len=4096, scratch=s)
+                if off is bad:
+                    with pytest.raises(hs.HsortError) as e:
+                        hs.hsort_check(s)
+                    assert "max_seg_len" in str(e.value)
+                    assert np.array_equal(t.cpu().numpy(), k)
+                else:
+                    hs.hsort_check(s)
+                    assert np.array_equal(t.cpu().numpy(), orc.sort_segmented(k, off)[0]), rep
+        finally:
+            hs.hsort_graph_mode(False)
+
+
 @pytest.mark.parametrize("what", ["keys_i32", "keys_i64", "pairs"])
 def test_plain_graph_replays(hs, orc, what):
     n = 3_000_017

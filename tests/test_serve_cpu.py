@@ -77,6 +77,7 @@ def test_budget_never_exceeded_and_admission_blocks(orc):
     assert st["peak_in_flight_bytes"] <= budget
     assert ex.max_running == 1  # the budget, not the 4 streams, limited concurrency
     assert all(len(b) == 1 for b in ex.batches)
+    assert st["budget_waits"] > 0  # free workers found requests waiting and no budget
 
 
 def test_oversized_request_is_rejected_others_proceed(orc):
