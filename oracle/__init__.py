@@ -69,6 +69,7 @@ def _bind(path):
     lib = ctypes.CDLL(path)
     P = ctypes.c_void_p
     I64 = ctypes.c_int64
+    I = ctypes.c_int
     sigs = {
         "oracle_plan_i32": [P, I64, P, P, P],
         "oracle_plan_i64": [P, I64, P, P, P],
@@ -86,6 +87,15 @@ def _bind(path):
         "oracle_bucket_tiles_i64": [P, I64, I64, P],
         "oracle_sort_segmented_i32": [P, P, I64, P],
         "oracle_sort_segmented_i64": [P, P, I64, P],
+        "oracle_bounds_digits_i32": [P, I64, I, P],
+        "oracle_bounds_digits_i64": [P, I64, I, P],
+        "oracle_radix_sort_keys_digits_i32": [P, I64, I, P],
+        "oracle_radix_sort_keys_digits_i64": [P, I64, I, P],
+        "oracle_radix_sort_pairs_digits_i32": [P, P, I64, I, P],
+        "oracle_scatter_digits_i32": [P, P, I64, I, P],
+        "oracle_scatter_digits_i64": [P, I64, I, P],
+        "oracle_bucket_tiles_digits_i32": [P, P, I64, I64, I, P],
+        "oracle_bucket_tiles_digits_i64": [P, I64, I64, I, P],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name)
@@ -118,6 +128,12 @@ def _sfx(a):
     return "i32" if a.dtype == np.int32 else "i64"
 
 
+def _nb(digits):
+    if digits not in (1, 2):
+        raise ValueError("digits must be 1 (ten buckets) or 2 (one hundred)")
+    return 10**digits
+
+
 class Oracle:
     """One loaded copy of the oracle library (the default one, or a variant)."""
 
@@ -135,11 +151,15 @@ class Oracle:
         _check(fn(_ptr(k), k.size, ctypes.byref(beta), ctypes.byref(D), ctypes.byref(p)), "plan")
         return beta.value, D.value, p.value
 
-    def bounds(self, keys):
-        """int64[11]: bounds[b] = number of keys whose bucket is below b."""
+    def bounds(self, keys, digits=1):
+        """int64[10^digits + 1]: bounds[b] = number of keys whose bucket is below b (digits = 1: the
+        ten-bucket rule, 2: the two-digit, hundred-bucket rule)."""
         k = np.ascontiguousarray(keys)
-        out = np.zeros(11, np.int64)
-        _check(getattr(self._lib, "oracle_bounds_" + _sfx(k))(_ptr(k), k.size, _ptr(out)), "bounds")
+        out = np.zeros(_nb(digits) + 1, np.int64)
+        if digits == 1:
+            _check(getattr(self._lib, "oracle_bounds_" + _sfx(k))(_ptr(k), k.size, _ptr(out)), "bounds")
+        else:
+            _check(getattr(self._lib, "oracle_bounds_digits_" + _sfx(k))(_ptr(k), k.size, digits, _ptr(out)), "bounds")
         return out
 
     def sort_keys(self, keys):
@@ -155,44 +175,66 @@ class Oracle:
         _check(self._lib.oracle_sort_pairs_i32(_ptr(k), _ptr(v), k.size), "sort_pairs")
         return k, v
 
-    def radix_sort_keys(self, keys):
-        """Section 3.4 run sequentially: scatter into ten buckets, sort each."""
+    def radix_sort_keys(self, keys, digits=1):
+        """Section 3.4 run sequentially: scatter into the buckets, sort each."""
         k = _keys(keys)
-        b = np.zeros(11, np.int64)
-        _check(getattr(self._lib, "oracle_radix_sort_keys_" + _sfx(k))(_ptr(k), k.size, _ptr(b)), "radix_sort_keys")
+        b = np.zeros(_nb(digits) + 1, np.int64)
+        if digits == 1:
+            fn, args = getattr(self._lib, "oracle_radix_sort_keys_" + _sfx(k)), (_ptr(k), k.size, _ptr(b))
+        else:
+            fn, args = getattr(self._lib, "oracle_radix_sort_keys_digits_" + _sfx(k)), (_ptr(k), k.size, digits, _ptr(b))
+        _check(fn(*args), "radix_sort_keys")
         return k, b
 
-    def radix_sort_pairs(self, keys, vals):
+    def radix_sort_pairs(self, keys, vals, digits=1):
         k = _keys(keys)
         v = np.ascontiguousarray(vals, dtype=np.uint32).copy()
-        b = np.zeros(11, np.int64)
-        _check(self._lib.oracle_radix_sort_pairs_i32(_ptr(k), _ptr(v), k.size, _ptr(b)), "radix_sort_pairs")
+        b = np.zeros(_nb(digits) + 1, np.int64)
+        if digits == 1:
+            _check(self._lib.oracle_radix_sort_pairs_i32(_ptr(k), _ptr(v), k.size, _ptr(b)), "radix_sort_pairs")
+        else:
+            _check(self._lib.oracle_radix_sort_pairs_digits_i32(_ptr(k), _ptr(v), k.size, digits, _ptr(b)),
+                   "radix_sort_pairs")
         return k, v, b
 
-    def scatter(self, keys, vals=None):
+    def scatter(self, keys, vals=None, digits=1):
         """The stable one-step MSD scatter alone: (keys, vals, bounds)."""
         k = _keys(keys)
-        b = np.zeros(11, np.int64)
+        b = np.zeros(_nb(digits) + 1, np.int64)
         if k.dtype == np.int32:
             v = None if vals is None else np.ascontiguousarray(vals, dtype=np.uint32).copy()
-            _check(self._lib.oracle_scatter_i32(_ptr(k), _ptr(v), k.size, _ptr(b)), "scatter")
+            if digits == 1:
+                _check(self._lib.oracle_scatter_i32(_ptr(k), _ptr(v), k.size, _ptr(b)), "scatter")
+            else:
+                _check(self._lib.oracle_scatter_digits_i32(_ptr(k), _ptr(v), k.size, digits, _ptr(b)), "scatter")
             return k, v, b
         if vals is not None:
             raise TypeError("int64 pairs are not supported")
-        _check(self._lib.oracle_scatter_i64(_ptr(k), k.size, _ptr(b)), "scatter")
+        if digits == 1:
+            _check(self._lib.oracle_scatter_i64(_ptr(k), k.size, _ptr(b)), "scatter")
+        else:
+            _check(self._lib.oracle_scatter_digits_i64(_ptr(k), k.size, digits, _ptr(b)), "scatter")
         return k, None, b
 
-    def bucket_tiles(self, keys, tile, vals=None):
+    def bucket_tiles(self, keys, tile, vals=None, digits=1):
         """Scatter, then sort each `tile`-key partition of every bucket."""
         k = _keys(keys)
-        b = np.zeros(11, np.int64)
+        b = np.zeros(_nb(digits) + 1, np.int64)
         if k.dtype == np.int32:
             v = None if vals is None else np.ascontiguousarray(vals, dtype=np.uint32).copy()
-            _check(self._lib.oracle_bucket_tiles_i32(_ptr(k), _ptr(v), k.size, int(tile), _ptr(b)), "bucket_tiles")
+            if digits == 1:
+                rc = self._lib.oracle_bucket_tiles_i32(_ptr(k), _ptr(v), k.size, int(tile), _ptr(b))
+            else:
+                rc = self._lib.oracle_bucket_tiles_digits_i32(_ptr(k), _ptr(v), k.size, int(tile), digits, _ptr(b))
+            _check(rc, "bucket_tiles")
             return k, v, b
         if vals is not None:
             raise TypeError("int64 pairs are not supported")
-        _check(self._lib.oracle_bucket_tiles_i64(_ptr(k), k.size, int(tile), _ptr(b)), "bucket_tiles")
+        if digits == 1:
+            rc = self._lib.oracle_bucket_tiles_i64(_ptr(k), k.size, int(tile), _ptr(b))
+        else:
+            rc = self._lib.oracle_bucket_tiles_digits_i64(_ptr(k), k.size, int(tile), digits, _ptr(b))
+        _check(rc, "bucket_tiles")
         return k, None, b
 
     def sort_segmented(self, keys, offsets):

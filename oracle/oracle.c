@@ -19,7 +19,11 @@
  *   - the one-step decimal MSD partition into ten buckets (abstract,
  *     Section 2.1, Section 3.4): the bucket of key k is the decimal digit in
  *     position D-1 of u = k - beta, where beta = min(min key, 0) and D is the
- *     number of decimal digits of max(u) (fixed-position digit reading).
+ *     number of decimal digits of max(u) (fixed-position digit reading);
+ *   - its finer one-step variant with the two most significant digits (one
+ *     hundred buckets, floor(u / 10^(D-2)), a one-digit u read as its digit
+ *     followed by a zero): the second-digit splitter the paper's MSD radix
+ *     would use next (Sections 2.3, 3.4), still one step.
  *
  * How it computes the sort (following the paper's algorithms, sequentially):
  *   1. split the array into CHUNKS contiguous partitions, one per "thread" of
@@ -215,6 +219,24 @@ static int bucket_of(const plan* pl, int64_t k) {
     return (int)(u / pl->p);
 }
 
+/* The finer one-step splitter (a second most significant digit, one hundred
+ * buckets): the bucket is the number formed by the first two of the D
+ * decimal digits of u, floor(u / 10^(D-2)); a one-digit u reads as its digit
+ * followed by a zero (10u).  Bucket b of the ten-bucket rule is the union of
+ * buckets 10b .. 10b+9 of this one, so both orders agree with the keys. */
+static int bucket2_of(const plan* pl, int64_t k) {
+    uint64_t u = (uint64_t)k - (uint64_t)pl->beta;
+    if (pl->D == 1) return (int)(10 * u);
+    return (int)(u / POW10[pl->D - 2]);
+}
+
+/* digits = 1: the ten buckets of Section 3.4; digits = 2: the hundred above. */
+static int bucket_n(const plan* pl, int64_t k, int digits) {
+    return digits == 2 ? bucket2_of(pl, k) : bucket_of(pl, k);
+}
+
+static int nbuckets(int digits) { return digits == 2 ? 100 : 10; }
+
 /* ------------------------------------------------------- exported: helpers */
 static item* load_items_i32(const int32_t* k, int64_t n) {
     item* s = (item*)malloc(sizeof(item) * (size_t)(n > 0 ? n : 1));
@@ -247,20 +269,22 @@ static plan plan_of(const item* s, int64_t n) {
     return make_plan(mn, mx);
 }
 
-/* bounds[b] = number of keys whose bucket is below b, b = 0..10 */
-static void bounds_of(const item* s, int64_t n, const plan* pl, int64_t bounds[11]) {
-    int64_t cnt[10] = {0};
-    for (int64_t i = 0; i < n; i++) cnt[bucket_of(pl, s[i].key)]++;
+/* bounds[b] = number of keys whose bucket is below b, b = 0..NB (NB = 10
+ * or 100 buckets) */
+static void bounds_of(const item* s, int64_t n, const plan* pl, int digits, int64_t* bounds) {
+    int64_t cnt[100] = {0};
+    const int nb = nbuckets(digits);
+    for (int64_t i = 0; i < n; i++) cnt[bucket_n(pl, s[i].key, digits)]++;
     bounds[0] = 0;
-    for (int b = 0; b < 10; b++) bounds[b + 1] = bounds[b] + cnt[b];
+    for (int b = 0; b < nb; b++) bounds[b + 1] = bounds[b] + cnt[b];
 }
 
-/* Stable counting scatter of s[0..n) into the ten buckets (the master's
+/* Stable counting scatter of s[0..n) into the buckets (the master's
  * one-step MSD radix, Section 3.4).  out must hold n items. */
-static void stable_scatter(const item* s, int64_t n, const plan* pl, const int64_t bounds[11], item* out) {
-    int64_t next[10];
-    for (int b = 0; b < 10; b++) next[b] = bounds[b];
-    for (int64_t i = 0; i < n; i++) out[next[bucket_of(pl, s[i].key)]++] = s[i];
+static void stable_scatter(const item* s, int64_t n, const plan* pl, int digits, const int64_t* bounds, item* out) {
+    int64_t next[100];
+    for (int b = 0; b < nbuckets(digits); b++) next[b] = bounds[b];
+    for (int64_t i = 0; i < n; i++) out[next[bucket_n(pl, s[i].key, digits)]++] = s[i];
 }
 
 /* ------------------------------------------------------- exported functions */
@@ -286,22 +310,34 @@ int oracle_plan_i64(const int64_t* k, int64_t n, int64_t* beta, int32_t* D, uint
     return 0;
 }
 
-int oracle_bounds_i32(const int32_t* k, int64_t n, int64_t bounds[11]) {
-    item* s = load_items_i32(k, n);
+/* bounds[0 .. 10^digits]: the bucket bounds of the array under the one-step
+ * rule with `digits` leading digits (1: ten buckets, 2: one hundred). */
+static int bounds_items(item* s, int64_t n, int digits, int64_t* bounds) {
     if (!s) return -1;
+    if (digits != 1 && digits != 2) {
+        free(s);
+        return -1;
+    }
     plan pl = plan_of(s, n);
-    bounds_of(s, n, &pl, bounds);
+    bounds_of(s, n, &pl, digits, bounds);
     free(s);
     return 0;
 }
 
+int oracle_bounds_digits_i32(const int32_t* k, int64_t n, int digits, int64_t* bounds) {
+    return bounds_items(load_items_i32(k, n), n, digits, bounds);
+}
+
+int oracle_bounds_digits_i64(const int64_t* k, int64_t n, int digits, int64_t* bounds) {
+    return bounds_items(load_items_i64(k, n), n, digits, bounds);
+}
+
+int oracle_bounds_i32(const int32_t* k, int64_t n, int64_t bounds[11]) {
+    return oracle_bounds_digits_i32(k, n, 1, bounds);
+}
+
 int oracle_bounds_i64(const int64_t* k, int64_t n, int64_t bounds[11]) {
-    item* s = load_items_i64(k, n);
-    if (!s) return -1;
-    plan pl = plan_of(s, n);
-    bounds_of(s, n, &pl, bounds);
-    free(s);
-    return 0;
+    return oracle_bounds_digits_i64(k, n, 1, bounds);
 }
 
 /* Plain mode: chunked quicksort + bottom-up merge on (key, index). */
@@ -353,17 +389,19 @@ int oracle_sort_pairs_i32(int32_t* k, uint32_t* v, int64_t n) {
     return 0;
 }
 
-/* Radix mode (Section 3.4 run sequentially): stable scatter into ten buckets,
- * the plain sort inside each bucket, buckets in digit order.  Also returns
- * the bucket bounds when bounds != NULL. */
-static int radix_mode(item* s, int64_t n, int64_t* bounds_out) {
+/* Radix mode (Section 3.4 run sequentially): stable scatter into the
+ * buckets, the plain sort inside each bucket, buckets in digit order.  Also
+ * returns the bucket bounds when bounds != NULL. */
+static int radix_mode(item* s, int64_t n, int digits, int64_t* bounds_out) {
+    if (digits != 1 && digits != 2) return -1;
+    const int nb = nbuckets(digits);
     plan pl = plan_of(s, n);
-    int64_t bounds[11];
-    bounds_of(s, n, &pl, bounds);
+    int64_t bounds[101];
+    bounds_of(s, n, &pl, digits, bounds);
     item* t = (item*)malloc(sizeof(item) * (size_t)(n > 0 ? n : 1));
     if (!t) return -1;
-    stable_scatter(s, n, &pl, bounds, t);
-    for (int b = 0; b < 10; b++) {
+    stable_scatter(s, n, &pl, digits, bounds, t);
+    for (int b = 0; b < nb; b++) {
         if (hybrid_sort(t + bounds[b], bounds[b + 1] - bounds[b])) {
             free(t);
             return -1;
@@ -372,14 +410,38 @@ static int radix_mode(item* s, int64_t n, int64_t* bounds_out) {
     memcpy(s, t, sizeof(item) * (size_t)n);
     free(t);
     if (bounds_out)
-        for (int b = 0; b < 11; b++) bounds_out[b] = bounds[b];
+        for (int b = 0; b <= nb; b++) bounds_out[b] = bounds[b];
+    return 0;
+}
+
+int oracle_radix_sort_keys_digits_i32(int32_t* k, int64_t n, int digits, int64_t* bounds) {
+    item* s = load_items_i32(k, n);
+    if (!s) return -1;
+    if (radix_mode(s, n, digits, bounds)) {
+        free(s);
+        return -1;
+    }
+    for (int64_t i = 0; i < n; i++) k[i] = (int32_t)s[i].key;
+    free(s);
+    return 0;
+}
+
+int oracle_radix_sort_keys_digits_i64(int64_t* k, int64_t n, int digits, int64_t* bounds) {
+    item* s = load_items_i64(k, n);
+    if (!s) return -1;
+    if (radix_mode(s, n, digits, bounds)) {
+        free(s);
+        return -1;
+    }
+    for (int64_t i = 0; i < n; i++) k[i] = s[i].key;
+    free(s);
     return 0;
 }
 
 int oracle_radix_sort_keys_i32(int32_t* k, int64_t n, int64_t* bounds) {
     item* s = load_items_i32(k, n);
     if (!s) return -1;
-    if (radix_mode(s, n, bounds)) {
+    if (radix_mode(s, n, 1, bounds)) {
         free(s);
         return -1;
     }
@@ -391,7 +453,7 @@ int oracle_radix_sort_keys_i32(int32_t* k, int64_t n, int64_t* bounds) {
 int oracle_radix_sort_keys_i64(int64_t* k, int64_t n, int64_t* bounds) {
     item* s = load_items_i64(k, n);
     if (!s) return -1;
-    if (radix_mode(s, n, bounds)) {
+    if (radix_mode(s, n, 1, bounds)) {
         free(s);
         return -1;
     }
@@ -400,7 +462,7 @@ int oracle_radix_sort_keys_i64(int64_t* k, int64_t n, int64_t* bounds) {
     return 0;
 }
 
-int oracle_radix_sort_pairs_i32(int32_t* k, uint32_t* v, int64_t n, int64_t* bounds) {
+int oracle_radix_sort_pairs_digits_i32(int32_t* k, uint32_t* v, int64_t n, int digits, int64_t* bounds) {
     item* s = load_items_i32(k, n);
     if (!s) return -1;
     uint32_t* v0 = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1));
@@ -409,7 +471,7 @@ int oracle_radix_sort_pairs_i32(int32_t* k, uint32_t* v, int64_t n, int64_t* bou
         return -1;
     }
     memcpy(v0, v, sizeof(uint32_t) * (size_t)n);
-    if (radix_mode(s, n, bounds)) {
+    if (radix_mode(s, n, digits, bounds)) {
         free(s);
         free(v0);
         return -1;
@@ -423,20 +485,25 @@ int oracle_radix_sort_pairs_i32(int32_t* k, uint32_t* v, int64_t n, int64_t* bou
     return 0;
 }
 
+int oracle_radix_sort_pairs_i32(int32_t* k, uint32_t* v, int64_t n, int64_t* bounds) {
+    return oracle_radix_sort_pairs_digits_i32(k, v, n, 1, bounds);
+}
+
 /* The intermediate after the one-step MSD radix alone: the stable scatter of
- * the input into bucket order (vals may be NULL).  Writes bounds[11]. */
-static int scatter_only(item* s, int64_t n, int64_t bounds[11]) {
+ * the input into bucket order (vals may be NULL).  Writes bounds[NB + 1]. */
+static int scatter_only(item* s, int64_t n, int digits, int64_t* bounds) {
+    if (digits != 1 && digits != 2) return -1;
     plan pl = plan_of(s, n);
-    bounds_of(s, n, &pl, bounds);
+    bounds_of(s, n, &pl, digits, bounds);
     item* t = (item*)malloc(sizeof(item) * (size_t)(n > 0 ? n : 1));
     if (!t) return -1;
-    stable_scatter(s, n, &pl, bounds, t);
+    stable_scatter(s, n, &pl, digits, bounds, t);
     memcpy(s, t, sizeof(item) * (size_t)n);
     free(t);
     return 0;
 }
 
-int oracle_scatter_i32(int32_t* k, uint32_t* v, int64_t n, int64_t bounds[11]) {
+int oracle_scatter_digits_i32(int32_t* k, uint32_t* v, int64_t n, int digits, int64_t* bounds) {
     item* s = load_items_i32(k, n);
     if (!s) return -1;
     uint32_t* v0 = NULL;
@@ -448,7 +515,7 @@ int oracle_scatter_i32(int32_t* k, uint32_t* v, int64_t n, int64_t bounds[11]) {
         }
         memcpy(v0, v, sizeof(uint32_t) * (size_t)n);
     }
-    if (scatter_only(s, n, bounds)) {
+    if (scatter_only(s, n, digits, bounds)) {
         free(s);
         free(v0);
         return -1;
@@ -462,10 +529,10 @@ int oracle_scatter_i32(int32_t* k, uint32_t* v, int64_t n, int64_t bounds[11]) {
     return 0;
 }
 
-int oracle_scatter_i64(int64_t* k, int64_t n, int64_t bounds[11]) {
+int oracle_scatter_digits_i64(int64_t* k, int64_t n, int digits, int64_t* bounds) {
     item* s = load_items_i64(k, n);
     if (!s) return -1;
-    if (scatter_only(s, n, bounds)) {
+    if (scatter_only(s, n, digits, bounds)) {
         free(s);
         return -1;
     }
@@ -473,13 +540,20 @@ int oracle_scatter_i64(int64_t* k, int64_t n, int64_t bounds[11]) {
     free(s);
     return 0;
 }
+
+int oracle_scatter_i32(int32_t* k, uint32_t* v, int64_t n, int64_t bounds[11]) {
+    return oracle_scatter_digits_i32(k, v, n, 1, bounds);
+}
+
+int oracle_scatter_i64(int64_t* k, int64_t n, int64_t bounds[11]) { return oracle_scatter_digits_i64(k, n, 1, bounds); }
 
 /* The intermediate after the local sorts: the input is scattered into
  * buckets, then every bucket is cut into consecutive partitions of `tile`
  * keys starting at the bucket's first key, and each partition is sorted
  * (stably) on its own (Section 3.4: each thread sorts its partition). */
-int oracle_bucket_tiles_i32(int32_t* k, uint32_t* v, int64_t n, int64_t tile, int64_t bounds[11]) {
+int oracle_bucket_tiles_digits_i32(int32_t* k, uint32_t* v, int64_t n, int64_t tile, int digits, int64_t* bounds) {
     if (tile < 1) return -1;
+    const int nb = nbuckets(digits);
     item* s = load_items_i32(k, n);
     if (!s) return -1;
     uint32_t* v0 = NULL;
@@ -491,12 +565,12 @@ int oracle_bucket_tiles_i32(int32_t* k, uint32_t* v, int64_t n, int64_t tile, in
         }
         memcpy(v0, v, sizeof(uint32_t) * (size_t)n);
     }
-    if (scatter_only(s, n, bounds)) {
+    if (scatter_only(s, n, digits, bounds)) {
         free(s);
         free(v0);
         return -1;
     }
-    for (int b = 0; b < 10; b++) {
+    for (int b = 0; b < nb; b++) {
         for (int64_t t = bounds[b]; t < bounds[b + 1]; t += tile) {
             int64_t e = t + tile < bounds[b + 1] ? t + tile : bounds[b + 1];
             quicksort(s, t, e - 1);
@@ -511,15 +585,16 @@ int oracle_bucket_tiles_i32(int32_t* k, uint32_t* v, int64_t n, int64_t tile, in
     return 0;
 }
 
-int oracle_bucket_tiles_i64(int64_t* k, int64_t n, int64_t tile, int64_t bounds[11]) {
+int oracle_bucket_tiles_digits_i64(int64_t* k, int64_t n, int64_t tile, int digits, int64_t* bounds) {
     if (tile < 1) return -1;
+    const int nb = nbuckets(digits);
     item* s = load_items_i64(k, n);
     if (!s) return -1;
-    if (scatter_only(s, n, bounds)) {
+    if (scatter_only(s, n, digits, bounds)) {
         free(s);
         return -1;
     }
-    for (int b = 0; b < 10; b++) {
+    for (int b = 0; b < nb; b++) {
         for (int64_t t = bounds[b]; t < bounds[b + 1]; t += tile) {
             int64_t e = t + tile < bounds[b + 1] ? t + tile : bounds[b + 1];
             quicksort(s, t, e - 1);
@@ -528,6 +603,14 @@ int oracle_bucket_tiles_i64(int64_t* k, int64_t n, int64_t tile, int64_t bounds[
     for (int64_t i = 0; i < n; i++) k[i] = s[i].key;
     free(s);
     return 0;
+}
+
+int oracle_bucket_tiles_i32(int32_t* k, uint32_t* v, int64_t n, int64_t tile, int64_t bounds[11]) {
+    return oracle_bucket_tiles_digits_i32(k, v, n, tile, 1, bounds);
+}
+
+int oracle_bucket_tiles_i64(int64_t* k, int64_t n, int64_t tile, int64_t bounds[11]) {
+    return oracle_bucket_tiles_digits_i64(k, n, tile, 1, bounds);
 }
 
 /* Segmented: every [off[i], off[i+1]) sorted on its own; bounds (may be

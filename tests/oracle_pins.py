@@ -67,6 +67,24 @@ def string_plan(keys):
     return beta, D, p, digits
 
 
+def string_plan2(keys):
+    """Two-digit buckets via decimal strings: the first two characters of u
+    written with D digits (a one-digit u gets a trailing zero)."""
+    beta, D, p, _ = string_plan(keys)
+    digits = [int((str(int(k) - beta).rjust(D, "0") + "0")[:2]) for k in keys]
+    return beta, D, p, digits
+
+
+def string_bounds2(keys):
+    cnt = [0] * 100
+    for d in string_plan2(keys)[3]:
+        cnt[d] += 1
+    b = [0]
+    for c in cnt:
+        b.append(b[-1] + c)
+    return b
+
+
 def string_bounds(keys):
     _, _, _, digits = string_plan(keys)
     cnt = [0] * 10
@@ -274,6 +292,106 @@ def pin_count(orc, seed=19):
             assert orc.count_lt_le(k, x) == (lt, le), (dt, x)
 
 
+def pin_two_digit_worked_examples(orc):
+    with open(GOLDEN) as f:
+        g = json.load(f)["two_digit"]
+    for ex in g["cases"]:
+        k = np.array(ex["keys"], np.int32 if ex["dtype"] == "int32" else np.int64)
+        assert string_plan2(ex["keys"])[3] == ex["digits"], ("fixture digits", ex)
+        full = []
+        steps = dict((b, v) for b, v in ex["bounds_steps"])
+        cur = 0
+        for b in range(101):
+            cur = steps.get(b, cur)
+            full.append(cur)
+        full[100] = len(ex["keys"])
+        assert orc.bounds(k, 2).tolist() == full, ("bounds100", ex)
+        assert orc.radix_sort_keys(k, 2)[1].tolist() == full, ("radix bounds100", ex)
+
+
+def pin_two_digit_string_route(orc, seed=24):
+    """Hundred-bucket bounds by decimal strings, by lower_bound of the sorted
+    output at beta + b*10^(D-2), and folded onto the ten-bucket bounds."""
+    rng = np.random.default_rng(seed)
+    cases = []
+    for D in range(1, 11):
+        hi = 10**D - 1 if D < 10 else I32.max
+        k = rng.integers(0, 10 ** (D - 1), 60, dtype=np.int64)
+        k[rng.integers(0, 60)] = rng.integers(10 ** (D - 1), hi, endpoint=True)
+        cases.append(k.astype(np.int32))
+    for D in range(1, 21):
+        if D < 20:
+            k = [int(x) for x in rng.integers(0, 10 ** (D - 1), 50, dtype=np.int64)]
+            k.append(int(rng.integers(10 ** (D - 1), min(10**D - 1, I64.max), endpoint=True, dtype=np.int64)))
+        else:
+            k = [I64.min, I64.max] + [int(x) for x in rng.integers(I64.min, I64.max, 40, dtype=np.int64)]
+        cases.append(np.array(k, np.int64))
+    for D in range(1, 20):
+        for top in (10 ** (D - 1), 10**D - 1, 10**D):
+            for dt, info in ((np.int32, I32), (np.int64, I64)):
+                if top <= info.max:
+                    cases.append(np.array([0, top // 7, top // 3, top], dt))
+    for _ in range(60):
+        dt = np.int32 if rng.random() < 0.5 else np.int64
+        info = np.iinfo(dt)
+        lo = int(rng.integers(info.min, info.max, dtype=dt)) if rng.random() < 0.5 else 0
+        hi = int(rng.integers(max(lo, 0), info.max, dtype=dt, endpoint=True))
+        cases.append(rng.integers(lo, hi, int(rng.integers(1, 400)), dtype=dt, endpoint=True))
+    for k in cases:
+        b2 = orc.bounds(k, 2).tolist()
+        assert b2 == string_bounds2(k.tolist()), k
+        assert b2[::10] == orc.bounds(k).tolist(), k  # bucket b = buckets 10b .. 10b+9
+        beta, D, p, _ = string_plan(k.tolist())
+        if D >= 2:
+            s = np.array(sorted(int(x) for x in k), dtype=object)
+            lb = [0] + [int(np.searchsorted(s, beta + b * (p // 10), side="left")) for b in range(1, 100)] + [len(s)]
+            assert b2 == lb, k
+
+
+def pin_two_digit_radix_and_stages(orc, seed=25):
+    """The hundred-bucket pipeline run sequentially equals the plain sort; its
+    scatter is stable and in bucket order; its local sorts sort each
+    partition of each bucket."""
+    rng = np.random.default_rng(seed)
+    for n in [0, 1, 9, 1000, 30_011]:
+        for dt in (np.int32, np.int64):
+            info = np.iinfo(dt)
+            for k in (rng.integers(info.min, info.max, n, dtype=dt, endpoint=True),
+                      rng.integers(0, 1000, n).astype(dt), rng.integers(0, 7, n).astype(dt)):
+                rk, rb = orc.radix_sort_keys(k, 2)
+                assert np.array_equal(rk, orc.sort_keys(k)), (n, dt)
+                assert rb.tolist() == string_bounds2(k.tolist()), (n, dt)
+        k = rng.integers(0, 1000, n, dtype=np.int32)
+        v = np.arange(n, dtype=np.uint32)
+        rk, rv, _ = orc.radix_sort_pairs(k, v, 2)
+        pk, pv = orc.sort_pairs(k, v)
+        assert np.array_equal(rk, pk) and np.array_equal(rv, pv), n
+    for n, T in [(0, 4), (1, 4), (500, 7), (20_000, 64), (50_000, 1000)]:
+        k = rng.integers(0, 3000, n, dtype=np.int32)
+        v = np.arange(n, dtype=np.uint32)
+        sk, sv, b = orc.scatter(k, v, 2)
+        assert b.tolist() == string_bounds2(k.tolist())
+        d_in, d_out = string_plan2(k.tolist())[3], string_plan2(sk.tolist())[3] if n else []
+        assert d_out == sorted(d_in), "buckets out of order"
+        assert np.array_equal(k[sv], sk), "payload does not follow its key"
+        for bk in range(100):
+            assert np.all(np.diff(sv[b[bk]:b[bk + 1]].astype(np.int64)) > 0), "scatter not stable"
+        tk, tv, tb = orc.bucket_tiles(k, T, v, 2)
+        assert np.array_equal(tb, b)
+        for bk in range(100):
+            for s0 in range(int(b[bk]), int(b[bk + 1]), T):
+                e = min(s0 + T, int(b[bk + 1]))
+                order = np.lexsort((sv[s0:e], sk[s0:e]))
+                assert np.array_equal(tk[s0:e], sk[s0:e][order]) and np.array_equal(tv[s0:e], sv[s0:e][order])
+        k64 = rng.integers(I64.min, I64.max, n, dtype=np.int64, endpoint=True)
+        sk, _, b = orc.scatter(k64, digits=2)
+        tk, _, _ = orc.bucket_tiles(k64, T, digits=2)
+        for bk in range(100):
+            for s0 in range(int(b[bk]), int(b[bk + 1]), T):
+                e = min(s0 + T, int(b[bk + 1]))
+                assert np.array_equal(tk[s0:e], np.sort(sk[s0:e])), (n, T, bk, s0)
+
+
 ALL_PINS = [
     pin_worked_examples,
     pin_exhaustive_small,
@@ -286,4 +404,7 @@ ALL_PINS = [
     pin_bucket_tiles,
     pin_segmented,
     pin_count,
+    pin_two_digit_worked_examples,
+    pin_two_digit_string_route,
+    pin_two_digit_radix_and_stages,
 ]

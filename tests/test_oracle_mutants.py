@@ -26,8 +26,14 @@ MUTANTS = [
     ("digits_off_by_one", "while (d < 20 && x >= POW10[d]) d++;", "while (d < 20 && x > POW10[d]) d++;"),
     ("pow10_typo", "10000000000000ULL,", "1000000000000ULL,"),
     ("bounds_shifted", "bounds[b + 1] = bounds[b] + cnt[b];", "bounds[b + 1] = bounds[b] + cnt[b ? b - 1 : 0];"),
-    ("scatter_reversed", "for (int64_t i = 0; i < n; i++) out[next[bucket_of(pl, s[i].key)]++] = s[i];",
-     "for (int64_t i = n - 1; i >= 0; i--) out[next[bucket_of(pl, s[i].key)]++] = s[i];"),
+    ("scatter_reversed", "for (int64_t i = 0; i < n; i++) out[next[bucket_n(pl, s[i].key, digits)]++] = s[i];",
+     "for (int64_t i = n - 1; i >= 0; i--) out[next[bucket_n(pl, s[i].key, digits)]++] = s[i];"),
+    ("two_digit_drops_second_digit", "return (int)(u / POW10[pl->D - 2]);", "return (int)(u / POW10[pl->D - 1] * 10);"),
+    ("one_digit_without_trailing_zero", "if (pl->D == 1) return (int)(10 * u);", "if (pl->D == 1) return (int)u;"),
+    ("scatter_ignores_digit_count", "out[next[bucket_n(pl, s[i].key, digits)]++] = s[i];",
+     "out[next[bucket_of(pl, s[i].key)]++] = s[i];"),
+    ("tiles_skip_upper_buckets", "    for (int b = 0; b < nb; b++) {\n        for (int64_t t = bounds[b]; t < bounds[b + 1]; t += tile) {",
+     "    for (int b = 0; b < 10; b++) {\n        for (int64_t t = bounds[b]; t < bounds[b + 1]; t += tile) {"),
     ("tile_not_bucket_aligned", "for (int64_t t = bounds[b]; t < bounds[b + 1]; t += tile) {\n            int64_t e = t + tile < bounds[b + 1] ? t + tile : bounds[b + 1];\n            quicksort(s, t, e - 1);\n        }\n    }\n    for (int64_t i = 0; i < n; i++) {",
      "for (int64_t t = bounds[b] - bounds[b] % tile; t < bounds[b + 1]; t += tile) {\n            int64_t e = t + tile < bounds[b + 1] ? t + tile : bounds[b + 1];\n            quicksort(s, t, e - 1);\n        }\n    }\n    for (int64_t i = 0; i < n; i++) {"),
     ("partition_skips_last", "for (int64_t j = low; j < high; j++) {", "for (int64_t j = low; j < high - 1; j++) {"),
