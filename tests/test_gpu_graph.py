@@ -109,8 +109,7 @@ def test_graph_replay_with_segment_beyond_hint(hs, orc):
         s = torch.empty(hs.scratch_bytes(hs.SEG_I32, n, nseg), dtype=torch.uint8, device="cuda")
         good = np.linspace(0, n, nseg + 1).astype(np.int64)  # 2000 keys each
         bad = good.copy()
-        bad[5] = bad[4] + 1
-        bad[6] = bad[5] + 9000  # one segment of 9000 keys, beyond the 4096 hint
+        bad[6:9] = bad[9]  # segment 5 spans 8000 keys, beyond the 4096 hint; 6 to 8 are empty
         hs.hsort_graph_mode(True)
         try:
             for rep, off in enumerate([good, bad, good]):
