@@ -80,8 +80,8 @@ int hsort_pairs(int32_t* keys, uint32_t* vals, int64_t n, void* scratch, size_t 
 
 /* Sorts each segment keys[offsets[i] .. offsets[i+1]) independently, for
  * i in [0, nseg) (Section 3.4: the buckets are independent units of work;
- * here every segment gets its own ten buckets and all buckets of all
- * segments form one flat work list).  Ascending, in place.
+ * here every segment gets its own buckets and all buckets of all segments
+ * form one flat work list).  Ascending, in place.
  *   keys:        device array of n keys (n bounds the offsets; keys outside
  *                [offsets[0], offsets[nseg]) are untouched).
  *   offsets:     nseg+1 device int64, non-decreasing, with 0 <= offsets[0]
@@ -125,7 +125,13 @@ const char* hsort_last_error(void);
  * plain arrays) up to this size are sorted wholly in LDS; fanin = runs
  * merged per round, 2 (pairwise rounds, Figure 1b) or 4 (each round merges
  * four runs: half as many rounds; a split point is placed by two-way
- * searches only, see the kernels).  merge_nv must divide tile.  Only compiled shapes are accepted (HSORT_ERR_UNSUPPORTED
+ * searches only, see the kernels); digits = decimal digits of the one-step
+ * partition, 1 (the ten buckets of Section 3.4) or 2 (one hundred buckets by
+ * the first two of the D digits, floor(u / 10^(D-2)), or 10u when D = 1: a
+ * finer splitter with the same order, so bucket b of the ten is buckets
+ * 10b .. 10b+9 of the hundred; smaller buckets need fewer merge rounds).
+ * The exported bounds are the ten-bucket bounds either way.  merge_nv must
+ * divide tile.  Only compiled shapes are accepted (HSORT_ERR_UNSUPPORTED
  * otherwise).  kind: any hsort_kind (the two segmented kinds share the
  * table of their key type).  Size classes 0..3 hold calls whose deciding
  * size -- n, or max_seg_len of a segmented call when given -- is at most
@@ -133,14 +139,15 @@ const char* hsort_last_error(void);
  * class); size_cls = -1 sets every class.  The table is process-wide, and
  * scratch sizes depend on it: size scratch after changing it. */
 int hsort_set_config(int kind, int size_cls, int64_t tile, int64_t tile_vt, int64_t merge_nv, int64_t merge_vt,
-                     int64_t small_max, int64_t fanin);
+                     int64_t small_max, int64_t fanin, int64_t digits);
 int hsort_get_config(int kind, int size_cls, int64_t* tile, int64_t* tile_vt, int64_t* merge_nv, int64_t* merge_vt,
-                     int64_t* small_max, int64_t* fanin);
+                     int64_t* small_max, int64_t* fanin, int64_t* digits);
 int hsort_size_class(int64_t n);
 
 /* Applies a tuning table written by the autotuner: text lines
- * "kind size_class tile tile_vt merge_nv merge_vt small_max fanin" ('#' starts a
- * comment line).  Stops at the first bad line and returns its error. */
+ * "kind size_class tile tile_vt merge_nv merge_vt small_max fanin [digits]"
+ * (digits 1 when left out; '#' starts a comment line).  Stops at the first
+ * bad line and returns its error. */
 int hsort_load_tuning(const char* path);
 
 /* ----------------------------------------------------- test observability

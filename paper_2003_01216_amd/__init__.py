@@ -87,8 +87,8 @@ def load_library(path: str = LIB_PATH):
         "hsort_bounds_offset": ([I, I64, I64], SZ),
         "hsort_check": ([P, P], I),
         "hsort_last_error": ([], ctypes.c_char_p),
-        "hsort_set_config": ([I, I, I64, I64, I64, I64, I64, I64], I),
-        "hsort_get_config": ([I, I, P, P, P, P, P, P], I),
+        "hsort_set_config": ([I, I, I64, I64, I64, I64, I64, I64, I64], I),
+        "hsort_get_config": ([I, I, P, P, P, P, P, P, P], I),
         "hsort_size_class": ([I64], I),
         "hsort_load_tuning": ([ctypes.c_char_p], I),
         "hsort_debug_stage": ([I, P, P, I64, I, P, SZ, P], I),
@@ -216,17 +216,18 @@ def read_bounds(scratch: torch.Tensor, kind: int, n: int, nseg: int = 1) -> torc
 
 
 def hsort_set_config(kind: int, tile: int, tile_vt: int, merge_nv: int, merge_vt: int, small_max: int,
-                     fanin: int = 2, size_class: int = -1) -> None:
-    _check(load_library().hsort_set_config(kind, size_class, tile, tile_vt, merge_nv, merge_vt, small_max, fanin))
+                     fanin: int = 2, size_class: int = -1, digits: int = 1) -> None:
+    _check(load_library().hsort_set_config(kind, size_class, tile, tile_vt, merge_nv, merge_vt, small_max, fanin,
+                                           digits))
 
 
 def hsort_get_config(kind: int, size_class: int | None = None, n: int | None = None):
-    """(tile, tile_vt, merge_nv, merge_vt, small_max, fanin) of a kind, for a size class or for n keys
-    (default: 2^28)."""
+    """(tile, tile_vt, merge_nv, merge_vt, small_max, fanin, digits) of a kind, for a size class or for n
+    keys (default: 2^28)."""
     lib = load_library()
     if size_class is None:
         size_class = lib.hsort_size_class(n if n is not None else 1 << 28)
-    vals = [ctypes.c_int64() for _ in range(6)]
+    vals = [ctypes.c_int64() for _ in range(7)]
     _check(lib.hsort_get_config(kind, size_class, *[ctypes.byref(v) for v in vals]))
     return tuple(v.value for v in vals)
 

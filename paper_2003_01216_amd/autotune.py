@@ -3,7 +3,9 @@
 For every key kind and size class it times each compiled shape on the
 device -- tile (keys per local-sort partition) x keys per thread, merge
 outputs per workgroup x per thread, the largest segment sorted wholly in
-LDS, and the merge fan-in (2 or 4 runs per round) -- on a representative synthetic workload of that class, and writes the
+LDS, the merge fan-in (2 or 4 runs per round) and the decimal digits of the
+one-step partition (1: ten buckets, 2: one hundred) -- on a representative
+synthetic workload of that class, and writes the
 fastest to a table (``tuning.txt``, applied by the binding when the library
 loads; see ``hsort_load_tuning``), and, with ``--report PATH``, a JSON log
 of every measurement (a log, kept out of the package).
@@ -49,15 +51,17 @@ NAMES = {KEYS_I32: "keys_i32", KEYS_I64: "keys_i64", PAIRS_I32_U32: "pairs_i32",
 
 
 FANINS = [2, 4]
+# decimal digits of the one-step partition: ten or one hundred buckets
+DIGITS = [1, 2]
 
 
 def candidates(kind):
     kt = KEY_TYPE[kind]
     smalls = SEG_SMALL if kind in (SEG_I32, SEG_I64) else SMALL[kt]
     for f in FANINS:
-        for (t, tv), (m, mv), s in itertools.product(TILES[kt], MERGES[f][kt], smalls):
+        for (t, tv), (m, mv), s, d in itertools.product(TILES[kt], MERGES[f][kt], smalls, DIGITS):
             if t % m == 0:
-                yield (t, tv, m, mv, s, f)
+                yield (t, tv, m, mv, s, f, d)
 
 
 def _rng_keys(kind, n, seed):
@@ -125,7 +129,7 @@ def time_config(wl, cfg, cls, reps):
     The same buffers are sorted every time (refilled outside the timed
     window), so in graph mode the warm-up captures and the timed calls replay.
     """
-    hsort_set_config(wl.kind, *cfg[:5], fanin=cfg[5], size_class=cls)
+    hsort_set_config(wl.kind, *cfg[:5], fanin=cfg[5], digits=cfg[6], size_class=cls)
     scratch = wl.scratch()
     work = wl.base.clone()
     wv = wl.vals.clone() if wl.kind == PAIRS_I32_U32 else None
@@ -169,7 +173,7 @@ def tune(kinds, classes, quick=False, reps=5, log=print):
                     if best is None or ms < best[0]:
                         best = (ms, cfg)
                 table[(kind, cls)] = best[1]
-                hsort_set_config(kind, *best[1][:5], fanin=best[1][5], size_class=cls)
+                hsort_set_config(kind, *best[1][:5], fanin=best[1][5], digits=best[1][6], size_class=cls)
                 del wl
                 torch.cuda.empty_cache()
     finally:
@@ -178,7 +182,7 @@ def tune(kinds, classes, quick=False, reps=5, log=print):
 
 
 def write_table(table, path, report=None, report_path=None):
-    lines = ["# hsort tuning table: kind size_class tile tile_vt merge_nv merge_vt small_max fanin",
+    lines = ["# hsort tuning table: kind size_class tile tile_vt merge_nv merge_vt small_max fanin digits",
              f"# written by paper_2003_01216_amd.autotune on {time.strftime('%Y-%m-%d %H:%M:%S')}"]
     for (kind, cls), cfg in sorted(table.items()):
         lines.append(f"{kind} {cls} " + " ".join(str(x) for x in cfg))

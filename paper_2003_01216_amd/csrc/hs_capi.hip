@@ -32,6 +32,7 @@ struct Config {
     int64_t merge_vt;   // outputs per thread of the merge
     int64_t small_max;  // segments up to this size never leave LDS
     int64_t fanin;      // runs merged per round: 2 or 4
+    int64_t digits = 1;  // decimal digits of the one-step partition: 1 (ten buckets) or 2 (one hundred)
 };
 
 std::mutex g_mu;
@@ -116,6 +117,7 @@ bool config_ok(int key_type_index, const Config& c) {
     if (c.tile % c.merge_nv) return false;  // merge chunks must tile a run
     if (c.small_max < 0 || c.small_max > 8192) return false;
     if (c.fanin != 2 && c.fanin != 4) return false;
+    if (c.digits != 1 && c.digits != 2) return false;
     switch (key_type_index) {
         case 0:
             return shapes_ok<int32_t, false>(c);
@@ -205,9 +207,10 @@ Layout make_layout(int kind, int64_t n, int64_t nseg, const Config& c) {
     Layout L{};
     L.large_bound = std::min<int64_t>(nseg, std::max<int64_t>(1, n / (c.small_max + 1)));
     L.tiles_bound = cdiv(n, kHistTile) + L.large_bound;
-    L.buckets = 10 * nseg;
-    L.ts_bound = cdiv(n, c.tile) + 10 * L.large_bound;
-    L.chunks_bound = cdiv(n, c.merge_nv) + 10 * L.large_bound;
+    const int64_t nbk = c.digits == 2 ? 100 : 10;
+    L.buckets = nbk * nseg;
+    L.ts_bound = cdiv(n, c.tile) + nbk * L.large_bound;
+    L.chunks_bound = cdiv(n, c.merge_nv) + nbk * L.large_bound;
     size_t o = 0;
     auto take = [&](size_t bytes) {
         size_t at = o;
@@ -228,8 +231,8 @@ Layout make_layout(int kind, int64_t n, int64_t nseg, const Config& c) {
     L.plans = take((ksz == 8 ? sizeof(DigitPlan<int64_t>) : sizeof(DigitPlan<int32_t>)) * nseg);
     L.tilecnt = take(4 * nseg);
     L.tilepre = take(4 * (nseg + 1));
-    L.counts = take(4 * 10 * L.tiles_bound);
-    L.pos = take(8 * (10 * L.tiles_bound + 1));
+    L.counts = take(4 * nbk * L.tiles_bound);
+    L.pos = take(8 * (nbk * L.tiles_bound + 1));
     L.bstart = take(8 * L.buckets);
     L.bsize = take(8 * L.buckets);
     L.tsc = take(4 * L.buckets);
@@ -242,7 +245,7 @@ Layout make_layout(int kind, int64_t n, int64_t nseg, const Config& c) {
     L.ssorted = take(sizeof(Split4) * L.chunks_bound);
     const int64_t p32 = std::max(scan_partial_count(nseg), scan_partial_count(L.buckets));
     L.part32 = take(4 * p32);
-    L.part64 = take(8 * scan_partial_count(10 * L.tiles_bound));
+    L.part64 = take(8 * scan_partial_count(nbk * L.tiles_bound));
     L.total = o;
     return L;
 }
@@ -281,6 +284,7 @@ Work<K> make_work(const Layout& L, char* scr, K* keys, uint32_t* vals, const int
     w.mdesc = (MergeDesc*)(scr + L.mdesc);
     w.ssorted = (Split4*)(scr + L.ssorted);
     w.err = (uint32_t*)(scr + L.err);
+    w.nbk = c.digits == 2 ? 100 : 10;
     w.tile = (int32_t)c.tile;
     w.fanin = (int32_t)c.fanin;
     w.nv = (int32_t)c.merge_nv;
@@ -414,7 +418,7 @@ int enqueue(int kind, K* keys, uint32_t* vals, int64_t n, const int64_t* off, in
         }
         {
             Timer t(st, "scan", 0);
-            HS_TRY(launch_scan_u32_i64(ScanSpec{w.tilepre + nseg, 10, 0}, 10 * L.tiles_bound, w.counts, w.pos,
+            HS_TRY(launch_scan_u32_i64(ScanSpec{w.tilepre + nseg, w.nbk, 0}, w.nbk * L.tiles_bound, w.counts, w.pos,
                                        (int64_t*)(scr + L.part64), st));
         }
         {
@@ -681,12 +685,12 @@ int hsort_check(const void* scratch, void* stream) {
 const char* hsort_last_error(void) { return g_err.c_str(); }
 
 int hsort_set_config(int kind, int size_cls, int64_t tile, int64_t tile_vt, int64_t merge_nv, int64_t merge_vt,
-                     int64_t small_max, int64_t fanin) {
+                     int64_t small_max, int64_t fanin, int64_t digits) {
     g_err.clear();
     const int ci = cfg_index(kind);
     if (ci < 0) return fail(HSORT_ERR_INVALID, "unknown kind");
     if (size_cls < -1 || size_cls >= kClasses) return fail(HSORT_ERR_INVALID, "size class out of range");
-    const Config c{tile, tile_vt, merge_nv, merge_vt, small_max, fanin};
+    const Config c{tile, tile_vt, merge_nv, merge_vt, small_max, fanin, digits};
     if (!config_ok(key_type(kind), c)) return fail(HSORT_ERR_UNSUPPORTED, "tile/merge shape not compiled");
     std::lock_guard<std::mutex> lk(g_mu);
     for (int k = 0; k < kClasses; k++)
@@ -695,10 +699,10 @@ int hsort_set_config(int kind, int size_cls, int64_t tile, int64_t tile_vt, int6
 }
 
 int hsort_get_config(int kind, int size_cls, int64_t* tile, int64_t* tile_vt, int64_t* merge_nv, int64_t* merge_vt,
-                     int64_t* small_max, int64_t* fanin) {
+                     int64_t* small_max, int64_t* fanin, int64_t* digits) {
     const int ci = cfg_index(kind);
     if (ci < 0 || size_cls < 0 || size_cls >= kClasses || !tile || !tile_vt || !merge_nv || !merge_vt || !small_max ||
-        !fanin)
+        !fanin || !digits)
         return fail(HSORT_ERR_INVALID, "bad arguments");
     Config c;
     {
@@ -711,6 +715,7 @@ int hsort_get_config(int kind, int size_cls, int64_t* tile, int64_t* tile_vt, in
     *merge_vt = c.merge_vt;
     *small_max = c.small_max;
     *fanin = c.fanin;
+    *digits = c.digits;
     return HSORT_OK;
 }
 
@@ -725,12 +730,13 @@ int hsort_load_tuning(const char* path) {
         lineno++;
         if (line[0] == '#' || line[0] == '\n') continue;
         int kind = 0, cls = 0;
-        long long t, tv, m, mv, sm, fi;
-        if (sscanf(line, "%d %d %lld %lld %lld %lld %lld %lld", &kind, &cls, &t, &tv, &m, &mv, &sm, &fi) != 8) {
+        long long t, tv, m, mv, sm, fi, dg = 1;
+        const int got = sscanf(line, "%d %d %lld %lld %lld %lld %lld %lld %lld", &kind, &cls, &t, &tv, &m, &mv, &sm, &fi, &dg);
+        if (got != 8 && got != 9) {  // the digits column is optional (1)
             rc = fail(HSORT_ERR_INVALID, std::string(path) + ": bad line " + std::to_string(lineno));
             break;
         }
-        if ((rc = hsort_set_config(kind, cls, t, tv, m, mv, sm, fi)) != HSORT_OK) break;
+        if ((rc = hsort_set_config(kind, cls, t, tv, m, mv, sm, fi, dg)) != HSORT_OK) break;
     }
     fclose(f);
     return rc;

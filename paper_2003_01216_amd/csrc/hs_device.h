@@ -46,12 +46,22 @@ struct Traits<int64_t> {
 // that u reaches -- nine unsigned compares, no division on the hot path.
 // thr[b-1] holds b*p - 1 saturated at the type's maximum, so that a threshold
 // beyond the unsigned range is never passed: digit = sum_b [u > thr[b-1]].
+//
+// The finer one-step splitter (a second most significant digit, one hundred
+// buckets) reads the first two of the D digits: bucket floor(u / q) with
+// q = 10^(D-2), or 10u when D = 1 (a one-digit u read with a trailing zero).
+// Bucket b of the ten-bucket rule is the union of buckets 10b .. 10b+9 of
+// this one, so both orders agree with the keys.
 template <typename K>
 struct DigitPlan {
     using U = typename Traits<K>::U;
-    U beta;          // (U)beta
-    U thr[9];        // b*p - 1, saturated
-    uint64_t magic;  // 32-bit keys: ceil(2^64 / p) for p >= 10, 0 for p == 1
+    U beta;           // (U)beta
+    U thr[9];         // b*p - 1, saturated
+    uint64_t magic;   // 32-bit keys: ceil(2^64 / p) for p >= 10, 0 for p == 1
+    // two-digit rule
+    U thr2[9];        // 64-bit keys: c*q - 1 for c = 1..9 (saturated; all-ones when D = 1)
+    uint64_t magic2;  // 32-bit keys: ceil(2^64 / q) for q >= 10, else 0
+    uint32_t mul2;    // 32-bit keys with magic2 = 0: the bucket is u * mul2 (1 when D = 2, 10 when D = 1)
 };
 
 template <typename K>
@@ -71,7 +81,18 @@ __host__ __device__ inline DigitPlan<K> make_digit_plan(K mn, K mx) {
     // p = 10^k does not divide 2^64 for k >= 1, so floor((2^64-1)/p) + 1 is
     // ceil(2^64/p)
     pl.magic = p == 1 ? 0 : ~0ull / (uint64_t)p + 1;
+    // two-digit rule: q = p / 10 (none when p = 1)
+    const U q = p / 10;
+    for (int c = 1; c <= 9; c++) pl.thr2[c - 1] = q == 0 ? umax : (U)((U)c * q - 1);  // c*q < 10q = p: fits
+    pl.magic2 = q >= 10 ? ~0ull / (uint64_t)q + 1 : 0;
+    pl.mul2 = q == 0 ? 10u : 1u;
     return pl;
+}
+
+// p of a plan (the largest power of ten not above max u, or 1).
+template <typename K>
+__host__ __device__ inline uint64_t plan_p(const DigitPlan<K>& pl) {
+    return (uint64_t)pl.thr[0] + 1;
 }
 
 // The key's decimal digit floor(u / p), u = k - beta.  32-bit keys: the high
@@ -80,7 +101,7 @@ __host__ __device__ inline DigitPlan<K> make_digit_plan(K mn, K mx) {
 // too little to cross the next integer); two multiply instructions.  64-bit
 // keys: nine compares against the saturated thresholds b*p - 1.
 template <typename K>
-__device__ __forceinline__ int digit_of(const DigitPlan<K>& pl, K k) {
+__host__ __device__ __forceinline__ int digit_of(const DigitPlan<K>& pl, K k) {
     using U = typename Traits<K>::U;
     U u = (U)k - pl.beta;
     if constexpr (sizeof(U) == 4) {
@@ -92,6 +113,58 @@ __device__ __forceinline__ int digit_of(const DigitPlan<K>& pl, K k) {
 #pragma unroll
         for (int b = 0; b < 9; b++) d += (u > pl.thr[b]) ? 1 : 0;
         return d;
+    }
+}
+
+// The key's two-digit bucket (0..99) under the one-hundred-bucket rule.
+// 32-bit keys: floor(u / q) by the same multiply-high as digit_of (exact,
+// q < 2^32), or u * mul2 for q = 1 and for D = 1.  64-bit keys: the first
+// digit d by nine compares, then the second by nine compares of
+// u - d*p (< p = 10q) against c*q - 1.
+template <typename K>
+__host__ __device__ __forceinline__ int bucket2_of(const DigitPlan<K>& pl, K k) {
+    using U = typename Traits<K>::U;
+    U u = (U)k - pl.beta;
+    if constexpr (sizeof(U) == 4) {
+        const uint64_t m = pl.magic2;
+        const uint64_t mid = (uint64_t)u * (uint32_t)(m >> 32) + (uint32_t)(((uint64_t)u * (uint32_t)m) >> 32);
+        return m ? (int)(mid >> 32) : (int)(u * pl.mul2);
+    } else {
+        int d = 0;
+#pragma unroll
+        for (int b = 0; b < 9; b++) d += (u > pl.thr[b]) ? 1 : 0;
+        const U r = u - (U)d * (pl.thr[0] + 1);
+        int e = 0;
+#pragma unroll
+        for (int c = 0; c < 9; c++) e += (r > pl.thr2[c]) ? 1 : 0;
+        return 10 * d + e;
+    }
+}
+
+// Bucket of a key under the rule with NBK buckets (10 or 100).
+template <int NBK, typename K>
+__host__ __device__ __forceinline__ int bucket_of(const DigitPlan<K>& pl, K k) {
+    static_assert(NBK == 10 || NBK == 100, "ten or one hundred buckets");
+    if constexpr (NBK == 10)
+        return digit_of(pl, k);
+    else
+        return bucket2_of(pl, k);
+}
+
+// The keys of bucket b (NBK buckets) lie in u in [lo, lo + width): the
+// local sorts narrow their words by it.
+template <typename K>
+__host__ __device__ __forceinline__ void bucket_span(const DigitPlan<K>& pl, int nbk, int b, uint64_t& lo, uint64_t& width) {
+    const uint64_t p = plan_p(pl);
+    if (nbk == 10) {
+        lo = (uint64_t)b * p;
+        width = p;
+    } else if (p >= 10) {
+        lo = (uint64_t)b * (p / 10);
+        width = p / 10;
+    } else {  // D = 1: bucket 10u
+        lo = (uint64_t)(b / 10);
+        width = 1;
     }
 }
 

@@ -321,10 +321,11 @@ __device__ __forceinline__ void block_minmax(T& mn, T& mx, T* rmn, T* rmx) {
 // the tiles whose p is smaller (every key then has digit 0) instead of
 // reading the keys again.  Keys are read strided (thread t: t, t + NT, ...),
 // coalesced per wave, and kept in registers for the count.
-template <typename K>
+template <typename K, int NBK>
 __global__ __launch_bounds__(kHistNT) void k_range(Work<K> w) {
     __shared__ K rmn[kHistNT / kWave], rmx[kHistNT / kWave];
     __shared__ uint32_t red[kHistNT / kWave][5];
+    __shared__ uint32_t h[NBK == 100 ? 100 : 1];
     const int t = blockIdx.x;
     const TileDesc td = w.tiles[t];
     if (td.cnt == 0) return;
@@ -370,14 +371,25 @@ __global__ __launch_bounds__(kHistNT) void k_range(Work<K> w) {
         return;
     }
     const DigitPlan<K> pl = make_digit_plan<K>(K(0), mx);
-    uint64_t c = 0;  // at most kHistVT = 16 keys per thread: fits the 5-bit fields
+    if constexpr (NBK == 10) {
+        uint64_t c = 0;  // at most kHistVT = 16 keys per thread: fits the 5-bit fields
 #pragma unroll
-    for (int v = 0; v < kHistVT; v++) c += (uint64_t)(vec || tid + v * kHistNT < cnt) << (5 * digit_of(pl, ks[v]));
-    uint32_t wd[5];
-    unpack5(c, wd);
-    block_sum5<kHistNT>(wd, red);
-    if (tid < 10) w.counts[10 * (int64_t)(t - td.idx) + tid * td.nt + td.idx] = field16(wd, tid);
-    if (tid == 0) w.tp[t] = (uint64_t)pl.thr[0] + 1;
+        for (int v = 0; v < kHistVT; v++) c += (uint64_t)(vec || tid + v * kHistNT < cnt) << (5 * digit_of(pl, ks[v]));
+        uint32_t wd[5];
+        unpack5(c, wd);
+        block_sum5<kHistNT>(wd, red);
+        if (tid < 10) w.counts[10 * (int64_t)(t - td.idx) + tid * td.nt + td.idx] = field16(wd, tid);
+    } else {
+        // one hundred buckets: LDS atomics (block_minmax ended with a barrier)
+        if (tid < 100) h[tid] = 0;
+        __syncthreads();
+#pragma unroll
+        for (int v = 0; v < kHistVT; v++)
+            if (vec || tid + v * kHistNT < cnt) atomicAdd(&h[bucket2_of(pl, ks[v])], 1u);
+        __syncthreads();
+        if (tid < 100) w.counts[100 * (int64_t)(t - td.idx) + tid * td.nt + td.idx] = h[tid];
+    }
+    if (tid == 0) w.tp[t] = plan_p(pl);
 }
 
 // Per large segment: min/max over its tiles, then the decimal digit plan.
@@ -406,9 +418,10 @@ __global__ __launch_bounds__(1024) void k_plans(Work<K> w) {
 // segment s, counts[10*tilepre[s] + d*tilecnt[s] + i] (bucket-major, tile
 // minor), so one exclusive scan of the whole array yields every tile's write
 // offset inside its bucket.
-template <typename K>
+template <typename K, int NBK>
 __global__ __launch_bounds__(kHistNT) void k_hist(Work<K> w, int64_t tiles_bound) {
     __shared__ uint32_t red[kHistNT / kWave][5];
+    __shared__ uint32_t h[NBK == 100 ? 100 : 1];
     __shared__ int64_t slow[kHistNT];
     __shared__ int nslow;
     const int tid = threadIdx.x;
@@ -427,16 +440,19 @@ __global__ __launch_bounds__(kHistNT) void k_hist(Work<K> w, int64_t tiles_bound
             if (td.cnt > 0) {
                 const DigitPlan<K> pl = w.plans[td.seg];
                 const uint64_t tp = w.tp[t];
-                if (pl.beta == 0 && tp != 0) {
-                    // counted by k_range under the tile's own plan: the
-                    // segment's plan, or one with a smaller p, and then every
-                    // key has digit 0
-                    if (tp != (uint64_t)pl.thr[0] + 1) {
-                        uint32_t* out = w.counts + 10 * (t - td.idx) + td.idx;
-                        out[0] = (uint32_t)td.cnt;
-                        for (int d = 1; d < 10; d++) out[d * td.nt] = 0;
-                    }
-                } else {
+                // counted by k_range under the tile's own plan: the
+                // segment's plan, or one with a smaller p (at most a tenth of
+                // the segment's).  Ten buckets: every key then has digit 0.
+                // One hundred: every key is in bucket 0 when the tile's p is
+                // at most a hundredth of the segment's; at a tenth the keys
+                // are counted again.
+                const uint64_t ps = plan_p(pl);
+                const bool own = pl.beta == 0 && tp != 0;
+                if (own && tp != ps && (NBK == 10 || tp <= ps / 100)) {
+                    uint32_t* out = w.counts + NBK * (t - td.idx) + td.idx;
+                    out[0] = (uint32_t)td.cnt;
+                    for (int d = 1; d < NBK; d++) out[d * td.nt] = 0;
+                } else if (!own || tp != ps) {
                     slow[atomicAdd(&nslow, 1)] = t;
                 }
             }
@@ -446,115 +462,113 @@ __global__ __launch_bounds__(kHistNT) void k_hist(Work<K> w, int64_t tiles_bound
         for (int k = 0; k < ns; k++) {
             const TileDesc td = w.tiles[slow[k]];
             const DigitPlan<K> pl = w.plans[td.seg];
-            uint64_t c = 0;  // a thread sees at most 16 + 3 + 3 keys: fits the 5-bit fields
-            load_run<K, kHistNT, kHistTile>(w.keys + td.base, td.cnt,
-                                            [&](int, K k) { c += 1ull << (5 * digit_of(pl, k)); });
-            uint32_t wd[5];
-            unpack5(c, wd);
-            block_sum5<kHistNT>(wd, red);
-            if (tid < 10) w.counts[10 * (slow[k] - td.idx) + tid * td.nt + td.idx] = field16(wd, tid);
+            if constexpr (NBK == 10) {
+                uint64_t c = 0;  // a thread sees at most 16 + 3 + 3 keys: fits the 5-bit fields
+                load_run<K, kHistNT, kHistTile>(w.keys + td.base, td.cnt,
+                                                [&](int, K k) { c += 1ull << (5 * digit_of(pl, k)); });
+                uint32_t wd[5];
+                unpack5(c, wd);
+                block_sum5<kHistNT>(wd, red);
+                if (tid < 10) w.counts[10 * (slow[k] - td.idx) + tid * td.nt + td.idx] = field16(wd, tid);
+            } else {
+                if (tid < 100) h[tid] = 0;
+                __syncthreads();
+                load_run<K, kHistNT, kHistTile>(w.keys + td.base, td.cnt,
+                                                [&](int, K k) { atomicAdd(&h[bucket2_of(pl, k)], 1u); });
+                __syncthreads();
+                if (tid < 100) w.counts[100 * (slow[k] - td.idx) + tid * td.nt + td.idx] = h[tid];
+                __syncthreads();
+            }
         }
         __syncthreads();
     }
 }
 
-// Bucket table: start and size of each of the ten buckets of every segment,
-// its local-sort tiles and merge chunks, and the bounds output.
+// Bucket table: start and size of each bucket (ten or one hundred per
+// segment), its local-sort tiles and merge chunks, and the ten-bucket bounds
+// output (with one hundred buckets, bound b is the start of bucket 10b).
 template <typename K>
 __global__ void k_btab(Work<K> w) {
     if (*w.err) return;
-    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < w.nseg; s += gridDim.x * blockDim.x) {
+    // one thread per bucket of every segment
+    const int nbk = w.nbk;
+    const int per = nbk / 10;  // buckets per ten-bucket bound
+    const int64_t nbt = (int64_t)nbk * w.nseg;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < nbt; j += (int64_t)gridDim.x * blockDim.x) {
+        const int s = (int)(j / nbk), d = (int)(j - (int64_t)s * nbk);
         const int nt = w.tilecnt[s];
         const int64_t a = w.off[s];
         if (nt == 0) {
-            for (int d = 0; d < 10; d++) {
-                w.bstart[10 * s + d] = a;
-                w.bsize[10 * s + d] = 0;
-                w.tsc[10 * s + d] = 0;
-                w.mcc[10 * s + d] = 0;
-            }
+            w.bstart[j] = a;
+            w.bsize[j] = 0;
+            w.tsc[j] = 0;
+            w.mcc[j] = 0;
             continue;
         }
-        const int64_t base = 10 * (int64_t)w.tilepre[s];
+        const int64_t base = (int64_t)nbk * w.tilepre[s];
         const int64_t p0 = w.pos[base];
-        for (int d = 0; d < 10; d++) {
-            const int64_t st = w.pos[base + (int64_t)d * nt] - p0;
-            const int64_t en = w.pos[base + (int64_t)(d + 1) * nt] - p0;
-            const int64_t sz = en - st;
-            w.bstart[10 * s + d] = a + st;
-            w.bsize[10 * s + d] = sz;
-            w.tsc[10 * s + d] = (int32_t)((sz + w.tile - 1) / w.tile);
-            w.mcc[10 * s + d] = (int32_t)((sz + w.nv - 1) / w.nv);
-            w.bounds_out[11 * (int64_t)s + d] = st;
-            const int r = merge_rounds(sz, w.tile, w.fanin);
-            if (r > 0) atomicMax(w.rounds, r);
-        }
-        w.bounds_out[11 * (int64_t)s + 10] = w.off[s + 1] - a;
+        const int64_t st = w.pos[base + (int64_t)d * nt] - p0;
+        const int64_t en = w.pos[base + (int64_t)(d + 1) * nt] - p0;
+        const int64_t sz = en - st;
+        w.bstart[j] = a + st;
+        w.bsize[j] = sz;
+        w.tsc[j] = (int32_t)((sz + w.tile - 1) / w.tile);
+        w.mcc[j] = (int32_t)((sz + w.nv - 1) / w.nv);
+        if (d % per == 0) w.bounds_out[11 * (int64_t)s + d / per] = st;
+        if (d == 0) w.bounds_out[11 * (int64_t)s + 10] = w.off[s + 1] - a;
+        const int r = merge_rounds(sz, w.tile, w.fanin);
+        if (r > 0) atomicMax(w.rounds, r);
     }
 }
 
 // ---------------------------------------------------------------- scatter
-// Stable one-step MSD scatter (Section 3.4: the master divides the keys into
-// ten parts by most significant digit).  Per tile: blocked ranks from packed
-// per-thread counters and a block scan, staging in LDS grouped by bucket,
-// then runs of consecutive keys written to their bucket in the scratch copy.
-template <typename K, bool PAIRS>
-__global__ __launch_bounds__(kHistNT) void k_scatter(Work<K> w) {
-    constexpr int NT = kHistNT, VT = kHistVT, HT = kHistTile;
-    __shared__ K sk[lds_padded_size<K>(HT)];
-    __shared__ uint32_t sv[PAIRS ? HT : 1];
-    __shared__ uint8_t sd[HT];
-    __shared__ uint32_t red[NT / kWave][5];
-    // each thread's staging start per bucket, read back by digit: an indexed
+// One stable counting pass of a tile held in LDS by a decimal digit 0..9:
+// every thread ranks its VT consecutive keys (blocked) with packed
+// per-thread counters, a block scan gives each thread's start per digit, and
+// the keys are staged back grouped by digit, in input order inside a digit.
+// dig(key, tag_in) returns the key's digit (bits 0..3) and the byte staged
+// with the key in sd (bits 8..15); with TAGIN, tag_in is the byte the key
+// carried in (a thread's VT = 16 bytes come in one 16-byte LDS read), else 0.
+// tot receives the tile's per-digit totals (packed).
+template <typename K, bool PAIRS, bool FULL, bool TAGIN, typename Dig>
+__device__ __forceinline__ void digit_pass(K* sk, uint32_t* sv, uint8_t* sd, uint32_t (*red)[5],
+                                           uint16_t (*offs)[kHistNT], int cnt, Dig&& dig, uint32_t (&tot)[5]) {
+    constexpr int NT = kHistNT, VT = kHistVT;
+    static_assert(VT == 16, "a thread's tags are one 16-byte word");
+    // each thread's staging start per digit, read back by digit: an indexed
     // LDS read is cheaper than selecting among registers, but the 5 KB cost
     // 64-bit keys and pairs a resident workgroup, so they select instead
     constexpr bool kOffsLds = sizeof(K) == 4 && !PAIRS;
-    __shared__ int32_t dbase[10];  // element index (n < 2^31) of bucket d's run, minus its staging start
-    __shared__ uint16_t offs[kOffsLds ? 10 : 1][NT];
-    const int t = blockIdx.x;
-    const TileDesc td = w.tiles[t];
-    if (td.cnt == 0) return;
     const int tid = threadIdx.x;
-    const int i = td.idx;
-    const int nt = td.nt;
-    const int64_t base = td.base;
-    const int cnt = td.cnt;
-    const DigitPlan<K> pl = w.plans[td.seg];
-    // 1. load in natural order (16-byte body)
-    load_run<K, NT, HT>(w.keys + base, cnt, [&](int q, K k) { sk[lds_pad<K>(q)] = k; });
-    if constexpr (PAIRS) load_run<uint32_t, NT, HT>(w.vals + base, cnt, [&](int q, uint32_t v) { sv[q] = v; });
-    if (tid < 10) {
-        const int64_t pbase = 10 * (int64_t)(t - i);
-        dbase[tid] = (int32_t)(td.seg_base + w.pos[pbase + (int64_t)tid * nt + i] - w.pos[pbase]);
-    }
-    __syncthreads();
-    // 2. blocked: digit and rank among this thread's own keys, packed as
-    //    rank << 4 | digit (digit 15 = no key)
     K key[VT];
     uint32_t val[PAIRS ? VT : 1];
-    uint32_t pk[VT];
+    uint32_t pk[VT];  // tag << 16 | rank << 4 | digit (digit 15 = no key)
+    uint32_t tg[4] = {0, 0, 0, 0};
+    if constexpr (TAGIN) {
+        const uint4 x = *reinterpret_cast<const uint4*>(sd + tid * VT);
+        tg[0] = x.x;
+        tg[1] = x.y;
+        tg[2] = x.z;
+        tg[3] = x.w;
+    }
     uint64_t c = 0;
-    auto rank_keys = [&](auto full) {  // full: every slot holds a key (no per-key bounds test)
 #pragma unroll
-        for (int v = 0; v < VT; v++) {
-            const int q = tid * VT + v;
-            const bool ok = decltype(full)::value || q < cnt;
-            key[v] = sk[lds_pad<K>(ok ? q : 0)];
-            if constexpr (PAIRS) val[v] = sv[ok ? q : 0];
-            const int d = digit_of(pl, key[v]);
-            pk[v] = ok ? ((((uint32_t)(c >> (5 * d)) & 31u) << 4) | (uint32_t)d) : 15u;
-            c += ok ? (1ull << (5 * d)) : 0ull;
-        }
-    };
-    if (cnt == HT)
-        rank_keys(std::true_type{});
-    else
-        rank_keys(std::false_type{});
-    // 3. exclusive scan over threads, and the tile's bucket totals
-    uint32_t wd[5], tot[5];
+    for (int v = 0; v < VT; v++) {
+        const int q = tid * VT + v;
+        const bool ok = FULL || q < cnt;
+        const int qq = ok ? q : 0;
+        key[v] = sk[lds_pad<K>(qq)];
+        if constexpr (PAIRS) val[v] = sv[qq];
+        const uint32_t dt = dig(key[v], (tg[v >> 2] >> (8 * (v & 3))) & 0xFFu);
+        const uint32_t d = dt & 15u;
+        const uint32_t r = (((uint32_t)(c >> (5 * d)) & 31u) << 4) | d;
+        pk[v] = ok ? ((dt & 0xFF00u) << 8) | r : 15u;
+        c += ok ? (1ull << (5 * d)) : 0ull;
+    }
+    uint32_t wd[5];
     unpack5(c, wd);
-    block_excl5<NT>(wd, tot, red);  // ends with a barrier: sk may be overwritten
-    // 4. tile-local bucket starts folded into the packed prefix
+    block_excl5<NT>(wd, tot, red);  // ends with a barrier: sk, sv and sd may be overwritten
+    // tile-local digit starts folded into the packed prefix
     uint32_t run = 0;
 #pragma unroll
     for (int m = 0; m < 5; m++) {
@@ -564,7 +578,6 @@ __global__ __launch_bounds__(kHistNT) void k_scatter(Work<K> w) {
         run += tot[m] >> 16;
         wd[m] += lo | (hi << 16);
     }
-    // 5. stage grouped by bucket
     if constexpr (kOffsLds) {
 #pragma unroll
         for (int m = 0; m < 5; m++) {
@@ -575,35 +588,121 @@ __global__ __launch_bounds__(kHistNT) void k_scatter(Work<K> w) {
 #pragma unroll
     for (int v = 0; v < VT; v++) {
         const uint32_t d = pk[v] & 15u;
-        if (d < 10) {
+        if (FULL || d < 10) {  // a full tile has no empty slot: no branch
             const uint32_t start = kOffsLds ? (uint32_t)offs[kOffsLds ? d : 0][tid] : field16(wd, (int)d);
-            const int sp = (int)(start + (pk[v] >> 4));
+            const int sp = (int)(start + ((pk[v] >> 4) & 31u));
             sk[lds_pad<K>(sp)] = key[v];
-            sd[sp] = (uint8_t)d;
+            sd[sp] = (uint8_t)(pk[v] >> 16);
             if constexpr (PAIRS) sv[sp] = val[v];
         }
     }
-    if (tid < 10) {  // dbase[d] -= tile-local start of bucket d
-        uint32_t st = 0, r2 = 0;
-#pragma unroll
-        for (int d = 0; d < 10; d++) {
-            st = (d == tid) ? r2 : st;
-            r2 += (tot[d >> 1] >> ((d & 1) * 16)) & 0xFFFFu;
-        }
-        dbase[tid] -= (int32_t)st;
+}
+
+// Stable one-step MSD scatter (Section 3.4: the master divides the keys into
+// ten parts by most significant digit; NBK = 100 is the finer two-digit
+// splitter).  Per tile: the keys are grouped by bucket in LDS -- ten buckets
+// by one counting pass on the digit, one hundred by two passes, first on the
+// second digit and then on the first (each pass stable, so the second keeps
+// the first's order inside a digit) -- and runs of consecutive keys are
+// written to their buckets in the scratch copy.  The bucket of a staged key
+// travels with it in a byte array, so each key's bucket is computed once.
+template <typename K, bool PAIRS, int NBK>
+__global__ __launch_bounds__(kHistNT) void k_scatter(Work<K> w) {
+    constexpr int NT = kHistNT, VT = kHistVT, HT = kHistTile;
+    __shared__ K sk[lds_padded_size<K>(HT)];
+    __shared__ uint32_t sv[PAIRS ? HT : 1];
+    __shared__ __align__(16) uint8_t sd[HT];
+    __shared__ uint32_t red[NT / kWave][5];
+    constexpr bool kOffsLds = sizeof(K) == 4 && !PAIRS;
+    __shared__ int32_t dbase[NBK];  // element index (n < 2^31) of bucket d's run, minus its staging start
+    __shared__ uint16_t offs[kOffsLds ? 10 : 1][NT];
+    const int t = blockIdx.x;
+    const TileDesc td = w.tiles[t];
+    if (td.cnt == 0) return;
+    const int tid = threadIdx.x;
+    const int i = td.idx;
+    const int nt = td.nt;
+    const int64_t base = td.base;
+    const int cnt = td.cnt;
+    const DigitPlan<K> pl = w.plans[td.seg];
+    const int64_t pbase = NBK * (int64_t)(t - i);
+    // the tile's write offset in each bucket (and, with one hundred buckets,
+    // its count there), loaded before the keys so that both round trips
+    // overlap
+    uint32_t cb = 0;
+    int64_t gp = 0;
+    if (tid < NBK) {
+        gp = w.pos[pbase + (int64_t)tid * nt + i] - w.pos[pbase];
+        if constexpr (NBK == 100) cb = w.counts[pbase + (int64_t)tid * nt + i];
+    }
+    // 1. load in natural order (16-byte body)
+    load_run<K, NT, HT>(w.keys + base, cnt, [&](int q, K k) { sk[lds_pad<K>(q)] = k; });
+    if constexpr (PAIRS) load_run<uint32_t, NT, HT>(w.vals + base, cnt, [&](int q, uint32_t v) { sv[q] = v; });
+    if constexpr (NBK == 10) {
+        if (tid < 10) dbase[tid] = (int32_t)(td.seg_base + gp);
+    } else {
+        // the tile's start of each bucket: exclusive scan of its counts
+        uint32_t all;
+        const uint32_t ls = block_excl_scan<uint32_t, NT>(cb, all, &red[0][0]);
+        if (tid < NBK) dbase[tid] = (int32_t)(td.seg_base + gp - (int64_t)ls);
     }
     __syncthreads();
-    // 6. coalesced runs out to the buckets (a per-bucket loop of 16-byte
-    //    stores measured no faster for keys and slower for pairs)
+    uint32_t tot[5];
+    auto passes = [&](auto full) {
+        constexpr bool F = decltype(full)::value;
+        if constexpr (NBK == 10) {
+            digit_pass<K, PAIRS, F, false>(sk, sv, sd, red, offs, cnt, [&](K k, uint32_t) {
+                const uint32_t d = (uint32_t)digit_of(pl, k);
+                return d | (d << 8);
+            }, tot);
+        } else {
+            // pass 1 on the second digit, pass 2 on the first; b = 10 d1 + d2
+            // (d1 = b * 205 >> 11, exact for b < 100)
+            digit_pass<K, PAIRS, F, false>(sk, sv, sd, red, offs, cnt, [&](K k, uint32_t) {
+                const uint32_t b = (uint32_t)bucket2_of(pl, k);
+                return (b - 10u * ((b * 205u) >> 11)) | (b << 8);
+            }, tot);
+            __syncthreads();
+            digit_pass<K, PAIRS, F, true>(sk, sv, sd, red, offs, cnt, [&](K, uint32_t b) {
+                return ((b * 205u) >> 11) | (b << 8);
+            }, tot);
+        }
+    };
+    if (cnt == HT)
+        passes(std::true_type{});
+    else
+        passes(std::false_type{});
+    if constexpr (NBK == 10) {
+        if (tid < 10) {  // dbase[d] -= tile-local start of bucket d
+            uint32_t st = 0, r2 = 0;
 #pragma unroll
-    for (int j = 0; j < VT; j++) {
-        const int q = j * NT + tid;
-        if (q < cnt) {
-            const uint32_t dst = (uint32_t)(dbase[sd[q]] + q);
-            w.skeys[dst] = sk[lds_pad<K>(q)];
-            if constexpr (PAIRS) w.svals[dst] = sv[q];
+            for (int d = 0; d < 10; d++) {
+                st = (d == tid) ? r2 : st;
+                r2 += (tot[d >> 1] >> ((d & 1) * 16)) & 0xFFFFu;
+            }
+            dbase[tid] -= (int32_t)st;
         }
     }
+    __syncthreads();
+    // 2. coalesced runs out to the buckets (a per-bucket loop of 16-byte
+    //    stores measured no faster for keys and slower for pairs)
+    auto write_out = [&](auto full) {
+#pragma unroll
+        for (int j = 0; j < VT; j++) {
+            const int q = j * NT + tid;
+            if (decltype(full)::value || q < cnt) {
+                const K k = sk[lds_pad<K>(q)];
+                const int b = sd[q];
+                const uint32_t dst = (uint32_t)(dbase[b] + q);
+                w.skeys[dst] = k;
+                if constexpr (PAIRS) w.svals[dst] = sv[q];
+            }
+        }
+    };
+    if (cnt == HT)
+        write_out(std::true_type{});
+    else
+        write_out(std::false_type{});
 }
 
 // Materialises the flat list of local-sort partitions (one thread per slot).
@@ -611,7 +710,7 @@ template <typename K>
 __global__ void k_sdesc(Work<K> w, int64_t bound) {
     const int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (item >= bound) return;
-    const int nb = 10 * w.nseg;
+    const int nb = w.nbk * w.nseg;
     SortDesc d{0, 0, 0, 0, 0};
     if (!*w.err && item < w.tsp[nb]) {
         const int j = owner_of(w.tsp, nb, (int)item);
@@ -673,10 +772,11 @@ __global__ __launch_bounds__(NT) void k_tilesort(Work<K> w) {
             using U = typename Traits<K>::U;
             constexpr int POS = NV <= 4096 ? 12 : 13;
             static_assert(NV <= (1 << POS), "indices fit the narrow word");
-            const DigitPlan<K> pl = w.plans[sd.bucket / 10];
-            const uint64_t p = (uint64_t)pl.thr[0] + 1;
-            if (p - 1 <= (uint64_t(1) << (32 - POS)) - 2) {
-                const U base = pl.beta + (U)(sd.bucket % 10) * (U)p;
+            const DigitPlan<K> pl = w.plans[sd.bucket / w.nbk];
+            uint64_t lo, width;
+            bucket_span(pl, w.nbk, sd.bucket % w.nbk, lo, width);
+            if (width - 1 <= (uint64_t(1) << (32 - POS)) - 2) {
+                const U base = pl.beta + (U)lo;
                 uint32_t* w32 = reinterpret_cast<uint32_t*>(words);
                 load_run<K, NT, NV>(srck, cnt, [&](int q, K k) {
                     w32[lds_pad<uint32_t>(q)] = ((uint32_t)((U)k - base) << POS) | (uint32_t)q;
@@ -720,7 +820,7 @@ template <typename K>
 __global__ __launch_bounds__(256) void k_partition(Work<K> w, int pass, int64_t bound) {
     const int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (item >= bound) return;
-    const int nb = 10 * w.nseg;
+    const int nb = w.nbk * w.nseg;
     MergeDesc d{0, 0, 0, 0, 0, 0, 0};
     if (!*w.err && pass < *w.rounds && item < w.msp[nb]) {
         const int j = owner_of(w.msp, nb, (int)item);
@@ -848,7 +948,7 @@ template <typename K>
 __global__ __launch_bounds__(256) void k_part4(Work<K> w, int round, int64_t bound) {
     const int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (item >= bound) return;
-    const int nb = 10 * w.nseg;
+    const int nb = w.nbk * w.nseg;
     Split4 d{};
     if (!*w.err && round < *w.rounds && item < w.msp[nb]) {
         const int j = owner_of(w.msp, nb, (int)item);
@@ -1267,7 +1367,7 @@ __global__ __launch_bounds__(NT) void k_small(Work<K> w, int64_t lo, int64_t hi)
 template <typename K>
 __global__ void k_collect(Work<K> w, int stage) {
     if (*w.err) return;
-    const int nb = 10 * w.nseg;
+    const int nb = w.nbk * w.nseg;
     for (int j = blockIdx.x; j < nb; j += gridDim.x) {
         const int64_t size = w.bsize[j];
         if (size == 0) continue;
@@ -1423,7 +1523,10 @@ hipError_t launch_setup(const Work<K>& w, int64_t* own_off, hipStream_t st) {
 
 template <typename K>
 hipError_t launch_range(const Work<K>& w, int64_t tiles_bound, hipStream_t st) {
-    k_range<K><<<grid_of(tiles_bound), kHistNT, 0, st>>>(w);
+    if (w.nbk == 100)
+        k_range<K, 100><<<grid_of(tiles_bound), kHistNT, 0, st>>>(w);
+    else
+        k_range<K, 10><<<grid_of(tiles_bound), kHistNT, 0, st>>>(w);
     return hipGetLastError();
 }
 
@@ -1436,20 +1539,27 @@ hipError_t launch_plans(const Work<K>& w, hipStream_t st) {
 
 template <typename K>
 hipError_t launch_hist(const Work<K>& w, int64_t tiles_bound, hipStream_t st) {
-    k_hist<K><<<grid_of(tiles_bound < kHistGrid ? tiles_bound : kHistGrid), kHistNT, 0, st>>>(w, tiles_bound);
+    const int g = grid_of(tiles_bound < kHistGrid ? tiles_bound : kHistGrid);
+    if (w.nbk == 100)
+        k_hist<K, 100><<<g, kHistNT, 0, st>>>(w, tiles_bound);
+    else
+        k_hist<K, 10><<<g, kHistNT, 0, st>>>(w, tiles_bound);
     return hipGetLastError();
 }
 
 template <typename K>
 hipError_t launch_btab(const Work<K>& w, hipStream_t st) {
-    const int g = (int)min((int64_t)1024, (int64_t)cdiv64(w.nseg, 256));
+    const int g = (int)min((int64_t)4096, (int64_t)cdiv64((int64_t)w.nbk * w.nseg, 256));
     k_btab<K><<<g < 1 ? 1 : g, 256, 0, st>>>(w);
     return hipGetLastError();
 }
 
 template <typename K, bool PAIRS>
 hipError_t launch_scatter(const Work<K>& w, int64_t tiles_bound, hipStream_t st) {
-    k_scatter<K, PAIRS><<<grid_of(tiles_bound), kHistNT, 0, st>>>(w);
+    if (w.nbk == 100)
+        k_scatter<K, PAIRS, 100><<<grid_of(tiles_bound), kHistNT, 0, st>>>(w);
+    else
+        k_scatter<K, PAIRS, 10><<<grid_of(tiles_bound), kHistNT, 0, st>>>(w);
     return hipGetLastError();
 }
 
@@ -1503,7 +1613,7 @@ hipError_t launch_small(const Work<K>& w, int64_t lo, int64_t hi, int64_t segs_b
 
 template <typename K>
 hipError_t launch_collect(const Work<K>& w, int stage, hipStream_t st) {
-    const int g = (int)min((int64_t)4096, (int64_t)10 * w.nseg);
+    const int g = (int)min((int64_t)4096, (int64_t)w.nbk * w.nseg);
     k_collect<K><<<g < 1 ? 1 : g, 256, 0, st>>>(w, stage);
     return hipGetLastError();
 }

@@ -28,7 +28,7 @@ struct SortDesc {
     int64_t start;   // first key
     int32_t cnt;     // keys (0: no work)
     int32_t odd;     // bit 0: write to the scratch copy (odd number of merge rounds); bit 1: odd partition
-    int32_t bucket;  // 10 * segment + digit
+    int32_t bucket;  // nbk * segment + bucket of the segment
     int32_t sbase;   // sample index of the partition's first 32-key block
 };
 
@@ -102,16 +102,16 @@ struct Work {
     int64_t* bounds_out;      // [nseg * 11] bucket bounds relative to the segment start
 
     // per histogram tile (flat over all large segments, bucket-major inside a segment)
-    uint32_t* counts;  // [10 * tiles]
-    int64_t* pos;      // [10 * tiles + 1] exclusive prefix of counts
+    uint32_t* counts;  // [nbk * tiles]
+    int64_t* pos;      // [nbk * tiles + 1] exclusive prefix of counts
 
-    // per bucket (10 per segment)
+    // per bucket (nbk per segment)
     int64_t* bstart;  // absolute first key of the bucket
     int64_t* bsize;
     int32_t* tsc;  // local-sort tiles of the bucket
-    int32_t* tsp;  // [10 * nseg + 1] prefix
+    int32_t* tsp;  // [nbk * nseg + 1] prefix
     int32_t* mcc;  // merge chunks of the bucket
-    int32_t* msp;  // [10 * nseg + 1] prefix
+    int32_t* msp;  // [nbk * nseg + 1] prefix
 
     TileDesc* tiles;   // [tiles bound]
     SortDesc* sdesc;   // [local-sort partitions bound]
@@ -120,6 +120,7 @@ struct Work {
     int32_t* rounds;  // largest number of merge rounds any bucket needs
     uint32_t* err;   // device-side validation flag (bad offsets)
 
+    int32_t nbk;        // buckets per segment: 10 (one decimal digit) or 100 (two)
     int32_t tile;       // keys per local-sort tile (T)
     int32_t fanin;      // runs merged per round: 2 or 4
     int32_t nv;         // outputs per merge workgroup (divides T)

@@ -97,17 +97,19 @@ def test_config_roundtrip(lib):
 
     assert [hs.hsort_size_class(n) for n in (1, 1 << 18, (1 << 18) + 1, 1 << 22, 1 << 26, 1 << 28)] == [0, 0, 1, 1, 2, 3]
     cfg = hs.hsort_get_config(hs.KEYS_I32, size_class=3)
-    t, tvt, m, mvt, s, fanin = cfg
-    assert t % m == 0 and s <= 8192 and t % tvt == 0 and m % mvt == 0 and fanin in (2, 4)
+    t, tvt, m, mvt, s, fanin, digits = cfg
+    assert t % m == 0 and s <= 8192 and t % tvt == 0 and m % mvt == 0 and fanin in (2, 4) and digits in (1, 2)
     with pytest.raises(hs.HsortError):
         hs.hsort_set_config(hs.KEYS_I32, 1000, 16, 4096, 16, 100)
     with pytest.raises(hs.HsortError):  # merge chunk does not divide the tile
         hs.hsort_set_config(hs.KEYS_I32, 4096, 16, 8192, 32, 100)
     with pytest.raises(hs.HsortError):  # fan-in must be 2 or 4
         hs.hsort_set_config(hs.KEYS_I32, t, tvt, m, mvt, s, fanin=3, size_class=3)
-    hs.hsort_set_config(hs.KEYS_I32, t, tvt, m, mvt, s, fanin=4, size_class=3)
-    assert hs.hsort_get_config(hs.KEYS_I32, size_class=3)[5] == 4
-    hs.hsort_set_config(hs.KEYS_I32, *cfg[:5], fanin=cfg[5], size_class=3)
+    with pytest.raises(hs.HsortError):  # digits must be 1 or 2
+        hs.hsort_set_config(hs.KEYS_I32, t, tvt, m, mvt, s, fanin=fanin, digits=3, size_class=3)
+    hs.hsort_set_config(hs.KEYS_I32, t, tvt, m, mvt, s, fanin=4, digits=3 - digits, size_class=3)
+    assert hs.hsort_get_config(hs.KEYS_I32, size_class=3)[5:] == (4, 3 - digits)
+    hs.hsort_set_config(hs.KEYS_I32, *cfg[:5], fanin=cfg[5], digits=cfg[6], size_class=3)
     assert hs.hsort_get_config(hs.KEYS_I32, size_class=3) == cfg
 
 
@@ -116,12 +118,17 @@ def test_tuning_file(lib, tmp_path):
 
     before = [hs.hsort_get_config(hs.KEYS_I64, size_class=c) for c in range(4)]
     f = tmp_path / "t.txt"
-    f.write_text("# kind class tile tile_vt merge_nv merge_vt small_max fanin\n1 2 8192 16 4096 16 2048 4\n")
+    f.write_text("# kind class tile tile_vt merge_nv merge_vt small_max fanin [digits]\n"
+                 "1 2 8192 16 4096 16 2048 4\n1 3 8192 16 4096 16 2048 4 2\n")
     hs.hsort_load_tuning(str(f))
-    assert hs.hsort_get_config(hs.KEYS_I64, size_class=2) == (8192, 16, 4096, 16, 2048, 4)
+    assert hs.hsort_get_config(hs.KEYS_I64, size_class=2) == (8192, 16, 4096, 16, 2048, 4, 1)
+    assert hs.hsort_get_config(hs.KEYS_I64, size_class=3) == (8192, 16, 4096, 16, 2048, 4, 2)
     assert hs.hsort_get_config(hs.KEYS_I64, size_class=1) == before[1]
+    f.write_text("1 2 8192 16 4096 16 2048 4 5\n")
+    with pytest.raises(hs.HsortError):
+        hs.hsort_load_tuning(str(f))
     f.write_text("1 2 999 16 4096 16 2048 2\n")
     with pytest.raises(hs.HsortError):
         hs.hsort_load_tuning(str(f))
     for c, cfg in enumerate(before):
-        hs.hsort_set_config(hs.KEYS_I64, *cfg[:5], fanin=cfg[5], size_class=c)
+        hs.hsort_set_config(hs.KEYS_I64, *cfg[:5], fanin=cfg[5], digits=cfg[6], size_class=c)

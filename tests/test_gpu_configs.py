@@ -1,8 +1,10 @@
 """Every configuration the autotuner can pick (local-sort tile shape, merge
-shape, fan-in 2 or 4, small-segment threshold) sorts bit-exactly like the
-oracle, so a tuning table can select none that is untested.  Inputs are sized
-so that the largest bucket holds more than four local-sort tiles (two fan-in-4
-rounds, three fan-in-2 rounds) and end in a ragged tile."""
+shape, fan-in 2 or 4, small-segment threshold, ten or one hundred buckets)
+sorts bit-exactly like the oracle, so a tuning table can select none that is
+untested.  Inputs are sized so that the largest bucket holds more than four
+local-sort tiles (two fan-in-4 rounds, three fan-in-2 rounds) and end in a
+ragged tile; with one hundred buckets, four fifths of the keys are drawn from
+the lowest two-digit bucket so that it still needs merge rounds."""
 import sys
 
 import numpy as np
@@ -27,7 +29,19 @@ def say(msg):
 
 
 def _cands(kind):
-    return [pytest.param(c, id="t{}x{}-m{}x{}-s{}-f{}".format(*c)) for c in autotune.candidates(kind)]
+    return [pytest.param(c, id="t{}x{}-m{}x{}-s{}-f{}-d{}".format(*c)) for c in autotune.candidates(kind)]
+
+
+def skew(keys, cfg, lo, width, seed):
+    """With one hundred buckets (cfg[6] == 2), put four fifths of the keys in
+    [lo, lo + width), the lowest two-digit bucket of the array's plan."""
+    if cfg[6] != 2:
+        return keys
+    r = np.random.default_rng(seed)
+    k = keys.copy()
+    m = r.random(k.size) < 0.8
+    k[m] = (lo + r.integers(0, width, int(m.sum()))).astype(k.dtype)
+    return k
 
 
 @pytest.fixture(scope="module")
@@ -38,12 +52,12 @@ def hs():
     saved = {(k, c): hsmod.hsort_get_config(k, size_class=c) for k in range(5) for c in range(4)}
     yield hsmod
     for (k, c), cfg in saved.items():
-        hsmod.hsort_set_config(k, *cfg[:5], fanin=cfg[5], size_class=c)
+        hsmod.hsort_set_config(k, *cfg[:5], fanin=cfg[5], digits=cfg[6], size_class=c)
 
 
 def use(hs, kind, cfg):
     for c in range(4):
-        hs.hsort_set_config(kind, *cfg[:5], fanin=cfg[5], size_class=c)
+        hs.hsort_set_config(kind, *cfg[:5], fanin=cfg[5], digits=cfg[6], size_class=c)
 
 
 def dev(a):
@@ -59,6 +73,7 @@ def test_keys_i32(hs, orc, cfg):
     # full int32 range: buckets 0..4 of the shifted keys, the largest ~23 %
     n = 18 * cfg[0] + RAGGED
     k = np.random.default_rng(cfg[0] + cfg[2] + cfg[5]).integers(I32.min, I32.max, n, dtype=np.int32, endpoint=True)
+    k = skew(k, cfg, int(I32.min), 10**8, n)  # u up to 2^32 - 1: D = 10, two-digit buckets of 10^8
     say(f"config keys_i32 {cfg} n={n}")
     use(hs, hs.KEYS_I32, cfg)
     t = dev(k)
@@ -73,6 +88,7 @@ def test_keys_i64(hs, orc, cfg):
     # full int64 range: two buckets of the shifted keys, the larger ~55 %
     n = 8 * cfg[0] + RAGGED
     k = np.random.default_rng(cfg[0] + cfg[2] + cfg[5]).integers(I64.min, I64.max, n, dtype=np.int64, endpoint=True)
+    k = skew(k, cfg, int(I64.min), 10**18, n)  # D = 20, two-digit buckets of 10^18
     say(f"config keys_i64 {cfg} n={n}")
     use(hs, hs.KEYS_I64, cfg)
     t = dev(k)
@@ -90,11 +106,13 @@ def test_pairs(hs, orc, cfg, span):
     if span == "dup":
         n = 45 * cfg[0] + RAGGED
         k, v = W.dup_pairs_i32(n, cfg[0] + cfg[2])
+        k = skew(k, cfg, 0, 10, n)  # D = 3: two-digit buckets of ten values
     else:
         n = 18 * cfg[0] + RAGGED
         r = np.random.default_rng(cfg[0] + cfg[2] + 7)
         k = r.integers(I32.min, I32.max, n, dtype=np.int32, endpoint=True)
         v = r.integers(0, 2**32 - 1, n, dtype=np.uint32, endpoint=True)
+        k = skew(k, cfg, int(I32.min), 10**8, n)
     say(f"config pairs {span} {cfg} n={n}")
     use(hs, hs.PAIRS_I32_U32, cfg)
     t, tv = dev(k), dev(v.view(np.int32))
@@ -106,14 +124,18 @@ def test_pairs(hs, orc, cfg, span):
     assert np.array_equal(tv.cpu().numpy().view(np.uint32), ov)
 
 
-def _segments(dtype, tile, seed):
+def _segments(dtype, cfg, seed):
     """One segment of 18 tiles, then 59 of log-uniform sizes in [1, 2 tiles]
-    (whole-LDS and pipeline segments both), keys over the full range."""
+    (whole-LDS and pipeline segments both), keys over the full range (the
+    first segment skewed as above with one hundred buckets)."""
+    tile = cfg[0]
     r = np.random.default_rng(seed)
     sizes = [18 * tile + 5] + np.exp(r.uniform(0, np.log(2 * tile), 59)).astype(np.int64).tolist()
     off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
     info = np.iinfo(dtype)
     keys = r.integers(info.min, info.max, int(off[-1]), dtype=dtype, endpoint=True)
+    first = keys[: sizes[0]]
+    first[:] = skew(first, cfg, int(info.min), 10**8 if dtype == np.int32 else 10**18, seed)
     return keys, off
 
 
@@ -121,7 +143,7 @@ def _segments(dtype, tile, seed):
 def test_segmented_every_config(hs, orc, dtype):
     kind = hs.SEG_I32 if dtype == np.int32 else hs.SEG_I64
     for cfg in autotune.candidates(kind):
-        keys, off = _segments(dtype, cfg[0], cfg[0] + cfg[4] + cfg[5])
+        keys, off = _segments(dtype, cfg, cfg[0] + cfg[4] + cfg[5])
         nseg = off.size - 1
         say(f"config seg {np.dtype(dtype).name} {cfg} n={keys.size}")
         use(hs, kind, cfg)

@@ -33,11 +33,11 @@ def hs4(request):
     nv, vt = request.param
     saved = {(k, c): hs.hsort_get_config(k, size_class=c) for k in range(5) for c in range(4)}
     for (k, c), cfg in saved.items():
-        hs.hsort_set_config(k, cfg[0], cfg[1], nv, vt, cfg[4], fanin=4, size_class=c)
+        hs.hsort_set_config(k, cfg[0], cfg[1], nv, vt, cfg[4], fanin=4, digits=cfg[6], size_class=c)
     say(f"fanin4 shape S={nv} VT={vt}")
     yield hs
     for (k, c), cfg in saved.items():
-        hs.hsort_set_config(k, *cfg[:5], fanin=cfg[5], size_class=c)
+        hs.hsort_set_config(k, *cfg[:5], fanin=cfg[5], digits=cfg[6], size_class=c)
 
 
 def dev(a):
@@ -124,7 +124,7 @@ def test_segmented(hs4, orc, dtype):
 
 def test_stage_local_sorts_parity_follows_fanin(hs4, orc):
     k = W.uniform_i32(300_000, 5)
-    tile = hs4.hsort_get_config(hs4.KEYS_I32, n=k.size)[0]
+    cfg = hs4.hsort_get_config(hs4.KEYS_I32, n=k.size)
     t = dev(k)
     hs4.hsort_debug_stage(t, 2)
-    assert np.array_equal(t.cpu().numpy(), orc.bucket_tiles(k, tile)[0])
+    assert np.array_equal(t.cpu().numpy(), orc.bucket_tiles(k, cfg[0], digits=cfg[6])[0])

@@ -150,47 +150,51 @@ def test_bounds_match_oracle(hs, orc, name):
 @pytest.mark.parametrize("name", sorted(_stage_inputs().keys()))
 def test_stage_scatter_matches_oracle(hs, orc, name):
     k = _stage_inputs()[name]
-    say(f"stage scatter {name}")
+    digits = hs.hsort_get_config(hs.KEYS_I32, n=k.size)[6]
+    say(f"stage scatter {name} digits={digits}")
     t = dev(k)
     hs.hsort_debug_stage(t, 1)
-    ok, _, _ = orc.scatter(k)
+    ok, _, _ = orc.scatter(k, digits=digits)
     assert np.array_equal(t.cpu().numpy(), ok)
 
 
 @pytest.mark.parametrize("name", sorted(_stage_inputs().keys()))
 def test_stage_local_sorts_match_oracle(hs, orc, name):
     k = _stage_inputs()[name]
-    tile = hs.hsort_get_config(hs.KEYS_I32, n=k.size)[0]
-    say(f"stage tiles {name} tile={tile}")
+    cfg = hs.hsort_get_config(hs.KEYS_I32, n=k.size)
+    tile, digits = cfg[0], cfg[6]
+    say(f"stage tiles {name} tile={tile} digits={digits}")
     t = dev(k)
     hs.hsort_debug_stage(t, 2)
-    ok, _, _ = orc.bucket_tiles(k, tile)
+    ok, _, _ = orc.bucket_tiles(k, tile, digits=digits)
     assert np.array_equal(t.cpu().numpy(), ok)
 
 
 def test_stage_pairs_scatter_and_tiles(hs, orc):
     k, v = W.dup_pairs_i32(200_003, 31)
-    tile = hs.hsort_get_config(hs.PAIRS_I32_U32, n=k.size)[0]
+    cfg = hs.hsort_get_config(hs.PAIRS_I32_U32, n=k.size)
+    tile, digits = cfg[0], cfg[6]
     for stage in (1, 2):
-        say(f"pairs stage {stage}")
+        say(f"pairs stage {stage} digits={digits}")
         tk, tv = dev(k), dev(v.view(np.int32))
         hs.hsort_debug_stage(tk, stage, vals=tv)
         if stage == 1:
-            ok, ov, _ = orc.scatter(k, v)
+            ok, ov, _ = orc.scatter(k, v, digits=digits)
         else:
-            ok, ov, _ = orc.bucket_tiles(k, tile, v)
+            ok, ov, _ = orc.bucket_tiles(k, tile, v, digits=digits)
         assert np.array_equal(tk.cpu().numpy(), ok)
         assert np.array_equal(tv.cpu().numpy().view(np.uint32), ov)
 
 
 def test_stage_int64(hs, orc):
     k = _i64_cases()["full_n100003"]
-    tile = hs.hsort_get_config(hs.KEYS_I64, n=k.size)[0]
+    cfg = hs.hsort_get_config(hs.KEYS_I64, n=k.size)
+    tile, digits = cfg[0], cfg[6]
     for stage in (1, 2):
-        say(f"int64 stage {stage}")
+        say(f"int64 stage {stage} digits={digits}")
         t = dev(k)
         hs.hsort_debug_stage(t, stage)
-        ok = orc.scatter(k)[0] if stage == 1 else orc.bucket_tiles(k, tile)[0]
+        ok = orc.scatter(k, digits=digits)[0] if stage == 1 else orc.bucket_tiles(k, tile, digits=digits)[0]
         assert np.array_equal(t.cpu().numpy(), ok)
 
 
