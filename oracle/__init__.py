@@ -101,6 +101,13 @@ def _bind(path):
         fn = getattr(lib, name)
         fn.argtypes = args
         fn.restype = ctypes.c_int
+    for name, args in {"oracle_sort_typed": [P, P, I, I, I64],
+                       "oracle_bounds_typed": [P, I, I, I64, I, P],
+                       "oracle_radix_sort_typed": [P, P, I, I, I64, I, P],
+                       "oracle_stage_typed": [P, P, I, I, I64, I64, I, P]}.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
     lib.oracle_count_lt_le_i32.argtypes = [P, I64, ctypes.c_int32, P, P]
     lib.oracle_count_lt_le_i32.restype = None
     lib.oracle_count_lt_le_i64.argtypes = [P, I64, ctypes.c_int64, P, P]
@@ -126,6 +133,27 @@ def _keys(a):
 
 def _sfx(a):
     return "i32" if a.dtype == np.int32 else "i64"
+
+
+# key types of the typed entry points (int32, uint32, float32, int64, uint64, float64)
+KEY_TYPES = {np.dtype(np.int32): 0, np.dtype(np.uint32): 1, np.dtype(np.float32): 2,
+             np.dtype(np.int64): 3, np.dtype(np.uint64): 4, np.dtype(np.float64): 5}
+
+
+def _typed(a):
+    a = np.ascontiguousarray(a)
+    if a.dtype not in KEY_TYPES:
+        raise TypeError(f"keys must be one of {[str(d) for d in KEY_TYPES]}")
+    return a.copy(), KEY_TYPES[a.dtype]
+
+
+def _vals(vals, n):
+    if vals is None:
+        return None
+    v = np.ascontiguousarray(vals, dtype=np.uint32).copy()
+    if v.size != n:
+        raise ValueError("keys and vals differ in length")
+    return v
 
 
 def _nb(digits):
@@ -247,6 +275,42 @@ class Oracle:
         _check(fn(_ptr(k), _ptr(off), nseg, _ptr(b)), "sort_segmented")
         return k, b
 
+    # -------------------------------------------------- other key types
+    def sort_typed(self, keys, vals=None, descending=False):
+        """Stable sort of int32/uint32/float32/int64/uint64/float64 keys (and a uint32 payload),
+        ascending or descending; floats in IEEE-754 total order.  Returns (keys, vals)."""
+        k, t = _typed(keys)
+        v = _vals(vals, k.size)
+        _check(self._lib.oracle_sort_typed(_ptr(k), _ptr(v), t, int(bool(descending)), k.size), "sort_typed")
+        return k, v
+
+    def bounds_typed(self, keys, descending=False, digits=1):
+        """Bucket bounds of the keys' order image (see oracle.c) under the one-step rule."""
+        k, t = _typed(keys)
+        out = np.zeros(_nb(digits) + 1, np.int64)
+        _check(self._lib.oracle_bounds_typed(_ptr(k), t, int(bool(descending)), k.size, digits, _ptr(out)),
+               "bounds_typed")
+        return out
+
+    def radix_sort_typed(self, keys, vals=None, descending=False, digits=1):
+        """Section 3.4 run sequentially on the order image: (keys, vals, bounds)."""
+        k, t = _typed(keys)
+        v = _vals(vals, k.size)
+        b = np.zeros(_nb(digits) + 1, np.int64)
+        _check(self._lib.oracle_radix_sort_typed(_ptr(k), _ptr(v), t, int(bool(descending)), k.size, digits,
+                                                 _ptr(b)), "radix_sort_typed")
+        return k, v, b
+
+    def stage_typed(self, keys, vals=None, descending=False, tile=0, digits=1):
+        """The stable bucket scatter (tile = 0) or the scatter followed by the local sorts of every
+        `tile`-key partition of every bucket: (keys, vals, bounds)."""
+        k, t = _typed(keys)
+        v = _vals(vals, k.size)
+        b = np.zeros(_nb(digits) + 1, np.int64)
+        _check(self._lib.oracle_stage_typed(_ptr(k), _ptr(v), t, int(bool(descending)), k.size, int(tile), digits,
+                                            _ptr(b)), "stage_typed")
+        return k, v, b
+
     def count_lt_le(self, keys, x):
         """(#{k < x}, #{k <= x}): o[j] == x iff lt <= j < le."""
         k = np.ascontiguousarray(keys)
@@ -281,4 +345,5 @@ def __getattr__(name):
 
 
 _PUBLIC = {"plan", "bounds", "sort_keys", "sort_pairs", "radix_sort_keys", "radix_sort_pairs", "scatter",
-           "bucket_tiles", "sort_segmented", "count_lt_le"}
+           "bucket_tiles", "sort_segmented", "count_lt_le", "sort_typed", "bounds_typed", "radix_sort_typed",
+           "stage_typed"}

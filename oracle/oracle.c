@@ -38,6 +38,17 @@
  * total order, so the result is the stable sort whatever the pivot choice
  * (the paper's quicksort alone is not stable).
  *
+ * Other key types and descending order (the key types a sort library is
+ * asked for; the paper sorts integers): every key is ordered through an
+ * integer order image written out from the type's definition of order --
+ * unsigned integers by value, IEEE-754 floats by the standard's total order
+ * (sign first, then the magnitude's bit pattern, so -NaN < -inf < ... < -0
+ * < +0 < ... < +inf < +NaN), descending order by the image reversed -- and
+ * the decimal bucket rule is applied to that image: signed images with
+ * beta = min(min image, 0) as above, unsigned keys with beta = 0 in the
+ * unsigned domain (u = the key itself).  Outputs are the input keys gathered
+ * in the order found, so no image is ever inverted.
+ *
  * The "radix mode" runs the paper's fourth model sequentially (Section 3.4):
  * stable counting scatter into the ten buckets, the same sort inside every
  * bucket, then the buckets in digit order.  It must equal the plain mode,
@@ -205,6 +216,15 @@ typedef struct {
     uint64_t p;
 } plan;
 
+static plan make_plan_beta(int64_t beta, int64_t mx) {
+    plan pl;
+    pl.beta = beta;
+    uint64_t top = (uint64_t)mx - (uint64_t)pl.beta;
+    pl.D = decimal_digits(top);
+    pl.p = POW10[pl.D - 1];
+    return pl;
+}
+
 static plan make_plan(int64_t mn, int64_t mx) {
     plan pl;
     pl.beta = mn < 0 ? mn : 0;
@@ -259,15 +279,20 @@ static item* load_items_i64(const int64_t* k, int64_t n) {
 }
 
 /* Plan of an array: *beta, *D, *p.  n == 0 gives beta 0, D 1, p 1. */
-static plan plan_of(const item* s, int64_t n) {
-    if (n == 0) return make_plan(0, 0);
+/* fixed != 0: the keys are unsigned 64-bit values shifted by -2^63 into
+ * int64 (order kept); their bias is fixed at that shift, so u is the
+ * unsigned value itself (beta = 0 in the unsigned domain). */
+static plan plan_of_mode(const item* s, int64_t n, int fixed) {
+    if (n == 0) return fixed ? make_plan_beta(INT64_MIN, INT64_MIN) : make_plan(0, 0);
     int64_t mn = s[0].key, mx = s[0].key;
     for (int64_t i = 1; i < n; i++) {
         if (s[i].key < mn) mn = s[i].key;
         if (s[i].key > mx) mx = s[i].key;
     }
-    return make_plan(mn, mx);
+    return fixed ? make_plan_beta(INT64_MIN, mx) : make_plan(mn, mx);
 }
+
+static plan plan_of(const item* s, int64_t n) { return plan_of_mode(s, n, 0); }
 
 /* bounds[b] = number of keys whose bucket is below b, b = 0..NB (NB = 10
  * or 100 buckets) */
@@ -312,16 +337,20 @@ int oracle_plan_i64(const int64_t* k, int64_t n, int64_t* beta, int32_t* D, uint
 
 /* bounds[0 .. 10^digits]: the bucket bounds of the array under the one-step
  * rule with `digits` leading digits (1: ten buckets, 2: one hundred). */
-static int bounds_items(item* s, int64_t n, int digits, int64_t* bounds) {
+static int bounds_items_mode(item* s, int64_t n, int digits, int fixed, int64_t* bounds) {
     if (!s) return -1;
     if (digits != 1 && digits != 2) {
         free(s);
         return -1;
     }
-    plan pl = plan_of(s, n);
+    plan pl = plan_of_mode(s, n, fixed);
     bounds_of(s, n, &pl, digits, bounds);
     free(s);
     return 0;
+}
+
+static int bounds_items(item* s, int64_t n, int digits, int64_t* bounds) {
+    return bounds_items_mode(s, n, digits, 0, bounds);
 }
 
 int oracle_bounds_digits_i32(const int32_t* k, int64_t n, int digits, int64_t* bounds) {
@@ -491,9 +520,9 @@ int oracle_radix_sort_pairs_i32(int32_t* k, uint32_t* v, int64_t n, int64_t* bou
 
 /* The intermediate after the one-step MSD radix alone: the stable scatter of
  * the input into bucket order (vals may be NULL).  Writes bounds[NB + 1]. */
-static int scatter_only(item* s, int64_t n, int digits, int64_t* bounds) {
+static int scatter_only_mode(item* s, int64_t n, int digits, int fixed, int64_t* bounds) {
     if (digits != 1 && digits != 2) return -1;
-    plan pl = plan_of(s, n);
+    plan pl = plan_of_mode(s, n, fixed);
     bounds_of(s, n, &pl, digits, bounds);
     item* t = (item*)malloc(sizeof(item) * (size_t)(n > 0 ? n : 1));
     if (!t) return -1;
@@ -501,6 +530,10 @@ static int scatter_only(item* s, int64_t n, int digits, int64_t* bounds) {
     memcpy(s, t, sizeof(item) * (size_t)n);
     free(t);
     return 0;
+}
+
+static int scatter_only(item* s, int64_t n, int digits, int64_t* bounds) {
+    return scatter_only_mode(s, n, digits, 0, bounds);
 }
 
 int oracle_scatter_digits_i32(int32_t* k, uint32_t* v, int64_t n, int digits, int64_t* bounds) {
@@ -633,6 +666,153 @@ int oracle_sort_segmented_i64(int64_t* k, const int64_t* off, int64_t nseg, int6
         if (oracle_sort_keys_i64(k + a, m)) return -1;
     }
     return 0;
+}
+
+/* ------------------------------------------------------- other key types
+ * Key types: 0 int32, 1 uint32, 2 float32, 3 int64, 4 uint64, 5 float64.
+ * The order image of key i (an int64 whose signed order is the key order
+ * asked for), written from each type's definition:
+ *   - signed integers: the value;
+ *   - unsigned 32-bit: the value (non-negative, so the signed bucket rule
+ *     has beta = 0 and reads the value itself);
+ *   - unsigned 64-bit: the value shifted by -2^63 into int64, with the bias
+ *     fixed at that shift (u = the value);
+ *   - IEEE-754 binary32/binary64: the standard's total order puts every
+ *     value with the sign bit set below every value without it, orders
+ *     same-sign values by the bit pattern of the magnitude (increasing for
+ *     positive, decreasing for negative; NaNs lie beyond the infinities),
+ *     and -0 just below +0: image = m for sign 0 and -1 - m for sign 1,
+ *     m = the magnitude bits as an integer;
+ *   - descending order: the image reversed, -1 - image (unsigned: the
+ *     largest value minus the value, so u stays unsigned).
+ * Equal images keep their input order (the index tie-break). */
+enum { T_I32 = 0, T_U32 = 1, T_F32 = 2, T_I64 = 3, T_U64 = 4, T_F64 = 5 };
+
+static size_t type_size(int t) { return (t == T_I32 || t == T_U32 || t == T_F32) ? 4 : 8; }
+
+static int64_t shift_u64(uint64_t y) { /* y - 2^63 as int64, without overflow */
+    const uint64_t h = 0x8000000000000000ull;
+    if (y >= h) return (int64_t)(y - h);
+    return y == 0 ? INT64_MIN : -(int64_t)(h - y);
+}
+
+static int64_t order_image(const void* k, int64_t i, int t, int desc) {
+    int64_t img = 0;
+    switch (t) {
+        case T_I32:
+            img = ((const int32_t*)k)[i];
+            break;
+        case T_I64:
+            img = ((const int64_t*)k)[i];
+            break;
+        case T_U32: {
+            const uint32_t x = ((const uint32_t*)k)[i];
+            return desc ? (int64_t)(UINT32_MAX - x) : (int64_t)x;
+        }
+        case T_U64: {
+            const uint64_t x = ((const uint64_t*)k)[i];
+            return shift_u64(desc ? UINT64_MAX - x : x);
+        }
+        case T_F32: {
+            uint32_t b;
+            memcpy(&b, (const char*)k + 4 * i, 4);
+            const int64_t m = (int64_t)(b & 0x7FFFFFFFu);
+            img = (b >> 31) ? -1 - m : m;
+            break;
+        }
+        case T_F64: {
+            uint64_t b;
+            memcpy(&b, (const char*)k + 8 * i, 8);
+            const int64_t m = (int64_t)(b & 0x7FFFFFFFFFFFFFFFull);
+            img = (b >> 63) ? -1 - m : m;
+            break;
+        }
+    }
+    return desc ? -1 - img : img;
+}
+
+static item* load_items_typed(const void* k, int t, int desc, int64_t n) {
+    item* s = (item*)malloc(sizeof(item) * (size_t)(n > 0 ? n : 1));
+    if (!s) return NULL;
+    for (int64_t i = 0; i < n; i++) {
+        s[i].key = order_image(k, i, t, desc);
+        s[i].idx = (uint64_t)i;
+    }
+    return s;
+}
+
+/* The input keys (and payload) gathered in the order of s. */
+static int gather_typed(void* k, uint32_t* v, int t, const item* s, int64_t n) {
+    const size_t w = type_size(t);
+    char* k0 = (char*)malloc(w * (size_t)(n > 0 ? n : 1));
+    uint32_t* v0 = v ? (uint32_t*)malloc(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1)) : NULL;
+    if (!k0 || (v && !v0)) {
+        free(k0);
+        free(v0);
+        return -1;
+    }
+    memcpy(k0, k, w * (size_t)n);
+    if (v) memcpy(v0, v, sizeof(uint32_t) * (size_t)n);
+    for (int64_t i = 0; i < n; i++) {
+        memcpy((char*)k + w * (size_t)i, k0 + w * (size_t)s[i].idx, w);
+        if (v) v[i] = v0[s[i].idx];
+    }
+    free(k0);
+    free(v0);
+    return 0;
+}
+
+static int valid_type(int t) { return t >= T_I32 && t <= T_F64; }
+
+/* Stable sort of keys of type t (vals may be NULL), ascending or descending. */
+int oracle_sort_typed(void* k, uint32_t* v, int t, int desc, int64_t n) {
+    if (!valid_type(t)) return -1;
+    item* s = load_items_typed(k, t, desc, n);
+    if (!s) return -1;
+    int rc = hybrid_sort(s, n);
+    if (!rc) rc = gather_typed(k, v, t, s, n);
+    free(s);
+    return rc;
+}
+
+int oracle_bounds_typed(const void* k, int t, int desc, int64_t n, int digits, int64_t* bounds) {
+    if (!valid_type(t)) return -1;
+    return bounds_items_mode(load_items_typed(k, t, desc, n), n, digits, t == T_U64, bounds);
+}
+
+int oracle_radix_sort_typed(void* k, uint32_t* v, int t, int desc, int64_t n, int digits, int64_t* bounds) {
+    if (!valid_type(t) || (digits != 1 && digits != 2)) return -1;
+    item* s = load_items_typed(k, t, desc, n);
+    if (!s) return -1;
+    int rc = 0;
+    int64_t b[101];
+    if (scatter_only_mode(s, n, digits, t == T_U64, b)) rc = -1;
+    for (int j = 0; !rc && j < nbuckets(digits); j++) rc = hybrid_sort(s + b[j], b[j + 1] - b[j]);
+    if (!rc) rc = gather_typed(k, v, t, s, n);
+    if (!rc && bounds)
+        for (int j = 0; j <= nbuckets(digits); j++) bounds[j] = b[j];
+    free(s);
+    return rc;
+}
+
+/* Intermediates: the stable scatter into buckets (tile <= 0), or that
+ * followed by the sort of every `tile`-key partition of every bucket. */
+int oracle_stage_typed(void* k, uint32_t* v, int t, int desc, int64_t n, int64_t tile, int digits, int64_t* bounds) {
+    if (!valid_type(t) || (digits != 1 && digits != 2)) return -1;
+    item* s = load_items_typed(k, t, desc, n);
+    if (!s) return -1;
+    int rc = scatter_only_mode(s, n, digits, t == T_U64, bounds);
+    if (!rc && tile > 0) {
+        for (int j = 0; j < nbuckets(digits); j++) {
+            for (int64_t a = bounds[j]; a < bounds[j + 1]; a += tile) {
+                const int64_t e = a + tile < bounds[j + 1] ? a + tile : bounds[j + 1];
+                quicksort(s, a, e - 1);
+            }
+        }
+    }
+    if (!rc) rc = gather_typed(k, v, t, s, n);
+    free(s);
+    return rc;
 }
 
 /* Order statistic by definition: the j-th smallest key o[j] is the value x

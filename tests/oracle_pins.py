@@ -18,6 +18,7 @@ from __future__ import annotations
 
 import itertools
 import json
+import math
 import os
 
 import numpy as np
@@ -392,6 +393,207 @@ def pin_two_digit_radix_and_stages(orc, seed=25):
                 assert np.array_equal(tk[s0:e], np.sort(sk[s0:e])), (n, T, bk, s0)
 
 
+# ------------------------------------------------------- other key types
+TYPED = [np.int32, np.uint32, np.float32, np.int64, np.uint64, np.float64]
+
+
+def total_order_key(x):
+    """IEEE-754 total order as a Python sort key, from the values alone (no
+    bit patterns): negative NaNs first, then the numbers by value with -0
+    before +0, then positive NaNs (NaN payloads are not mixed here)."""
+    x = float(x)
+    neg = math.copysign(1.0, x) < 0
+    if math.isnan(x):
+        return (0,) if neg else (2,)
+    return (1, x, 0 if neg else 1)
+
+
+def typed_order_key(dt):
+    if np.dtype(dt).kind == "f":
+        return total_order_key
+    return int
+
+
+def brute_typed(keys, desc):
+    """Stable order of the positions by Python's sort (stable also with
+    reverse=True: equal keys keep their input order)."""
+    kf = typed_order_key(keys.dtype)
+    return sorted(range(len(keys)), key=lambda i: kf(keys[i]), reverse=desc)
+
+
+def typed_samples(dt, n, rng):
+    info = np.finfo(dt) if np.dtype(dt).kind == "f" else np.iinfo(dt)
+    if np.dtype(dt).kind == "f":
+        special = np.array([0.0, -0.0, np.inf, -np.inf, np.nan, -np.nan, 1.5, -1.5, info.tiny, -info.tiny,
+                            info.max, -info.max, info.smallest_subnormal, -info.smallest_subnormal], dt)
+        body = (rng.standard_normal(n) * 10.0 ** rng.integers(-5, 6, n)).astype(dt)
+        body[rng.random(n) < 0.1] = 0.0
+        return np.where(rng.random(n) < 0.2, rng.choice(special, n), body).astype(dt)
+    special = np.array([info.min, info.max, 0, 1, info.max - 1], dt)
+    body = rng.integers(info.min, info.max, n, dtype=dt, endpoint=True)
+    small = rng.integers(0, 50, n).astype(dt)
+    pick = rng.random(n)
+    return np.where(pick < 0.15, rng.choice(special, n), np.where(pick < 0.5, small, body)).astype(dt)
+
+
+def order_image_py(k, desc):
+    """The order image of the oracle's reading for other key types, and
+    whether its bucket rule is unsigned (u = image) or signed (u = image -
+    min(min image, 0)).  Floats: m = the magnitude bits, image m or -1 - m."""
+    dt = k.dtype
+    if dt.kind == "u":
+        top = int(np.iinfo(dt).max)
+        return [top - int(x) if desc else int(x) for x in k], True
+    if dt.kind == "f":
+        ib = np.uint32 if dt.itemsize == 4 else np.uint64
+        bits = k.view(ib)
+        w = 8 * dt.itemsize
+        img = []
+        for b in bits:
+            b = int(b)
+            m = b & ((1 << (w - 1)) - 1)
+            img.append(-1 - m if b >> (w - 1) else m)
+    else:
+        img = [int(x) for x in k]
+    return ([-1 - v for v in img] if desc else img), False
+
+
+def string_buckets_typed(k, desc, digits):
+    """Each key's bucket: the first one or two characters of the decimal
+    string of u, written with D digits (a one-digit u gets a trailing zero)."""
+    img, unsigned = order_image_py(k, desc)
+    if not img:
+        return []
+    beta = 0 if unsigned else min(min(img), 0)
+    us = [v - beta for v in img]
+    D = len(str(max(us)))
+    if digits == 1:
+        return [int(str(u).rjust(D, "0")[0]) for u in us]
+    return [int((str(u).rjust(D, "0") + "0")[:2]) for u in us]
+
+
+def string_bounds_typed(k, desc, digits):
+    ds = string_buckets_typed(k, desc, digits)
+    cnt = [0] * 10**digits
+    for d in ds:
+        cnt[d] += 1
+    b = [0]
+    for c in cnt:
+        b.append(b[-1] + c)
+    return b
+
+
+def pin_typed_brute(orc, seed=31):
+    """Every key type, both directions, against Python's stable sort with
+    comparison keys taken from the values (never from bit patterns); the
+    payload (input positions) must come out in the same stable order."""
+    rng = np.random.default_rng(seed)
+    for dt in TYPED:
+        for n in [0, 1, 2, 5, 40, 300]:
+            k = typed_samples(dt, n, rng)
+            for desc in (False, True):
+                want = brute_typed(k, desc)
+                gk, gv = orc.sort_typed(k, np.arange(n, dtype=np.uint32), descending=desc)
+                assert gv.tolist() == want, (np.dtype(dt).name, n, desc)
+                assert np.array_equal(gk.view(np.uint8), k[want].view(np.uint8)), (np.dtype(dt).name, n, desc)
+
+
+def pin_typed_zero_and_nan_order(orc):
+    """Hand-worked: -NaN < -inf < -1.5 < -0 < +0 < 1.5 < +inf < +NaN, and the
+    reverse for descending order, whatever the input order."""
+    for dt in (np.float32, np.float64):
+        k = np.array([0.0, np.nan, -0.0, 1.5, -np.inf, -1.5, np.inf, -np.nan], dt)
+        asc = [7, 4, 5, 2, 0, 3, 6, 1]
+        gk, gv = orc.sort_typed(k, np.arange(8, dtype=np.uint32))
+        assert gv.tolist() == asc, np.dtype(dt).name
+        gk, gv = orc.sort_typed(k, np.arange(8, dtype=np.uint32), descending=True)
+        assert gv.tolist() == asc[::-1], np.dtype(dt).name
+        gk, gv = orc.sort_typed(np.array([0.0, -0.0, 0.0, -0.0], dt), np.arange(4, dtype=np.uint32))
+        assert gv.tolist() == [1, 3, 0, 2], np.dtype(dt).name
+
+
+def pin_typed_library(orc, seed=32):
+    """numpy's stable sort on larger inputs: unsigned keys directly, floats
+    without NaN or -0 (where numpy's order is the total order), descending as
+    the stable ascending order of the negated floats / complemented
+    unsigned values."""
+    rng = np.random.default_rng(seed)
+    for n in [1000, 40_001]:
+        for dt in (np.uint32, np.uint64):
+            k = typed_samples(dt, n, rng)
+            idx = np.arange(n, dtype=np.uint32)
+            gk, gv = orc.sort_typed(k, idx)
+            assert np.array_equal(gv, np.argsort(k, kind="stable")), np.dtype(dt).name
+            comp = np.iinfo(dt).max - k
+            gk, gv = orc.sort_typed(k, idx, descending=True)
+            assert np.array_equal(gv, np.argsort(comp, kind="stable")), np.dtype(dt).name
+        for dt in (np.float32, np.float64):
+            k = (rng.standard_normal(n) * 1e3).astype(dt)
+            k[k == 0] = 1.0
+            k[: n // 10] = k[n // 10: 2 * (n // 10)]  # duplicates
+            idx = np.arange(n, dtype=np.uint32)
+            assert np.array_equal(orc.sort_typed(k, idx)[1], np.argsort(k, kind="stable")), np.dtype(dt).name
+            assert np.array_equal(orc.sort_typed(k, idx, descending=True)[1], np.argsort(-k, kind="stable"))
+        for dt in (np.int32, np.int64):
+            k = typed_samples(dt, n, rng)
+            assert np.array_equal(orc.sort_typed(k)[0], orc.sort_keys(k)), np.dtype(dt).name
+
+
+def pin_typed_bounds(orc, seed=33):
+    """Bucket bounds of every type and direction by decimal strings of the
+    order image's u, with ten and one hundred buckets."""
+    rng = np.random.default_rng(seed)
+    for dt in TYPED:
+        for n in [0, 1, 7, 200]:
+            for _ in range(4):
+                k = typed_samples(dt, n, rng)
+                for desc in (False, True):
+                    for digits in (1, 2):
+                        assert orc.bounds_typed(k, desc, digits).tolist() == string_bounds_typed(k, desc, digits), \
+                            (np.dtype(dt).name, n, desc, digits, k)
+
+
+def pin_typed_worked_examples(orc):
+    with open(GOLDEN) as f:
+        g = json.load(f)["typed"]
+    for ex in g["cases"]:
+        k = np.array(ex["keys"], dtype=ex["dtype"]) if "keys" in ex else np.array(ex["bits"], dtype=ex["bits_dtype"]).view(ex["dtype"])
+        assert orc.bounds_typed(k, ex["descending"]).tolist() == ex["bounds"], ex["why"]
+        assert orc.sort_typed(k, np.arange(k.size, dtype=np.uint32), ex["descending"])[1].tolist() == ex["order"], ex["why"]
+
+
+def pin_typed_radix_and_stages(orc, seed=34):
+    """Section 3.4 run sequentially on the order image equals the plain
+    typed sort (ten and one hundred buckets); the scatter keeps input order
+    inside a bucket; the local sorts sort every partition of every bucket."""
+    rng = np.random.default_rng(seed)
+    for dt in TYPED:
+        for n, T in [(0, 4), (9, 4), (3000, 64), (20_000, 1000)]:
+            k = typed_samples(dt, n, rng)
+            v = np.arange(n, dtype=np.uint32)
+            for desc in (False, True):
+                pk, pv = orc.sort_typed(k, v, desc)
+                for digits in (1, 2):
+                    rk, rv, rb = orc.radix_sort_typed(k, v, desc, digits)
+                    assert np.array_equal(rv, pv), (np.dtype(dt).name, n, desc, digits)
+                    assert rb.tolist() == string_bounds_typed(k, desc, digits)
+                    sk, sv, sb = orc.stage_typed(k, v, desc, 0, digits)
+                    assert np.array_equal(sb, rb)
+                    assert np.array_equal(sk.view(np.uint8), k[sv].view(np.uint8)), "key does not follow its position"
+                    bk = string_buckets_typed(k, desc, digits)
+                    out_b = [bk[i] for i in sv.tolist()]
+                    assert out_b == sorted(out_b), "scatter not in bucket order"
+                    for b in range(10**digits):
+                        assert np.all(np.diff(sv[sb[b]:sb[b + 1]].astype(np.int64)) > 0), "scatter not stable"
+                    tk, tv, _ = orc.stage_typed(k, v, desc, T, digits)
+                    for b in range(10**digits):
+                        for s0 in range(int(sb[b]), int(sb[b + 1]), T):
+                            e = min(s0 + T, int(sb[b + 1]))
+                            # the partition's positions, sorted stably by the typed order
+                            want = [int(sv[s0 + i]) for i in brute_typed(sk[s0:e], desc)]
+                            assert tv[s0:e].tolist() == want, (np.dtype(dt).name, n, desc, digits, b)
+
+
 ALL_PINS = [
     pin_worked_examples,
     pin_exhaustive_small,
@@ -407,4 +609,10 @@ ALL_PINS = [
     pin_two_digit_worked_examples,
     pin_two_digit_string_route,
     pin_two_digit_radix_and_stages,
+    pin_typed_brute,
+    pin_typed_zero_and_nan_order,
+    pin_typed_library,
+    pin_typed_bounds,
+    pin_typed_worked_examples,
+    pin_typed_radix_and_stages,
 ]

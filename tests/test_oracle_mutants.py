@@ -39,6 +39,15 @@ MUTANTS = [
     ("partition_skips_last", "for (int64_t j = low; j < high; j++) {", "for (int64_t j = low; j < high - 1; j++) {"),
     ("segment_bounds_unshifted", "if (bounds && oracle_bounds_i32(k + a, m, bounds + 11 * g)) return -1;",
      "if (bounds && oracle_bounds_i32(k, m, bounds + 11 * g)) return -1;"),
+    ("float_negative_image_without_offset", "img = (b >> 31) ? -1 - m : m;", "img = (b >> 31) ? -m : m;"),
+    ("float64_sign_ignored", "img = (b >> 63) ? -1 - m : m;", "img = m;"),
+    ("descending_not_reversed", "return desc ? -1 - img : img;", "return img;"),
+    ("unsigned_descending_not_reversed", "return desc ? (int64_t)(UINT32_MAX - x) : (int64_t)x;", "return (int64_t)x;"),
+    ("u64_shift_wraps", "if (y >= h) return (int64_t)(y - h);", "if (y >= h) return (int64_t)y;"),
+    ("u64_bias_not_fixed", "bounds_items_mode(load_items_typed(k, t, desc, n), n, digits, t == T_U64, bounds);",
+     "bounds_items_mode(load_items_typed(k, t, desc, n), n, digits, 0, bounds);"),
+    ("typed_gather_keeps_input_order", "memcpy((char*)k + w * (size_t)i, k0 + w * (size_t)s[i].idx, w);",
+     "memcpy((char*)k + w * (size_t)i, k0 + w * (size_t)i, w);"),
     ("count_le_strict", "b += k[i] <= x;\n    }\n    *lt = a;\n    *le = b;\n}\n\nvoid oracle_count_lt_le_i64",
      "b += k[i] < x;\n    }\n    *lt = a;\n    *le = b;\n}\n\nvoid oracle_count_lt_le_i64"),
 ]
