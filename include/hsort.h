@@ -74,6 +74,21 @@ size_t hsort_scratch_bytes(int kind, int64_t n, int64_t nseg);
 int hsort_keys_i32(int32_t* keys, int64_t n, void* scratch, size_t scratch_bytes, void* stream);
 int hsort_keys_i64(int64_t* keys, int64_t n, void* scratch, size_t scratch_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * sort as hsort_keys_i32, with no scratch argument.  It works in a scratch
+ * array of HSORT_NOALLOC_SCRATCH_BYTES that the library owns, one per GPU,
+ * held until the process ends; it calls no hipMalloc, hipFree or other
+ * allocating routine, and bypasses the graph cache and the timing records.
+ * n above HSORT_NOALLOC_MAX_KEYS: HSORT_ERR_UNSUPPORTED at once (also if a
+ * tuning table picks shapes whose scratch would not fit).  Every call on one
+ * GPU shares that GPU's array, which keeps the last call's contents: calls
+ * that overlap on one GPU (concurrent streams or threads) race and must be
+ * serialised by the caller. */
+#define HSORT_NOALLOC_MAX_KEYS ((int64_t)4194304)
+#define HSORT_NOALLOC_SCRATCH_BYTES (24u << 20)
+int hsort_keys_i32_noalloc(int32_t* keys, int64_t n, void* stream);
+
 /* Sorts keys[0..n) ascending and permutes vals[0..n) with them.  Stable:
  * equal keys keep their input order (merge sort's stability, Section 2.1). */
 int hsort_pairs(int32_t* keys, uint32_t* vals, int64_t n, void* scratch, size_t scratch_bytes, void* stream);

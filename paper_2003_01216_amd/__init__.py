@@ -39,6 +39,7 @@ EXPORTS = [
     "hsort_scratch_bytes",
     "hsort_keys_i32",
     "hsort_keys_i64",
+    "hsort_keys_i32_noalloc",
     "hsort_pairs",
     "hsort_segmented",
     "hsort_segmented_i64",
@@ -81,6 +82,7 @@ def load_library(path: str = LIB_PATH):
         "hsort_scratch_bytes": ([I, I64, I64], SZ),
         "hsort_keys_i32": ([P, I64, P, SZ, P], I),
         "hsort_keys_i64": ([P, I64, P, SZ, P], I),
+        "hsort_keys_i32_noalloc": ([P, I64, P], I),
         "hsort_pairs": ([P, P, I64, P, SZ, P], I),
         "hsort_segmented": ([P, I64, P, I64, I64, P, SZ, P], I),
         "hsort_segmented_i64": ([P, I64, P, I64, I64, P, SZ, P], I),
@@ -174,6 +176,18 @@ def hsort_keys_i64(keys, scratch=None):
     if keys.dtype != torch.int64:
         raise TypeError("hsort_keys_i64 takes int64 keys")
     return hsort_keys(keys, scratch)
+
+
+def hsort_keys_i32_noalloc(keys: torch.Tensor) -> torch.Tensor:
+    """Sort int32 device keys in place with the library's own scratch array (no allocation; at most
+    HSORT_NOALLOC_MAX_KEYS keys; calls that overlap on one GPU race)."""
+    _dev_tensor(keys, (torch.int32,), "keys")
+    n = keys.numel()
+    _check(load_library().hsort_keys_i32_noalloc(_ptr(keys), n, _stream(keys)))
+    return keys
+
+
+NOALLOC_MAX_KEYS = 4194304
 
 
 def hsort_pairs(keys: torch.Tensor, vals: torch.Tensor, scratch: torch.Tensor | None = None):

@@ -587,6 +587,43 @@ int check_common(const void* keys, int64_t n, const void* scratch) {
     return HSORT_OK;
 }
 
+// ------------------------------------------------- library-owned scratch
+// hsort_keys_i32_noalloc works in a scratch array the library owns, one per
+// GPU (see `scratch` below), found once per device by hipGetSymbolAddress.
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+void* g_static_ptr[kMaxDevices] = {};
+
+}  // namespace
+
+// The scratch array of hsort_keys_i32_noalloc: file scope, one copy on every
+// GPU the library runs on, held until the process ends.  In host code this
+// name stands for a host-side shadow, not the device array: the device
+// address comes from hipGetSymbolAddress (static_scratch), and only that
+// address reaches kernels.
+static __device__ __align__(256) unsigned char scratch[HSORT_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+// Device address of the current GPU's scratch array (looked up on the first
+// call on that GPU, with that GPU current).
+int static_scratch(void** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(HSORT_ERR_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices) return fail(HSORT_ERR_UNSUPPORTED, "device ordinal above 63");
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (!g_static_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(HSORT_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_static_ptr[dev] = p;
+    }
+    *out = g_static_ptr[dev];
+    return HSORT_OK;
+}
+
 }  // namespace
 
 // ===================================================================== C ABI
@@ -639,6 +676,32 @@ int hsort_pairs(int32_t* keys, uint32_t* vals, int64_t n, void* scratch, size_t 
     if (!vals) return fail(HSORT_ERR_INVALID, "null vals");
     return run<int32_t, true>(HSORT_PAIRS_I32_U32, keys, vals, n, nullptr, 1, 0, scratch, scratch_bytes,
                               (hipStream_t)stream, 3, -1);
+}
+
+int hsort_keys_i32_noalloc(int32_t* keys, int64_t n, void* stream) {
+    g_err.clear();
+    if (n < 0) return fail(HSORT_ERR_INVALID, "n < 0");
+    if (n > HSORT_NOALLOC_MAX_KEYS)
+        return fail(HSORT_ERR_UNSUPPORTED, "n = " + std::to_string(n) + " above HSORT_NOALLOC_MAX_KEYS (" +
+                                               std::to_string(HSORT_NOALLOC_MAX_KEYS) + ")");
+    if (n > 0 && !keys) return fail(HSORT_ERR_INVALID, "null keys");
+    if (n == 0) return HSORT_OK;
+    const Config c = get_cfg(HSORT_KEYS_I32, n);
+    const size_t need = make_layout(HSORT_KEYS_I32, n, 1, c).total;
+    if (need > (size_t)HSORT_NOALLOC_SCRATCH_BYTES)
+        return fail(HSORT_ERR_UNSUPPORTED, "the configured shapes need " + std::to_string(need) +
+                                               " bytes of scratch, above HSORT_NOALLOC_SCRATCH_BYTES");
+    void* scr = nullptr;
+    int rc = static_scratch(&scr);
+    if (rc != HSORT_OK) return rc;
+    // straight to the launch sequence: no graph cache (its instantiation
+    // allocates) and no timing events
+    const bool was = g_capturing;
+    g_capturing = true;
+    rc = enqueue<int32_t, false>(HSORT_KEYS_I32, keys, nullptr, n, nullptr, 1, 0, scr,
+                                 (size_t)HSORT_NOALLOC_SCRATCH_BYTES, (hipStream_t)stream, 3, -1);
+    g_capturing = was;
+    return rc;
 }
 
 static int seg_args(const void* keys, int64_t n, const int64_t* offsets, int64_t nseg, int64_t max_seg_len,

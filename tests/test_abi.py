@@ -132,3 +132,18 @@ def test_tuning_file(lib, tmp_path):
         hs.hsort_load_tuning(str(f))
     for c, cfg in enumerate(before):
         hs.hsort_set_config(hs.KEYS_I64, *cfg[:5], fanin=cfg[5], digits=cfg[6], size_class=c)
+
+
+def test_noalloc_argument_errors(lib):
+    # sizes beyond the library-owned scratch array are refused before any
+    # device work, with a message naming the limit
+    import paper_2003_01216_amd as hs
+
+    assert hs.NOALLOC_MAX_KEYS == 4194304
+    assert lib.hsort_keys_i32_noalloc(None, hs.NOALLOC_MAX_KEYS + 1, None) == hs.HSORT_ERR_UNSUPPORTED
+    assert b"HSORT_NOALLOC_MAX_KEYS" in lib.hsort_last_error()
+    assert lib.hsort_keys_i32_noalloc(None, -1, None) == hs.HSORT_ERR_INVALID
+    assert lib.hsort_keys_i32_noalloc(None, 5, None) == hs.HSORT_ERR_INVALID
+    assert lib.hsort_keys_i32_noalloc(None, 0, None) == hs.HSORT_OK
+    # every size class's tuned shapes fit the array at the largest size
+    assert hs.scratch_bytes(hs.KEYS_I32, hs.NOALLOC_MAX_KEYS) <= 24 << 20
