@@ -57,8 +57,21 @@ typedef enum {
     HSORT_KEYS_I64 = 1,      /* int64 keys */
     HSORT_PAIRS_I32_U32 = 2, /* int32 keys + uint32 payload, stable */
     HSORT_SEG_I32 = 3,       /* segmented int32 keys */
-    HSORT_SEG_I64 = 4        /* segmented int64 keys */
+    HSORT_SEG_I64 = 4,       /* segmented int64 keys */
+    HSORT_PAIRS_I64_U32 = 5  /* int64 keys + uint32 payload, stable */
 } hsort_kind;
+
+/* Key types of hsort_sort (Section 3.4's integers, and the types a sort
+ * library is asked for besides). */
+typedef enum {
+    HSORT_I32 = 0, /* int32 */
+    HSORT_U32 = 1, /* uint32 */
+    HSORT_F32 = 2, /* IEEE-754 binary32 */
+    HSORT_I64 = 3, /* int64 */
+    HSORT_U64 = 4, /* uint64 */
+    HSORT_F64 = 5  /* IEEE-754 binary64 */
+} hsort_key_type;
+#define HSORT_DESCENDING 1 /* flag of hsort_sort: largest key first */
 
 /* Largest number of keys in one call (and in one segment). */
 #define HSORT_MAX_KEYS ((int64_t)2147483647)
@@ -92,6 +105,24 @@ int hsort_keys_i32_noalloc(int32_t* keys, int64_t n, void* stream);
 /* Sorts keys[0..n) ascending and permutes vals[0..n) with them.  Stable:
  * equal keys keep their input order (merge sort's stability, Section 2.1). */
 int hsort_pairs(int32_t* keys, uint32_t* vals, int64_t n, void* scratch, size_t scratch_bytes, void* stream);
+
+/* Sorts keys[0..n) of any hsort_key_type, ascending or (flags =
+ * HSORT_DESCENDING) descending, and permutes vals[0..n) with them when vals
+ * is not NULL.  Stable: equal keys keep their input order in both
+ * directions.  Floats follow the IEEE-754 total order (-NaN < -inf < ... <
+ * -0 < +0 < ... < +inf < +NaN; NaNs by sign and payload), so every bit
+ * pattern has one place and the output is unique.  The method is the one of
+ * Section 3.4 applied to an order image of the keys: a signed integer of
+ * the same width whose order is the order asked for (unsigned: the sign bit
+ * flipped; floats: the magnitude bits of negative values flipped;
+ * descending: the image complemented), formed in place before the sort and
+ * undone after it.  The bucket rule reads that image (unsigned keys keep
+ * their value: u = k, no bias; the bounds left in scratch are the image's).
+ * Scratch: hsort_sort_scratch_bytes(key_type, vals != NULL, n) bytes.
+ * Unknown key_type or flags: HSORT_ERR_INVALID at once. */
+int hsort_sort(void* keys, uint32_t* vals, int64_t n, int key_type, int flags, void* scratch, size_t scratch_bytes,
+               void* stream);
+size_t hsort_sort_scratch_bytes(int key_type, int with_vals, int64_t n);
 
 /* Sorts each segment keys[offsets[i] .. offsets[i+1]) independently, for
  * i in [0, nseg) (Section 3.4: the buckets are independent units of work;
@@ -145,7 +176,11 @@ const char* hsort_last_error(void);
  * the first two of the D digits, floor(u / 10^(D-2)), or 10u when D = 1: a
  * finer splitter with the same order, so bucket b of the ten is buckets
  * 10b .. 10b+9 of the hundred; smaller buckets need fewer merge rounds).
- * The exported bounds are the ten-bucket bounds either way.  merge_nv must
+ * The exported bounds are the ten-bucket bounds either way.  local = the
+ * local sort: 0 (a register network, merges across lanes, then merge levels
+ * in LDS) or 1 (the non-recursive merge sort of Figure 1b: each thread sorts
+ * its tile_vt keys -- pairs when tile_vt = 2 -- and every merge level runs
+ * bottom up in LDS).  merge_nv must
  * divide tile.  Only compiled shapes are accepted (HSORT_ERR_UNSUPPORTED
  * otherwise).  kind: any hsort_kind (the two segmented kinds share the
  * table of their key type).  Size classes 0..3 hold calls whose deciding
@@ -154,14 +189,14 @@ const char* hsort_last_error(void);
  * class); size_cls = -1 sets every class.  The table is process-wide, and
  * scratch sizes depend on it: size scratch after changing it. */
 int hsort_set_config(int kind, int size_cls, int64_t tile, int64_t tile_vt, int64_t merge_nv, int64_t merge_vt,
-                     int64_t small_max, int64_t fanin, int64_t digits);
+                     int64_t small_max, int64_t fanin, int64_t digits, int64_t local);
 int hsort_get_config(int kind, int size_cls, int64_t* tile, int64_t* tile_vt, int64_t* merge_nv, int64_t* merge_vt,
-                     int64_t* small_max, int64_t* fanin, int64_t* digits);
+                     int64_t* small_max, int64_t* fanin, int64_t* digits, int64_t* local);
 int hsort_size_class(int64_t n);
 
 /* Applies a tuning table written by the autotuner: text lines
- * "kind size_class tile tile_vt merge_nv merge_vt small_max fanin [digits]"
- * (digits 1 when left out; '#' starts a comment line).  Stops at the first
+ * "kind size_class tile tile_vt merge_nv merge_vt small_max fanin [digits [local]]"
+ * (digits 1 and local 0 when left out; '#' starts a comment line).  Stops at the first
  * bad line and returns its error. */
 int hsort_load_tuning(const char* path);
 
@@ -175,6 +210,10 @@ int hsort_load_tuning(const char* path);
  * except for pairs. */
 int hsort_debug_stage(int kind, void* keys, uint32_t* vals, int64_t n, int stage, void* scratch,
                       size_t scratch_bytes, void* stream);
+/* The same for hsort_sort's key types and flags (the intermediate is left
+ * in the caller's key values: the order image is undone after the stage). */
+int hsort_debug_stage_typed(void* keys, uint32_t* vals, int64_t n, int key_type, int flags, int stage, void* scratch,
+                            size_t scratch_bytes, void* stream);
 
 /* ----------------------------------------------------------- hipGraphs
  * With graph mode on, each distinct call -- same entry point, sizes,

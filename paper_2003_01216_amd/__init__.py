@@ -34,6 +34,15 @@ KEYS_I64 = 1
 PAIRS_I32_U32 = 2
 SEG_I32 = 3
 SEG_I64 = 4
+PAIRS_I64_U32 = 5
+
+# key types of hsort_sort
+I32, U32, F32, I64, U64, F64 = range(6)
+DESCENDING = 1
+_KEY_TYPE_OF_DTYPE = {torch.int32: I32, torch.float32: F32, torch.int64: I64, torch.float64: F64}
+for _name, _kt in (("uint32", U32), ("uint64", U64)):
+    if hasattr(torch, _name):
+        _KEY_TYPE_OF_DTYPE[getattr(torch, _name)] = _kt
 
 EXPORTS = [
     "hsort_scratch_bytes",
@@ -41,6 +50,8 @@ EXPORTS = [
     "hsort_keys_i64",
     "hsort_keys_i32_noalloc",
     "hsort_pairs",
+    "hsort_sort",
+    "hsort_sort_scratch_bytes",
     "hsort_segmented",
     "hsort_segmented_i64",
     "hsort_bounds_offset",
@@ -51,6 +62,7 @@ EXPORTS = [
     "hsort_size_class",
     "hsort_load_tuning",
     "hsort_debug_stage",
+    "hsort_debug_stage_typed",
     "hsort_graph_mode",
     "hsort_graph_clear",
     "hsort_graph_count",
@@ -84,13 +96,16 @@ def load_library(path: str = LIB_PATH):
         "hsort_keys_i64": ([P, I64, P, SZ, P], I),
         "hsort_keys_i32_noalloc": ([P, I64, P], I),
         "hsort_pairs": ([P, P, I64, P, SZ, P], I),
+        "hsort_sort": ([P, P, I64, I, I, P, SZ, P], I),
+        "hsort_sort_scratch_bytes": ([I, I, I64], SZ),
+        "hsort_debug_stage_typed": ([P, P, I64, I, I, I, P, SZ, P], I),
         "hsort_segmented": ([P, I64, P, I64, I64, P, SZ, P], I),
         "hsort_segmented_i64": ([P, I64, P, I64, I64, P, SZ, P], I),
         "hsort_bounds_offset": ([I, I64, I64], SZ),
         "hsort_check": ([P, P], I),
         "hsort_last_error": ([], ctypes.c_char_p),
-        "hsort_set_config": ([I, I, I64, I64, I64, I64, I64, I64, I64], I),
-        "hsort_get_config": ([I, I, P, P, P, P, P, P, P], I),
+        "hsort_set_config": ([I, I, I64, I64, I64, I64, I64, I64, I64, I64], I),
+        "hsort_get_config": ([I, I, P, P, P, P, P, P, P, P], I),
         "hsort_size_class": ([I64], I),
         "hsort_load_tuning": ([ctypes.c_char_p], I),
         "hsort_debug_stage": ([I, P, P, I64, I, P, SZ, P], I),
@@ -202,6 +217,58 @@ def hsort_pairs(keys: torch.Tensor, vals: torch.Tensor, scratch: torch.Tensor | 
     return keys, vals
 
 
+def _key_type(keys, key_type):
+    if not isinstance(keys, torch.Tensor) or not keys.is_cuda:
+        raise TypeError("keys must be a CUDA (HIP) tensor")
+    if not keys.is_contiguous():
+        raise ValueError("keys must be contiguous")
+    if key_type is None:
+        if keys.dtype not in _KEY_TYPE_OF_DTYPE:
+            raise TypeError(f"no key type for dtype {keys.dtype}; pass key_type")
+        key_type = _KEY_TYPE_OF_DTYPE[keys.dtype]
+    if key_type not in range(6):
+        raise ValueError("key_type must be one of I32, U32, F32, I64, U64, F64")
+    if keys.element_size() != (4 if key_type < I64 else 8):
+        raise TypeError("keys' element size does not match the key type")
+    return key_type
+
+
+def sort_scratch_bytes(key_type: int, with_vals: bool, n: int) -> int:
+    return int(load_library().hsort_sort_scratch_bytes(key_type, 1 if with_vals else 0, n))
+
+
+def hsort_sort(keys: torch.Tensor, vals: torch.Tensor | None = None, descending: bool = False,
+               key_type: int | None = None, scratch: torch.Tensor | None = None):
+    """Sort keys of any supported type in place (int32/uint32/float32/int64/uint64/float64, the type taken
+    from the dtype or given as key_type for a tensor holding the bits), ascending or descending, stable,
+    permuting a 32-bit payload `vals` with them; floats in IEEE-754 total order."""
+    kt = _key_type(keys, key_type)
+    n = keys.numel()
+    if vals is not None:
+        _dev_tensor(vals, (torch.int32,) + ((torch.uint32,) if hasattr(torch, "uint32") else ()), "vals")
+        if vals.numel() != n:
+            raise ValueError("keys and vals differ in length")
+    need = sort_scratch_bytes(kt, vals is not None, n)
+    if scratch is None:
+        scratch = torch.empty(max(need, 1), dtype=torch.uint8, device=keys.device)
+    elif _nbytes(scratch) < need:
+        raise HsortError(HSORT_ERR_SCRATCH, f"scratch needs {need} bytes")
+    _check(load_library().hsort_sort(_ptr(keys), _ptr(vals), n, kt, DESCENDING if descending else 0, _ptr(scratch),
+                                     _nbytes(scratch), _stream(keys)))
+    return keys, vals
+
+
+def hsort_debug_stage_typed(keys: torch.Tensor, stage: int, vals: torch.Tensor | None = None,
+                            descending: bool = False, key_type: int | None = None) -> torch.Tensor:
+    """hsort_sort's pipeline up to `stage` (1 scatter, 2 local sorts, 3 all), in place."""
+    kt = _key_type(keys, key_type)
+    n = keys.numel()
+    s = torch.empty(max(sort_scratch_bytes(kt, vals is not None, n), 1), dtype=torch.uint8, device=keys.device)
+    _check(load_library().hsort_debug_stage_typed(_ptr(keys), _ptr(vals), n, kt, DESCENDING if descending else 0,
+                                                  stage, _ptr(s), _nbytes(s), _stream(keys)))
+    return keys
+
+
 def hsort_segmented(keys: torch.Tensor, offsets: torch.Tensor, max_seg_len: int = 0,
                     scratch: torch.Tensor | None = None) -> torch.Tensor:
     """Sort every keys[offsets[i]:offsets[i+1]] in place (int32 or int64 keys, int64 offsets)."""
@@ -230,18 +297,23 @@ def read_bounds(scratch: torch.Tensor, kind: int, n: int, nseg: int = 1) -> torc
 
 
 def hsort_set_config(kind: int, tile: int, tile_vt: int, merge_nv: int, merge_vt: int, small_max: int,
-                     fanin: int = 2, size_class: int = -1, digits: int = 1) -> None:
+                     fanin: int = 2, size_class: int = -1, digits: int = 1, local: int = 0) -> None:
     _check(load_library().hsort_set_config(kind, size_class, tile, tile_vt, merge_nv, merge_vt, small_max, fanin,
-                                           digits))
+                                           digits, local))
+
+
+def hsort_set_config_tuple(kind: int, cfg, size_class: int = -1) -> None:
+    """Apply a (tile, tile_vt, merge_nv, merge_vt, small_max, fanin, digits, local) tuple."""
+    hsort_set_config(kind, *cfg[:5], fanin=cfg[5], digits=cfg[6], local=cfg[7], size_class=size_class)
 
 
 def hsort_get_config(kind: int, size_class: int | None = None, n: int | None = None):
-    """(tile, tile_vt, merge_nv, merge_vt, small_max, fanin, digits) of a kind, for a size class or for n
-    keys (default: 2^28)."""
+    """(tile, tile_vt, merge_nv, merge_vt, small_max, fanin, digits, local) of a kind, for a size class or
+    for n keys (default: 2^28)."""
     lib = load_library()
     if size_class is None:
         size_class = lib.hsort_size_class(n if n is not None else 1 << 28)
-    vals = [ctypes.c_int64() for _ in range(7)]
+    vals = [ctypes.c_int64() for _ in range(8)]
     _check(lib.hsort_get_config(kind, size_class, *[ctypes.byref(v) for v in vals]))
     return tuple(v.value for v in vals)
 

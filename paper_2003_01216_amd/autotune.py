@@ -3,8 +3,9 @@
 For every key kind and size class it times each compiled shape on the
 device -- tile (keys per local-sort partition) x keys per thread, merge
 outputs per workgroup x per thread, the largest segment sorted wholly in
-LDS, the merge fan-in (2 or 4 runs per round) and the decimal digits of the
-one-step partition (1: ten buckets, 2: one hundred) -- on a representative
+LDS, the merge fan-in (2 or 4 runs per round), the decimal digits of the
+one-step partition (1: ten buckets, 2: one hundred) and the local sort (0:
+network and lane merges, 1: bottom-up LDS merge) -- on a representative
 synthetic workload of that class, and writes the
 fastest to a table (``tuning.txt``, applied by the binding when the library
 loads; see ``hsort_load_tuning``), and, with ``--report PATH``, a JSON log
@@ -28,45 +29,53 @@ import time
 import numpy as np
 import torch
 
-from . import (KEYS_I32, KEYS_I64, PAIRS_I32_U32, SEG_I32, SEG_I64, TUNING_PATH, HsortError, hsort_graph_mode,
-               hsort_keys, hsort_pairs, hsort_segmented, hsort_set_config, load_library, scratch_bytes)
+from . import (KEYS_I32, KEYS_I64, PAIRS_I32_U32, PAIRS_I64_U32, SEG_I32, SEG_I64, TUNING_PATH, HsortError,
+               hsort_graph_mode, hsort_keys, hsort_pairs, hsort_segmented, hsort_set_config, hsort_sort, load_library,
+               scratch_bytes)
 
 TILES = {
     KEYS_I32: [(8192, 16), (8192, 32), (16384, 32), (32768, 32)],
     KEYS_I64: [(4096, 16), (8192, 16)],
     PAIRS_I32_U32: [(4096, 16), (8192, 16)],
+    PAIRS_I64_U32: [(2048, 8), (4096, 8)],
 }
 # merge shapes (outputs per workgroup, per thread) by fan-in; for fan-in 4
 # the first number is also the sampling stride S (a workgroup holds <= 2S)
 MERGES = {
-    2: {KEYS_I32: [(4096, 16), (8192, 16), (8192, 32)], KEYS_I64: [(4096, 16)], PAIRS_I32_U32: [(4096, 16)]},
+    2: {KEYS_I32: [(4096, 16), (8192, 16), (8192, 32)], KEYS_I64: [(4096, 16)], PAIRS_I32_U32: [(4096, 16)],
+        PAIRS_I64_U32: [(2048, 8)]},
     4: {KEYS_I32: [(4096, 16), (2048, 16), (2048, 8)], KEYS_I64: [(4096, 16), (2048, 16), (2048, 8)],
-        PAIRS_I32_U32: [(4096, 16), (2048, 16), (2048, 8)]},
+        PAIRS_I32_U32: [(4096, 16), (2048, 16), (2048, 8)], PAIRS_I64_U32: [(1024, 8), (2048, 8)]},
 }
-SMALL = {KEYS_I32: [8192], KEYS_I64: [4096], PAIRS_I32_U32: [4096]}
+SMALL = {KEYS_I32: [8192], KEYS_I64: [4096], PAIRS_I32_U32: [4096], PAIRS_I64_U32: [4096]}
 SEG_SMALL = [2048, 4096, 8192]
-KEY_TYPE = {KEYS_I32: KEYS_I32, SEG_I32: KEYS_I32, KEYS_I64: KEYS_I64, SEG_I64: KEYS_I64, PAIRS_I32_U32: PAIRS_I32_U32}
+KEY_TYPE = {KEYS_I32: KEYS_I32, SEG_I32: KEYS_I32, KEYS_I64: KEYS_I64, SEG_I64: KEYS_I64, PAIRS_I32_U32: PAIRS_I32_U32,
+            PAIRS_I64_U32: PAIRS_I64_U32}
 CLASS_SIZES = {0: 1 << 18, 1: 1 << 22, 2: 1 << 26, 3: 1 << 28}
-NAMES = {KEYS_I32: "keys_i32", KEYS_I64: "keys_i64", PAIRS_I32_U32: "pairs_i32", SEG_I32: "seg_i32", SEG_I64: "seg_i64"}
+NAMES = {KEYS_I32: "keys_i32", KEYS_I64: "keys_i64", PAIRS_I32_U32: "pairs_i32", SEG_I32: "seg_i32", SEG_I64: "seg_i64",
+         PAIRS_I64_U32: "pairs_i64"}
 
 
 FANINS = [2, 4]
 # decimal digits of the one-step partition: ten or one hundred buckets
 DIGITS = [1, 2]
+# local-sort shapes of the bottom-up LDS merge (local = 1; Figure 1b from pairs when tile_vt = 2)
+TILES_BU = {KEYS_I32: [(2048, 2), (4096, 8)], PAIRS_I32_U32: [(2048, 2)], KEYS_I64: [(2048, 2)]}
 
 
 def candidates(kind):
     kt = KEY_TYPE[kind]
     smalls = SEG_SMALL if kind in (SEG_I32, SEG_I64) else SMALL[kt]
+    tiles = [(t, tv, 0) for t, tv in TILES[kt]] + [(t, tv, 1) for t, tv in TILES_BU.get(kt, [])]
     for f in FANINS:
-        for (t, tv), (m, mv), s, d in itertools.product(TILES[kt], MERGES[f][kt], smalls, DIGITS):
+        for (t, tv, lc), (m, mv), s, d in itertools.product(tiles, MERGES[f][kt], smalls, DIGITS):
             if t % m == 0:
-                yield (t, tv, m, mv, s, f, d)
+                yield (t, tv, m, mv, s, f, d, lc)
 
 
 def _rng_keys(kind, n, seed):
     rng = np.random.default_rng(seed)
-    if KEY_TYPE[kind] == KEYS_I64:
+    if KEY_TYPE[kind] in (KEYS_I64, PAIRS_I64_U32):
         info = np.iinfo(np.int64)
         return rng.integers(info.min, info.max, n, dtype=np.int64, endpoint=True)
     return rng.integers(0, 2**31 - 1, n, dtype=np.int32)
@@ -107,7 +116,7 @@ class Workload:
                 n = min(n, 1 << 24)
             self.n = n
             self.base = torch.from_numpy(_rng_keys(kind, n, 5 + cls)).to(dev)
-            if kind == PAIRS_I32_U32:
+            if kind in (PAIRS_I32_U32, PAIRS_I64_U32):
                 self.vals = torch.arange(n, dtype=torch.int32, device=dev)
             self.nseg = 1
 
@@ -119,6 +128,8 @@ class Workload:
             hsort_segmented(keys, self.off, max_seg_len=self.max_len, scratch=scratch)
         elif self.kind == PAIRS_I32_U32:
             hsort_pairs(keys, vals, scratch=scratch)
+        elif self.kind == PAIRS_I64_U32:
+            hsort_sort(keys, vals, scratch=scratch)
         else:
             hsort_keys(keys, scratch=scratch)
 
@@ -129,10 +140,10 @@ def time_config(wl, cfg, cls, reps):
     The same buffers are sorted every time (refilled outside the timed
     window), so in graph mode the warm-up captures and the timed calls replay.
     """
-    hsort_set_config(wl.kind, *cfg[:5], fanin=cfg[5], digits=cfg[6], size_class=cls)
+    hsort_set_config(wl.kind, *cfg[:5], fanin=cfg[5], digits=cfg[6], local=cfg[7], size_class=cls)
     scratch = wl.scratch()
     work = wl.base.clone()
-    wv = wl.vals.clone() if wl.kind == PAIRS_I32_U32 else None
+    wv = wl.vals.clone() if wl.kind in (PAIRS_I32_U32, PAIRS_I64_U32) else None
     times = []
     for r in range(reps + 1):
         work.copy_(wl.base)
@@ -173,7 +184,7 @@ def tune(kinds, classes, quick=False, reps=5, log=print):
                     if best is None or ms < best[0]:
                         best = (ms, cfg)
                 table[(kind, cls)] = best[1]
-                hsort_set_config(kind, *best[1][:5], fanin=best[1][5], digits=best[1][6], size_class=cls)
+                hsort_set_config(kind, *best[1][:5], fanin=best[1][5], digits=best[1][6], local=best[1][7], size_class=cls)
                 del wl
                 torch.cuda.empty_cache()
     finally:
@@ -182,7 +193,7 @@ def tune(kinds, classes, quick=False, reps=5, log=print):
 
 
 def write_table(table, path, report=None, report_path=None):
-    lines = ["# hsort tuning table: kind size_class tile tile_vt merge_nv merge_vt small_max fanin digits",
+    lines = ["# hsort tuning table: kind size_class tile tile_vt merge_nv merge_vt small_max fanin digits local",
              f"# written by paper_2003_01216_amd.autotune on {time.strftime('%Y-%m-%d %H:%M:%S')}"]
     for (kind, cls), cfg in sorted(table.items()):
         lines.append(f"{kind} {cls} " + " ".join(str(x) for x in cfg))
@@ -199,7 +210,7 @@ def main(argv=None):
     ap.add_argument("--out", default=TUNING_PATH)
     ap.add_argument("--report", default="", help="write the JSON log of every measurement to this path")
     ap.add_argument("--quick", action="store_true", help="smaller workloads (sizes capped at 2^24)")
-    ap.add_argument("--kinds", default="keys_i32,keys_i64,pairs_i32,seg_i32,seg_i64")
+    ap.add_argument("--kinds", default="keys_i32,keys_i64,pairs_i32,seg_i32,seg_i64,pairs_i64")
     ap.add_argument("--classes", default="0,1,2,3")
     ap.add_argument("--reps", type=int, default=5)
     args = ap.parse_args(argv)

@@ -33,6 +33,7 @@ struct Config {
     int64_t small_max;  // segments up to this size never leave LDS
     int64_t fanin;      // runs merged per round: 2 or 4
     int64_t digits = 1;  // decimal digits of the one-step partition: 1 (ten buckets) or 2 (one hundred)
+    int64_t local = 0;   // local sort: 0 network + lane merges + LDS levels, 1 bottom-up LDS merge from VT-runs
 };
 
 std::mutex g_mu;
@@ -40,7 +41,7 @@ std::mutex g_mu;
 // 2 int32 pairs, 3 segmented int32, 4 segmented int64); size class by the
 // number of keys that decides the merge depth (n for a plain sort, the
 // longest segment for a segmented one when the caller gives it).
-constexpr int kKinds = 5;
+constexpr int kKinds = 6;
 constexpr int kClasses = 4;
 constexpr int64_t kClassTop[kClasses - 1] = {1 << 18, 1 << 22, 1 << 26};
 Config g_cfg[kKinds][kClasses] = {
@@ -49,12 +50,18 @@ Config g_cfg[kKinds][kClasses] = {
     {{4096, 16, 4096, 16, 4096, 2}, {4096, 16, 4096, 16, 4096, 2}, {4096, 16, 4096, 16, 4096, 2}, {4096, 16, 4096, 16, 4096, 2}},
     {{8192, 16, 4096, 16, 8192, 2}, {8192, 16, 4096, 16, 8192, 2}, {16384, 32, 4096, 16, 8192, 2}, {16384, 32, 4096, 16, 8192, 2}},
     {{4096, 16, 4096, 16, 4096, 2}, {4096, 16, 4096, 16, 4096, 2}, {4096, 16, 4096, 16, 4096, 2}, {4096, 16, 4096, 16, 4096, 2}},
+    {{4096, 8, 2048, 8, 4096, 2}, {4096, 8, 2048, 8, 4096, 2}, {4096, 8, 1024, 8, 4096, 4, 2}, {4096, 8, 1024, 8, 4096, 4, 2}},
 };
 
 int cfg_index(int kind) { return (kind >= 0 && kind < kKinds) ? kind : -1; }
 
-// key type of a kind: 0 int32 keys, 1 int64 keys, 2 int32 pairs
-int key_type(int kind) { return kind == HSORT_KEYS_I64 || kind == HSORT_SEG_I64 ? 1 : kind == HSORT_PAIRS_I32_U32 ? 2 : 0; }
+// key type of a kind: 0 int32 keys, 1 int64 keys, 2 int32 pairs, 3 int64 pairs
+int key_type(int kind) {
+    return kind == HSORT_KEYS_I64 || kind == HSORT_SEG_I64 ? 1
+           : kind == HSORT_PAIRS_I32_U32                 ? 2
+           : kind == HSORT_PAIRS_I64_U32                 ? 3
+                                                         : 0;
+}
 
 int size_class(int64_t n) {
     int c = 0;
@@ -85,6 +92,16 @@ bool tile_shape_ok(int64_t nt, int64_t vt) {
 }
 
 template <typename K, bool PAIRS>
+bool bu_tile_shape_ok(int64_t nt, int64_t vt) {
+#define X(KK, P, NT_, VT_) \
+    if constexpr (std::is_same_v<K, KK> && PAIRS == P) \
+        if (nt == NT_ && vt == VT_) return true;
+    HS_TILE_BU_VARIANTS(X)
+#undef X
+    return false;
+}
+
+template <typename K, bool PAIRS>
 bool merge_shape_ok(int64_t nt, int64_t vt) {
 #define X(KK, P, NT_, VT_) \
     if constexpr (std::is_same_v<K, KK> && PAIRS == P) \
@@ -107,7 +124,7 @@ bool merge4_shape_ok(int64_t nv, int64_t vt) {
 template <typename K, bool PAIRS>
 bool shapes_ok(const Config& c) {
     const int64_t tn = c.tile / c.tile_vt, mn = c.merge_nv / c.merge_vt;
-    if (!tile_shape_ok<K, PAIRS>(tn, c.tile_vt)) return false;
+    if (c.local == 1 ? !bu_tile_shape_ok<K, PAIRS>(tn, c.tile_vt) : !tile_shape_ok<K, PAIRS>(tn, c.tile_vt)) return false;
     if (c.fanin == 2) return merge_shape_ok<K, PAIRS>(mn, c.merge_vt);
     return merge4_shape_ok<K, PAIRS>(c.merge_nv, c.merge_vt);
 }
@@ -118,6 +135,7 @@ bool config_ok(int key_type_index, const Config& c) {
     if (c.small_max < 0 || c.small_max > 8192) return false;
     if (c.fanin != 2 && c.fanin != 4) return false;
     if (c.digits != 1 && c.digits != 2) return false;
+    if (c.local != 0 && c.local != 1) return false;
     switch (key_type_index) {
         case 0:
             return shapes_ok<int32_t, false>(c);
@@ -125,6 +143,8 @@ bool config_ok(int key_type_index, const Config& c) {
             return shapes_ok<int64_t, false>(c);
         case 2:
             return shapes_ok<int32_t, true>(c);
+        case 3:  // 16-byte words: the whole-segment sort holds at most 4096
+            return c.small_max <= 4096 && shapes_ok<int64_t, true>(c);
     }
     return false;
 }
@@ -202,8 +222,8 @@ Layout make_layout(int kind, int64_t n, int64_t nseg, const Config& c) {
     // at least one segment is always counted as large.
     const bool seg = kind == HSORT_SEG_I32 || kind == HSORT_SEG_I64;
     if (!seg) nseg = 1;
-    const size_t ksz = (kind == HSORT_KEYS_I64 || kind == HSORT_SEG_I64) ? 8 : 4;
-    const bool pairs = kind == HSORT_PAIRS_I32_U32;
+    const size_t ksz = (kind == HSORT_KEYS_I64 || kind == HSORT_SEG_I64 || kind == HSORT_PAIRS_I64_U32) ? 8 : 4;
+    const bool pairs = kind == HSORT_PAIRS_I32_U32 || kind == HSORT_PAIRS_I64_U32;
     Layout L{};
     L.large_bound = std::min<int64_t>(nseg, std::max<int64_t>(1, n / (c.small_max + 1)));
     L.tiles_bound = cdiv(n, kHistTile) + L.large_bound;
@@ -297,9 +317,17 @@ Work<K> make_work(const Layout& L, char* scr, K* keys, uint32_t* vals, const int
 template <typename K, bool PAIRS>
 hipError_t tilesort_by_shape(const Config& c, const Work<K>& w, int64_t items, hipStream_t st) {
     const int64_t nt = c.tile / c.tile_vt, vt = c.tile_vt;
+    if (c.local == 1) {
 #define X(KK, P, NT_, VT_) \
     if constexpr (std::is_same_v<K, KK> && PAIRS == P) \
-        if (nt == NT_ && vt == VT_) return launch_tilesort<KK, P, NT_, VT_>(w, items, st);
+        if (nt == NT_ && vt == VT_) return launch_tilesort<KK, P, NT_, VT_, true>(w, items, st);
+        HS_TILE_BU_VARIANTS(X)
+#undef X
+        return hipErrorInvalidValue;
+    }
+#define X(KK, P, NT_, VT_) \
+    if constexpr (std::is_same_v<K, KK> && PAIRS == P) \
+        if (nt == NT_ && vt == VT_) return launch_tilesort<KK, P, NT_, VT_, false>(w, items, st);
     HS_TILE_VARIANTS(X)
 #undef X
     return hipErrorInvalidValue;
@@ -329,6 +357,17 @@ hipError_t merge4_by_shape(const Config& c, const Work<K>& w, int round, int64_t
 
 template <typename K, bool PAIRS>
 hipError_t small_by_shape(int64_t cap, const Work<K>& w, int64_t lo, int64_t hi, int64_t segs, hipStream_t st) {
+    if constexpr (PAIRS && sizeof(K) == 8) {  // 16-byte words: at most 8 per thread
+        switch (cap) {
+            case 4096:
+                return launch_small<K, PAIRS, 512, 8>(w, lo, hi, segs, st);
+            case 2048:
+                return launch_small<K, PAIRS, 256, 8>(w, lo, hi, segs, st);
+            case 256:
+                return launch_small<K, PAIRS, 64, 4>(w, lo, hi, segs, st);
+        }
+        return hipErrorInvalidValue;
+    }
     switch (cap) {
         case 8192:
             return launch_small<K, PAIRS, 512, 16>(w, lo, hi, segs, st);
@@ -369,8 +408,8 @@ std::vector<SmallClass> small_classes(int64_t small_max) {
 // and the configuration, never on device data, so the sequence can be
 // captured into a graph and replayed.
 template <typename K, bool PAIRS>
-int enqueue(int kind, K* keys, uint32_t* vals, int64_t n, const int64_t* off, int64_t nseg, int64_t max_seg_len,
-        void* scratch, size_t scratch_bytes, hipStream_t st, int stage, int64_t small_override) {
+int enqueue_body(int kind, K* keys, uint32_t* vals, int64_t n, const int64_t* off, int64_t nseg, int64_t max_seg_len,
+                 void* scratch, size_t scratch_bytes, hipStream_t st, int stage, int64_t small_override, int img) {
     const Config c = get_cfg(kind, class_size(kind, n, max_seg_len));
     const bool seg = off != nullptr;
     if (!seg) nseg = 1;
@@ -381,6 +420,7 @@ int enqueue(int kind, K* keys, uint32_t* vals, int64_t n, const int64_t* off, in
     const int64_t small_max = small_override >= 0 ? small_override : c.small_max;
     char* scr = (char*)scratch;
     Work<K> w = make_work<K>(L, scr, keys, vals, off, n, nseg, c, small_max, seg ? max_seg_len : 0);
+    w.ufix = (img & kImgUnsigned) ? 1 : 0;
     const double kb = sizeof(K) + (PAIRS ? 4.0 : 0.0);
     {
         Timer t(st, "setup", 0);
@@ -481,6 +521,24 @@ int enqueue(int kind, K* keys, uint32_t* vals, int64_t n, const int64_t* off, in
     return HSORT_OK;
 }
 
+// Keys of other types (img != 0, plain sorts only) are turned into their
+// order image in place before the pipeline and back after it.
+template <typename K, bool PAIRS>
+int enqueue(int kind, K* keys, uint32_t* vals, int64_t n, const int64_t* off, int64_t nseg, int64_t max_seg_len,
+            void* scratch, size_t scratch_bytes, hipStream_t st, int stage, int64_t small_override, int img = 0) {
+    if (img) {
+        Timer t(st, "image", 2.0 * sizeof(K) * n);
+        HS_TRY(launch_image<K>(keys, n, img, false, st));
+    }
+    const int rc = enqueue_body<K, PAIRS>(kind, keys, vals, n, off, nseg, max_seg_len, scratch, scratch_bytes, st,
+                                          stage, small_override, img);
+    if (rc == HSORT_OK && img) {
+        Timer t(st, "image", 2.0 * sizeof(K) * n);
+        HS_TRY(launch_image<K>(keys, n, img, true, st));
+    }
+    return rc;
+}
+
 // ------------------------------------------------------------ graph cache
 // With graph mode on, each distinct call (kind, sizes, pointers, shapes,
 // stream) is captured once into a hipGraph and replayed afterwards; the
@@ -488,6 +546,7 @@ int enqueue(int kind, K* keys, uint32_t* vals, int64_t n, const int64_t* off, in
 struct GraphKey {
     int kind, stage;
     int64_t n, nseg, max_seg_len, small_override;
+    int img;
     const void *keys, *vals, *off, *scratch;
     hipStream_t st;
     Config c;
@@ -511,7 +570,7 @@ void destroy_entry(GraphEntry& e) {
 
 template <typename K, bool PAIRS>
 int run(int kind, K* keys, uint32_t* vals, int64_t n, const int64_t* off, int64_t nseg, int64_t max_seg_len,
-        void* scratch, size_t scratch_bytes, hipStream_t st, int stage, int64_t small_override) {
+        void* scratch, size_t scratch_bytes, hipStream_t st, int stage, int64_t small_override, int img = 0) {
     bool graphs;
     {
         std::lock_guard<std::mutex> lk(g_mu);
@@ -521,7 +580,7 @@ int run(int kind, K* keys, uint32_t* vals, int64_t n, const int64_t* off, int64_
     if (graphs && st) (void)hipStreamIsCapturing(st, &cap);
     if (!graphs || !st || cap != hipStreamCaptureStatusNone)
         return enqueue<K, PAIRS>(kind, keys, vals, n, off, nseg, max_seg_len, scratch, scratch_bytes, st, stage,
-                                 small_override);
+                                 small_override, img);
     GraphKey key;
     memset(&key, 0, sizeof key);
     key.kind = kind;
@@ -530,6 +589,7 @@ int run(int kind, K* keys, uint32_t* vals, int64_t n, const int64_t* off, int64_
     key.nseg = nseg;
     key.max_seg_len = max_seg_len;
     key.small_override = small_override;
+    key.img = img;
     key.keys = keys;
     key.vals = vals;
     key.off = off;
@@ -553,7 +613,7 @@ int run(int kind, K* keys, uint32_t* vals, int64_t n, const int64_t* off, int64_
         HS_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
         g_capturing = true;
         const int rc = enqueue<K, PAIRS>(kind, keys, vals, n, off, nseg, max_seg_len, scratch, scratch_bytes, st,
-                                         stage, small_override);
+                                         stage, small_override, img);
         g_capturing = false;
         hipGraph_t graph = nullptr;
         const hipError_t e = hipStreamEndCapture(st, &graph);
@@ -731,6 +791,60 @@ int hsort_segmented_i64(int64_t* keys, int64_t n, const int64_t* offsets, int64_
                                (hipStream_t)stream, 3, -1);
 }
 
+// ------------------------------------------------------- other key types
+static int typed_mode(int key_type, int flags, int* img, bool* wide) {
+    if (key_type < HSORT_I32 || key_type > HSORT_F64) return fail(HSORT_ERR_INVALID, "unknown key type");
+    if (flags & ~HSORT_DESCENDING) return fail(HSORT_ERR_INVALID, "unknown flags");
+    const int base = key_type % 3;  // 0 signed, 1 unsigned, 2 float
+    *img = (base == 1 ? kImgUnsigned : base == 2 ? kImgFloat : 0) | ((flags & HSORT_DESCENDING) ? kImgDesc : 0);
+    *wide = key_type >= HSORT_I64;
+    return HSORT_OK;
+}
+
+size_t hsort_sort_scratch_bytes(int key_type, int with_vals, int64_t n) {
+    if (key_type < HSORT_I32 || key_type > HSORT_F64) return 0;
+    const bool wide = key_type >= HSORT_I64;
+    const int kind = wide ? (with_vals ? HSORT_PAIRS_I64_U32 : HSORT_KEYS_I64)
+                          : (with_vals ? HSORT_PAIRS_I32_U32 : HSORT_KEYS_I32);
+    return hsort_scratch_bytes(kind, n, 1);
+}
+
+static int sort_typed(void* keys, uint32_t* vals, int64_t n, int key_type, int flags, int stage, void* scratch,
+                      size_t scratch_bytes, hipStream_t st) {
+    int img = 0;
+    bool wide = false;
+    int rc = typed_mode(key_type, flags, &img, &wide);
+    if (rc) return rc;
+    rc = check_common(keys, n, scratch);
+    if (rc || n == 0) return rc;
+    const int64_t small = stage == 3 ? -1 : 0;  // debug stages run the whole pipeline
+    if (!wide) {
+        if (vals)
+            return run<int32_t, true>(HSORT_PAIRS_I32_U32, (int32_t*)keys, vals, n, nullptr, 1, 0, scratch,
+                                      scratch_bytes, st, stage, small, img);
+        return run<int32_t, false>(HSORT_KEYS_I32, (int32_t*)keys, nullptr, n, nullptr, 1, 0, scratch, scratch_bytes,
+                                   st, stage, small, img);
+    }
+    if (vals)
+        return run<int64_t, true>(HSORT_PAIRS_I64_U32, (int64_t*)keys, vals, n, nullptr, 1, 0, scratch,
+                                  scratch_bytes, st, stage, small, img);
+    return run<int64_t, false>(HSORT_KEYS_I64, (int64_t*)keys, nullptr, n, nullptr, 1, 0, scratch, scratch_bytes, st,
+                               stage, small, img);
+}
+
+int hsort_sort(void* keys, uint32_t* vals, int64_t n, int key_type, int flags, void* scratch, size_t scratch_bytes,
+               void* stream) {
+    g_err.clear();
+    return sort_typed(keys, vals, n, key_type, flags, 3, scratch, scratch_bytes, (hipStream_t)stream);
+}
+
+int hsort_debug_stage_typed(void* keys, uint32_t* vals, int64_t n, int key_type, int flags, int stage, void* scratch,
+                            size_t scratch_bytes, void* stream) {
+    g_err.clear();
+    if (stage < 1 || stage > 3) return fail(HSORT_ERR_INVALID, "stage must be 1, 2 or 3");
+    return sort_typed(keys, vals, n, key_type, flags, stage, scratch, scratch_bytes, (hipStream_t)stream);
+}
+
 int hsort_check(const void* scratch, void* stream) {
     g_err.clear();
     if (!scratch) return fail(HSORT_ERR_INVALID, "null scratch");
@@ -748,12 +862,12 @@ int hsort_check(const void* scratch, void* stream) {
 const char* hsort_last_error(void) { return g_err.c_str(); }
 
 int hsort_set_config(int kind, int size_cls, int64_t tile, int64_t tile_vt, int64_t merge_nv, int64_t merge_vt,
-                     int64_t small_max, int64_t fanin, int64_t digits) {
+                     int64_t small_max, int64_t fanin, int64_t digits, int64_t local) {
     g_err.clear();
     const int ci = cfg_index(kind);
     if (ci < 0) return fail(HSORT_ERR_INVALID, "unknown kind");
     if (size_cls < -1 || size_cls >= kClasses) return fail(HSORT_ERR_INVALID, "size class out of range");
-    const Config c{tile, tile_vt, merge_nv, merge_vt, small_max, fanin, digits};
+    const Config c{tile, tile_vt, merge_nv, merge_vt, small_max, fanin, digits, local};
     if (!config_ok(key_type(kind), c)) return fail(HSORT_ERR_UNSUPPORTED, "tile/merge shape not compiled");
     std::lock_guard<std::mutex> lk(g_mu);
     for (int k = 0; k < kClasses; k++)
@@ -762,10 +876,10 @@ int hsort_set_config(int kind, int size_cls, int64_t tile, int64_t tile_vt, int6
 }
 
 int hsort_get_config(int kind, int size_cls, int64_t* tile, int64_t* tile_vt, int64_t* merge_nv, int64_t* merge_vt,
-                     int64_t* small_max, int64_t* fanin, int64_t* digits) {
+                     int64_t* small_max, int64_t* fanin, int64_t* digits, int64_t* local) {
     const int ci = cfg_index(kind);
     if (ci < 0 || size_cls < 0 || size_cls >= kClasses || !tile || !tile_vt || !merge_nv || !merge_vt || !small_max ||
-        !fanin || !digits)
+        !fanin || !digits || !local)
         return fail(HSORT_ERR_INVALID, "bad arguments");
     Config c;
     {
@@ -779,6 +893,7 @@ int hsort_get_config(int kind, int size_cls, int64_t* tile, int64_t* tile_vt, in
     *small_max = c.small_max;
     *fanin = c.fanin;
     *digits = c.digits;
+    *local = c.local;
     return HSORT_OK;
 }
 
@@ -793,13 +908,14 @@ int hsort_load_tuning(const char* path) {
         lineno++;
         if (line[0] == '#' || line[0] == '\n') continue;
         int kind = 0, cls = 0;
-        long long t, tv, m, mv, sm, fi, dg = 1;
-        const int got = sscanf(line, "%d %d %lld %lld %lld %lld %lld %lld %lld", &kind, &cls, &t, &tv, &m, &mv, &sm, &fi, &dg);
-        if (got != 8 && got != 9) {  // the digits column is optional (1)
+        long long t, tv, m, mv, sm, fi, dg = 1, lc = 0;
+        const int got = sscanf(line, "%d %d %lld %lld %lld %lld %lld %lld %lld %lld", &kind, &cls, &t, &tv, &m, &mv, &sm,
+                               &fi, &dg, &lc);
+        if (got < 8) {  // the digits (1) and local-sort (0) columns are optional
             rc = fail(HSORT_ERR_INVALID, std::string(path) + ": bad line " + std::to_string(lineno));
             break;
         }
-        if ((rc = hsort_set_config(kind, cls, t, tv, m, mv, sm, fi, dg)) != HSORT_OK) break;
+        if ((rc = hsort_set_config(kind, cls, t, tv, m, mv, sm, fi, dg, lc)) != HSORT_OK) break;
     }
     fclose(f);
     return rc;
@@ -822,6 +938,10 @@ int hsort_debug_stage(int kind, void* keys, uint32_t* vals, int64_t n, int stage
         case HSORT_PAIRS_I32_U32:
             if (!vals) return fail(HSORT_ERR_INVALID, "null vals");
             return run<int32_t, true>(kind, (int32_t*)keys, vals, n, nullptr, 1, 0, scratch, scratch_bytes, st,
+                                      stage, 0);
+        case HSORT_PAIRS_I64_U32:
+            if (!vals) return fail(HSORT_ERR_INVALID, "null vals");
+            return run<int64_t, true>(kind, (int64_t*)keys, vals, n, nullptr, 1, 0, scratch, scratch_bytes, st,
                                       stage, 0);
     }
     return fail(HSORT_ERR_INVALID, "kind must be a plain kind");

@@ -64,11 +64,15 @@ struct DigitPlan {
     uint32_t mul2;    // 32-bit keys with magic2 = 0: the bucket is u * mul2 (1 when D = 2, 10 when D = 1)
 };
 
+// fixed: the keys are images of unsigned keys (the unsigned value x maps
+// to x + type minimum, keeping the order), and beta is fixed at the type's
+// minimum, so u is the unsigned value itself (no bias, as for non-negative
+// signed keys).  Otherwise beta = min(mn, 0).
 template <typename K>
-__host__ __device__ inline DigitPlan<K> make_digit_plan(K mn, K mx) {
+__host__ __device__ inline DigitPlan<K> make_digit_plan(K mn, K mx, bool fixed = false) {
     using U = typename Traits<K>::U;
     DigitPlan<K> pl;
-    K beta = mn < 0 ? mn : K(0);
+    K beta = fixed ? Traits<K>::kMin : (mn < 0 ? mn : K(0));
     pl.beta = (U)beta;
     U top = (U)mx - (U)beta;  // exact: mx >= beta
     U p = 1;
@@ -180,6 +184,31 @@ __device__ __forceinline__ uint64_t pair_word(int32_t k, uint32_t pos) {
 __device__ __forceinline__ int32_t pair_key(uint64_t w) { return (int32_t)((uint32_t)(w >> 32) ^ 0x80000000u); }
 __device__ __forceinline__ uint32_t pair_pos(uint64_t w) { return (uint32_t)w; }
 
+// Stable 64-bit key + payload sorts: a 128-bit word (sign-flipped key, then
+// position), compared lexicographically -- the same strict order.
+struct W128 {
+    uint64_t lo;  // position
+    uint64_t hi;  // key ^ 2^63 (unsigned order = signed key order)
+};
+__device__ __forceinline__ bool operator<(const W128& a, const W128& b) {
+    return a.hi < b.hi || (a.hi == b.hi && a.lo < b.lo);
+}
+__device__ __forceinline__ W128 pair_word(int64_t k, uint32_t pos) {
+    return W128{(uint64_t)pos, (uint64_t)k ^ 0x8000000000000000ull};
+}
+__device__ __forceinline__ int64_t pair_key(const W128& w) { return (int64_t)(w.hi ^ 0x8000000000000000ull); }
+__device__ __forceinline__ uint32_t pair_pos(const W128& w) { return (uint32_t)w.lo; }
+
+// Keeps a loaded word live and unconditional (see lds_corank).
+template <typename W>
+__device__ __forceinline__ void keep_word(W& x) {
+    if constexpr (sizeof(W) == 16) {
+        asm volatile("" : "+v"(x.lo), "+v"(x.hi));
+    } else {
+        asm volatile("" : "+v"(x));
+    }
+}
+
 template <typename W>
 struct WordMin;
 template <>
@@ -208,11 +237,31 @@ template <>
 struct WordMax<uint64_t> {
     static constexpr uint64_t v = ~0ull;
 };
+template <>
+struct WordMax<W128> {
+    static constexpr W128 v = {~0ull, ~0ull};
+};
+
+// c ? a : b for sort words; 16-byte words select field by field (a
+// conditional on two struct lvalues would select an address and move the
+// words to scratch memory).
+template <typename W>
+__device__ __forceinline__ W wsel(bool c, const W& a, const W& b) {
+    if constexpr (sizeof(W) == 16) {
+        W r;
+        r.lo = c ? a.lo : b.lo;
+        r.hi = c ? a.hi : b.hi;
+        return r;
+    } else {
+        return c ? a : b;
+    }
+}
 
 template <typename W>
 __device__ __forceinline__ void cas_up(W& a, W& b) {  // a <- min, b <- max
-    W lo = b < a ? b : a;
-    W hi = b < a ? a : b;
+    const bool sw = b < a;
+    const W lo = wsel(sw, b, a);
+    const W hi = wsel(sw, a, b);
     a = lo;
     b = hi;
 }
@@ -230,8 +279,9 @@ __device__ __forceinline__ int lds_pad(int i) {
 // a shift and one add-shift instruction.
 template <typename W>
 __device__ __forceinline__ W lds_at_padded(const W* words, int i) {
-    constexpr unsigned per_log2 = sizeof(W) == 8 ? 4 : 5;  // 128-byte pad period
-    constexpr unsigned size_log2 = sizeof(W) == 8 ? 3 : 2;
+    static_assert(sizeof(W) == 4 || sizeof(W) == 8 || sizeof(W) == 16, "4-, 8- or 16-byte words");
+    constexpr unsigned size_log2 = sizeof(W) == 16 ? 4 : sizeof(W) == 8 ? 3 : 2;
+    constexpr unsigned per_log2 = 7 - size_log2;  // 128-byte pad period
     const unsigned u = (unsigned)i;
     const unsigned off = (u + (u >> per_log2)) << size_log2;
     return *reinterpret_cast<const W*>(reinterpret_cast<const char*>(words) + off);
@@ -295,6 +345,8 @@ template <int MASK, typename W>
 __device__ __forceinline__ W lane_xor(W x) {
     if constexpr (sizeof(W) == 4) {
         return (W)lane_xor32<MASK>((int)x);
+    } else if constexpr (sizeof(W) == 16) {
+        return W{lane_xor<MASK>(x.lo), lane_xor<MASK>(x.hi)};
     } else {
         const uint64_t u = (uint64_t)x;
         const uint32_t lo = (uint32_t)lane_xor32<MASK>((int)(uint32_t)u);
@@ -334,8 +386,7 @@ __device__ __forceinline__ void lane_stage(W (&v)[VT], bool lower) {
 #pragma unroll
         for (int i = 0; i < VT; i++) {
             const bool lt = p[i] < v[i];
-            const W lo = lt ? p[i] : v[i], hi = lt ? v[i] : p[i];
-            v[i] = lower ? lo : hi;
+            v[i] = wsel(lt == lower, p[i], v[i]);  // lower: the smaller, else the larger
         }
     }
 }
@@ -406,7 +457,8 @@ __device__ __forceinline__ int lds_corank(const W* lds, int sa, int sb, int diag
         // both reads are used unconditionally: otherwise the compiler moves
         // them under a branch on m < hi, and every probe pays for the exec
         // mask bookkeeping in scalar instructions
-        asm volatile("" : "+v"(a), "+v"(b));
+        keep_word(a);
+        keep_word(b);
         pos = (m < hi && !(b < a)) ? pos + step : pos;
     }
     return pos;
@@ -425,7 +477,7 @@ __device__ __forceinline__ void lds_read_padded(const W* lds, int p0, W (&r)[VT]
 #pragma unroll
     for (int i = 0; i <= VT; i++) x[i] = base[i];
 #pragma unroll
-    for (int i = 0; i < VT; i++) r[i] = i >= cut ? x[i + 1] : x[i];
+    for (int i = 0; i < VT; i++) r[i] = wsel(i >= cut, x[i + 1], x[i]);
 }
 
 // The VT outputs that follow co-rank (ai, bi) of a merge: the VT smallest
@@ -438,7 +490,7 @@ __device__ __forceinline__ void lds_merge_window(const W* lds, int pa, int pb, W
     lds_read_padded<W, VT>(lds, pa, v);
     lds_read_padded<W, VT>(lds, pb, b);
 #pragma unroll
-    for (int i = 0; i < VT; i++) v[i] = b[VT - 1 - i] < v[i] ? b[VT - 1 - i] : v[i];
+    for (int i = 0; i < VT; i++) v[i] = wsel(b[VT - 1 - i] < v[i], b[VT - 1 - i], v[i]);
     bitonic_merge<W, VT>(v);
 }
 

@@ -40,6 +40,10 @@ template <>
 struct WordOf<int32_t, true> {
     using type = uint64_t;
 };
+template <>
+struct WordOf<int64_t, true> {
+    using type = W128;
+};
 
 template <typename K, bool PAIRS>
 __device__ __forceinline__ typename WordOf<K, PAIRS>::type make_word(K k, int q) {
@@ -160,7 +164,7 @@ __device__ __forceinline__ void gather_merge(const W* words, int a0, int b0, int
         int idx = from_a ? (a0 + ai + i) : (b0 + bi + (VT - 1 - i));
         idx = sentinel ? a0 : idx;
         W val = lds_at_padded(words, idx);
-        v[i] = sentinel ? WordMax<W>::v : val;
+        v[i] = wsel(sentinel, WordMax<W>::v, val);
     }
     bitonic_merge<W, VT>(v);
 }
@@ -210,7 +214,12 @@ __device__ __forceinline__ void block_sort_levels(W* words, int* sp, W (&v)[VT],
 // 32-bit words, 32) lanes (lane permutations, in registers), then the
 // remaining merge levels in LDS, fully unrolled.  Result in blocked layout
 // (thread t holds outputs t*VT .. t*VT+VT-1, also in LDS).
-template <typename W, int NT, int VT>
+//
+// BU (the alternative local sort, the non-recursive merge sort of Figure 1b
+// as it stands): each thread sorts its VT words (VT = 2: the pairs of the
+// figure's first step), then every merge level runs in LDS, bottom up from
+// runs of VT, with no lane merges.
+template <typename W, int NT, int VT, bool BU = false>
 __device__ __forceinline__ void block_sort(W* words, int* sp) {
     static_assert((128 / (int)sizeof(W)) % VT == 0, "a VT-run must not straddle a pad word");
     static_assert(NT >= 32, "lane merges need groups of 32 threads");
@@ -220,6 +229,14 @@ __device__ __forceinline__ void block_sort(W* words, int* sp) {
 #pragma unroll
     for (int i = 0; i < VT; i++) v[i] = words[base + i];
     register_sort<W, VT>(v);
+    if constexpr (BU) {
+        block_sort_levels<W, NT, VT, VT>(words, sp, v, tid, base);
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < VT; i++) words[base + i] = v[i];
+        __syncthreads();
+        return;
+    }
     lane_merge<W, VT, 2>(v, tid);
     lane_merge<W, VT, 4>(v, tid);
     lane_merge<W, VT, 8>(v, tid);
@@ -316,7 +333,8 @@ __device__ __forceinline__ void block_minmax(T& mn, T& mx, T* rmn, T* rmx) {
 
 // Per tile: min and max, and the bucket counts under the tile's own digit
 // plan when the tile holds no negative key (beta 0, p the largest power of
-// ten not above the tile's max).  If the segment's plan has beta 0 as well,
+// ten not above the tile's max; images of unsigned keys always, with their
+// fixed beta).  If the segment's plan has beta 0 as well,
 // it has the same p or a larger one, so the histogram pass only has to fix
 // the tiles whose p is smaller (every key then has digit 0) instead of
 // reading the keys again.  Keys are read strided (thread t: t, t + NT, ...),
@@ -366,11 +384,11 @@ __global__ __launch_bounds__(kHistNT) void k_range(Work<K> w) {
         w.tmin[t] = mn;
         w.tmax[t] = mx;
     }
-    if (mn < 0) {
+    if (mn < 0 && !w.ufix) {
         if (tid == 0) w.tp[t] = 0;
         return;
     }
-    const DigitPlan<K> pl = make_digit_plan<K>(K(0), mx);
+    const DigitPlan<K> pl = make_digit_plan<K>(K(0), mx, w.ufix);
     if constexpr (NBK == 10) {
         uint64_t c = 0;  // at most kHistVT = 16 keys per thread: fits the 5-bit fields
 #pragma unroll
@@ -409,7 +427,7 @@ __global__ __launch_bounds__(1024) void k_plans(Work<K> w) {
             mx = b > mx ? b : mx;
         }
         block_minmax<K, 1024>(mn, mx, rmn, rmx);
-        if (threadIdx.x == 0) w.plans[s] = make_digit_plan<K>(mn, mx);
+        if (threadIdx.x == 0) w.plans[s] = make_digit_plan<K>(mn, mx, w.ufix);
     }
 }
 
@@ -447,7 +465,7 @@ __global__ __launch_bounds__(kHistNT) void k_hist(Work<K> w, int64_t tiles_bound
                 // at most a hundredth of the segment's; at a tenth the keys
                 // are counted again.
                 const uint64_t ps = plan_p(pl);
-                const bool own = pl.beta == 0 && tp != 0;
+                const bool own = (w.ufix || pl.beta == 0) && tp != 0;
                 if (own && tp != ps && (NBK == 10 || tp <= ps / 100)) {
                     uint32_t* out = w.counts + NBK * (t - td.idx) + td.idx;
                     out[0] = (uint32_t)td.cnt;
@@ -746,7 +764,7 @@ __device__ __forceinline__ void store_block_samples(const Work<K>& w, int64_t sb
 // merge rounds is written to the caller's buffer when P is even and to the
 // scratch copy when P is odd, so that its last round lands in the caller's
 // buffer with no final copy.
-template <typename K, bool PAIRS, int NT, int VT>
+template <typename K, bool PAIRS, int NT, int VT, bool BU>
 __global__ __launch_bounds__(NT) void k_tilesort(Work<K> w) {
     using W = typename WordOf<K, PAIRS>::type;
     constexpr int NV = NT * VT;
@@ -763,32 +781,34 @@ __global__ __launch_bounds__(NT) void k_tilesort(Work<K> w) {
         uint32_t* dv = PAIRS ? ((sd.odd & 1) ? w.svals : w.vals) + start : nullptr;
         const K* srck = w.skeys + start;
         const uint32_t* srcv = PAIRS ? w.svals + start : nullptr;
-        if constexpr (PAIRS && sizeof(K) == 4) {
-            // Every key of the partition has its bucket's digit d, so
-            // u - d*p (u = k - beta) lies in [0, p).  When p fits next to the
-            // key's index in 32 bits the sort runs on words
-            // (u - d*p) << POS | q: the same strict order as the 64-bit
-            // words, half the LDS traffic and cheaper compares.
+        if constexpr (PAIRS) {
+            // Every key of the partition lies in its bucket's span, so
+            // u - lo (u = k - beta) lies in [0, width).  When width fits next
+            // to the key's index in a word of the key's width, the sort runs
+            // on words (u - lo) << POS | q: the same strict order as the wide
+            // composite words, half the LDS traffic and cheaper compares.
             using U = typename Traits<K>::U;
+            using NW = U;
+            constexpr int BITS = 8 * (int)sizeof(NW);
             constexpr int POS = NV <= 4096 ? 12 : 13;
             static_assert(NV <= (1 << POS), "indices fit the narrow word");
             const DigitPlan<K> pl = w.plans[sd.bucket / w.nbk];
             uint64_t lo, width;
             bucket_span(pl, w.nbk, sd.bucket % w.nbk, lo, width);
-            if (width - 1 <= (uint64_t(1) << (32 - POS)) - 2) {
+            if (width - 1 <= (uint64_t(1) << (BITS - POS)) - 2) {
                 const U base = pl.beta + (U)lo;
-                uint32_t* w32 = reinterpret_cast<uint32_t*>(words);
+                NW* wn = reinterpret_cast<NW*>(words);
                 load_run<K, NT, NV>(srck, cnt, [&](int q, K k) {
-                    w32[lds_pad<uint32_t>(q)] = ((uint32_t)((U)k - base) << POS) | (uint32_t)q;
+                    wn[lds_pad<NW>(q)] = ((NW)((U)k - base) << POS) | (NW)q;
                 });
                 load_run<uint32_t, NT, NV>(srcv, cnt, [&](int q, uint32_t v) { sv[q] = v; });
-                for (int q = cnt + tid; q < NV; q += NT) w32[lds_pad<uint32_t>(q)] = WordMax<uint32_t>::v;
+                for (int q = cnt + tid; q < NV; q += NT) wn[lds_pad<NW>(q)] = WordMax<NW>::v;
                 __syncthreads();
-                block_sort<uint32_t, NT, VT>(w32, sp);
-                auto key_at = [&](int q) { return (K)((U)(lds_at_padded(w32, q) >> POS) + base); };
+                block_sort<NW, NT, VT, BU>(wn, sp);
+                auto key_at = [&](int q) { return (K)((U)(lds_at_padded(wn, q) >> POS) + base); };
                 store_keys<K, NT, NV>(dk, cnt, key_at);
-                store_run<uint32_t, NT, NV>(dv, cnt,
-                                            [&](int q) { return sv[lds_at_padded(w32, q) & ((1u << POS) - 1)]; });
+                store_run<uint32_t, NT, NV>(
+                    dv, cnt, [&](int q) { return sv[(uint32_t)lds_at_padded(wn, q) & ((1u << POS) - 1)]; });
                 if (w.fanin == 4) store_block_samples<K, NT>(w, sd.sbase, cnt, !(sd.odd & 2), key_at);
                 return;
             }
@@ -799,7 +819,7 @@ __global__ __launch_bounds__(NT) void k_tilesort(Work<K> w) {
             for (int q = cnt + tid; q < NV; q += NT) words[lds_pad<W>(q)] = WordMax<W>::v;
         }
         __syncthreads();
-        block_sort<W, NT, VT>(words, sp);
+        block_sort<W, NT, VT, BU>(words, sp);
         auto key_at = [&](int q) { return word_key<K, PAIRS>(lds_at_padded(words, q)); };
         store_keys<K, NT, NV>(dk, cnt, key_at);
         if constexpr (PAIRS)
@@ -1245,16 +1265,18 @@ __device__ __forceinline__ void merge4_chunk(W* words, const uint32_t* sv, const
     store_chunk_samples<NT>(g, c, [&](int q) { return key_of(lds_at_padded(words, q)); });
 }
 
-// Stable pairs whose chunk spans fewer than 2^19 - 1 key values (the keys of
-// each window lie between its first and last; both are read by every lane)
-// merge 32-bit words ((key - kmin) << 13 | q) instead of 64-bit ones: the
-// same strict order (key, then index q < 2^13 in the concatenated windows),
-// half the LDS traffic and far fewer VALU operations per compare.  The
-// largest word stays below the all-ones sentinel.
+// Stable pairs whose chunk spans fewer than 2^(w-13) - 1 key values (w the
+// key's width; the keys of each window lie between its first and last, both
+// read by every lane) merge words of the key's width ((key - kmin) << 13 |
+// q) instead of the wide composite ones: the same strict order (key, then
+// index q < 2^13 in the concatenated windows), half the LDS traffic and far
+// fewer VALU operations per compare.  The largest word stays below the
+// all-ones sentinel.
 constexpr int kNarrowPosBits = 13;
-constexpr int64_t kNarrowSpan = (int64_t(1) << (32 - kNarrowPosBits)) - 2;
 template <typename K>
 __device__ __forceinline__ bool narrow_chunk(const Chunk4<K>& g, K& kmin) {
+    using U = typename Traits<K>::U;
+    constexpr U span = (U(1) << (8 * sizeof(K) - kNarrowPosBits)) - 2;
     K lo = Traits<K>::kMax, hi = Traits<K>::kMin;
 #pragma unroll
     for (int r = 0; r < 4; r++) {
@@ -1265,7 +1287,7 @@ __device__ __forceinline__ bool narrow_chunk(const Chunk4<K>& g, K& kmin) {
         }
     }
     kmin = lo;
-    return (int64_t)hi - (int64_t)lo <= kNarrowSpan;
+    return hi >= lo && (U)hi - (U)lo <= span;
 }
 
 // One workgroup per chunk.
@@ -1277,25 +1299,26 @@ __global__ __launch_bounds__(NT) void k_merge4(Work<K> w, int round, int64_t bou
     if (!g.active) return;
     Merge4Loads<K, PAIRS, NT, VT, JOBS> ld;
     ld.issue(g);
-    if constexpr (PAIRS && sizeof(K) == 4) {
+    if constexpr (PAIRS) {
+        using U = typename Traits<K>::U;
         static_assert(NT * VT * JOBS <= (1 << kNarrowPosBits), "window indices fit the narrow word");
         K kmin;
         const bool narrow = narrow_chunk(g, kmin);  // the same on every lane
         if (narrow) {
-            uint32_t* words = reinterpret_cast<uint32_t*>(sm.words);
-            stage4<uint32_t>(words, sm.sv, ld, g,
-                             [=](int q, K k) { return ((uint32_t)(k - kmin) << kNarrowPosBits) | (uint32_t)q; });
+            U* words = reinterpret_cast<U*>(sm.words);
+            stage4<U>(words, sm.sv, ld, g,
+                      [=](int q, K k) { return ((U)((U)k - (U)kmin) << kNarrowPosBits) | (U)q; });
             __syncthreads();
-            merge4_chunk<uint32_t, K, PAIRS, NT, VT, JOBS>(
-                words, sm.sv, g, [=](uint32_t x) { return (K)(kmin + (K)(x >> kNarrowPosBits)); },
-                [](uint32_t x) { return x & ((1u << kNarrowPosBits) - 1); });
+            merge4_chunk<U, K, PAIRS, NT, VT, JOBS>(
+                words, sm.sv, g, [=](U x) { return (K)((U)kmin + (x >> kNarrowPosBits)); },
+                [](U x) { return (uint32_t)x & ((1u << kNarrowPosBits) - 1); });
             return;
         }
     }
     stage4<W>(sm.words, sm.sv, ld, g, [](int q, K k) { return make_word<K, PAIRS>(k, q); });
     __syncthreads();
     merge4_chunk<W, K, PAIRS, NT, VT, JOBS>(sm.words, sm.sv, g, [](W x) { return word_key<K, PAIRS>(x); },
-                                           [](W x) { return pair_pos((uint64_t)x); });
+                                           [](W x) { return pair_pos(x); });
 }
 
 // --------------------------------------------------------- small segments
@@ -1339,7 +1362,7 @@ __global__ __launch_bounds__(NT) void k_small(Work<K> w, int64_t lo, int64_t hi)
         if (m > 0) {
             const K mn = word_key<K, PAIRS>(lds_at_padded(words, 0));
             const K mx = word_key<K, PAIRS>(lds_at_padded(words, m - 1));
-            const DigitPlan<K> pl = make_digit_plan<K>(mn, mx);
+            const DigitPlan<K> pl = make_digit_plan<K>(mn, mx, w.ufix);
 #pragma unroll
             for (int v = 0; v < VT; v++) {
                 const int q = tid * VT + v;
@@ -1378,6 +1401,46 @@ __global__ void k_collect(Work<K> w, int stage) {
             if (w.vals) w.vals[st + q] = w.svals[st + q];
         }
     }
+}
+
+// ------------------------------------------------------- other key types
+// Keys of other types are sorted through a signed-integer image of the same
+// width whose order is the order asked for (the same order-preserving maps
+// the oracle writes out from each type's definition):
+//   unsigned: flip the sign bit (x + type minimum);
+//   IEEE-754 float: flip the magnitude bits of negative values (the
+//     standard's total order: -NaN < -inf < ... < -0 < +0 < ... < +NaN);
+//   descending: the bitwise complement of the image (-1 - image).
+// Forward before the pipeline, inverse after it, in place; both are
+// involutions of the caller's bits.
+template <typename K>
+__device__ __forceinline__ K image_of(K x, int mode, bool inverse) {
+    constexpr K sign = Traits<K>::kMin;
+    if (inverse && (mode & kImgDesc)) x = ~x;
+    if (mode & kImgUnsigned) x ^= sign;
+    if (mode & kImgFloat) x ^= (x >> (8 * sizeof(K) - 1)) & ~sign;  // arithmetic shift: all ones when negative
+    if (!inverse && (mode & kImgDesc)) x = ~x;
+    return x;
+}
+
+template <typename K>
+__global__ __launch_bounds__(256) void k_image(K* keys, int64_t n, int mode, int inverse) {
+    using V = typename Vec16<K>::type;
+    constexpr int E = Vec16<K>::n;
+    const int h = head_len(keys, (int)(n < 16 ? n : 16));
+    const int64_t body = (n - h) / E;
+    const int64_t tail = h + body * E;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, stride = (int64_t)gridDim.x * blockDim.x;
+    V* vs = reinterpret_cast<V*>(keys + h);
+    for (int64_t i = tid; i < body; i += stride) {
+        V x = vs[i];
+        K* e = reinterpret_cast<K*>(&x);
+#pragma unroll
+        for (int j = 0; j < E; j++) e[j] = image_of(e[j], mode, inverse != 0);
+        vs[i] = x;
+    }
+    if (tid < h) keys[tid] = image_of(keys[tid], mode, inverse != 0);
+    if (tail + tid < n) keys[tail + tid] = image_of(keys[tail + tid], mode, inverse != 0);
 }
 
 // ------------------------------------------------------------ device scan
@@ -1563,9 +1626,9 @@ hipError_t launch_scatter(const Work<K>& w, int64_t tiles_bound, hipStream_t st)
     return hipGetLastError();
 }
 
-template <typename K, bool PAIRS, int NT, int VT>
+template <typename K, bool PAIRS, int NT, int VT, bool BU>
 hipError_t launch_tilesort(const Work<K>& w, int64_t items_bound, hipStream_t st) {
-    k_tilesort<K, PAIRS, NT, VT><<<grid_of(items_bound), NT, 0, st>>>(w);
+    k_tilesort<K, PAIRS, NT, VT, BU><<<grid_of(items_bound), NT, 0, st>>>(w);
     return hipGetLastError();
 }
 
@@ -1618,6 +1681,15 @@ hipError_t launch_collect(const Work<K>& w, int stage, hipStream_t st) {
     return hipGetLastError();
 }
 
+template <typename K>
+hipError_t launch_image(K* keys, int64_t n, int mode, bool inverse, hipStream_t st) {
+    if (n <= 0 || mode == 0) return hipSuccess;
+    const int64_t vecs = n / Vec16<K>::n + 1;
+    const int g = (int)min((int64_t)8 * cu_count(), (vecs + 255) / 256);
+    k_image<K><<<g < 1 ? 1 : g, 256, 0, st>>>(keys, n, mode, inverse ? 1 : 0);
+    return hipGetLastError();
+}
+
 hipError_t launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t st) {
     const int64_t n16 = bytes / 16;
     k_copy<<<4 * cu_count(), 256, 0, st>>>((const uint4*)src, (uint4*)dst, n16);
@@ -1635,17 +1707,22 @@ hipError_t launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t st
     template hipError_t launch_tiles<K>(const Work<K>&, int64_t, hipStream_t);           \
     template hipError_t launch_sdesc<K>(const Work<K>&, int64_t, hipStream_t);           \
     template hipError_t launch_part4<K>(const Work<K>&, int, int64_t, hipStream_t);      \
-    template hipError_t launch_collect<K>(const Work<K>&, int, hipStream_t);
+    template hipError_t launch_collect<K>(const Work<K>&, int, hipStream_t);                \
+    template hipError_t launch_image<K>(K*, int64_t, int, bool, hipStream_t);
 HS_INST_K(int32_t)
 HS_INST_K(int64_t)
 
 template hipError_t launch_scatter<int32_t, false>(const Work<int32_t>&, int64_t, hipStream_t);
 template hipError_t launch_scatter<int32_t, true>(const Work<int32_t>&, int64_t, hipStream_t);
 template hipError_t launch_scatter<int64_t, false>(const Work<int64_t>&, int64_t, hipStream_t);
+template hipError_t launch_scatter<int64_t, true>(const Work<int64_t>&, int64_t, hipStream_t);
 
 #define HS_INST_TILE(K, PAIRS, NT, VT) \
-    template hipError_t launch_tilesort<K, PAIRS, NT, VT>(const Work<K>&, int64_t, hipStream_t);
+    template hipError_t launch_tilesort<K, PAIRS, NT, VT, false>(const Work<K>&, int64_t, hipStream_t);
 HS_TILE_VARIANTS(HS_INST_TILE)
+#define HS_INST_TILE_BU(K, PAIRS, NT, VT) \
+    template hipError_t launch_tilesort<K, PAIRS, NT, VT, true>(const Work<K>&, int64_t, hipStream_t);
+HS_TILE_BU_VARIANTS(HS_INST_TILE_BU)
 #define HS_INST_SMALL(K, PAIRS, NT, VT) \
     template hipError_t launch_small<K, PAIRS, NT, VT>(const Work<K>&, int64_t, int64_t, int64_t, hipStream_t);
 HS_SMALL_VARIANTS(HS_INST_SMALL)

@@ -121,12 +121,16 @@ struct Work {
     uint32_t* err;   // device-side validation flag (bad offsets)
 
     int32_t nbk;        // buckets per segment: 10 (one decimal digit) or 100 (two)
+    int32_t ufix;       // keys are images of unsigned keys: beta fixed at the type's minimum
     int32_t tile;       // keys per local-sort tile (T)
     int32_t fanin;      // runs merged per round: 2 or 4
     int32_t nv;         // outputs per merge workgroup (divides T)
     int64_t small_max;  // segments up to this size are sorted wholly in LDS
     int64_t max_seg_len;  // the caller's bound on the longest segment (merge rounds launched), 0 if none
 };
+
+// Order-image modes of other key types (bits; see k_image).
+constexpr int kImgUnsigned = 1, kImgFloat = 2, kImgDesc = 4;
 
 // Bits of the device-side error word (read by hsort_check).
 constexpr uint32_t kErrOffsets = 1;      // offsets decreasing or outside [0, n]

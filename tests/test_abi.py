@@ -97,7 +97,7 @@ def test_config_roundtrip(lib):
 
     assert [hs.hsort_size_class(n) for n in (1, 1 << 18, (1 << 18) + 1, 1 << 22, 1 << 26, 1 << 28)] == [0, 0, 1, 1, 2, 3]
     cfg = hs.hsort_get_config(hs.KEYS_I32, size_class=3)
-    t, tvt, m, mvt, s, fanin, digits = cfg
+    t, tvt, m, mvt, s, fanin, digits, local = cfg
     assert t % m == 0 and s <= 8192 and t % tvt == 0 and m % mvt == 0 and fanin in (2, 4) and digits in (1, 2)
     with pytest.raises(hs.HsortError):
         hs.hsort_set_config(hs.KEYS_I32, 1000, 16, 4096, 16, 100)
@@ -108,8 +108,14 @@ def test_config_roundtrip(lib):
     with pytest.raises(hs.HsortError):  # digits must be 1 or 2
         hs.hsort_set_config(hs.KEYS_I32, t, tvt, m, mvt, s, fanin=fanin, digits=3, size_class=3)
     hs.hsort_set_config(hs.KEYS_I32, t, tvt, m, mvt, s, fanin=4, digits=3 - digits, size_class=3)
-    assert hs.hsort_get_config(hs.KEYS_I32, size_class=3)[5:] == (4, 3 - digits)
-    hs.hsort_set_config(hs.KEYS_I32, *cfg[:5], fanin=cfg[5], digits=cfg[6], size_class=3)
+    assert hs.hsort_get_config(hs.KEYS_I32, size_class=3)[5:] == (4, 3 - digits, local)
+    with pytest.raises(hs.HsortError):  # local must be 0 or 1
+        hs.hsort_set_config(hs.KEYS_I32, t, tvt, m, mvt, s, fanin=fanin, local=2, size_class=3)
+    with pytest.raises(hs.HsortError):  # no bottom-up local sort of this shape
+        hs.hsort_set_config(hs.KEYS_I32, 16384, 32, m, mvt, s, fanin=fanin, local=1, size_class=3)
+    hs.hsort_set_config(hs.KEYS_I32, 2048, 2, 2048, 16, s, fanin=4, local=1, size_class=3)
+    assert hs.hsort_get_config(hs.KEYS_I32, size_class=3)[7] == 1
+    hs.hsort_set_config(hs.KEYS_I32, *cfg[:5], fanin=cfg[5], digits=cfg[6], local=cfg[7], size_class=3)
     assert hs.hsort_get_config(hs.KEYS_I32, size_class=3) == cfg
 
 
@@ -121,8 +127,8 @@ def test_tuning_file(lib, tmp_path):
     f.write_text("# kind class tile tile_vt merge_nv merge_vt small_max fanin [digits]\n"
                  "1 2 8192 16 4096 16 2048 4\n1 3 8192 16 4096 16 2048 4 2\n")
     hs.hsort_load_tuning(str(f))
-    assert hs.hsort_get_config(hs.KEYS_I64, size_class=2) == (8192, 16, 4096, 16, 2048, 4, 1)
-    assert hs.hsort_get_config(hs.KEYS_I64, size_class=3) == (8192, 16, 4096, 16, 2048, 4, 2)
+    assert hs.hsort_get_config(hs.KEYS_I64, size_class=2) == (8192, 16, 4096, 16, 2048, 4, 1, 0)
+    assert hs.hsort_get_config(hs.KEYS_I64, size_class=3) == (8192, 16, 4096, 16, 2048, 4, 2, 0)
     assert hs.hsort_get_config(hs.KEYS_I64, size_class=1) == before[1]
     f.write_text("1 2 8192 16 4096 16 2048 4 5\n")
     with pytest.raises(hs.HsortError):
@@ -131,7 +137,7 @@ def test_tuning_file(lib, tmp_path):
     with pytest.raises(hs.HsortError):
         hs.hsort_load_tuning(str(f))
     for c, cfg in enumerate(before):
-        hs.hsort_set_config(hs.KEYS_I64, *cfg[:5], fanin=cfg[5], digits=cfg[6], size_class=c)
+        hs.hsort_set_config(hs.KEYS_I64, *cfg[:5], fanin=cfg[5], digits=cfg[6], local=cfg[7], size_class=c)
 
 
 def test_noalloc_argument_errors(lib):
@@ -147,3 +153,19 @@ def test_noalloc_argument_errors(lib):
     assert lib.hsort_keys_i32_noalloc(None, 0, None) == hs.HSORT_OK
     # every size class's tuned shapes fit the array at the largest size
     assert hs.scratch_bytes(hs.KEYS_I32, hs.NOALLOC_MAX_KEYS) <= 24 << 20
+
+
+def test_typed_sort_argument_errors(lib):
+    import paper_2003_01216_amd as hs
+
+    assert lib.hsort_sort(None, None, 10, 6, 0, None, 0, None) == hs.HSORT_ERR_INVALID  # unknown key type
+    assert lib.hsort_sort(None, None, 10, 0, 2, None, 0, None) == hs.HSORT_ERR_INVALID  # unknown flag
+    assert lib.hsort_sort(None, None, 10, hs.F32, hs.DESCENDING, None, 0, None) == hs.HSORT_ERR_INVALID  # null
+    assert lib.hsort_sort(None, None, 0, hs.U64, 0, None, 0, None) == hs.HSORT_OK
+    assert lib.hsort_debug_stage_typed(None, None, 10, hs.I32, 0, 4, None, 0, None) == hs.HSORT_ERR_INVALID
+    n = 1 << 20
+    assert hs.sort_scratch_bytes(hs.U32, False, n) == hs.scratch_bytes(hs.KEYS_I32, n)
+    assert hs.sort_scratch_bytes(hs.F64, False, n) == hs.scratch_bytes(hs.KEYS_I64, n)
+    assert hs.sort_scratch_bytes(hs.F32, True, n) == hs.scratch_bytes(hs.PAIRS_I32_U32, n)
+    assert hs.sort_scratch_bytes(hs.I64, True, n) == hs.scratch_bytes(hs.PAIRS_I64_U32, n) >= 12 * n
+    assert hs.sort_scratch_bytes(9, False, n) == 0

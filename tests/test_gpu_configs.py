@@ -29,7 +29,7 @@ def say(msg):
 
 
 def _cands(kind):
-    return [pytest.param(c, id="t{}x{}-m{}x{}-s{}-f{}-d{}".format(*c)) for c in autotune.candidates(kind)]
+    return [pytest.param(c, id="t{}x{}-m{}x{}-s{}-f{}-d{}-l{}".format(*c)) for c in autotune.candidates(kind)]
 
 
 def skew(keys, cfg, lo, width, seed):
@@ -49,15 +49,15 @@ def hs():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     hsmod.load_library()
-    saved = {(k, c): hsmod.hsort_get_config(k, size_class=c) for k in range(5) for c in range(4)}
+    saved = {(k, c): hsmod.hsort_get_config(k, size_class=c) for k in range(6) for c in range(4)}
     yield hsmod
     for (k, c), cfg in saved.items():
-        hsmod.hsort_set_config(k, *cfg[:5], fanin=cfg[5], digits=cfg[6], size_class=c)
+        hsmod.hsort_set_config(k, *cfg[:5], fanin=cfg[5], digits=cfg[6], local=cfg[7], size_class=c)
 
 
 def use(hs, kind, cfg):
     for c in range(4):
-        hs.hsort_set_config(kind, *cfg[:5], fanin=cfg[5], digits=cfg[6], size_class=c)
+        hs.hsort_set_config(kind, *cfg[:5], fanin=cfg[5], digits=cfg[6], local=cfg[7], size_class=c)
 
 
 def dev(a):
@@ -120,6 +120,32 @@ def test_pairs(hs, orc, cfg, span):
     hs.hsort_pairs(t, tv, scratch=s)
     hs.hsort_check(s)
     ok, ov = orc.sort_pairs(k, v)
+    assert np.array_equal(t.cpu().numpy(), ok)
+    assert np.array_equal(tv.cpu().numpy().view(np.uint32), ov)
+
+
+@pytest.mark.parametrize("span", ["dup", "full"])
+@pytest.mark.parametrize("cfg", _cands(hsmod.PAIRS_I64_U32))
+def test_pairs_i64(hs, orc, cfg, span):
+    # "dup": keys in [0, 1000) (narrow 8-byte words); "full": the whole int64
+    # range (16-byte words)
+    r = np.random.default_rng(cfg[0] + cfg[2] + 13)
+    if span == "dup":
+        n = 45 * cfg[0] + RAGGED
+        k = r.integers(0, 1000, n).astype(np.int64)
+        k = skew(k, cfg, 0, 10, n)
+    else:
+        n = 18 * cfg[0] + RAGGED
+        k = r.integers(I64.min, I64.max, n, dtype=np.int64, endpoint=True)
+        k = skew(k, cfg, int(I64.min), 10**18, n)
+    v = r.integers(0, 2**32 - 1, n, dtype=np.uint32, endpoint=True)
+    say(f"config pairs_i64 {span} {cfg} n={n}")
+    use(hs, hs.PAIRS_I64_U32, cfg)
+    t, tv = dev(k), dev(v.view(np.int32))
+    s = scratch(hs, hs.PAIRS_I64_U32, n)
+    hs.hsort_sort(t, tv, scratch=s)
+    hs.hsort_check(s)
+    ok, ov = orc.sort_typed(k, v)
     assert np.array_equal(t.cpu().numpy(), ok)
     assert np.array_equal(tv.cpu().numpy().view(np.uint32), ov)
 

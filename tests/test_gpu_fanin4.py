@@ -31,13 +31,14 @@ def hs4(request):
 
     hs.load_library()
     nv, vt = request.param
+    # kinds 0-4 (int64 pairs have 16-byte words and their own shapes, covered by test_gpu_configs)
     saved = {(k, c): hs.hsort_get_config(k, size_class=c) for k in range(5) for c in range(4)}
     for (k, c), cfg in saved.items():
-        hs.hsort_set_config(k, cfg[0], cfg[1], nv, vt, cfg[4], fanin=4, digits=cfg[6], size_class=c)
+        hs.hsort_set_config(k, cfg[0], cfg[1], nv, vt, cfg[4], fanin=4, digits=cfg[6], local=cfg[7], size_class=c)
     say(f"fanin4 shape S={nv} VT={vt}")
     yield hs
     for (k, c), cfg in saved.items():
-        hs.hsort_set_config(k, *cfg[:5], fanin=cfg[5], digits=cfg[6], size_class=c)
+        hs.hsort_set_config(k, *cfg[:5], fanin=cfg[5], digits=cfg[6], local=cfg[7], size_class=c)
 
 
 def dev(a):

@@ -31,13 +31,13 @@ def hs():
     import paper_2003_01216_amd as hs
 
     hs.load_library()
-    saved = {(k, c): hs.hsort_get_config(k, size_class=c) for k in range(5) for c in range(4)}
+    saved = {(k, c): hs.hsort_get_config(k, size_class=c) for k in range(6) for c in range(4)}
     for (k, c), cfg in saved.items():
-        hs.hsort_set_config(k, *cfg[:5], fanin=cfg[5], digits=2, size_class=c)
+        hs.hsort_set_config(k, *cfg[:5], fanin=cfg[5], digits=2, local=cfg[7], size_class=c)
     print("two-digit partition on every kind", flush=True)
     yield hs
     for (k, c), cfg in saved.items():
-        hs.hsort_set_config(k, *cfg[:5], fanin=cfg[5], digits=cfg[6], size_class=c)
+        hs.hsort_set_config(k, *cfg[:5], fanin=cfg[5], digits=cfg[6], local=cfg[7], size_class=c)
 
 
 def say(msg):

@@ -13,6 +13,9 @@ the workloads the hot path is measured on:
 * ``segments_i32``  16384 arrays, sizes log-uniform in [1, 2^16]  (batched)
 * ``request_stream`` Poisson arrivals of int64 arrays, sizes log-uniform in
   [2^10, 2^24], keys uniform over the full int64 range          (serving)
+* ``typed_keys``    keys of the other supported types (uint32/uint64, float32/
+  float64 with NaNs, infinities, signed zeros and subnormals mixed in, and
+  int32/int64 with their extremes), with duplicates
 
 All use numpy's PCG64 ``default_rng(seed)``.
 """
@@ -108,3 +111,26 @@ def adversarial_i32(T: int = 8192):
     cases["loguniform"] = loguniform_i32(n, 3)
     cases["sawtooth"] = (np.arange(n, dtype=np.int64) % 1000).astype(np.int32)
     return cases
+
+
+def typed_keys(dtype, n: int, seed: int = 0) -> np.ndarray:
+    """Keys of `dtype` (any of int32/uint32/float32/int64/uint64/float64): a
+    fifth special values (extremes; for floats also NaN of both signs, the
+    infinities, both zeros and the smallest subnormals), a third small
+    values (duplicates), the rest over the type's whole range (floats:
+    normal values of every magnitude)."""
+    dt = np.dtype(dtype)
+    rng = np.random.default_rng(seed)
+    if dt.kind == "f":
+        fi = np.finfo(dt)
+        special = np.array([0.0, -0.0, np.inf, -np.inf, np.nan, -np.nan, 1.0, -1.0, fi.tiny, -fi.tiny, fi.max,
+                            -fi.max, fi.smallest_subnormal, -fi.smallest_subnormal], dt)
+        body = (rng.standard_normal(n) * 10.0 ** rng.integers(fi.minexp // 4, fi.maxexp // 4, n)).astype(dt)
+        small = rng.integers(-20, 20, n).astype(dt)
+    else:
+        ii = np.iinfo(dt)
+        special = np.array([ii.min, ii.max, 0, 1, ii.max - 1, ii.min + 1], dt)
+        body = rng.integers(ii.min, ii.max, n, dtype=dt, endpoint=True)
+        small = rng.integers(0, 40, n).astype(dt)
+    pick = rng.random(n)
+    return np.where(pick < 0.2, rng.choice(special, n), np.where(pick < 0.55, small, body)).astype(dt)
