@@ -157,6 +157,25 @@ def bench_keys(hs, torch, k, steps, warmup):
     return k.size * steps / (ms * 1e-3) / 1e9, kernel_table(rec, steps)
 
 
+def bench_typed(hs, torch, k, vals, desc, steps, warmup):
+    """hsort_sort on keys of any supported dtype (bits moved as a signed tensor of the same width)."""
+    kt = {np.dtype(np.int32): hs.I32, np.dtype(np.uint32): hs.U32, np.dtype(np.float32): hs.F32,
+          np.dtype(np.int64): hs.I64, np.dtype(np.uint64): hs.U64, np.dtype(np.float64): hs.F64}[k.dtype]
+    base = torch.from_numpy(k.view(np.int32 if k.dtype.itemsize == 4 else np.int64)).cuda()
+    bv = None if vals is None else torch.from_numpy(vals.view(np.int32)).cuda()
+    scratch = torch.empty(hs.sort_scratch_bytes(kt, vals is not None, k.size), dtype=torch.uint8, device="cuda")
+
+    def make(m):
+        return [(base.clone(), None if bv is None else bv.clone()) for _ in range(m)]
+
+    ms, rec, copies = timed_sorts(hs, torch, make,
+                                  lambda kv: hs.hsort_sort(kv[0], kv[1], descending=desc, key_type=kt, scratch=scratch),
+                                  steps, warmup)
+    del copies
+    torch.cuda.empty_cache()
+    return round(k.size * steps / (ms * 1e-3) / 1e9, 3), kernel_table(rec, steps)
+
+
 def bench_small_keys(hs, torch, n, steps=50, warmup=5):
     """n uniform int32 keys (seed 0): per-call time of the plain sort, eager and replayed from a hipGraph,
     refilling the same buffer from a resident copy outside the timed window before every call."""
@@ -283,11 +302,12 @@ def bench_segmented(hs, torch, steps, warmup, loop=True):
     return out
 
 
-def bench_serving(count=1000, budget=64 << 30, small_budget=1 << 30, streams=3, load=0.7):
+def bench_serving(count=1000, budget=64 << 30, small_budget=384 << 20, streams=3, load=0.7):
     """Poisson stream of int64 sort requests (sizes log-uniform in [2^10, 2^24], keys over the full int64
     range) through the continuous-batching server with a 64 GiB HBM budget.  The arrival rate is `load` times
     the saturation rate measured first with every request submitted at once.  The same arrivals are then
-    replayed against a 1 GiB budget, under which admission has to wait for memory."""
+    replayed against a 384 MiB budget (the largest request needs 270 MiB with its scratch), under which two
+    large requests cannot be in flight together and admission has to wait for memory."""
     import threading
 
     import paper_2003_01216_amd.serve as serve
@@ -383,8 +403,8 @@ def main():
     ap.add_argument("--log2n", type=int, default=28, help="keys in the metric workload (2^log2n)")
     ap.add_argument("--no-extras", action="store_true", help="only the metric workload")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--extras", default="small,pairs,keys,segmented,serving",
-                    help="comma list of the extra workloads to run: small, pairs, keys, segmented, serving")
+    ap.add_argument("--extras", default="small,pairs,keys,typed,segmented,serving",
+                    help="comma list of the extra workloads to run: small, pairs, keys, typed, segmented, serving")
     ap.add_argument("--no-loop", action="store_true", help="segmented: skip the per-array loop of plain calls")
     args = ap.parse_args()
 
@@ -394,10 +414,10 @@ def main():
               "the sort runs on one GPU (no multi-GPU path)", file=sys.stderr)
         sys.exit(2)
     extras = set() if args.no_extras else {e.strip() for e in args.extras.split(",") if e.strip()}
-    unknown = extras - {"small", "pairs", "keys", "segmented", "serving"}
+    unknown = extras - {"small", "pairs", "keys", "typed", "segmented", "serving"}
     if unknown:
         print(f"bench.py: unknown extra workloads {sorted(unknown)} "
-              "(choose from small, pairs, keys, segmented, serving)", file=sys.stderr)
+              "(choose from small, pairs, keys, typed, segmented, serving)", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -455,6 +475,16 @@ def main():
         extra["uniform_2e26_Gkeys_s"] = round(bench_keys(hs, torch, W.uniform_i32(2**26, 0), 10, 2)[0], 3)
         extra["loguniform_2e26_Gkeys_s"] = round(bench_keys(hs, torch, W.loguniform_i32(2**26, 0), 10, 2)[0], 3)
         extra["int64_full_range_2e26_Gkeys_s"] = round(bench_keys(hs, torch, W.uniform_i64(2**26, 0), 10, 2)[0], 3)
+    if "typed" in extras:
+        log("[bench] other key types: float32 2^28, int32 descending 2^28, int64 + payload 2^26")
+        r = np.random.default_rng(0)
+        f32 = (r.standard_normal(2**28, dtype=np.float32) * np.float32(1e3))
+        extra["float32_2e28_Gkeys_s"], _ = bench_typed(hs, torch, f32, None, False, 5, 1)
+        del f32
+        extra["int32_descending_2e28_Gkeys_s"], _ = bench_typed(hs, torch, W.uniform_i32(2**28, 0), None, True, 5, 1)
+        k64 = W.uniform_i64(2**26, 0)
+        extra["int64_pairs_2e26_Gkeys_s"], extra["int64_pairs_kernels"] = bench_typed(
+            hs, torch, k64, np.arange(2**26, dtype=np.uint32), False, 5, 1)
     if "segmented" in extras:
         log("[bench] batched segmented" + ("" if args.no_loop else " vs per-array loop"))
         extra["segmented"] = bench_segmented(hs, torch, 10, 2, loop=not args.no_loop)

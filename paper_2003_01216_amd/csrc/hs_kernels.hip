@@ -967,7 +967,7 @@ __device__ __forceinline__ K elem_at_corank(const K* A, int64_t na, const K* B, 
 template <typename K>
 __global__ __launch_bounds__(256) void k_part4(Work<K> w, int round, int64_t bound) {
     const int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (item >= bound) return;
+    if (item >= bound || round >= *w.rounds) return;  // no bucket needs this round: k_merge4 skips it too
     const int nb = w.nbk * w.nseg;
     Split4 d{};
     if (!*w.err && round < *w.rounds && item < w.msp[nb]) {
@@ -1295,6 +1295,10 @@ template <typename K, bool PAIRS, int NT, int VT, int JOBS>
 __global__ __launch_bounds__(NT) void k_merge4(Work<K> w, int round, int64_t bound) {
     using W = typename WordOf<K, PAIRS>::type;
     __shared__ Merge4Lds<K, PAIRS, NT, VT, JOBS> sm;
+    // The host launches the rounds the whole array could need; a round no
+    // bucket needs ends here, on one word every workgroup reads (it stays in
+    // the scalar cache), before any descriptor is read.
+    if (round >= *w.rounds) return;
     const Chunk4<K> g = chunk4_of<K, PAIRS, NT * VT * JOBS / 2, VT>(w, round, blockIdx.x, bound);
     if (!g.active) return;
     Merge4Loads<K, PAIRS, NT, VT, JOBS> ld;
