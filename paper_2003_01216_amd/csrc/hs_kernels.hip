@@ -624,6 +624,9 @@ __device__ __forceinline__ void digit_pass(K* sk, uint32_t* sv, uint8_t* sd, uin
 // the first's order inside a digit) -- and runs of consecutive keys are
 // written to their buckets in the scratch copy.  The bucket of a staged key
 // travels with it in a byte array, so each key's bucket is computed once.
+// Keys-only sorts with one hundred buckets place the keys by LDS cursors
+// instead: their scatter is not stable (nothing of it can be seen in the
+// sorted result), pairs keep the stable passes.
 template <typename K, bool PAIRS, int NBK>
 __global__ __launch_bounds__(kHistNT) void k_scatter(Work<K> w) {
     constexpr int NT = kHistNT, VT = kHistVT, HT = kHistTile;
@@ -634,6 +637,9 @@ __global__ __launch_bounds__(kHistNT) void k_scatter(Work<K> w) {
     constexpr bool kOffsLds = sizeof(K) == 4 && !PAIRS;
     __shared__ int32_t dbase[NBK];  // element index (n < 2^31) of bucket d's run, minus its staging start
     __shared__ uint16_t offs[kOffsLds ? 10 : 1][NT];
+    // keys only with one hundred buckets: each bucket's next free staging slot
+    constexpr bool kCursor = NBK == 100 && !PAIRS;
+    __shared__ uint32_t cur[kCursor ? NBK : 1];
     const int t = blockIdx.x;
     const TileDesc td = w.tiles[t];
     if (td.cnt == 0) return;
@@ -662,7 +668,10 @@ __global__ __launch_bounds__(kHistNT) void k_scatter(Work<K> w) {
         // the tile's start of each bucket: exclusive scan of its counts
         uint32_t all;
         const uint32_t ls = block_excl_scan<uint32_t, NT>(cb, all, &red[0][0]);
-        if (tid < NBK) dbase[tid] = (int32_t)(td.seg_base + gp - (int64_t)ls);
+        if (tid < NBK) {
+            dbase[tid] = (int32_t)(td.seg_base + gp - (int64_t)ls);
+            if constexpr (kCursor) cur[tid] = ls;
+        }
     }
     __syncthreads();
     uint32_t tot[5];
@@ -673,6 +682,30 @@ __global__ __launch_bounds__(kHistNT) void k_scatter(Work<K> w) {
                 const uint32_t d = (uint32_t)digit_of(pl, k);
                 return d | (d << 8);
             }, tot);
+        } else if constexpr (kCursor) {
+            // Keys only: the order of the keys inside a bucket cannot be seen
+            // in the result (equal keys are identical, and the local sorts
+            // order the rest), so each key takes the next slot of its bucket
+            // from an LDS cursor (one atomic add with return) in place of the
+            // two stable counting passes; the tile's counts give every
+            // bucket exactly its slots.
+            K key[VT];
+            uint32_t bk[VT];
+#pragma unroll
+            for (int v = 0; v < VT; v++) {
+                const int q = tid * VT + v;
+                key[v] = sk[lds_pad<K>(F || q < cnt ? q : 0)];
+                bk[v] = (uint32_t)bucket2_of(pl, key[v]);
+            }
+            __syncthreads();  // every key is read before any slot is written
+#pragma unroll
+            for (int v = 0; v < VT; v++) {
+                if (F || tid * VT + v < cnt) {
+                    const uint32_t slot = atomicAdd(&cur[bk[v]], 1u);
+                    sk[lds_pad<K>((int)slot)] = key[v];
+                    sd[slot] = (uint8_t)bk[v];
+                }
+            }
         } else {
             // pass 1 on the second digit, pass 2 on the first; b = 10 d1 + d2
             // (d1 = b * 205 >> 11, exact for b < 100)

@@ -13,6 +13,7 @@ import numpy as np
 import pytest
 
 import workloads as W
+from stage_check import check_keys_stage
 
 pytestmark = pytest.mark.gpu
 
@@ -154,8 +155,8 @@ def test_stage_scatter_matches_oracle(hs, orc, name):
     say(f"stage scatter {name} digits={digits}")
     t = dev(k)
     hs.hsort_debug_stage(t, 1)
-    ok, _, _ = orc.scatter(k, digits=digits)
-    assert np.array_equal(t.cpu().numpy(), ok)
+    ok, _, b = orc.scatter(k, digits=digits)
+    check_keys_stage(t.cpu().numpy(), ok, b, 1, 0, stable=digits == 1)
 
 
 @pytest.mark.parametrize("name", sorted(_stage_inputs().keys()))
@@ -166,8 +167,8 @@ def test_stage_local_sorts_match_oracle(hs, orc, name):
     say(f"stage tiles {name} tile={tile} digits={digits}")
     t = dev(k)
     hs.hsort_debug_stage(t, 2)
-    ok, _, _ = orc.bucket_tiles(k, tile, digits=digits)
-    assert np.array_equal(t.cpu().numpy(), ok)
+    ok, _, b = orc.bucket_tiles(k, tile, digits=digits)
+    check_keys_stage(t.cpu().numpy(), ok, b, 2, tile, stable=digits == 1)
 
 
 def test_stage_pairs_scatter_and_tiles(hs, orc):
@@ -194,8 +195,8 @@ def test_stage_int64(hs, orc):
         say(f"int64 stage {stage} digits={digits}")
         t = dev(k)
         hs.hsort_debug_stage(t, stage)
-        ok = orc.scatter(k, digits=digits)[0] if stage == 1 else orc.bucket_tiles(k, tile, digits=digits)[0]
-        assert np.array_equal(t.cpu().numpy(), ok)
+        ok, _, b = orc.scatter(k, digits=digits) if stage == 1 else orc.bucket_tiles(k, tile, digits=digits)
+        check_keys_stage(t.cpu().numpy(), ok, b, stage, tile, stable=digits == 1)
 
 
 def _mixed_magnitudes(dtype, seed):

@@ -16,6 +16,7 @@ import numpy as np
 import pytest
 
 import workloads as W
+from stage_check import check_keys_stage
 
 pytestmark = pytest.mark.gpu
 
@@ -90,10 +91,11 @@ def test_stages_and_sort_i32(hs, orc, name):
     say(f"two-digit int32 {name} n={k.size} cfg={cfg}")
     t = dev(k)
     hs.hsort_debug_stage(t, 1)
-    assert np.array_equal(t.cpu().numpy(), orc.scatter(k, digits=2)[0]), "scatter"
+    ok, _, b = orc.scatter(k, digits=2)
+    check_keys_stage(t.cpu().numpy(), ok, b, 1, 0, stable=False)
     t = dev(k)
     hs.hsort_debug_stage(t, 2)
-    assert np.array_equal(t.cpu().numpy(), orc.bucket_tiles(k, cfg[0], digits=2)[0]), "local sorts"
+    check_keys_stage(t.cpu().numpy(), orc.bucket_tiles(k, cfg[0], digits=2)[0], b, 2, cfg[0], stable=False)
     t = dev(k)
     s = scratch(hs, hs.KEYS_I32, k.size)
     hs.hsort_keys(t, scratch=s)
@@ -120,10 +122,11 @@ def test_stages_and_sort_i64(hs, orc, name):
     say(f"two-digit int64 {name} n={k.size} cfg={cfg}")
     t = dev(k)
     hs.hsort_debug_stage(t, 1)
-    assert np.array_equal(t.cpu().numpy(), orc.scatter(k, digits=2)[0]), "scatter"
+    ok, _, b = orc.scatter(k, digits=2)
+    check_keys_stage(t.cpu().numpy(), ok, b, 1, 0, stable=False)
     t = dev(k)
     hs.hsort_debug_stage(t, 2)
-    assert np.array_equal(t.cpu().numpy(), orc.bucket_tiles(k, cfg[0], digits=2)[0]), "local sorts"
+    check_keys_stage(t.cpu().numpy(), orc.bucket_tiles(k, cfg[0], digits=2)[0], b, 2, cfg[0], stable=False)
     t = dev(k)
     s = scratch(hs, hs.KEYS_I64, k.size)
     hs.hsort_keys(t, scratch=s)
