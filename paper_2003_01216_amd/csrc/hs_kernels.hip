@@ -398,12 +398,26 @@ __global__ __launch_bounds__(kHistNT) void k_range(Work<K> w) {
         block_sum5<kHistNT>(wd, red);
         if (tid < 10) w.counts[10 * (int64_t)(t - td.idx) + tid * td.nt + td.idx] = field16(wd, tid);
     } else {
-        // one hundred buckets: LDS atomics (block_minmax ended with a barrier)
+        // one hundred buckets: LDS atomics (block_minmax ended with a
+        // barrier), one per run of equal buckets among a thread's keys -- an
+        // LDS atomic serves the lanes on one address one at a time, and in a
+        // skewed tile most lanes of a wave share a bucket
         if (tid < 100) h[tid] = 0;
         __syncthreads();
+        uint32_t rb = (uint32_t)bucket2_of(pl, ks[0]), rn = 0;
 #pragma unroll
-        for (int v = 0; v < kHistVT; v++)
-            if (vec || tid + v * kHistNT < cnt) atomicAdd(&h[bucket2_of(pl, ks[v])], 1u);
+        for (int v = 0; v < kHistVT; v++) {
+            if (vec || tid + v * kHistNT < cnt) {
+                const uint32_t b = (uint32_t)bucket2_of(pl, ks[v]);
+                if (b != rb) {
+                    atomicAdd(&h[rb], rn);
+                    rb = b;
+                    rn = 0;
+                }
+                rn++;
+            }
+        }
+        if (rn) atomicAdd(&h[rb], rn);
         __syncthreads();
         if (tid < 100) w.counts[100 * (int64_t)(t - td.idx) + tid * td.nt + td.idx] = h[tid];
     }
@@ -491,8 +505,18 @@ __global__ __launch_bounds__(kHistNT) void k_hist(Work<K> w, int64_t tiles_bound
             } else {
                 if (tid < 100) h[tid] = 0;
                 __syncthreads();
-                load_run<K, kHistNT, kHistTile>(w.keys + td.base, td.cnt,
-                                                [&](int, K k) { atomicAdd(&h[bucket2_of(pl, k)], 1u); });
+                // one atomic per run of equal buckets, as in k_range
+                uint32_t rb = 0, rn = 0;
+                load_run<K, kHistNT, kHistTile>(w.keys + td.base, td.cnt, [&](int, K k) {
+                    const uint32_t b = (uint32_t)bucket2_of(pl, k);
+                    if (b != rb) {
+                        if (rn) atomicAdd(&h[rb], rn);
+                        rb = b;
+                        rn = 0;
+                    }
+                    rn++;
+                });
+                if (rn) atomicAdd(&h[rb], rn);
                 __syncthreads();
                 if (tid < 100) w.counts[100 * (slow[k] - td.idx) + tid * td.nt + td.idx] = h[tid];
                 __syncthreads();
@@ -640,6 +664,7 @@ __global__ __launch_bounds__(kHistNT) void k_scatter(Work<K> w) {
     // keys only with one hundred buckets: each bucket's next free staging slot
     constexpr bool kCursor = NBK == 100 && !PAIRS;
     __shared__ uint32_t cur[kCursor ? NBK : 1];
+    __shared__ int heavy;  // some bucket holds more than an eighth of the tile
     const int t = blockIdx.x;
     const TileDesc td = w.tiles[t];
     if (td.cnt == 0) return;
@@ -665,12 +690,17 @@ __global__ __launch_bounds__(kHistNT) void k_scatter(Work<K> w) {
     if constexpr (NBK == 10) {
         if (tid < 10) dbase[tid] = (int32_t)(td.seg_base + gp);
     } else {
-        // the tile's start of each bucket: exclusive scan of its counts
+        // the tile's start of each bucket: exclusive scan of its counts (its
+        // barriers order the flag's reset before the writes of 1)
+        if (kCursor && tid == 0) heavy = 0;
         uint32_t all;
         const uint32_t ls = block_excl_scan<uint32_t, NT>(cb, all, &red[0][0]);
         if (tid < NBK) {
             dbase[tid] = (int32_t)(td.seg_base + gp - (int64_t)ls);
-            if constexpr (kCursor) cur[tid] = ls;
+            if constexpr (kCursor) {
+                cur[tid] = ls;
+                if (8 * cb > (uint32_t)cnt) heavy = 1;
+            }
         }
     }
     __syncthreads();
@@ -698,12 +728,35 @@ __global__ __launch_bounds__(kHistNT) void k_scatter(Work<K> w) {
                 bk[v] = (uint32_t)bucket2_of(pl, key[v]);
             }
             __syncthreads();  // every key is read before any slot is written
+            if (heavy) {
+                // lanes on one LDS address are served one at a time, so when
+                // a bucket is large each run of equal buckets among a
+                // thread's consecutive keys takes all its slots at once
+                uint32_t len[VT];
+                len[VT - 1] = 1;
 #pragma unroll
-            for (int v = 0; v < VT; v++) {
-                if (F || tid * VT + v < cnt) {
-                    const uint32_t slot = atomicAdd(&cur[bk[v]], 1u);
-                    sk[lds_pad<K>((int)slot)] = key[v];
-                    sd[slot] = (uint8_t)bk[v];
+                for (int v = VT - 2; v >= 0; v--)
+                    len[v] = bk[v] == bk[v + 1] && (F || tid * VT + v + 1 < cnt) ? len[v + 1] + 1 : 1u;
+                uint32_t slot = 0;
+#pragma unroll
+                for (int v = 0; v < VT; v++) {
+                    if (F || tid * VT + v < cnt) {
+                        if (v == 0 || bk[v] != bk[v - 1])
+                            slot = atomicAdd(&cur[bk[v]], len[v]);
+                        else
+                            slot++;
+                        sk[lds_pad<K>((int)slot)] = key[v];
+                        sd[slot] = (uint8_t)bk[v];
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int v = 0; v < VT; v++) {
+                    if (F || tid * VT + v < cnt) {
+                        const uint32_t slot = atomicAdd(&cur[bk[v]], 1u);
+                        sk[lds_pad<K>((int)slot)] = key[v];
+                        sd[slot] = (uint8_t)bk[v];
+                    }
                 }
             }
         } else {
