@@ -157,8 +157,8 @@ def _vals(vals, n):
 
 
 def _nb(digits):
-    if digits not in (1, 2):
-        raise ValueError("digits must be 1 (ten buckets) or 2 (one hundred)")
+    if digits not in (1, 2, 3):
+        raise ValueError("digits must be 1 (ten buckets), 2 (one hundred) or 3 (one thousand)")
     return 10**digits
 
 

@@ -20,10 +20,11 @@
  *     Section 2.1, Section 3.4): the bucket of key k is the decimal digit in
  *     position D-1 of u = k - beta, where beta = min(min key, 0) and D is the
  *     number of decimal digits of max(u) (fixed-position digit reading);
- *   - its finer one-step variant with the two most significant digits (one
- *     hundred buckets, floor(u / 10^(D-2)), a one-digit u read as its digit
- *     followed by a zero): the second-digit splitter the paper's MSD radix
- *     would use next (Sections 2.3, 3.4), still one step.
+ *   - its finer one-step variants with the two or three most significant
+ *     digits (one hundred buckets, floor(u / 10^(D-2)), or one thousand,
+ *     floor(u / 10^(D-3)); a u with fewer digits read as its digits followed
+ *     by zeros): the next digits the paper's MSD radix would split on
+ *     (Sections 2.3, 3.4), taken in the same single step.
  *
  * How it computes the sort (following the paper's algorithms, sequentially):
  *   1. split the array into CHUNKS contiguous partitions, one per "thread" of
@@ -250,12 +251,26 @@ static int bucket2_of(const plan* pl, int64_t k) {
     return (int)(u / POW10[pl->D - 2]);
 }
 
-/* digits = 1: the ten buckets of Section 3.4; digits = 2: the hundred above. */
+/* One thousand buckets: the number formed by the first three of the D
+ * digits of u, floor(u / 10^(D-3)); a u of one or two digits reads as its
+ * digits followed by zeros (100u, 10u).  Buckets 10c .. 10c+9 of this rule
+ * make up bucket c of the hundred-bucket rule. */
+static int bucket3_of(const plan* pl, int64_t k) {
+    uint64_t u = (uint64_t)k - (uint64_t)pl->beta;
+    if (pl->D < 3) return (int)(u * POW10[3 - pl->D]);
+    return (int)(u / POW10[pl->D - 3]);
+}
+
+/* digits = 1: the ten buckets of Section 3.4; 2 and 3: the finer rules
+ * above. */
 static int bucket_n(const plan* pl, int64_t k, int digits) {
+    if (digits == 3) return bucket3_of(pl, k);
     return digits == 2 ? bucket2_of(pl, k) : bucket_of(pl, k);
 }
 
-static int nbuckets(int digits) { return digits == 2 ? 100 : 10; }
+static int nbuckets(int digits) { return (int)POW10[digits]; }
+
+static int digits_ok(int digits) { return digits >= 1 && digits <= 3; }
 
 /* ------------------------------------------------------- exported: helpers */
 static item* load_items_i32(const int32_t* k, int64_t n) {
@@ -294,10 +309,10 @@ static plan plan_of_mode(const item* s, int64_t n, int fixed) {
 
 static plan plan_of(const item* s, int64_t n) { return plan_of_mode(s, n, 0); }
 
-/* bounds[b] = number of keys whose bucket is below b, b = 0..NB (NB = 10
- * or 100 buckets) */
+/* bounds[b] = number of keys whose bucket is below b, b = 0..NB (NB = 10,
+ * 100 or 1000 buckets) */
 static void bounds_of(const item* s, int64_t n, const plan* pl, int digits, int64_t* bounds) {
-    int64_t cnt[100] = {0};
+    int64_t cnt[1000] = {0};
     const int nb = nbuckets(digits);
     for (int64_t i = 0; i < n; i++) cnt[bucket_n(pl, s[i].key, digits)]++;
     bounds[0] = 0;
@@ -307,7 +322,7 @@ static void bounds_of(const item* s, int64_t n, const plan* pl, int digits, int6
 /* Stable counting scatter of s[0..n) into the buckets (the master's
  * one-step MSD radix, Section 3.4).  out must hold n items. */
 static void stable_scatter(const item* s, int64_t n, const plan* pl, int digits, const int64_t* bounds, item* out) {
-    int64_t next[100];
+    int64_t next[1000];
     for (int b = 0; b < nbuckets(digits); b++) next[b] = bounds[b];
     for (int64_t i = 0; i < n; i++) out[next[bucket_n(pl, s[i].key, digits)]++] = s[i];
 }
@@ -336,10 +351,11 @@ int oracle_plan_i64(const int64_t* k, int64_t n, int64_t* beta, int32_t* D, uint
 }
 
 /* bounds[0 .. 10^digits]: the bucket bounds of the array under the one-step
- * rule with `digits` leading digits (1: ten buckets, 2: one hundred). */
+ * rule with `digits` leading digits (1: ten buckets, 2: one hundred, 3: one
+ * thousand). */
 static int bounds_items_mode(item* s, int64_t n, int digits, int fixed, int64_t* bounds) {
     if (!s) return -1;
-    if (digits != 1 && digits != 2) {
+    if (!digits_ok(digits)) {
         free(s);
         return -1;
     }
@@ -422,10 +438,10 @@ int oracle_sort_pairs_i32(int32_t* k, uint32_t* v, int64_t n) {
  * buckets, the plain sort inside each bucket, buckets in digit order.  Also
  * returns the bucket bounds when bounds != NULL. */
 static int radix_mode(item* s, int64_t n, int digits, int64_t* bounds_out) {
-    if (digits != 1 && digits != 2) return -1;
+    if (!digits_ok(digits)) return -1;
     const int nb = nbuckets(digits);
     plan pl = plan_of(s, n);
-    int64_t bounds[101];
+    int64_t bounds[1001];
     bounds_of(s, n, &pl, digits, bounds);
     item* t = (item*)malloc(sizeof(item) * (size_t)(n > 0 ? n : 1));
     if (!t) return -1;
@@ -521,7 +537,7 @@ int oracle_radix_sort_pairs_i32(int32_t* k, uint32_t* v, int64_t n, int64_t* bou
 /* The intermediate after the one-step MSD radix alone: the stable scatter of
  * the input into bucket order (vals may be NULL).  Writes bounds[NB + 1]. */
 static int scatter_only_mode(item* s, int64_t n, int digits, int fixed, int64_t* bounds) {
-    if (digits != 1 && digits != 2) return -1;
+    if (!digits_ok(digits)) return -1;
     plan pl = plan_of_mode(s, n, fixed);
     bounds_of(s, n, &pl, digits, bounds);
     item* t = (item*)malloc(sizeof(item) * (size_t)(n > 0 ? n : 1));
@@ -781,11 +797,11 @@ int oracle_bounds_typed(const void* k, int t, int desc, int64_t n, int digits, i
 }
 
 int oracle_radix_sort_typed(void* k, uint32_t* v, int t, int desc, int64_t n, int digits, int64_t* bounds) {
-    if (!valid_type(t) || (digits != 1 && digits != 2)) return -1;
+    if (!valid_type(t) || !digits_ok(digits)) return -1;
     item* s = load_items_typed(k, t, desc, n);
     if (!s) return -1;
     int rc = 0;
-    int64_t b[101];
+    int64_t b[1001];
     if (scatter_only_mode(s, n, digits, t == T_U64, b)) rc = -1;
     for (int j = 0; !rc && j < nbuckets(digits); j++) rc = hybrid_sort(s + b[j], b[j + 1] - b[j]);
     if (!rc) rc = gather_typed(k, v, t, s, n);
@@ -798,7 +814,7 @@ int oracle_radix_sort_typed(void* k, uint32_t* v, int t, int desc, int64_t n, in
 /* Intermediates: the stable scatter into buckets (tile <= 0), or that
  * followed by the sort of every `tile`-key partition of every bucket. */
 int oracle_stage_typed(void* k, uint32_t* v, int t, int desc, int64_t n, int64_t tile, int digits, int64_t* bounds) {
-    if (!valid_type(t) || (digits != 1 && digits != 2)) return -1;
+    if (!valid_type(t) || !digits_ok(digits)) return -1;
     item* s = load_items_typed(k, t, desc, n);
     if (!s) return -1;
     int rc = scatter_only_mode(s, n, digits, t == T_U64, bounds);

@@ -76,6 +76,24 @@ def string_plan2(keys):
     return beta, D, p, digits
 
 
+def string_plan3(keys):
+    """Three-digit buckets via decimal strings: the first three characters of
+    u written with D digits (a u of one or two digits gets trailing zeros)."""
+    beta, D, p, _ = string_plan(keys)
+    digits = [int((str(int(k) - beta).rjust(D, "0") + "00")[:3]) for k in keys]
+    return beta, D, p, digits
+
+
+def string_bounds3(keys):
+    cnt = [0] * 1000
+    for d in string_plan3(keys)[3]:
+        cnt[d] += 1
+    b = [0]
+    for c in cnt:
+        b.append(b[-1] + c)
+    return b
+
+
 def string_bounds2(keys):
     cnt = [0] * 100
     for d in string_plan2(keys)[3]:
@@ -349,6 +367,93 @@ def pin_two_digit_string_route(orc, seed=24):
             assert b2 == lb, k
 
 
+def pin_three_digit_worked_examples(orc):
+    with open(GOLDEN) as f:
+        g = json.load(f)["three_digit"]
+    for ex in g["cases"]:
+        k = np.array(ex["keys"], np.int32 if ex["dtype"] == "int32" else np.int64)
+        assert string_plan3(ex["keys"])[3] == ex["digits"], ("fixture digits", ex)
+        steps = dict((b, v) for b, v in ex["bounds_steps"])
+        full, cur = [], 0
+        for b in range(1001):
+            cur = steps.get(b, cur)
+            full.append(cur)
+        full[1000] = len(ex["keys"])
+        assert orc.bounds(k, 3).tolist() == full, ("bounds1000", ex)
+        assert orc.radix_sort_keys(k, 3)[1].tolist() == full, ("radix bounds1000", ex)
+
+
+def pin_three_digit_string_route(orc, seed=26):
+    """Thousand-bucket bounds by decimal strings, by lower_bound of the sorted
+    output at beta + b*10^(D-3), and folded onto the hundred-bucket bounds."""
+    rng = np.random.default_rng(seed)
+    cases = []
+    for D in range(1, 11):
+        hi = 10**D - 1 if D < 10 else I32.max
+        k = rng.integers(0, 10 ** (D - 1), 80, dtype=np.int64)
+        k[rng.integers(0, 80)] = rng.integers(10 ** (D - 1), hi, endpoint=True)
+        cases.append(k.astype(np.int32))
+    for D in range(1, 21):
+        if D < 20:
+            k = [int(x) for x in rng.integers(0, 10 ** (D - 1), 60, dtype=np.int64)]
+            k.append(int(rng.integers(10 ** (D - 1), min(10**D - 1, I64.max), endpoint=True, dtype=np.int64)))
+        else:
+            k = [I64.min, I64.max] + [int(x) for x in rng.integers(I64.min, I64.max, 40, dtype=np.int64)]
+        cases.append(np.array(k, np.int64))
+    for D in range(1, 20):
+        for top in (10 ** (D - 1), 10**D - 1, 10**D):
+            for dt, info in ((np.int32, I32), (np.int64, I64)):
+                if top <= info.max:
+                    cases.append(np.array([0, top // 7, top // 3, top // 101, top], dt))
+    for _ in range(40):
+        dt = np.int32 if rng.random() < 0.5 else np.int64
+        info = np.iinfo(dt)
+        lo = int(rng.integers(info.min, info.max, dtype=dt)) if rng.random() < 0.5 else 0
+        hi = int(rng.integers(max(lo, 0), info.max, dtype=dt, endpoint=True))
+        cases.append(rng.integers(lo, hi, int(rng.integers(1, 2000)), dtype=dt, endpoint=True))
+    for k in cases:
+        b3 = orc.bounds(k, 3).tolist()
+        assert b3 == string_bounds3(k.tolist()), k
+        assert b3[::10] == orc.bounds(k, 2).tolist(), k  # bucket c of 100 = buckets 10c .. 10c+9
+        beta, D, p, _ = string_plan(k.tolist())
+        if D >= 3:
+            s = np.array(sorted(int(x) for x in k), dtype=object)
+            lb = [0] + [int(np.searchsorted(s, beta + b * (p // 100), side="left")) for b in range(1, 1000)] + [len(s)]
+            assert b3 == lb, k
+
+
+def pin_three_digit_radix_and_stages(orc, seed=27):
+    """The thousand-bucket pipeline run sequentially equals the plain sort; its
+    scatter is stable and in bucket order; its local sorts sort each
+    partition of each bucket."""
+    rng = np.random.default_rng(seed)
+    for n in [0, 1, 9, 1000, 30_011]:
+        for dt in (np.int32, np.int64):
+            info = np.iinfo(dt)
+            for k in (rng.integers(info.min, info.max, n, dtype=dt, endpoint=True),
+                      rng.integers(0, 100_000, n).astype(dt), rng.integers(0, 7, n).astype(dt)):
+                rk, rb = orc.radix_sort_keys(k, 3)
+                assert np.array_equal(rk, orc.sort_keys(k)), (n, dt)
+                assert rb.tolist() == string_bounds3(k.tolist()), (n, dt)
+    for n, T in [(0, 4), (1, 4), (700, 7), (40_000, 64)]:
+        k = rng.integers(0, 30_000, n, dtype=np.int32)
+        v = np.arange(n, dtype=np.uint32)
+        sk, sv, b = orc.scatter(k, v, 3)
+        assert b.tolist() == string_bounds3(k.tolist())
+        d_in, d_out = string_plan3(k.tolist())[3], string_plan3(sk.tolist())[3] if n else []
+        assert d_out == sorted(d_in), "buckets out of order"
+        assert np.array_equal(k[sv], sk), "payload does not follow its key"
+        for bk in range(1000):
+            assert np.all(np.diff(sv[b[bk]:b[bk + 1]].astype(np.int64)) > 0), "scatter not stable"
+        tk, tv, tb = orc.bucket_tiles(k, T, v, 3)
+        assert np.array_equal(tb, b)
+        for bk in range(1000):
+            for s0 in range(int(b[bk]), int(b[bk + 1]), T):
+                e = min(s0 + T, int(b[bk + 1]))
+                order = np.lexsort((sv[s0:e], sk[s0:e]))
+                assert np.array_equal(tk[s0:e], sk[s0:e][order]) and np.array_equal(tv[s0:e], sv[s0:e][order])
+
+
 def pin_two_digit_radix_and_stages(orc, seed=25):
     """The hundred-bucket pipeline run sequentially equals the plain sort; its
     scatter is stable and in bucket order; its local sorts sort each
@@ -459,17 +564,16 @@ def order_image_py(k, desc):
 
 
 def string_buckets_typed(k, desc, digits):
-    """Each key's bucket: the first one or two characters of the decimal
-    string of u, written with D digits (a one-digit u gets a trailing zero)."""
+    """Each key's bucket: the first one, two or three characters of the
+    decimal string of u, written with D digits (a shorter u gets trailing
+    zeros)."""
     img, unsigned = order_image_py(k, desc)
     if not img:
         return []
     beta = 0 if unsigned else min(min(img), 0)
     us = [v - beta for v in img]
     D = len(str(max(us)))
-    if digits == 1:
-        return [int(str(u).rjust(D, "0")[0]) for u in us]
-    return [int((str(u).rjust(D, "0") + "0")[:2]) for u in us]
+    return [int((str(u).rjust(D, "0") + "00")[:digits]) for u in us]
 
 
 def string_bounds_typed(k, desc, digits):
@@ -541,14 +645,14 @@ def pin_typed_library(orc, seed=32):
 
 def pin_typed_bounds(orc, seed=33):
     """Bucket bounds of every type and direction by decimal strings of the
-    order image's u, with ten and one hundred buckets."""
+    order image's u, with ten, one hundred and one thousand buckets."""
     rng = np.random.default_rng(seed)
     for dt in TYPED:
         for n in [0, 1, 7, 200]:
             for _ in range(4):
                 k = typed_samples(dt, n, rng)
                 for desc in (False, True):
-                    for digits in (1, 2):
+                    for digits in (1, 2, 3):
                         assert orc.bounds_typed(k, desc, digits).tolist() == string_bounds_typed(k, desc, digits), \
                             (np.dtype(dt).name, n, desc, digits, k)
 
@@ -564,7 +668,7 @@ def pin_typed_worked_examples(orc):
 
 def pin_typed_radix_and_stages(orc, seed=34):
     """Section 3.4 run sequentially on the order image equals the plain
-    typed sort (ten and one hundred buckets); the scatter keeps input order
+    typed sort (ten, one hundred and one thousand buckets); the scatter keeps input order
     inside a bucket; the local sorts sort every partition of every bucket."""
     rng = np.random.default_rng(seed)
     for dt in TYPED:
@@ -573,7 +677,7 @@ def pin_typed_radix_and_stages(orc, seed=34):
             v = np.arange(n, dtype=np.uint32)
             for desc in (False, True):
                 pk, pv = orc.sort_typed(k, v, desc)
-                for digits in (1, 2):
+                for digits in (1, 2, 3):
                     rk, rv, rb = orc.radix_sort_typed(k, v, desc, digits)
                     assert np.array_equal(rv, pv), (np.dtype(dt).name, n, desc, digits)
                     assert rb.tolist() == string_bounds_typed(k, desc, digits)
@@ -609,6 +713,9 @@ ALL_PINS = [
     pin_two_digit_worked_examples,
     pin_two_digit_string_route,
     pin_two_digit_radix_and_stages,
+    pin_three_digit_worked_examples,
+    pin_three_digit_string_route,
+    pin_three_digit_radix_and_stages,
     pin_typed_brute,
     pin_typed_zero_and_nan_order,
     pin_typed_library,

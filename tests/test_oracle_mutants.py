@@ -30,6 +30,9 @@ MUTANTS = [
      "for (int64_t i = n - 1; i >= 0; i--) out[next[bucket_n(pl, s[i].key, digits)]++] = s[i];"),
     ("two_digit_drops_second_digit", "return (int)(u / POW10[pl->D - 2]);", "return (int)(u / POW10[pl->D - 1] * 10);"),
     ("one_digit_without_trailing_zero", "if (pl->D == 1) return (int)(10 * u);", "if (pl->D == 1) return (int)u;"),
+    ("three_digit_reads_two", "return (int)(u / POW10[pl->D - 3]);", "return (int)(u / POW10[pl->D - 2] * 10);"),
+    ("three_digit_short_u_unpadded", "if (pl->D < 3) return (int)(u * POW10[3 - pl->D]);", "if (pl->D < 3) return (int)(u * 10);"),
+    ("three_digit_uses_two_digit_rule", "if (digits == 3) return bucket3_of(pl, k);", "if (digits == 3) return 10 * bucket2_of(pl, k);"),
     ("scatter_ignores_digit_count", "out[next[bucket_n(pl, s[i].key, digits)]++] = s[i];",
      "out[next[bucket_of(pl, s[i].key)]++] = s[i];"),
     ("tiles_skip_upper_buckets", "    for (int b = 0; b < nb; b++) {\n        for (int64_t t = bounds[b]; t < bounds[b + 1]; t += tile) {",
