@@ -175,8 +175,12 @@ const char* hsort_last_error(void);
  * partition, 1 (the ten buckets of Section 3.4) or 2 (one hundred buckets by
  * the first two of the D digits, floor(u / 10^(D-2)), or 10u when D = 1: a
  * finer splitter with the same order, so bucket b of the ten is buckets
- * 10b .. 10b+9 of the hundred; smaller buckets need fewer merge rounds).
- * The exported bounds are the ten-bucket bounds either way.  local = the
+ * 10b .. 10b+9 of the hundred; smaller buckets need fewer merge rounds)
+ * or 3 (one thousand buckets, floor(u / 10^(D-3)), the digits of a shorter u
+ * followed by zeros; plain int32 keys-only sorts only, kind
+ * HSORT_KEYS_I32, and with it the uint32/float32 sorts of hsort_sort; its
+ * partition tiles hold 16384 keys instead of 4096).  The exported bounds are
+ * the ten-bucket bounds in every case.  local = the
  * local sort: 0 (a register network, merges across lanes, then merge levels
  * in LDS) or 1 (the non-recursive merge sort of Figure 1b: each thread sorts
  * its tile_vt keys -- pairs when tile_vt = 2 -- and every merge level runs

@@ -57,8 +57,10 @@ NAMES = {KEYS_I32: "keys_i32", KEYS_I64: "keys_i64", PAIRS_I32_U32: "pairs_i32",
 
 
 FANINS = [2, 4]
-# decimal digits of the one-step partition: ten or one hundred buckets
-DIGITS = [1, 2]
+# decimal digits of the one-step partition: ten, one hundred or (plain
+# int32 keys only) one thousand buckets
+DIGITS = {KEYS_I32: [1, 2, 3]}
+DIGITS_DEFAULT = [1, 2]
 # local-sort shapes of the bottom-up LDS merge (local = 1; Figure 1b from pairs when tile_vt = 2)
 TILES_BU = {KEYS_I32: [(2048, 2), (4096, 8)], PAIRS_I32_U32: [(2048, 2)], KEYS_I64: [(2048, 2)]}
 
@@ -68,7 +70,8 @@ def candidates(kind):
     smalls = SEG_SMALL if kind in (SEG_I32, SEG_I64) else SMALL[kt]
     tiles = [(t, tv, 0) for t, tv in TILES[kt]] + [(t, tv, 1) for t, tv in TILES_BU.get(kt, [])]
     for f in FANINS:
-        for (t, tv, lc), (m, mv), s, d in itertools.product(tiles, MERGES[f][kt], smalls, DIGITS):
+        for (t, tv, lc), (m, mv), s, d in itertools.product(tiles, MERGES[f][kt], smalls,
+                                                            DIGITS.get(kind, DIGITS_DEFAULT)):
             if t % m == 0:
                 yield (t, tv, m, mv, s, f, d, lc)
 

@@ -32,7 +32,7 @@ struct Config {
     int64_t merge_vt;   // outputs per thread of the merge
     int64_t small_max;  // segments up to this size never leave LDS
     int64_t fanin;      // runs merged per round: 2 or 4
-    int64_t digits = 1;  // decimal digits of the one-step partition: 1 (ten buckets) or 2 (one hundred)
+    int64_t digits = 1;  // decimal digits of the one-step partition: 1 (ten buckets), 2 (one hundred) or 3 (one thousand)
     int64_t local = 0;   // local sort: 0 network + lane merges + LDS levels, 1 bottom-up LDS merge from VT-runs
 };
 
@@ -134,7 +134,8 @@ bool config_ok(int key_type_index, const Config& c) {
     if (c.tile % c.merge_nv) return false;  // merge chunks must tile a run
     if (c.small_max < 0 || c.small_max > 8192) return false;
     if (c.fanin != 2 && c.fanin != 4) return false;
-    if (c.digits != 1 && c.digits != 2) return false;
+    if (c.digits < 1 || c.digits > 3) return false;
+    if (c.digits == 3 && key_type_index != 0) return false;  // one thousand buckets: int32 keys only
     if (c.local != 0 && c.local != 1) return false;
     switch (key_type_index) {
         case 0:
@@ -209,6 +210,10 @@ constexpr size_t kAlign = 256;
 size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// Buckets per segment and keys per partition tile of a configuration.
+int64_t buckets_of(const Config& c) { return c.digits == 3 ? 1000 : c.digits == 2 ? 100 : 10; }
+int64_t partition_tile(const Config& c) { return c.digits == 3 ? PartShape<1000>::HT : kHistTile; }
+
 struct Layout {
     // byte offsets into scratch
     size_t err, own_off, skeys, svals, tmin, tmax, tp, smpf, smpl, rounds, plans, tilecnt, tilepre, bounds, counts, pos, bstart, bsize, tsc,
@@ -226,8 +231,8 @@ Layout make_layout(int kind, int64_t n, int64_t nseg, const Config& c) {
     const bool pairs = kind == HSORT_PAIRS_I32_U32 || kind == HSORT_PAIRS_I64_U32;
     Layout L{};
     L.large_bound = std::min<int64_t>(nseg, std::max<int64_t>(1, n / (c.small_max + 1)));
-    L.tiles_bound = cdiv(n, kHistTile) + L.large_bound;
-    const int64_t nbk = c.digits == 2 ? 100 : 10;
+    const int64_t nbk = buckets_of(c);
+    L.tiles_bound = cdiv(n, partition_tile(c)) + L.large_bound;
     L.buckets = nbk * nseg;
     L.ts_bound = cdiv(n, c.tile) + nbk * L.large_bound;
     L.chunks_bound = cdiv(n, c.merge_nv) + nbk * L.large_bound;
@@ -304,7 +309,8 @@ Work<K> make_work(const Layout& L, char* scr, K* keys, uint32_t* vals, const int
     w.mdesc = (MergeDesc*)(scr + L.mdesc);
     w.ssorted = (Split4*)(scr + L.ssorted);
     w.err = (uint32_t*)(scr + L.err);
-    w.nbk = c.digits == 2 ? 100 : 10;
+    w.nbk = (int32_t)buckets_of(c);
+    w.ptile = (int32_t)partition_tile(c);
     w.tile = (int32_t)c.tile;
     w.fanin = (int32_t)c.fanin;
     w.nv = (int32_t)c.merge_nv;
@@ -869,6 +875,8 @@ int hsort_set_config(int kind, int size_cls, int64_t tile, int64_t tile_vt, int6
     if (size_cls < -1 || size_cls >= kClasses) return fail(HSORT_ERR_INVALID, "size class out of range");
     const Config c{tile, tile_vt, merge_nv, merge_vt, small_max, fanin, digits, local};
     if (!config_ok(key_type(kind), c)) return fail(HSORT_ERR_UNSUPPORTED, "tile/merge shape not compiled");
+    if (digits == 3 && kind != HSORT_KEYS_I32)
+        return fail(HSORT_ERR_UNSUPPORTED, "one thousand buckets: plain int32 keys-only sorts only");
     std::lock_guard<std::mutex> lk(g_mu);
     for (int k = 0; k < kClasses; k++)
         if (size_cls < 0 || k == size_cls) g_cfg[ci][k] = c;

@@ -62,6 +62,9 @@ struct DigitPlan {
     U thr2[9];        // 64-bit keys: c*q - 1 for c = 1..9 (saturated; all-ones when D = 1)
     uint64_t magic2;  // 32-bit keys: ceil(2^64 / q) for q >= 10, else 0
     uint32_t mul2;    // 32-bit keys with magic2 = 0: the bucket is u * mul2 (1 when D = 2, 10 when D = 1)
+    // three-digit rule (32-bit keys only)
+    uint64_t magic3;  // ceil(2^64 / r), r = p / 100, for r >= 10, else 0
+    uint32_t mul3;    // with magic3 = 0: the bucket is u * mul3 (1 when D = 3, 10 when D = 2, 100 when D = 1)
 };
 
 // fixed: the keys are images of unsigned keys (the unsigned value x maps
@@ -90,6 +93,10 @@ __host__ __device__ inline DigitPlan<K> make_digit_plan(K mn, K mx, bool fixed =
     for (int c = 1; c <= 9; c++) pl.thr2[c - 1] = q == 0 ? umax : (U)((U)c * q - 1);  // c*q < 10q = p: fits
     pl.magic2 = q >= 10 ? ~0ull / (uint64_t)q + 1 : 0;
     pl.mul2 = q == 0 ? 10u : 1u;
+    // three-digit rule: r = p / 100 (none when p < 100)
+    const U r = p / 100;
+    pl.magic3 = r >= 10 ? ~0ull / (uint64_t)r + 1 : 0;
+    pl.mul3 = p == 1 ? 100u : p == 10 ? 10u : 1u;
     return pl;
 }
 
@@ -145,14 +152,30 @@ __host__ __device__ __forceinline__ int bucket2_of(const DigitPlan<K>& pl, K k) 
     }
 }
 
-// Bucket of a key under the rule with NBK buckets (10 or 100).
+// The key's three-digit bucket (0..999) under the one-thousand-bucket rule,
+// 32-bit keys: floor(u / r), r = p / 100, by the same exact multiply-high as
+// digit_of when r >= 10, else u * mul3 (r = 1, or D < 3: the digits of u
+// followed by zeros).
+template <typename K>
+__host__ __device__ __forceinline__ int bucket3_of(const DigitPlan<K>& pl, K k) {
+    using U = typename Traits<K>::U;
+    static_assert(sizeof(U) == 4, "one thousand buckets: 32-bit keys");
+    U u = (U)k - pl.beta;
+    const uint64_t m = pl.magic3;
+    const uint64_t mid = (uint64_t)u * (uint32_t)(m >> 32) + (uint32_t)(((uint64_t)u * (uint32_t)m) >> 32);
+    return m ? (int)(mid >> 32) : (int)(u * pl.mul3);
+}
+
+// Bucket of a key under the rule with NBK buckets (10, 100 or 1000).
 template <int NBK, typename K>
 __host__ __device__ __forceinline__ int bucket_of(const DigitPlan<K>& pl, K k) {
-    static_assert(NBK == 10 || NBK == 100, "ten or one hundred buckets");
+    static_assert(NBK == 10 || NBK == 100 || NBK == 1000, "ten, one hundred or one thousand buckets");
     if constexpr (NBK == 10)
         return digit_of(pl, k);
-    else
+    else if constexpr (NBK == 100)
         return bucket2_of(pl, k);
+    else
+        return bucket3_of(pl, k);
 }
 
 // The keys of bucket b (NBK buckets) lie in u in [lo, lo + width): the
@@ -163,11 +186,17 @@ __host__ __device__ __forceinline__ void bucket_span(const DigitPlan<K>& pl, int
     if (nbk == 10) {
         lo = (uint64_t)b * p;
         width = p;
-    } else if (p >= 10) {
+    } else if (nbk == 100 && p >= 10) {
         lo = (uint64_t)b * (p / 10);
         width = p / 10;
-    } else {  // D = 1: bucket 10u
+    } else if (nbk == 100) {  // D = 1: bucket 10u
         lo = (uint64_t)(b / 10);
+        width = 1;
+    } else if (p >= 100) {
+        lo = (uint64_t)b * (p / 100);
+        width = p / 100;
+    } else {  // D = 2: bucket 10u; D = 1: bucket 100u
+        lo = (uint64_t)(b / (p == 10 ? 10 : 100));
         width = 1;
     }
 }
@@ -496,6 +525,18 @@ __device__ __forceinline__ void lds_merge_window(const W* lds, int pa, int pb, W
 
 // --------------------------------------------------------- wave/block helpers
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+// The dispatcher hands workgroups to the eight XCDs in turn (workgroup b to
+// XCD b mod 8), and each XCD has an L2 of its own.  Units (tiles, chunks)
+// whose edges share cache lines -- per-tile counts stored tile-minor, runs
+// written back to back -- should meet in one L2, so workgroup b takes unit
+// x*q + min(x, r) + b/8 (x = b mod 8, q = G/8, r = G mod 8): each XCD works
+// through one contiguous range of units in order.  A bijection on [0, G).
+__device__ __forceinline__ int64_t xcd_unit(int64_t b, int64_t G) {
+    constexpr int64_t kXcd = 8;
+    const int64_t q = G / kXcd, r = G % kXcd, x = b % kXcd;
+    return x * q + (x < r ? x : r) + b / kXcd;
+}
 
 // 32-bit wave scans and reductions by DPP (no LDS traffic): shifts by 1, 2,
 // 4 and 8 lanes within each row of 16 (lanes shifted in from outside the

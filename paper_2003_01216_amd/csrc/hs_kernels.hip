@@ -283,7 +283,7 @@ __global__ void k_classify(Work<K> w) {
         if (bad) atomicOr(w.err, kErrOffsets);
         const int64_t m = b - a;
         if (!bad && w.max_seg_len > 0 && m > w.max_seg_len) atomicOr(w.err, kErrSegLen);
-        w.tilecnt[s] = (!bad && m > w.small_max) ? (int32_t)((m + kHistTile - 1) / kHistTile) : 0;
+        w.tilecnt[s] = (!bad && m > w.small_max) ? (int32_t)((m + w.ptile - 1) / w.ptile) : 0;
     }
 }
 
@@ -300,10 +300,10 @@ __global__ void k_tiles(Work<K> w, int64_t tiles_bound) {
         const int s = owner_of(w.tilepre, w.nseg, (int)t);
         const int i = (int)t - w.tilepre[s];
         const int64_t a = w.off[s];
-        const int64_t base = a + (int64_t)i * kHistTile;
+        const int64_t base = a + (int64_t)i * w.ptile;
         d.base = base;
         d.seg_base = a;
-        d.cnt = (int)min((int64_t)kHistTile, w.off[s + 1] - base);
+        d.cnt = (int)min((int64_t)w.ptile, w.off[s + 1] - base);
         d.seg = s;
         d.idx = i;
         d.nt = w.tilecnt[s];
@@ -340,46 +340,47 @@ __device__ __forceinline__ void block_minmax(T& mn, T& mx, T* rmn, T* rmx) {
 // reading the keys again.  Keys are read strided (thread t: t, t + NT, ...),
 // coalesced per wave, and kept in registers for the count.
 template <typename K, int NBK>
-__global__ __launch_bounds__(kHistNT) void k_range(Work<K> w) {
-    __shared__ K rmn[kHistNT / kWave], rmx[kHistNT / kWave];
-    __shared__ uint32_t red[kHistNT / kWave][5];
-    __shared__ uint32_t h[NBK == 100 ? 100 : 1];
-    const int t = blockIdx.x;
+__global__ __launch_bounds__(PartShape<NBK>::NT) void k_range(Work<K> w) {
+    constexpr int NT = PartShape<NBK>::NT, VT = PartShape<NBK>::VT, HT = PartShape<NBK>::HT;
+    __shared__ K rmn[NT / kWave], rmx[NT / kWave];
+    __shared__ uint32_t red[NT / kWave][5];
+    __shared__ uint32_t h[NBK >= 100 ? NBK : 1];
+    const int t = (int)xcd_unit(blockIdx.x, gridDim.x);
     const TileDesc td = w.tiles[t];
     if (td.cnt == 0) return;
     const int tid = threadIdx.x;
     const int cnt = td.cnt;
     const K* src = w.keys + td.base;
     const K k0 = src[0];
-    K ks[kHistVT];
+    K ks[VT];
     // a full, 16-byte aligned tile is read in 16-byte vectors (consecutive
     // threads on consecutive vectors), any other strided by element (then
     // key v of a thread is element tid + v*NT; the counts need no order)
     using V = typename Vec16<K>::type;
     constexpr int E = Vec16<K>::n;
-    const bool vec = cnt == kHistTile && ((uintptr_t)src & 15) == 0;
+    const bool vec = cnt == HT && ((uintptr_t)src & 15) == 0;
     if (vec) {
         const V* sv = reinterpret_cast<const V*>(src);
 #pragma unroll
-        for (int j = 0; j < kHistVT / E; j++) {
-            const V x = sv[tid + j * kHistNT];
+        for (int j = 0; j < VT / E; j++) {
+            const V x = sv[tid + j * NT];
 #pragma unroll
             for (int e = 0; e < E; e++) ks[j * E + e] = (K)Vec16<K>::get(x, e);
         }
     } else {
 #pragma unroll
-        for (int v = 0; v < kHistVT; v++) {
-            const int q = tid + v * kHistNT;
+        for (int v = 0; v < VT; v++) {
+            const int q = tid + v * NT;
             ks[v] = q < cnt ? src[q] : k0;  // k0 leaves the min and max unchanged
         }
     }
     K mn = ks[0], mx = ks[0];
 #pragma unroll
-    for (int v = 1; v < kHistVT; v++) {
+    for (int v = 1; v < VT; v++) {
         mn = ks[v] < mn ? ks[v] : mn;
         mx = ks[v] > mx ? ks[v] : mx;
     }
-    block_minmax<K, kHistNT>(mn, mx, rmn, rmx);
+    block_minmax<K, NT>(mn, mx, rmn, rmx);
     if (tid == 0) {
         w.tmin[t] = mn;
         w.tmax[t] = mx;
@@ -390,25 +391,25 @@ __global__ __launch_bounds__(kHistNT) void k_range(Work<K> w) {
     }
     const DigitPlan<K> pl = make_digit_plan<K>(K(0), mx, w.ufix);
     if constexpr (NBK == 10) {
-        uint64_t c = 0;  // at most kHistVT = 16 keys per thread: fits the 5-bit fields
+        uint64_t c = 0;  // at most VT = 16 keys per thread: fits the 5-bit fields
 #pragma unroll
-        for (int v = 0; v < kHistVT; v++) c += (uint64_t)(vec || tid + v * kHistNT < cnt) << (5 * digit_of(pl, ks[v]));
+        for (int v = 0; v < VT; v++) c += (uint64_t)(vec || tid + v * NT < cnt) << (5 * digit_of(pl, ks[v]));
         uint32_t wd[5];
         unpack5(c, wd);
-        block_sum5<kHistNT>(wd, red);
+        block_sum5<NT>(wd, red);
         if (tid < 10) w.counts[10 * (int64_t)(t - td.idx) + tid * td.nt + td.idx] = field16(wd, tid);
     } else {
-        // one hundred buckets: LDS atomics (block_minmax ended with a
-        // barrier), one per run of equal buckets among a thread's keys -- an
-        // LDS atomic serves the lanes on one address one at a time, and in a
-        // skewed tile most lanes of a wave share a bucket
-        if (tid < 100) h[tid] = 0;
+        // one hundred or one thousand buckets: LDS atomics (block_minmax
+        // ended with a barrier), one per run of equal buckets among a
+        // thread's keys -- an LDS atomic serves the lanes on one address one
+        // at a time, and in a skewed tile most lanes of a wave share a bucket
+        for (int b = tid; b < NBK; b += NT) h[b] = 0;
         __syncthreads();
-        uint32_t rb = (uint32_t)bucket2_of(pl, ks[0]), rn = 0;
+        uint32_t rb = (uint32_t)bucket_of<NBK>(pl, ks[0]), rn = 0;
 #pragma unroll
-        for (int v = 0; v < kHistVT; v++) {
-            if (vec || tid + v * kHistNT < cnt) {
-                const uint32_t b = (uint32_t)bucket2_of(pl, ks[v]);
+        for (int v = 0; v < VT; v++) {
+            if (vec || tid + v * NT < cnt) {
+                const uint32_t b = (uint32_t)bucket_of<NBK>(pl, ks[v]);
                 if (b != rb) {
                     atomicAdd(&h[rb], rn);
                     rb = b;
@@ -419,7 +420,7 @@ __global__ __launch_bounds__(kHistNT) void k_range(Work<K> w) {
         }
         if (rn) atomicAdd(&h[rb], rn);
         __syncthreads();
-        if (tid < 100) w.counts[100 * (int64_t)(t - td.idx) + tid * td.nt + td.idx] = h[tid];
+        for (int b = tid; b < NBK; b += NT) w.counts[NBK * (int64_t)(t - td.idx) + (int64_t)b * td.nt + td.idx] = h[b];
     }
     if (tid == 0) w.tp[t] = plan_p(pl);
 }
@@ -453,7 +454,7 @@ __global__ __launch_bounds__(1024) void k_plans(Work<K> w) {
 template <typename K, int NBK>
 __global__ __launch_bounds__(kHistNT) void k_hist(Work<K> w, int64_t tiles_bound) {
     __shared__ uint32_t red[kHistNT / kWave][5];
-    __shared__ uint32_t h[NBK == 100 ? 100 : 1];
+    __shared__ uint32_t h[NBK >= 100 ? NBK : 1];
     __shared__ int64_t slow[kHistNT];
     __shared__ int nslow;
     const int tid = threadIdx.x;
@@ -477,10 +478,11 @@ __global__ __launch_bounds__(kHistNT) void k_hist(Work<K> w, int64_t tiles_bound
                 // the segment's).  Ten buckets: every key then has digit 0.
                 // One hundred: every key is in bucket 0 when the tile's p is
                 // at most a hundredth of the segment's; at a tenth the keys
-                // are counted again.
+                // are counted again.  One thousand: counted again (filling
+                // a thousand zeros here would take one thread as long).
                 const uint64_t ps = plan_p(pl);
                 const bool own = (w.ufix || pl.beta == 0) && tp != 0;
-                if (own && tp != ps && (NBK == 10 || tp <= ps / 100)) {
+                if (own && tp != ps && (NBK == 10 || (NBK == 100 && tp <= ps / 100))) {
                     uint32_t* out = w.counts + NBK * (t - td.idx) + td.idx;
                     out[0] = (uint32_t)td.cnt;
                     for (int d = 1; d < NBK; d++) out[d * td.nt] = 0;
@@ -503,12 +505,12 @@ __global__ __launch_bounds__(kHistNT) void k_hist(Work<K> w, int64_t tiles_bound
                 block_sum5<kHistNT>(wd, red);
                 if (tid < 10) w.counts[10 * (slow[k] - td.idx) + tid * td.nt + td.idx] = field16(wd, tid);
             } else {
-                if (tid < 100) h[tid] = 0;
+                for (int b = tid; b < NBK; b += kHistNT) h[b] = 0;
                 __syncthreads();
                 // one atomic per run of equal buckets, as in k_range
                 uint32_t rb = 0, rn = 0;
-                load_run<K, kHistNT, kHistTile>(w.keys + td.base, td.cnt, [&](int, K k) {
-                    const uint32_t b = (uint32_t)bucket2_of(pl, k);
+                load_run<K, kHistNT, PartShape<NBK>::HT>(w.keys + td.base, td.cnt, [&](int, K k) {
+                    const uint32_t b = (uint32_t)bucket_of<NBK>(pl, k);
                     if (b != rb) {
                         if (rn) atomicAdd(&h[rb], rn);
                         rb = b;
@@ -518,7 +520,8 @@ __global__ __launch_bounds__(kHistNT) void k_hist(Work<K> w, int64_t tiles_bound
                 });
                 if (rn) atomicAdd(&h[rb], rn);
                 __syncthreads();
-                if (tid < 100) w.counts[100 * (slow[k] - td.idx) + tid * td.nt + td.idx] = h[tid];
+                for (int b = tid; b < NBK; b += kHistNT)
+                    w.counts[NBK * (slow[k] - td.idx) + (int64_t)b * td.nt + td.idx] = h[b];
                 __syncthreads();
             }
         }
@@ -642,17 +645,16 @@ __device__ __forceinline__ void digit_pass(K* sk, uint32_t* sv, uint8_t* sd, uin
 
 // Stable one-step MSD scatter (Section 3.4: the master divides the keys into
 // ten parts by most significant digit; NBK = 100 is the finer two-digit
-// splitter).  Per tile: the keys are grouped by bucket in LDS -- ten buckets
-// by one counting pass on the digit, one hundred by two passes, first on the
-// second digit and then on the first (each pass stable, so the second keeps
-// the first's order inside a digit) -- and runs of consecutive keys are
-// written to their buckets in the scratch copy.  The bucket of a staged key
-// travels with it in a byte array, so each key's bucket is computed once.
-// Keys-only sorts with one hundred buckets place the keys by LDS cursors
-// instead: their scatter is not stable (nothing of it can be seen in the
-// sorted result), pairs keep the stable passes.
+// splitter, here for stable pairs).  Per tile: the keys are grouped by
+// bucket in LDS -- ten buckets by one counting pass on the digit, one
+// hundred by two passes, first on the second digit and then on the first
+// (each pass stable, so the second keeps the first's order inside a digit)
+// -- and runs of consecutive keys are written to their buckets in the
+// scratch copy.  The bucket of a staged key travels with it in a byte array,
+// so each key's bucket is computed once.
 template <typename K, bool PAIRS, int NBK>
 __global__ __launch_bounds__(kHistNT) void k_scatter(Work<K> w) {
+    static_assert(NBK == 10 || NBK == 100, "ten or one hundred buckets");
     constexpr int NT = kHistNT, VT = kHistVT, HT = kHistTile;
     __shared__ K sk[lds_padded_size<K>(HT)];
     __shared__ uint32_t sv[PAIRS ? HT : 1];
@@ -661,11 +663,7 @@ __global__ __launch_bounds__(kHistNT) void k_scatter(Work<K> w) {
     constexpr bool kOffsLds = sizeof(K) == 4 && !PAIRS;
     __shared__ int32_t dbase[NBK];  // element index (n < 2^31) of bucket d's run, minus its staging start
     __shared__ uint16_t offs[kOffsLds ? 10 : 1][NT];
-    // keys only with one hundred buckets: each bucket's next free staging slot
-    constexpr bool kCursor = NBK == 100 && !PAIRS;
-    __shared__ uint32_t cur[kCursor ? NBK : 1];
-    __shared__ int heavy;  // some bucket holds more than an eighth of the tile
-    const int t = blockIdx.x;
+    const int t = (int)xcd_unit(blockIdx.x, gridDim.x);
     const TileDesc td = w.tiles[t];
     if (td.cnt == 0) return;
     const int tid = threadIdx.x;
@@ -690,18 +688,10 @@ __global__ __launch_bounds__(kHistNT) void k_scatter(Work<K> w) {
     if constexpr (NBK == 10) {
         if (tid < 10) dbase[tid] = (int32_t)(td.seg_base + gp);
     } else {
-        // the tile's start of each bucket: exclusive scan of its counts (its
-        // barriers order the flag's reset before the writes of 1)
-        if (kCursor && tid == 0) heavy = 0;
+        // the tile's start of each bucket: exclusive scan of its counts
         uint32_t all;
         const uint32_t ls = block_excl_scan<uint32_t, NT>(cb, all, &red[0][0]);
-        if (tid < NBK) {
-            dbase[tid] = (int32_t)(td.seg_base + gp - (int64_t)ls);
-            if constexpr (kCursor) {
-                cur[tid] = ls;
-                if (8 * cb > (uint32_t)cnt) heavy = 1;
-            }
-        }
+        if (tid < NBK) dbase[tid] = (int32_t)(td.seg_base + gp - (int64_t)ls);
     }
     __syncthreads();
     uint32_t tot[5];
@@ -712,53 +702,6 @@ __global__ __launch_bounds__(kHistNT) void k_scatter(Work<K> w) {
                 const uint32_t d = (uint32_t)digit_of(pl, k);
                 return d | (d << 8);
             }, tot);
-        } else if constexpr (kCursor) {
-            // Keys only: the order of the keys inside a bucket cannot be seen
-            // in the result (equal keys are identical, and the local sorts
-            // order the rest), so each key takes the next slot of its bucket
-            // from an LDS cursor (one atomic add with return) in place of the
-            // two stable counting passes; the tile's counts give every
-            // bucket exactly its slots.
-            K key[VT];
-            uint32_t bk[VT];
-#pragma unroll
-            for (int v = 0; v < VT; v++) {
-                const int q = tid * VT + v;
-                key[v] = sk[lds_pad<K>(F || q < cnt ? q : 0)];
-                bk[v] = (uint32_t)bucket2_of(pl, key[v]);
-            }
-            __syncthreads();  // every key is read before any slot is written
-            if (heavy) {
-                // lanes on one LDS address are served one at a time, so when
-                // a bucket is large each run of equal buckets among a
-                // thread's consecutive keys takes all its slots at once
-                uint32_t len[VT];
-                len[VT - 1] = 1;
-#pragma unroll
-                for (int v = VT - 2; v >= 0; v--)
-                    len[v] = bk[v] == bk[v + 1] && (F || tid * VT + v + 1 < cnt) ? len[v + 1] + 1 : 1u;
-                uint32_t slot = 0;
-#pragma unroll
-                for (int v = 0; v < VT; v++) {
-                    if (F || tid * VT + v < cnt) {
-                        if (v == 0 || bk[v] != bk[v - 1])
-                            slot = atomicAdd(&cur[bk[v]], len[v]);
-                        else
-                            slot++;
-                        sk[lds_pad<K>((int)slot)] = key[v];
-                        sd[slot] = (uint8_t)bk[v];
-                    }
-                }
-            } else {
-#pragma unroll
-                for (int v = 0; v < VT; v++) {
-                    if (F || tid * VT + v < cnt) {
-                        const uint32_t slot = atomicAdd(&cur[bk[v]], 1u);
-                        sk[lds_pad<K>((int)slot)] = key[v];
-                        sd[slot] = (uint8_t)bk[v];
-                    }
-                }
-            }
         } else {
             // pass 1 on the second digit, pass 2 on the first; b = 10 d1 + d2
             // (d1 = b * 205 >> 11, exact for b < 100)
@@ -807,6 +750,143 @@ __global__ __launch_bounds__(kHistNT) void k_scatter(Work<K> w) {
         write_out(std::true_type{});
     else
         write_out(std::false_type{});
+}
+
+// Keys-only scatter with one hundred or one thousand buckets.  The order of
+// the keys inside a bucket cannot be seen in the result (equal keys are
+// identical, and the local sorts order the rest), so no stable pass is
+// needed: each thread holds its keys in registers (read straight from
+// memory), takes the next slots of their buckets from LDS cursors (the tile's
+// counts give every bucket exactly its slots), stages them there, and the
+// staged runs go out coalesced.  Lanes on one LDS address are served one at
+// a time, so in a tile where some bucket is large each run of equal buckets
+// among a thread's keys takes all its slots with one atomic add.  One
+// hundred buckets keep each staged key's bucket in a byte; one thousand
+// recompute it from the key on the way out (two bytes a key would cost the
+// second resident workgroup).
+template <typename K, int NBK>
+__global__ __launch_bounds__(ScatterShape<NBK>::NT) void k_scatter_keys(Work<K> w) {
+    static_assert(NBK == 100 || NBK == 1000, "one hundred or one thousand buckets");
+    constexpr int NT = ScatterShape<NBK>::NT, VT = ScatterShape<NBK>::VT, HT = NT * VT;
+    static_assert(HT == PartShape<NBK>::HT, "the scatter tile is the partition tile");
+    constexpr int BPT = (NBK + NT - 1) / NT;  // buckets per thread for the counts scan
+    constexpr bool kTag = NBK <= 256;
+    using V = typename Vec16<K>::type;
+    constexpr int E = Vec16<K>::n;
+    __shared__ K sk[lds_padded_size<K>(HT)];
+    __shared__ __align__(16) uint8_t sd[kTag ? HT : 1];
+    __shared__ uint32_t red[NT / kWave][5];
+    __shared__ int32_t dbase[NBK];  // element index (n < 2^31) of bucket b's run, minus its staging start
+    __shared__ uint32_t cur[NBK];   // bucket b's next free staging slot
+    __shared__ int heavy;           // some bucket holds more than an eighth of the tile
+    const int t = (int)xcd_unit(blockIdx.x, gridDim.x);
+    const TileDesc td = w.tiles[t];
+    if (td.cnt == 0) return;
+    const int tid = threadIdx.x;
+    const int i = td.idx;
+    const int nt = td.nt;
+    const int cnt = td.cnt;
+    const DigitPlan<K> pl = w.plans[td.seg];
+    const int64_t pbase = NBK * (int64_t)(t - i);
+    // the tile's write offset and count in buckets tid*BPT .. tid*BPT+BPT-1
+    uint32_t cb[BPT];
+    int64_t gp[BPT];
+#pragma unroll
+    for (int j = 0; j < BPT; j++) {
+        const int b = tid * BPT + j;
+        cb[j] = 0;
+        gp[j] = 0;
+        if (b < NBK) {
+            gp[j] = w.pos[pbase + (int64_t)b * nt + i] - w.pos[pbase];
+            cb[j] = w.counts[pbase + (int64_t)b * nt + i];
+        }
+    }
+    // the keys, straight into registers: a full, 16-byte aligned tile in
+    // 16-byte vectors (consecutive threads on consecutive vectors), any other
+    // strided by element (key v of a thread is element tid + v*NT)
+    const K* src = w.keys + td.base;
+    K ks[VT];
+    const bool vec = cnt == HT && ((uintptr_t)src & 15) == 0;
+    if (vec) {
+        const V* sv = reinterpret_cast<const V*>(src);
+#pragma unroll
+        for (int j = 0; j < VT / E; j++) {
+            const V x = sv[tid + j * NT];
+#pragma unroll
+            for (int e = 0; e < E; e++) ks[j * E + e] = (K)Vec16<K>::get(x, e);
+        }
+    } else {
+#pragma unroll
+        for (int v = 0; v < VT; v++) {
+            const int q = tid + v * NT;
+            ks[v] = q < cnt ? src[q] : src[0];
+        }
+    }
+    // the tile's start of each bucket: exclusive scan of its counts (its
+    // barriers order the flag's reset before the writes of 1)
+    if (tid == 0) heavy = 0;
+    {
+        uint32_t mine = 0;
+#pragma unroll
+        for (int j = 0; j < BPT; j++) mine += cb[j];
+        uint32_t all;
+        uint32_t ls = block_excl_scan<uint32_t, NT>(mine, all, &red[0][0]);
+#pragma unroll
+        for (int j = 0; j < BPT; j++) {
+            const int b = tid * BPT + j;
+            if (b < NBK) {
+                dbase[b] = (int32_t)(td.seg_base + gp[j] - (int64_t)ls);
+                cur[b] = ls;
+                if (8 * cb[j] > (uint32_t)cnt) heavy = 1;
+            }
+            ls += cb[j];
+        }
+    }
+    uint32_t bk[VT];
+#pragma unroll
+    for (int v = 0; v < VT; v++) bk[v] = (uint32_t)bucket_of<NBK>(pl, ks[v]);
+    __syncthreads();
+    // key v is real when the tile is full or tid + v*NT < cnt (so the real
+    // keys of a thread are its first ones)
+    if (heavy) {
+        uint32_t len[VT];
+        len[VT - 1] = 1;
+#pragma unroll
+        for (int v = VT - 2; v >= 0; v--)
+            len[v] = bk[v] == bk[v + 1] && (vec || tid + (v + 1) * NT < cnt) ? len[v + 1] + 1 : 1u;
+        uint32_t slot = 0;
+#pragma unroll
+        for (int v = 0; v < VT; v++) {
+            if (vec || tid + v * NT < cnt) {
+                if (v == 0 || bk[v] != bk[v - 1])
+                    slot = atomicAdd(&cur[bk[v]], len[v]);
+                else
+                    slot++;
+                sk[lds_pad<K>((int)slot)] = ks[v];
+                if constexpr (kTag) sd[slot] = (uint8_t)bk[v];
+            }
+        }
+    } else {
+#pragma unroll
+        for (int v = 0; v < VT; v++) {
+            if (vec || tid + v * NT < cnt) {
+                const uint32_t slot = atomicAdd(&cur[bk[v]], 1u);
+                sk[lds_pad<K>((int)slot)] = ks[v];
+                if constexpr (kTag) sd[slot] = (uint8_t)bk[v];
+            }
+        }
+    }
+    __syncthreads();
+    // coalesced runs out to the buckets
+#pragma unroll
+    for (int j = 0; j < VT; j++) {
+        const int q = j * NT + tid;
+        if (q < cnt) {
+            const K k = sk[lds_pad<K>(q)];
+            const int b = kTag ? (int)sd[q] : bucket_of<NBK>(pl, k);
+            w.skeys[(uint32_t)(dbase[b] + q)] = k;
+        }
+    }
 }
 
 // Materialises the flat list of local-sort partitions (one thread per slot).
@@ -1676,10 +1756,16 @@ hipError_t launch_setup(const Work<K>& w, int64_t* own_off, hipStream_t st) {
 
 template <typename K>
 hipError_t launch_range(const Work<K>& w, int64_t tiles_bound, hipStream_t st) {
-    if (w.nbk == 100)
+    if (w.nbk == 1000) {
+        if constexpr (sizeof(K) == 4)
+            k_range<K, 1000><<<grid_of(tiles_bound), PartShape<1000>::NT, 0, st>>>(w);
+        else
+            return hipErrorInvalidValue;  // one thousand buckets: 32-bit keys only
+    } else if (w.nbk == 100) {
         k_range<K, 100><<<grid_of(tiles_bound), kHistNT, 0, st>>>(w);
-    else
+    } else {
         k_range<K, 10><<<grid_of(tiles_bound), kHistNT, 0, st>>>(w);
+    }
     return hipGetLastError();
 }
 
@@ -1693,10 +1779,16 @@ hipError_t launch_plans(const Work<K>& w, hipStream_t st) {
 template <typename K>
 hipError_t launch_hist(const Work<K>& w, int64_t tiles_bound, hipStream_t st) {
     const int g = grid_of(tiles_bound < kHistGrid ? tiles_bound : kHistGrid);
-    if (w.nbk == 100)
+    if (w.nbk == 1000) {
+        if constexpr (sizeof(K) == 4)
+            k_hist<K, 1000><<<g, kHistNT, 0, st>>>(w, tiles_bound);
+        else
+            return hipErrorInvalidValue;
+    } else if (w.nbk == 100) {
         k_hist<K, 100><<<g, kHistNT, 0, st>>>(w, tiles_bound);
-    else
+    } else {
         k_hist<K, 10><<<g, kHistNT, 0, st>>>(w, tiles_bound);
+    }
     return hipGetLastError();
 }
 
@@ -1709,10 +1801,19 @@ hipError_t launch_btab(const Work<K>& w, hipStream_t st) {
 
 template <typename K, bool PAIRS>
 hipError_t launch_scatter(const Work<K>& w, int64_t tiles_bound, hipStream_t st) {
-    if (w.nbk == 100)
-        k_scatter<K, PAIRS, 100><<<grid_of(tiles_bound), kHistNT, 0, st>>>(w);
-    else
+    if (w.nbk == 1000) {
+        if constexpr (sizeof(K) == 4 && !PAIRS)
+            k_scatter_keys<K, 1000><<<grid_of(tiles_bound), ScatterShape<1000>::NT, 0, st>>>(w);
+        else
+            return hipErrorInvalidValue;  // one thousand buckets: 32-bit keys only
+    } else if (w.nbk == 100) {
+        if constexpr (PAIRS)
+            k_scatter<K, true, 100><<<grid_of(tiles_bound), kHistNT, 0, st>>>(w);
+        else
+            k_scatter_keys<K, 100><<<grid_of(tiles_bound), ScatterShape<100>::NT, 0, st>>>(w);
+    } else {
         k_scatter<K, PAIRS, 10><<<grid_of(tiles_bound), kHistNT, 0, st>>>(w);
+    }
     return hipGetLastError();
 }
 

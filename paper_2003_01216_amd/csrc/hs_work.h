@@ -13,6 +13,25 @@ constexpr int kHistVT = 16;
 constexpr int kHistTile = kHistNT * kHistVT;
 constexpr int64_t kHistGrid = 8192;  // workgroups of the histogram pass (it strides over the tiles)
 
+// Partition tiles (range counts, histogram, scatter) by the number of
+// buckets: 256 threads x 16 keys for ten and one hundred; 1024 x 16 for one
+// thousand, so that the per-tile counts (one word per bucket and tile) stay
+// near a sixteenth of the keys.
+template <int NBK>
+struct PartShape {
+    static constexpr int NT = NBK == 1000 ? 1024 : kHistNT;
+    static constexpr int VT = kHistVT;
+    static constexpr int HT = NT * VT;
+};
+// Threads and keys per thread of the keys-only scatter on those tiles (512
+// x 32 with one thousand buckets: two workgroups fit a CU's LDS and
+// registers).
+template <int NBK>
+struct ScatterShape {
+    static constexpr int NT = NBK == 1000 ? 512 : kHistNT;
+    static constexpr int VT = PartShape<NBK>::HT / NT;
+};
+
 // One histogram tile of a large segment (range, histogram and scatter read it).
 struct TileDesc {
     int64_t base;      // first key of the tile
@@ -120,7 +139,8 @@ struct Work {
     int32_t* rounds;  // largest number of merge rounds any bucket needs
     uint32_t* err;   // device-side validation flag (bad offsets)
 
-    int32_t nbk;        // buckets per segment: 10 (one decimal digit) or 100 (two)
+    int32_t nbk;        // buckets per segment: 10 (one decimal digit), 100 (two) or 1000 (three)
+    int32_t ptile;      // keys per partition tile (PartShape<nbk>::HT)
     int32_t ufix;       // keys are images of unsigned keys: beta fixed at the type's minimum
     int32_t tile;       // keys per local-sort tile (T)
     int32_t fanin;      // runs merged per round: 2 or 4

@@ -1,7 +1,7 @@
 // Host-side check of the GPU library's decimal digit rules (hs_device.h):
-// digit_of (ten buckets), bucket2_of (one hundred) and bucket_span, for
-// int32 and int64 keys, against integer division by powers of ten written
-// out here.  Plans come from make_digit_plan(min, max) of each case; keys
+// digit_of (ten buckets), bucket2_of (one hundred), bucket3_of (one
+// thousand, int32 keys) and bucket_span, for int32 and int64 keys, against
+// integer division by powers of ten written out here.  Plans come from make_digit_plan(min, max) of each case; keys
 // cover the edges c*q - 1, c*q, c*q + 1 of every bucket and random values.
 // Prints the number of mismatches and exits non-zero if there are any.
 #include <stdint.h>
@@ -47,13 +47,21 @@ static void check_key(const hs::DigitPlan<K>& pl, K mn, K mx, K k) {
     uint64_t lo1, w1, lo2, w2;
     hs::bucket_span(pl, 10, want1, lo1, w1);
     hs::bucket_span(pl, 100, want2, lo2, w2);
-    const bool span_ok = u >= lo1 && u - lo1 < w1 && u >= lo2 && u - lo2 < w2;
+    bool span_ok = u >= lo1 && u - lo1 < w1 && u >= lo2 && u - lo2 < w2;
+    int got3 = 0, want3 = 0;
+    if constexpr (sizeof(K) == 4) {
+        want3 = D <= 2 ? (int)(u * pow10u(3 - D)) : (int)(u / pow10u(D - 3));
+        got3 = hs::bucket3_of(pl, k);
+        uint64_t lo3, w3;
+        hs::bucket_span(pl, 1000, want3, lo3, w3);
+        span_ok = span_ok && u >= lo3 && u - lo3 < w3;
+    }
     g_checked++;
-    if (got1 != want1 || got2 != want2 || !span_ok || hs::plan_p(pl) != p) {
+    if (got1 != want1 || got2 != want2 || got3 != want3 || !span_ok || hs::plan_p(pl) != p) {
         if (g_bad < 10)
-            printf("mismatch: %d-bit min %lld max %lld key %lld: digit %d/%d bucket2 %d/%d span %d\n",
-                   (int)(8 * sizeof(K)), (long long)mn, (long long)mx, (long long)k, got1, want1, got2, want2,
-                   (int)span_ok);
+            printf("mismatch: %d-bit min %lld max %lld key %lld: digit %d/%d bucket2 %d/%d bucket3 %d/%d span %d\n",
+                   (int)(8 * sizeof(K)), (long long)mn, (long long)mx, (long long)k, got1, want1, got2, want2, got3,
+                   want3, (int)span_ok);
         g_bad++;
     }
 }
@@ -82,6 +90,18 @@ static void check_case(K mn, K mx) {
             const U u = e + (U)dlt;
             if ((dlt < 0 && e == 0) || (dlt > 0 && u < e)) continue;
             if (in_range(u)) check_key<K>(pl, mn, mx, key_of(u));
+        }
+    }
+    if constexpr (sizeof(K) == 4) {  // the edges of every three-digit bucket
+        const U q3 = p >= 100 ? p / 100 : 1;
+        for (U c = 0; c <= 999; c++) {
+            if (c > (~U(0)) / q3) break;
+            const U e = c * q3;
+            for (int dlt = -1; dlt <= 1; dlt++) {
+                const U u = e + (U)dlt;
+                if ((dlt < 0 && e == 0) || (dlt > 0 && u < e)) continue;
+                if (in_range(u)) check_key<K>(pl, mn, mx, key_of(u));
+            }
         }
     }
     for (int r = 0; r < 2000; r++) {

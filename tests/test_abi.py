@@ -98,17 +98,24 @@ def test_config_roundtrip(lib):
     assert [hs.hsort_size_class(n) for n in (1, 1 << 18, (1 << 18) + 1, 1 << 22, 1 << 26, 1 << 28)] == [0, 0, 1, 1, 2, 3]
     cfg = hs.hsort_get_config(hs.KEYS_I32, size_class=3)
     t, tvt, m, mvt, s, fanin, digits, local = cfg
-    assert t % m == 0 and s <= 8192 and t % tvt == 0 and m % mvt == 0 and fanin in (2, 4) and digits in (1, 2)
+    assert t % m == 0 and s <= 8192 and t % tvt == 0 and m % mvt == 0 and fanin in (2, 4) and digits in (1, 2, 3)
     with pytest.raises(hs.HsortError):
         hs.hsort_set_config(hs.KEYS_I32, 1000, 16, 4096, 16, 100)
     with pytest.raises(hs.HsortError):  # merge chunk does not divide the tile
         hs.hsort_set_config(hs.KEYS_I32, 4096, 16, 8192, 32, 100)
     with pytest.raises(hs.HsortError):  # fan-in must be 2 or 4
         hs.hsort_set_config(hs.KEYS_I32, t, tvt, m, mvt, s, fanin=3, size_class=3)
-    with pytest.raises(hs.HsortError):  # digits must be 1 or 2
-        hs.hsort_set_config(hs.KEYS_I32, t, tvt, m, mvt, s, fanin=fanin, digits=3, size_class=3)
-    hs.hsort_set_config(hs.KEYS_I32, t, tvt, m, mvt, s, fanin=4, digits=3 - digits, size_class=3)
-    assert hs.hsort_get_config(hs.KEYS_I32, size_class=3)[5:] == (4, 3 - digits, local)
+    with pytest.raises(hs.HsortError):  # digits must be 1, 2 or 3
+        hs.hsort_set_config(hs.KEYS_I32, t, tvt, m, mvt, s, fanin=fanin, digits=4, size_class=3)
+    with pytest.raises(hs.HsortError):  # one thousand buckets: plain int32 keys only
+        hs.hsort_set_config(hs.SEG_I32, t, tvt, m, mvt, s, fanin=fanin, digits=3, size_class=3)
+    with pytest.raises(hs.HsortError):
+        hs.hsort_set_config(hs.PAIRS_I32_U32, 4096, 16, 4096, 16, 4096, fanin=4, digits=3, size_class=3)
+    with pytest.raises(hs.HsortError):
+        hs.hsort_set_config(hs.KEYS_I64, 4096, 16, 4096, 16, 4096, fanin=4, digits=3, size_class=3)
+    for d in (1, 2, 3):
+        hs.hsort_set_config(hs.KEYS_I32, t, tvt, m, mvt, s, fanin=4, digits=d, size_class=3)
+        assert hs.hsort_get_config(hs.KEYS_I32, size_class=3)[5:] == (4, d, local)
     with pytest.raises(hs.HsortError):  # local must be 0 or 1
         hs.hsort_set_config(hs.KEYS_I32, t, tvt, m, mvt, s, fanin=fanin, local=2, size_class=3)
     with pytest.raises(hs.HsortError):  # no bottom-up local sort of this shape

@@ -1,11 +1,12 @@
 """The GPU library's decimal digit rules, checked on the host.
 
 `tests/host/digit_rule_check.cpp` includes the library's device header and
-compares digit_of (ten buckets), bucket2_of (one hundred buckets) and
-bucket_span with integer division by powers of ten written out in the check
-itself, for int32 and int64 keys over every digit count, the edges of every
-bucket, negative minima and the types' extremes (the one-step rule of
-Section 3.4 and its two-digit refinement).  No GPU is needed: the functions
+compares digit_of (ten buckets), bucket2_of (one hundred buckets),
+bucket3_of (one thousand, int32 keys) and bucket_span with integer division
+by powers of ten written out in the check itself, for int32 and int64 keys
+over every digit count, the edges of every bucket, negative minima and the
+types' extremes (the one-step rule of Section 3.4 and its two- and
+three-digit refinements).  No GPU is needed: the functions
 are host-callable and the program launches nothing.
 """
 import os
