@@ -197,6 +197,19 @@ def tune(kinds, classes, quick=False, reps=5, log=print):
     return table, report
 
 
+def read_table(path):
+    """{(kind, class): config tuple} of an existing tuning file (missing columns take their defaults)."""
+    table = {}
+    with open(path) as f:
+        for line in f:
+            if not line.strip() or line.startswith("#"):
+                continue
+            x = [int(v) for v in line.split()]
+            cfg = tuple(x[2:10]) + (1, 0)[len(x) - 8:] if len(x) < 10 else tuple(x[2:10])
+            table[(x[0], x[1])] = cfg
+    return table
+
+
 def write_table(table, path, report=None, report_path=None):
     lines = ["# hsort tuning table: kind size_class tile tile_vt merge_nv merge_vt small_max fanin digits local",
              f"# written by paper_2003_01216_amd.autotune on {time.strftime('%Y-%m-%d %H:%M:%S')}"]
@@ -218,12 +231,16 @@ def main(argv=None):
     ap.add_argument("--kinds", default="keys_i32,keys_i64,pairs_i32,seg_i32,seg_i64,pairs_i64")
     ap.add_argument("--classes", default="0,1,2,3")
     ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--update", action="store_true",
+                    help="keep the rows of the existing --out file that this run does not tune")
     args = ap.parse_args(argv)
     by_name = {v: k for k, v in NAMES.items()}
     kinds = [by_name[k] for k in args.kinds.split(",")]
     classes = [int(c) for c in args.classes.split(",")]
     t0 = time.time()
     table, report = tune(kinds, classes, args.quick, args.reps, log=lambda m: print(m, flush=True))
+    if args.update and os.path.exists(args.out):
+        table = {**read_table(args.out), **table}
     write_table(table, args.out, report, args.report)
     print(f"wrote {args.out} ({len(table)} entries) in {time.time() - t0:.0f} s", flush=True)
     return 0

@@ -1616,17 +1616,20 @@ __global__ __launch_bounds__(256) void k_image(K* keys, int64_t n, int mode, int
 // ------------------------------------------------------------ device scan
 // Exclusive prefix sum of `in` (length L read on the device as
 // len_mul * *len_ptr, or len_const when len_ptr is null); out[L] = total.
+// Sums of kScanTile-value blocks are scanned the same way, level by level,
+// so a level's length is ceil(L / per) with per = kScanTile^level.
 constexpr int kScanNT = 256, kScanVT = 16, kScanTile = kScanNT * kScanVT;
 constexpr int kScanTopNT = 1024, kScanTopVT = 16;
 
-__device__ __forceinline__ int64_t scan_len(const ScanSpec& sp) {
-    return sp.len_ptr ? sp.len_mul * (int64_t)(*sp.len_ptr) : sp.len_const;
+__device__ __forceinline__ int64_t scan_len(const ScanSpec& sp, int64_t per) {
+    const int64_t L = sp.len_ptr ? sp.len_mul * (int64_t)(*sp.len_ptr) : sp.len_const;
+    return (L + per - 1) / per;
 }
 
 template <typename Tin, typename Tout>
-__global__ __launch_bounds__(kScanNT) void k_scan_reduce(ScanSpec sp, const Tin* in, Tout* partial) {
+__global__ __launch_bounds__(kScanNT) void k_scan_reduce(ScanSpec sp, const Tin* in, Tout* partial, int64_t per) {
     __shared__ Tout red[kScanNT / kWave];
-    const int64_t L = scan_len(sp);
+    const int64_t L = scan_len(sp, per);
     const int64_t b0 = (int64_t)blockIdx.x * kScanTile;
     if (b0 >= L) return;
     Tout s = 0;
@@ -1648,10 +1651,9 @@ __global__ __launch_bounds__(kScanNT) void k_scan_reduce(ScanSpec sp, const Tin*
 // One workgroup: exclusive scan of up to kScanTopNT*kScanTopVT values in
 // place (the partials, or a short input when in != out).
 template <typename Tin, typename Tout>
-__global__ __launch_bounds__(kScanTopNT) void k_scan_single(ScanSpec sp, const Tin* in, Tout* out, int per_block) {
+__global__ __launch_bounds__(kScanTopNT) void k_scan_single(ScanSpec sp, const Tin* in, Tout* out, int64_t per) {
     __shared__ Tout red[kScanTopNT / kWave];
-    const int64_t Lfull = scan_len(sp);
-    const int64_t L = per_block > 0 ? (Lfull + per_block - 1) / per_block : Lfull;
+    const int64_t L = scan_len(sp, per);
     const int tid = threadIdx.x;
     Tout v[kScanTopVT];
     Tout run = 0;
@@ -1672,29 +1674,66 @@ __global__ __launch_bounds__(kScanTopNT) void k_scan_single(ScanSpec sp, const T
     if (tid == 0) out[L] = total;
 }
 
+// A thread scans kScanVT consecutive values; where they lie wholly inside
+// [0, L) and both arrays are 16-byte aligned there, they move in 16-byte
+// vectors (the scratch arrays are), else element by element.
 template <typename Tin, typename Tout>
-__global__ __launch_bounds__(kScanNT) void k_scan_down(ScanSpec sp, const Tin* in, const Tout* partial, Tout* out) {
+__global__ __launch_bounds__(kScanNT) void k_scan_down(ScanSpec sp, const Tin* in, const Tout* partial, Tout* out,
+                                                       int64_t per) {
+    static_assert(sizeof(Tin) == 4 || sizeof(Tin) == 8, "4- or 8-byte values");
     __shared__ Tout red[kScanNT / kWave];
-    const int64_t L = scan_len(sp);
+    const int64_t L = scan_len(sp, per);
     const int64_t b0 = (int64_t)blockIdx.x * kScanTile;
     if (L == 0 && blockIdx.x == 0 && threadIdx.x == 0) out[0] = 0;
     if (b0 >= L) return;
     const int tid = threadIdx.x;
+    const int64_t q0 = b0 + (int64_t)tid * kScanVT;
+    const bool vec = q0 + kScanVT <= L && ((uintptr_t)(in + q0) & 15) == 0 && ((uintptr_t)(out + q0) & 15) == 0;
     Tout v[kScanVT];
     Tout run = 0;
+    if (vec) {
+        constexpr int PIN = 16 / sizeof(Tin);  // inputs per 16-byte vector
+        const uint4* src = reinterpret_cast<const uint4*>(in + q0);
 #pragma unroll
-    for (int i = 0; i < kScanVT; i++) {
-        const int64_t q = b0 + (int64_t)tid * kScanVT + i;
-        v[i] = q < L ? (Tout)in[q] : Tout(0);
-        run += v[i];
+        for (int j = 0; j < kScanVT / PIN; j++) {
+            const uint4 x = src[j];
+            Tin a[PIN];
+            __builtin_memcpy(a, &x, 16);
+#pragma unroll
+            for (int e = 0; e < PIN; e++) v[PIN * j + e] = (Tout)a[e];
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < kScanVT; i++) {
+            const int64_t q = q0 + i;
+            v[i] = q < L ? (Tout)in[q] : Tout(0);
+        }
     }
+#pragma unroll
+    for (int i = 0; i < kScanVT; i++) run += v[i];
     Tout total;
     Tout pre = block_excl_scan<Tout, kScanNT>(run, total, red) + partial[blockIdx.x];
+    Tout o[kScanVT];
 #pragma unroll
     for (int i = 0; i < kScanVT; i++) {
-        const int64_t q = b0 + (int64_t)tid * kScanVT + i;
-        if (q < L) out[q] = pre;
+        o[i] = pre;
         pre += v[i];
+    }
+    if (vec) {
+        constexpr int PER = 16 / sizeof(Tout);  // outputs per 16-byte vector
+        uint4* dst = reinterpret_cast<uint4*>(out + q0);
+#pragma unroll
+        for (int j = 0; j < kScanVT / PER; j++) {
+            uint4 x;
+            __builtin_memcpy(&x, &o[j * PER], 16);
+            dst[j] = x;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < kScanVT; i++) {
+            const int64_t q = q0 + i;
+            if (q < L) out[q] = o[i];
+        }
     }
     const int64_t nblk = (L + kScanTile - 1) / kScanTile;
     if (blockIdx.x == nblk - 1 && tid == 0) out[L] = partial[nblk];
@@ -1709,30 +1748,41 @@ __global__ void k_copy(const uint4* __restrict__ src, uint4* __restrict__ dst, i
 // =================================================================== host
 static inline int cdiv64(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
+// One level: a single workgroup when the level fits one, else block sums
+// into `partial`, their own scan in place (the next level's partials after
+// them), and the down-sweep.
 template <typename Tin, typename Tout>
 static hipError_t scan_impl(const ScanSpec& sp, int64_t len_bound, const Tin* in, Tout* out, Tout* partial,
-                            hipStream_t st) {
+                            int64_t per, hipStream_t st) {
     if (len_bound <= (int64_t)kScanTopNT * kScanTopVT) {
-        k_scan_single<Tin, Tout><<<1, kScanTopNT, 0, st>>>(sp, in, out, 0);
+        k_scan_single<Tin, Tout><<<1, kScanTopNT, 0, st>>>(sp, in, out, per);
         return hipGetLastError();
     }
-    const int nblk = cdiv64(len_bound, kScanTile);
-    if (nblk > kScanTopNT * kScanTopVT) return hipErrorInvalidValue;
-    k_scan_reduce<Tin, Tout><<<nblk, kScanNT, 0, st>>>(sp, in, partial);
-    k_scan_single<Tout, Tout><<<1, kScanTopNT, 0, st>>>(sp, partial, partial, kScanTile);
-    k_scan_down<Tin, Tout><<<nblk, kScanNT, 0, st>>>(sp, in, partial, out);
+    const int64_t nblk = cdiv64(len_bound, kScanTile);
+    k_scan_reduce<Tin, Tout><<<(unsigned)nblk, kScanNT, 0, st>>>(sp, in, partial, per);
+    const hipError_t e = scan_impl<Tout, Tout>(sp, nblk, partial, partial, partial + nblk + 1, per * kScanTile, st);
+    if (e != hipSuccess) return e;
+    k_scan_down<Tin, Tout><<<(unsigned)nblk, kScanNT, 0, st>>>(sp, in, partial, out, per);
     return hipGetLastError();
 }
 
 hipError_t launch_scan_i32(const ScanSpec& sp, int64_t len_bound, const int32_t* in, int32_t* out, int32_t* partial,
                            hipStream_t st) {
-    return scan_impl<int32_t, int32_t>(sp, len_bound, in, out, partial, st);
+    return scan_impl<int32_t, int32_t>(sp, len_bound, in, out, partial, 1, st);
 }
 hipError_t launch_scan_u32_i64(const ScanSpec& sp, int64_t len_bound, const uint32_t* in, int64_t* out,
                                int64_t* partial, hipStream_t st) {
-    return scan_impl<uint32_t, int64_t>(sp, len_bound, in, out, partial, st);
+    return scan_impl<uint32_t, int64_t>(sp, len_bound, in, out, partial, 1, st);
 }
-int64_t scan_partial_count(int64_t len_bound) { return cdiv64(len_bound, kScanTile) + 1; }
+// Partials of every level (each level's block sums and its total).
+int64_t scan_partial_count(int64_t len_bound) {
+    int64_t c = 0;
+    while (len_bound > (int64_t)kScanTopNT * kScanTopVT) {
+        len_bound = cdiv64(len_bound, kScanTile);
+        c += len_bound + 1;
+    }
+    return c + 1;
+}
 
 static int cu_count() {
     static int cus = 0;

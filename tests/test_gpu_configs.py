@@ -1,10 +1,10 @@
 """Every configuration the autotuner can pick (local-sort tile shape, merge
-shape, fan-in 2 or 4, small-segment threshold, ten or one hundred buckets)
+shape, fan-in 2 or 4, small-segment threshold, ten, one hundred or one thousand buckets)
 sorts bit-exactly like the oracle, so a tuning table can select none that is
 untested.  Inputs are sized so that the largest bucket holds more than four
 local-sort tiles (two fan-in-4 rounds, three fan-in-2 rounds) and end in a
-ragged tile; with one hundred buckets, four fifths of the keys are drawn from
-the lowest two-digit bucket so that it still needs merge rounds."""
+ragged tile; with one hundred or one thousand buckets, four fifths of the
+keys are drawn from the lowest bucket so that it still needs merge rounds."""
 import sys
 
 import numpy as np
@@ -34,9 +34,13 @@ def _cands(kind):
 
 def skew(keys, cfg, lo, width, seed):
     """With one hundred buckets (cfg[6] == 2), put four fifths of the keys in
-    [lo, lo + width), the lowest two-digit bucket of the array's plan."""
-    if cfg[6] != 2:
+    [lo, lo + width), the lowest two-digit bucket of the array's plan; with
+    one thousand (cfg[6] == 3) in the lowest three-digit bucket, a tenth of
+    that."""
+    if cfg[6] == 1:
         return keys
+    if cfg[6] == 3:
+        width //= 10
     r = np.random.default_rng(seed)
     k = keys.copy()
     m = r.random(k.size) < 0.8
