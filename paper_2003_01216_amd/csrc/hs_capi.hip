@@ -216,10 +216,11 @@ int64_t partition_tile(const Config& c) { return c.digits == 3 ? PartShape<1000>
 
 struct Layout {
     // byte offsets into scratch
-    size_t err, own_off, skeys, svals, tmin, tmax, tp, smpf, smpl, rounds, plans, tilecnt, tilepre, bounds, counts, pos, bstart, bsize, tsc,
-        tsp, mcc, msp, tiles, sdesc, mdesc, ssorted, part32, part64, total;
+    size_t err, own_off, skeys, svals, tmin, tmax, tp, smpf, smpl, rounds, plans, tilecnt, tilepre, groupcnt, grouppre,
+        bounds, counts, intra, gsum, gpos, gbase, bstart, bsize, tsc, tsp, mcc, msp, tiles, sdesc, mdesc, ssorted, part32,
+        part64, total;
     // item bounds
-    int64_t large_bound, tiles_bound, buckets, ts_bound, chunks_bound;
+    int64_t large_bound, tiles_bound, groups_bound, buckets, ts_bound, chunks_bound;
 };
 
 Layout make_layout(int kind, int64_t n, int64_t nseg, const Config& c) {
@@ -233,6 +234,7 @@ Layout make_layout(int kind, int64_t n, int64_t nseg, const Config& c) {
     L.large_bound = std::min<int64_t>(nseg, std::max<int64_t>(1, n / (c.small_max + 1)));
     const int64_t nbk = buckets_of(c);
     L.tiles_bound = cdiv(n, partition_tile(c)) + L.large_bound;
+    L.groups_bound = cdiv(L.tiles_bound, kGroupTiles) + L.large_bound;
     L.buckets = nbk * nseg;
     L.ts_bound = cdiv(n, c.tile) + nbk * L.large_bound;
     L.chunks_bound = cdiv(n, c.merge_nv) + nbk * L.large_bound;
@@ -256,8 +258,13 @@ Layout make_layout(int kind, int64_t n, int64_t nseg, const Config& c) {
     L.plans = take((ksz == 8 ? sizeof(DigitPlan<int64_t>) : sizeof(DigitPlan<int32_t>)) * nseg);
     L.tilecnt = take(4 * nseg);
     L.tilepre = take(4 * (nseg + 1));
+    L.groupcnt = take(4 * nseg);
+    L.grouppre = take(4 * (nseg + 1));
     L.counts = take(4 * nbk * L.tiles_bound);
-    L.pos = take(8 * (nbk * L.tiles_bound + 1));
+    L.intra = take(4 * nbk * L.tiles_bound);
+    L.gsum = take(4 * nbk * L.groups_bound);
+    L.gpos = take(8 * (nbk * L.groups_bound + 1));
+    L.gbase = take(4 * nbk * L.groups_bound);
     L.bstart = take(8 * L.buckets);
     L.bsize = take(8 * L.buckets);
     L.tsc = take(4 * L.buckets);
@@ -270,7 +277,7 @@ Layout make_layout(int kind, int64_t n, int64_t nseg, const Config& c) {
     L.ssorted = take(sizeof(Split4) * L.chunks_bound);
     const int64_t p32 = std::max(scan_partial_count(nseg), scan_partial_count(L.buckets));
     L.part32 = take(4 * p32);
-    L.part64 = take(8 * scan_partial_count(nbk * L.tiles_bound));
+    L.part64 = take(8 * scan_partial_count(nbk * L.groups_bound));
     L.total = o;
     return L;
 }
@@ -295,9 +302,14 @@ Work<K> make_work(const Layout& L, char* scr, K* keys, uint32_t* vals, const int
     w.plans = (DigitPlan<K>*)(scr + L.plans);
     w.tilecnt = (int32_t*)(scr + L.tilecnt);
     w.tilepre = (int32_t*)(scr + L.tilepre);
+    w.groupcnt = (int32_t*)(scr + L.groupcnt);
+    w.grouppre = (int32_t*)(scr + L.grouppre);
     w.bounds_out = (int64_t*)(scr + L.bounds);
     w.counts = (uint32_t*)(scr + L.counts);
-    w.pos = (int64_t*)(scr + L.pos);
+    w.intra = (uint32_t*)(scr + L.intra);
+    w.gsum = (uint32_t*)(scr + L.gsum);
+    w.gpos = (int64_t*)(scr + L.gpos);
+    w.gbase = (int32_t*)(scr + L.gbase);
     w.bstart = (int64_t*)(scr + L.bstart);
     w.bsize = (int64_t*)(scr + L.bsize);
     w.tsc = (int32_t*)(scr + L.tsc);
@@ -445,6 +457,7 @@ int enqueue_body(int kind, K* keys, uint32_t* vals, int64_t n, const int64_t* of
     {
         Timer t(st, "scan", 0);
         HS_TRY(launch_scan_i32(ScanSpec{nullptr, 0, nseg}, nseg, w.tilecnt, w.tilepre, (int32_t*)(scr + L.part32), st));
+        HS_TRY(launch_scan_i32(ScanSpec{nullptr, 0, nseg}, nseg, w.groupcnt, w.grouppre, (int32_t*)(scr + L.part32), st));
     }
     if (any_large) {
         {
@@ -464,8 +477,10 @@ int enqueue_body(int kind, K* keys, uint32_t* vals, int64_t n, const int64_t* of
         }
         {
             Timer t(st, "scan", 0);
-            HS_TRY(launch_scan_u32_i64(ScanSpec{w.tilepre + nseg, w.nbk, 0}, w.nbk * L.tiles_bound, w.counts, w.pos,
+            HS_TRY(launch_colsum<K>(w, L.groups_bound, st));
+            HS_TRY(launch_scan_u32_i64(ScanSpec{w.grouppre + nseg, w.nbk, 0}, w.nbk * L.groups_bound, w.gsum, w.gpos,
                                        (int64_t*)(scr + L.part64), st));
+            HS_TRY(launch_gbase<K>(w, L.groups_bound, st));
         }
         {
             Timer t(st, "btab", 0);

@@ -283,7 +283,9 @@ __global__ void k_classify(Work<K> w) {
         if (bad) atomicOr(w.err, kErrOffsets);
         const int64_t m = b - a;
         if (!bad && w.max_seg_len > 0 && m > w.max_seg_len) atomicOr(w.err, kErrSegLen);
-        w.tilecnt[s] = (!bad && m > w.small_max) ? (int32_t)((m + w.ptile - 1) / w.ptile) : 0;
+        const int32_t nt = (!bad && m > w.small_max) ? (int32_t)((m + w.ptile - 1) / w.ptile) : 0;
+        w.tilecnt[s] = nt;
+        w.groupcnt[s] = (nt + kGroupTiles - 1) / kGroupTiles;
     }
 }
 
@@ -295,7 +297,7 @@ __global__ void k_tiles(Work<K> w, int64_t tiles_bound) {
     const int total = w.tilepre[w.nseg];
     TileDesc d;
     if (*w.err || t >= total) {
-        d = TileDesc{0, 0, 0, 0, 0, 0};
+        d = TileDesc{0, 0, 0, 0, 0, 0, 0, 0};
     } else {
         const int s = owner_of(w.tilepre, w.nseg, (int)t);
         const int i = (int)t - w.tilepre[s];
@@ -307,6 +309,8 @@ __global__ void k_tiles(Work<K> w, int64_t tiles_bound) {
         d.seg = s;
         d.idx = i;
         d.nt = w.tilecnt[s];
+        d.grp = w.grouppre[s] + i / kGroupTiles;
+        d.pad = 0;
     }
     w.tiles[t] = d;
 }
@@ -397,7 +401,7 @@ __global__ __launch_bounds__(PartShape<NBK>::NT) void k_range(Work<K> w) {
         uint32_t wd[5];
         unpack5(c, wd);
         block_sum5<NT>(wd, red);
-        if (tid < 10) w.counts[10 * (int64_t)(t - td.idx) + tid * td.nt + td.idx] = field16(wd, tid);
+        if (tid < 10) w.counts[10 * (int64_t)t + tid] = field16(wd, tid);
     } else {
         // one hundred or one thousand buckets: LDS atomics (block_minmax
         // ended with a barrier), one per run of equal buckets among a
@@ -420,7 +424,7 @@ __global__ __launch_bounds__(PartShape<NBK>::NT) void k_range(Work<K> w) {
         }
         if (rn) atomicAdd(&h[rb], rn);
         __syncthreads();
-        for (int b = tid; b < NBK; b += NT) w.counts[NBK * (int64_t)(t - td.idx) + (int64_t)b * td.nt + td.idx] = h[b];
+        for (int b = tid; b < NBK; b += NT) w.counts[NBK * (int64_t)t + b] = h[b];
     }
     if (tid == 0) w.tp[t] = plan_p(pl);
 }
@@ -483,9 +487,9 @@ __global__ __launch_bounds__(kHistNT) void k_hist(Work<K> w, int64_t tiles_bound
                 const uint64_t ps = plan_p(pl);
                 const bool own = (w.ufix || pl.beta == 0) && tp != 0;
                 if (own && tp != ps && (NBK == 10 || (NBK == 100 && tp <= ps / 100))) {
-                    uint32_t* out = w.counts + NBK * (t - td.idx) + td.idx;
+                    uint32_t* out = w.counts + NBK * t;
                     out[0] = (uint32_t)td.cnt;
-                    for (int d = 1; d < NBK; d++) out[d * td.nt] = 0;
+                    for (int d = 1; d < NBK; d++) out[d] = 0;
                 } else if (!own || tp != ps) {
                     slow[atomicAdd(&nslow, 1)] = t;
                 }
@@ -503,7 +507,7 @@ __global__ __launch_bounds__(kHistNT) void k_hist(Work<K> w, int64_t tiles_bound
                 uint32_t wd[5];
                 unpack5(c, wd);
                 block_sum5<kHistNT>(wd, red);
-                if (tid < 10) w.counts[10 * (slow[k] - td.idx) + tid * td.nt + td.idx] = field16(wd, tid);
+                if (tid < 10) w.counts[10 * slow[k] + tid] = field16(wd, tid);
             } else {
                 for (int b = tid; b < NBK; b += kHistNT) h[b] = 0;
                 __syncthreads();
@@ -520,13 +524,66 @@ __global__ __launch_bounds__(kHistNT) void k_hist(Work<K> w, int64_t tiles_bound
                 });
                 if (rn) atomicAdd(&h[rb], rn);
                 __syncthreads();
-                for (int b = tid; b < NBK; b += kHistNT)
-                    w.counts[NBK * (slow[k] - td.idx) + (int64_t)b * td.nt + td.idx] = h[b];
+                for (int b = tid; b < NBK; b += kHistNT) w.counts[NBK * slow[k] + b] = h[b];
                 __syncthreads();
             }
         }
         __syncthreads();
     }
+}
+
+// Column pass over the tile-major counts: one workgroup per group of up to
+// kGroupTiles consecutive tiles of one segment, one thread per bucket,
+// walking the group's tiles in order: intra = the bucket's count so far in
+// the group, and the group's sum, stored bucket-major inside the segment
+// (bucket b of group gi of segment s at nbk*grouppre[s] + b*groupcnt[s] + gi)
+// for the scan that follows.
+template <int NBK>
+constexpr int kColNT = (NBK + kWave - 1) / kWave * kWave;  // one thread per bucket, whole waves
+template <int NBK>
+__global__ __launch_bounds__(kColNT<NBK>) void k_colsum(const int32_t* tilepre, const int32_t* tilecnt,
+                                                                const int32_t* grouppre, const int32_t* groupcnt,
+                                                                int32_t nseg, const uint32_t* err,
+                                                                const uint32_t* __restrict__ counts,
+                                                                uint32_t* __restrict__ intra, uint32_t* __restrict__ gsum) {
+    if (*err) return;
+    const int g = blockIdx.x;
+    if (g >= grouppre[nseg]) return;
+    const int b = threadIdx.x;
+    if (b >= NBK) return;
+    const int s = owner_of(grouppre, nseg, g);
+    const int gi = g - grouppre[s];
+    const int64_t t0 = tilepre[s] + (int64_t)gi * kGroupTiles;
+    const int cnt = min(kGroupTiles, tilecnt[s] - gi * kGroupTiles);
+    const uint32_t* src = counts + NBK * t0 + b;
+    uint32_t* dst = intra + NBK * t0 + b;
+    uint32_t run = 0;
+    for (int i0 = 0; i0 < cnt; i0 += 8) {  // eight loads in flight before their stores
+        uint32_t c[8];
+#pragma unroll
+        for (int j = 0; j < 8; j++) c[j] = i0 + j < cnt ? src[(int64_t)NBK * (i0 + j)] : 0u;
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+            if (i0 + j < cnt) dst[(int64_t)NBK * (i0 + j)] = run;
+            run += c[j];
+        }
+    }
+    gsum[(int64_t)NBK * grouppre[s] + (int64_t)b * groupcnt[s] + gi] = run;
+}
+
+// Group bases: one thread per (group, bucket), the group's start in the
+// bucket relative to its segment's first key, stored tile-major like the
+// counts (row g holds buckets 0 .. nbk-1).
+template <typename K>
+__global__ void k_gbase(Work<K> w, int64_t bound) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= bound || *w.err) return;
+    const int nbk = w.nbk;
+    const int g = (int)(e / nbk), b = (int)(e - (int64_t)g * nbk);
+    if (g >= w.grouppre[w.nseg]) return;
+    const int s = owner_of(w.grouppre, w.nseg, g);
+    const int64_t base = (int64_t)nbk * w.grouppre[s];
+    w.gbase[e] = (int32_t)(w.gpos[base + (int64_t)b * w.groupcnt[s] + (g - w.grouppre[s])] - w.gpos[base]);
 }
 
 // Bucket table: start and size of each bucket (ten or one hundred per
@@ -550,10 +607,12 @@ __global__ void k_btab(Work<K> w) {
             w.mcc[j] = 0;
             continue;
         }
-        const int64_t base = (int64_t)nbk * w.tilepre[s];
-        const int64_t p0 = w.pos[base];
-        const int64_t st = w.pos[base + (int64_t)d * nt] - p0;
-        const int64_t en = w.pos[base + (int64_t)(d + 1) * nt] - p0;
+        // the scan of the group sums, bucket-major inside the segment
+        const int ng = w.groupcnt[s];
+        const int64_t base = (int64_t)nbk * w.grouppre[s];
+        const int64_t p0 = w.gpos[base];
+        const int64_t st = w.gpos[base + (int64_t)d * ng] - p0;
+        const int64_t en = w.gpos[base + (int64_t)(d + 1) * ng] - p0;
         const int64_t sz = en - st;
         w.bstart[j] = a + st;
         w.bsize[j] = sz;
@@ -667,20 +726,17 @@ __global__ __launch_bounds__(kHistNT) void k_scatter(Work<K> w) {
     const TileDesc td = w.tiles[t];
     if (td.cnt == 0) return;
     const int tid = threadIdx.x;
-    const int i = td.idx;
-    const int nt = td.nt;
     const int64_t base = td.base;
     const int cnt = td.cnt;
     const DigitPlan<K> pl = w.plans[td.seg];
-    const int64_t pbase = NBK * (int64_t)(t - i);
     // the tile's write offset in each bucket (and, with one hundred buckets,
     // its count there), loaded before the keys so that both round trips
     // overlap
     uint32_t cb = 0;
     int64_t gp = 0;
     if (tid < NBK) {
-        gp = w.pos[pbase + (int64_t)tid * nt + i] - w.pos[pbase];
-        if constexpr (NBK == 100) cb = w.counts[pbase + (int64_t)tid * nt + i];
+        gp = (int64_t)w.gbase[NBK * (int64_t)td.grp + tid] + w.intra[NBK * (int64_t)t + tid];
+        if constexpr (NBK == 100) cb = w.counts[NBK * (int64_t)t + tid];
     }
     // 1. load in natural order (16-byte body)
     load_run<K, NT, HT>(w.keys + base, cnt, [&](int q, K k) { sk[lds_pad<K>(q)] = k; });
@@ -783,11 +839,8 @@ __global__ __launch_bounds__(ScatterShape<NBK>::NT) void k_scatter_keys(Work<K> 
     const TileDesc td = w.tiles[t];
     if (td.cnt == 0) return;
     const int tid = threadIdx.x;
-    const int i = td.idx;
-    const int nt = td.nt;
     const int cnt = td.cnt;
     const DigitPlan<K> pl = w.plans[td.seg];
-    const int64_t pbase = NBK * (int64_t)(t - i);
     // the tile's write offset and count in buckets tid*BPT .. tid*BPT+BPT-1
     uint32_t cb[BPT];
     int64_t gp[BPT];
@@ -797,8 +850,8 @@ __global__ __launch_bounds__(ScatterShape<NBK>::NT) void k_scatter_keys(Work<K> 
         cb[j] = 0;
         gp[j] = 0;
         if (b < NBK) {
-            gp[j] = w.pos[pbase + (int64_t)b * nt + i] - w.pos[pbase];
-            cb[j] = w.counts[pbase + (int64_t)b * nt + i];
+            gp[j] = (int64_t)w.gbase[NBK * (int64_t)td.grp + b] + w.intra[NBK * (int64_t)t + b];
+            cb[j] = w.counts[NBK * (int64_t)t + b];
         }
     }
     // the keys, straight into registers: a full, 16-byte aligned tile in
@@ -1843,6 +1896,28 @@ hipError_t launch_hist(const Work<K>& w, int64_t tiles_bound, hipStream_t st) {
 }
 
 template <typename K>
+hipError_t launch_colsum(const Work<K>& w, int64_t groups_bound, hipStream_t st) {
+    const int g = grid_of(groups_bound);
+    if (w.nbk == 1000)
+        k_colsum<1000><<<g, kColNT<1000>, 0, st>>>(w.tilepre, w.tilecnt, w.grouppre, w.groupcnt, w.nseg, w.err, w.counts,
+                                            w.intra, w.gsum);
+    else if (w.nbk == 100)
+        k_colsum<100><<<g, kColNT<100>, 0, st>>>(w.tilepre, w.tilecnt, w.grouppre, w.groupcnt, w.nseg, w.err, w.counts,
+                                         w.intra, w.gsum);
+    else
+        k_colsum<10><<<g, kColNT<10>, 0, st>>>(w.tilepre, w.tilecnt, w.grouppre, w.groupcnt, w.nseg, w.err, w.counts,
+                                       w.intra, w.gsum);
+    return hipGetLastError();
+}
+
+template <typename K>
+hipError_t launch_gbase(const Work<K>& w, int64_t groups_bound, hipStream_t st) {
+    const int64_t bound = (int64_t)w.nbk * groups_bound;
+    k_gbase<K><<<cdiv64(bound, 256), 256, 0, st>>>(w, bound);
+    return hipGetLastError();
+}
+
+template <typename K>
 hipError_t launch_btab(const Work<K>& w, hipStream_t st) {
     const int g = (int)min((int64_t)4096, (int64_t)cdiv64((int64_t)w.nbk * w.nseg, 256));
     k_btab<K><<<g < 1 ? 1 : g, 256, 0, st>>>(w);
@@ -1944,6 +2019,8 @@ hipError_t launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t st
     template hipError_t launch_plans<K>(const Work<K>&, hipStream_t);                    \
     template hipError_t launch_hist<K>(const Work<K>&, int64_t, hipStream_t);            \
     template hipError_t launch_btab<K>(const Work<K>&, hipStream_t);                     \
+    template hipError_t launch_colsum<K>(const Work<K>&, int64_t, hipStream_t);          \
+    template hipError_t launch_gbase<K>(const Work<K>&, int64_t, hipStream_t);           \
     template hipError_t launch_partition<K>(const Work<K>&, int, int64_t, hipStream_t);  \
     template hipError_t launch_tiles<K>(const Work<K>&, int64_t, hipStream_t);           \
     template hipError_t launch_sdesc<K>(const Work<K>&, int64_t, hipStream_t);           \

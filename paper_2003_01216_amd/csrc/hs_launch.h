@@ -60,6 +60,10 @@ template <typename K>
 hipError_t launch_hist(const Work<K>& w, int64_t tiles_bound, hipStream_t st);
 template <typename K>
 hipError_t launch_btab(const Work<K>& w, hipStream_t st);
+template <typename K>
+hipError_t launch_colsum(const Work<K>& w, int64_t groups_bound, hipStream_t st);
+template <typename K>
+hipError_t launch_gbase(const Work<K>& w, int64_t groups_bound, hipStream_t st);
 template <typename K, bool PAIRS>
 hipError_t launch_scatter(const Work<K>& w, int64_t tiles_bound, hipStream_t st);
 template <typename K, bool PAIRS, int NT, int VT, bool BU>

@@ -32,6 +32,14 @@ struct ScatterShape {
     static constexpr int VT = PartShape<NBK>::HT / NT;
 };
 
+// Per-tile bucket counts are stored tile-major (one row of nbk words per
+// tile, so each pass reads or writes a tile's row in one piece), and their
+// offsets are formed in two parts: the exclusive prefix of a tile's counts
+// over the earlier tiles of its group of kGroupTiles consecutive tiles of
+// one segment, plus the group's start in each bucket (a scan over the group
+// sums, bucket-major, and its transpose).
+constexpr int kGroupTiles = 64;
+
 // One histogram tile of a large segment (range, histogram and scatter read it).
 struct TileDesc {
     int64_t base;      // first key of the tile
@@ -40,6 +48,8 @@ struct TileDesc {
     int32_t seg;       // segment index
     int32_t idx;       // tile index inside the segment
     int32_t nt;        // tiles of the segment
+    int32_t grp;       // flat index of the tile's group
+    int32_t pad;
 };
 
 // One local-sort partition of a bucket.
@@ -118,11 +128,17 @@ struct Work {
     DigitPlan<K>* plans;      // [nseg]
     int32_t* tilecnt;         // [nseg] histogram tiles of a large segment, 0 otherwise
     int32_t* tilepre;         // [nseg + 1] exclusive prefix of tilecnt
+    int32_t* groupcnt;        // [nseg] groups of kGroupTiles tiles of a large segment
+    int32_t* grouppre;        // [nseg + 1] exclusive prefix of groupcnt
     int64_t* bounds_out;      // [nseg * 11] bucket bounds relative to the segment start
 
-    // per histogram tile (flat over all large segments, bucket-major inside a segment)
-    uint32_t* counts;  // [nbk * tiles]
-    int64_t* pos;      // [nbk * tiles + 1] exclusive prefix of counts
+    // per histogram tile, tile-major: [nbk * t + b] (t flat over all large segments)
+    uint32_t* counts;  // keys of tile t in bucket b
+    uint32_t* intra;   // sum of counts[t'][b] over the earlier tiles t' of t's group
+    // per group of tiles
+    uint32_t* gsum;    // [nbk * groups] group sums, bucket-major inside a segment (as the scan reads them)
+    int64_t* gpos;     // [nbk * groups + 1] exclusive prefix of gsum
+    int32_t* gbase;    // [nbk * g + b] group g's start in bucket b, relative to its segment's first key
 
     // per bucket (nbk per segment)
     int64_t* bstart;  // absolute first key of the bucket
