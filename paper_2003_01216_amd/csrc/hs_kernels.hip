@@ -183,29 +183,37 @@ __device__ __forceinline__ void gather_merge_full(const W* words, int a_first, i
 
 // One LDS merge level of the block sort: runs of L (one per VT/L... threads)
 // merged pairwise; each thread produces VT outputs.  `base` is the padded
-// start of this thread's VT-run (runs never straddle a pad word).
+// start of this thread's VT-run (runs never straddle a pad word).  Slots at
+// or past `cnt` hold the largest word, so a pair of runs that starts there
+// is already merged: its threads only keep the barriers.
 template <typename W, int NT, int VT, int L>
-__device__ __forceinline__ void block_sort_level(W* words, int* sp, W (&v)[VT], int tid, int base) {
+__device__ __forceinline__ void block_sort_level(W* words, int* sp, W (&v)[VT], int tid, int base, int cnt) {
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < VT; i++) words[base + i] = v[i];
     __syncthreads();
     const int gb = (tid * VT) & ~(2 * L - 1);
     const int diag = tid * VT - gb;
+    const bool live = gb < cnt;
     auto A = [&](int i) { return lds_at_padded(words, gb + i); };
     auto B = [&](int i) { return lds_at_padded(words, gb + L + i); };
-    const int ai = merge_path_fixed<L>(diag, L, L, A, B);
+    const int ai = live ? merge_path_fixed<L>(diag, L, L, A, B) : 0;
     sp[tid] = ai;
     __syncthreads();
-    const int an = (diag + VT == 2 * L) ? L : sp[tid + 1];
-    gather_merge_full<W, VT>(words, gb + ai, gb + L + (diag - ai) + VT - 1, an - ai, v);
+    if (live) {
+        const int an = (diag + VT == 2 * L) ? L : sp[tid + 1];
+        gather_merge_full<W, VT>(words, gb + ai, gb + L + (diag - ai) + VT - 1, an - ai, v);
+    }
 }
 
+// The levels from runs of L up; once L >= cnt (the same on every thread)
+// every real key is in the first run, sorted, and the rest is padding.
 template <typename W, int NT, int VT, int L>
-__device__ __forceinline__ void block_sort_levels(W* words, int* sp, W (&v)[VT], int tid, int base) {
+__device__ __forceinline__ void block_sort_levels(W* words, int* sp, W (&v)[VT], int tid, int base, int cnt) {
     if constexpr (L < NT * VT) {
-        block_sort_level<W, NT, VT, L>(words, sp, v, tid, base);
-        block_sort_levels<W, NT, VT, 2 * L>(words, sp, v, tid, base);
+        if (L >= cnt) return;
+        block_sort_level<W, NT, VT, L>(words, sp, v, tid, base, cnt);
+        block_sort_levels<W, NT, VT, 2 * L>(words, sp, v, tid, base, cnt);
     }
 }
 
@@ -213,14 +221,17 @@ __device__ __forceinline__ void block_sort_levels(W* words, int* sp, W (&v)[VT],
 // network per thread, merge levels across groups of 2, 4, 8, 16 (and, for
 // 32-bit words, 32) lanes (lane permutations, in registers), then the
 // remaining merge levels in LDS, fully unrolled.  Result in blocked layout
-// (thread t holds outputs t*VT .. t*VT+VT-1, also in LDS).
+// (thread t holds outputs t*VT .. t*VT+VT-1, also in LDS).  Slots at or past
+// cnt must hold the largest word: a wave whose slots all lie there has
+// nothing to sort in registers, and levels whose runs already cover cnt are
+// skipped.
 //
 // BU (the alternative local sort, the non-recursive merge sort of Figure 1b
 // as it stands): each thread sorts its VT words (VT = 2: the pairs of the
 // figure's first step), then every merge level runs in LDS, bottom up from
 // runs of VT, with no lane merges.
 template <typename W, int NT, int VT, bool BU = false>
-__device__ __forceinline__ void block_sort(W* words, int* sp) {
+__device__ __forceinline__ void block_sort(W* words, int* sp, int cnt) {
     static_assert((128 / (int)sizeof(W)) % VT == 0, "a VT-run must not straddle a pad word");
     static_assert(NT >= 32, "lane merges need groups of 32 threads");
     const int tid = threadIdx.x;
@@ -228,27 +239,31 @@ __device__ __forceinline__ void block_sort(W* words, int* sp) {
     W v[VT];
 #pragma unroll
     for (int i = 0; i < VT; i++) v[i] = words[base + i];
-    register_sort<W, VT>(v);
+    const bool live = (tid / kWave) * kWave * VT < cnt;  // the same on every lane of the wave
     if constexpr (BU) {
-        block_sort_levels<W, NT, VT, VT>(words, sp, v, tid, base);
+        if (live) register_sort<W, VT>(v);
+        block_sort_levels<W, NT, VT, VT>(words, sp, v, tid, base, cnt);
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < VT; i++) words[base + i] = v[i];
         __syncthreads();
         return;
     }
-    lane_merge<W, VT, 2>(v, tid);
-    lane_merge<W, VT, 4>(v, tid);
-    lane_merge<W, VT, 8>(v, tid);
-    lane_merge<W, VT, 16>(v, tid);
-    if constexpr (sizeof(W) == 4) {
+    if (live) {
+        register_sort<W, VT>(v);
+        lane_merge<W, VT, 2>(v, tid);
+        lane_merge<W, VT, 4>(v, tid);
+        lane_merge<W, VT, 8>(v, tid);
+        lane_merge<W, VT, 16>(v, tid);
         // 32-bit words: a fifth lane level (lane ^ 31 by a swizzle) is
         // cheaper than the LDS level it replaces; 64-bit words need two
         // exchanges and a compare-and-select per register, and it is not
-        lane_merge<W, VT, 32>(v, tid);
-        block_sort_levels<W, NT, VT, 32 * VT>(words, sp, v, tid, base);
+        if constexpr (sizeof(W) == 4) lane_merge<W, VT, 32>(v, tid);
+    }
+    if constexpr (sizeof(W) == 4) {
+        block_sort_levels<W, NT, VT, 32 * VT>(words, sp, v, tid, base, cnt);
     } else {
-        block_sort_levels<W, NT, VT, 16 * VT>(words, sp, v, tid, base);
+        block_sort_levels<W, NT, VT, 16 * VT>(words, sp, v, tid, base, cnt);
     }
     __syncthreads();
 #pragma unroll
@@ -1023,7 +1038,7 @@ __global__ __launch_bounds__(NT) void k_tilesort(Work<K> w) {
                 load_run<uint32_t, NT, NV>(srcv, cnt, [&](int q, uint32_t v) { sv[q] = v; });
                 for (int q = cnt + tid; q < NV; q += NT) wn[lds_pad<NW>(q)] = WordMax<NW>::v;
                 __syncthreads();
-                block_sort<NW, NT, VT, BU>(wn, sp);
+                block_sort<NW, NT, VT, BU>(wn, sp, cnt);
                 auto key_at = [&](int q) { return (K)((U)(lds_at_padded(wn, q) >> POS) + base); };
                 store_keys<K, NT, NV>(dk, cnt, key_at);
                 store_run<uint32_t, NT, NV>(
@@ -1038,7 +1053,7 @@ __global__ __launch_bounds__(NT) void k_tilesort(Work<K> w) {
             for (int q = cnt + tid; q < NV; q += NT) words[lds_pad<W>(q)] = WordMax<W>::v;
         }
         __syncthreads();
-        block_sort<W, NT, VT, BU>(words, sp);
+        block_sort<W, NT, VT, BU>(words, sp, cnt);
         auto key_at = [&](int q) { return word_key<K, PAIRS>(lds_at_padded(words, q)); };
         store_keys<K, NT, NV>(dk, cnt, key_at);
         if constexpr (PAIRS)
@@ -1572,7 +1587,7 @@ __global__ __launch_bounds__(NT) void k_small(Work<K> w, int64_t lo, int64_t hi)
             if constexpr (PAIRS) load_run<uint32_t, NT, NV>(w.vals + a, m, [&](int q, uint32_t x) { sv[q] = x; });
             for (int q = m + tid; q < NV; q += NT) words[lds_pad<W>(q)] = WordMax<W>::v;
             __syncthreads();
-            block_sort<W, NT, VT>(words, sp);
+            block_sort<W, NT, VT>(words, sp, m);
             store_keys<K, NT, NV>(w.keys + a, m, [&](int q) { return word_key<K, PAIRS>(lds_at_padded(words, q)); });
             if constexpr (PAIRS)
                 store_run<uint32_t, NT, NV>(w.vals + a, m, [&](int q) { return sv[pair_pos(lds_at_padded(words, q))]; });
