@@ -58,8 +58,8 @@ NAMES = {KEYS_I32: "keys_i32", KEYS_I64: "keys_i64", PAIRS_I32_U32: "pairs_i32",
 
 FANINS = [2, 4]
 # decimal digits of the one-step partition: ten, one hundred or (plain
-# int32 keys only) one thousand buckets
-DIGITS = {KEYS_I32: [1, 2, 3]}
+# int32 keys or pairs only) one thousand buckets
+DIGITS = {KEYS_I32: [1, 2, 3], PAIRS_I32_U32: [1, 2, 3]}
 DIGITS_DEFAULT = [1, 2]
 # local-sort shapes of the bottom-up LDS merge (local = 1; Figure 1b from pairs when tile_vt = 2)
 TILES_BU = {KEYS_I32: [(2048, 2), (4096, 8)], PAIRS_I32_U32: [(2048, 2)], KEYS_I64: [(2048, 2)]}

@@ -135,7 +135,7 @@ bool config_ok(int key_type_index, const Config& c) {
     if (c.small_max < 0 || c.small_max > 8192) return false;
     if (c.fanin != 2 && c.fanin != 4) return false;
     if (c.digits < 1 || c.digits > 3) return false;
-    if (c.digits == 3 && key_type_index != 0) return false;  // one thousand buckets: int32 keys only
+    if (c.digits == 3 && key_type_index != 0 && key_type_index != 2) return false;  // one thousand buckets: 32-bit keys
     if (c.local != 0 && c.local != 1) return false;
     switch (key_type_index) {
         case 0:
@@ -158,6 +158,7 @@ struct Rec {
     // merge rounds: bytes = per_key * keys of the buckets still merging,
     // read from the bucket table left in scratch when the records are read
     const int64_t* bsize = nullptr;
+    const int32_t* brounds = nullptr;
     int64_t nb = 0, tile = 0;
     int pass = 0, fanin = 2;
     double per_key = 0;
@@ -195,8 +196,10 @@ struct Timer {
         std::lock_guard<std::mutex> lk(g_mu);
         g_recs.push_back(r);
     }
-    void per_active_key(const int64_t* bsize, int64_t nb, int64_t tile, int pass, double per_key, int fanin) {
+    void per_active_key(const int64_t* bsize, const int32_t* brounds, int64_t nb, int64_t tile, int pass,
+                        double per_key, int fanin) {
         deferred.bsize = bsize;
+        deferred.brounds = brounds;
         deferred.nb = nb;
         deferred.tile = tile;
         deferred.pass = pass;
@@ -212,15 +215,20 @@ int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // Buckets per segment and keys per partition tile of a configuration.
 int64_t buckets_of(const Config& c) { return c.digits == 3 ? 1000 : c.digits == 2 ? 100 : 10; }
-int64_t partition_tile(const Config& c) { return c.digits == 3 ? PartShape<1000>::HT : kHistTile; }
+// (pairs with one thousand buckets keep 4096-key tiles: their stable scatter
+// stages keys, payload and 16-bit bucket tags in LDS)
+int64_t partition_tile(const Config& c, bool pairs) {
+    return c.digits == 3 && !pairs ? PartShape<1000>::HT : kHistTile;
+}
 
 struct Layout {
     // byte offsets into scratch
     size_t err, own_off, skeys, svals, tmin, tmax, tp, smpf, smpl, rounds, plans, tilecnt, tilepre, groupcnt, grouppre,
-        bounds, counts, intra, gsum, gpos, gbase, bstart, bsize, tsc, tsp, mcc, msp, tiles, sdesc, mdesc, ssorted, part32,
+        bounds, counts, intra, gsum, gpos, gbase, bstart, bsize, tsc, tsp, mcc, msp, brounds, tiles, sdesc, mdesc, ssorted, part32,
         part64, total;
     // item bounds
     int64_t large_bound, tiles_bound, groups_bound, buckets, ts_bound, chunks_bound;
+    int64_t ptile;  // keys per partition tile
 };
 
 Layout make_layout(int kind, int64_t n, int64_t nseg, const Config& c) {
@@ -233,7 +241,8 @@ Layout make_layout(int kind, int64_t n, int64_t nseg, const Config& c) {
     Layout L{};
     L.large_bound = std::min<int64_t>(nseg, std::max<int64_t>(1, n / (c.small_max + 1)));
     const int64_t nbk = buckets_of(c);
-    L.tiles_bound = cdiv(n, partition_tile(c)) + L.large_bound;
+    L.ptile = partition_tile(c, pairs);
+    L.tiles_bound = cdiv(n, L.ptile) + L.large_bound;
     L.groups_bound = cdiv(L.tiles_bound, kGroupTiles) + L.large_bound;
     L.buckets = nbk * nseg;
     L.ts_bound = cdiv(n, c.tile) + nbk * L.large_bound;
@@ -271,6 +280,7 @@ Layout make_layout(int kind, int64_t n, int64_t nseg, const Config& c) {
     L.tsp = take(4 * (L.buckets + 1));
     L.mcc = take(4 * L.buckets);
     L.msp = take(4 * (L.buckets + 1));
+    L.brounds = take(4 * L.buckets);
     L.tiles = take(sizeof(TileDesc) * L.tiles_bound);
     L.sdesc = take(sizeof(SortDesc) * L.ts_bound);
     L.mdesc = take(sizeof(MergeDesc) * L.chunks_bound);
@@ -316,13 +326,14 @@ Work<K> make_work(const Layout& L, char* scr, K* keys, uint32_t* vals, const int
     w.tsp = (int32_t*)(scr + L.tsp);
     w.mcc = (int32_t*)(scr + L.mcc);
     w.msp = (int32_t*)(scr + L.msp);
+    w.brounds = (int32_t*)(scr + L.brounds);
     w.tiles = (TileDesc*)(scr + L.tiles);
     w.sdesc = (SortDesc*)(scr + L.sdesc);
     w.mdesc = (MergeDesc*)(scr + L.mdesc);
     w.ssorted = (Split4*)(scr + L.ssorted);
     w.err = (uint32_t*)(scr + L.err);
     w.nbk = (int32_t)buckets_of(c);
-    w.ptile = (int32_t)partition_tile(c);
+    w.ptile = (int32_t)L.ptile;
     w.tile = (int32_t)c.tile;
     w.fanin = (int32_t)c.fanin;
     w.nv = (int32_t)c.merge_nv;
@@ -518,7 +529,7 @@ int enqueue_body(int kind, K* keys, uint32_t* vals, int64_t n, const int64_t* of
                     HS_TRY(launch_part4<K>(w, p, L.chunks_bound, st));
                 }
                 Timer t(st, "merge", 0);
-                t.per_active_key(w.bsize, L.buckets, c.tile, p, 2 * kb, 4);
+                t.per_active_key(w.bsize, w.brounds, L.buckets, c.tile, p, 2 * kb, 4);
                 HS_TRY((merge4_by_shape<K, PAIRS>(c, w, p, L.chunks_bound, st)));
                 continue;
             }
@@ -528,7 +539,7 @@ int enqueue_body(int kind, K* keys, uint32_t* vals, int64_t n, const int64_t* of
             }
             {
                 Timer t(st, "merge", 0);
-                t.per_active_key(w.bsize, L.buckets, c.tile, p, 2 * kb, 2);
+                t.per_active_key(w.bsize, w.brounds, L.buckets, c.tile, p, 2 * kb, 2);
                 HS_TRY((merge_by_shape<K, PAIRS>(c, w, L.chunks_bound, st)));
             }
         }
@@ -890,8 +901,8 @@ int hsort_set_config(int kind, int size_cls, int64_t tile, int64_t tile_vt, int6
     if (size_cls < -1 || size_cls >= kClasses) return fail(HSORT_ERR_INVALID, "size class out of range");
     const Config c{tile, tile_vt, merge_nv, merge_vt, small_max, fanin, digits, local};
     if (!config_ok(key_type(kind), c)) return fail(HSORT_ERR_UNSUPPORTED, "tile/merge shape not compiled");
-    if (digits == 3 && kind != HSORT_KEYS_I32)
-        return fail(HSORT_ERR_UNSUPPORTED, "one thousand buckets: plain int32 keys-only sorts only");
+    if (digits == 3 && kind != HSORT_KEYS_I32 && kind != HSORT_PAIRS_I32_U32)
+        return fail(HSORT_ERR_UNSUPPORTED, "one thousand buckets: plain int32 sorts (keys only or pairs) only");
     std::lock_guard<std::mutex> lk(g_mu);
     for (int k = 0; k < kClasses; k++)
         if (size_cls < 0 || k == size_cls) g_cfg[ci][k] = c;
@@ -1008,18 +1019,21 @@ int64_t hsort_timing_read(char* out, int64_t cap) {
     std::vector<Agg> agg;
     const int64_t* cached_ptr = nullptr;
     std::vector<int64_t> sizes;
+    std::vector<int32_t> rounds;
     for (Rec& r : recs) {
         float ms = 0;
         hipEventSynchronize(r.b);
         if (r.bsize) {
             if (r.bsize != cached_ptr || (int64_t)sizes.size() != r.nb) {
                 sizes.assign((size_t)r.nb, 0);
+                rounds.assign((size_t)r.nb, 0);
                 hipMemcpy(sizes.data(), r.bsize, sizeof(int64_t) * r.nb, hipMemcpyDeviceToHost);
+                hipMemcpy(rounds.data(), r.brounds, sizeof(int32_t) * r.nb, hipMemcpyDeviceToHost);
                 cached_ptr = r.bsize;
             }
             double active = 0;
-            for (int64_t v : sizes)
-                if (merge_rounds(v, r.tile, r.fanin) > r.pass) active += (double)v;
+            for (size_t b = 0; b < sizes.size(); b++)
+                if (bucket_rounds(rounds[b]) > r.pass) active += (double)sizes[b];
             r.bytes = r.per_key * active;
         }
         hipEventElapsedTime(&ms, r.a, r.b);

@@ -358,9 +358,9 @@ __device__ __forceinline__ void block_minmax(T& mn, T& mx, T* rmn, T* rmx) {
 // the tiles whose p is smaller (every key then has digit 0) instead of
 // reading the keys again.  Keys are read strided (thread t: t, t + NT, ...),
 // coalesced per wave, and kept in registers for the count.
-template <typename K, int NBK>
-__global__ __launch_bounds__(PartShape<NBK>::NT) void k_range(Work<K> w) {
-    constexpr int NT = PartShape<NBK>::NT, VT = PartShape<NBK>::VT, HT = PartShape<NBK>::HT;
+template <typename K, int NBK, int HT>
+__global__ __launch_bounds__(HT / kHistVT) void k_range(Work<K> w) {
+    constexpr int VT = kHistVT, NT = HT / VT;
     __shared__ K rmn[NT / kWave], rmx[NT / kWave];
     __shared__ uint32_t red[NT / kWave][5];
     __shared__ uint32_t h[NBK >= 100 ? NBK : 1];
@@ -470,7 +470,7 @@ __global__ __launch_bounds__(1024) void k_plans(Work<K> w) {
 // segment s, counts[10*tilepre[s] + d*tilecnt[s] + i] (bucket-major, tile
 // minor), so one exclusive scan of the whole array yields every tile's write
 // offset inside its bucket.
-template <typename K, int NBK>
+template <typename K, int NBK, int HT>
 __global__ __launch_bounds__(kHistNT) void k_hist(Work<K> w, int64_t tiles_bound) {
     __shared__ uint32_t red[kHistNT / kWave][5];
     __shared__ uint32_t h[NBK >= 100 ? NBK : 1];
@@ -528,7 +528,7 @@ __global__ __launch_bounds__(kHistNT) void k_hist(Work<K> w, int64_t tiles_bound
                 __syncthreads();
                 // one atomic per run of equal buckets, as in k_range
                 uint32_t rb = 0, rn = 0;
-                load_run<K, kHistNT, PartShape<NBK>::HT>(w.keys + td.base, td.cnt, [&](int, K k) {
+                load_run<K, kHistNT, HT>(w.keys + td.base, td.cnt, [&](int, K k) {
                     const uint32_t b = (uint32_t)bucket_of<NBK>(pl, k);
                     if (b != rb) {
                         if (rn) atomicAdd(&h[rb], rn);
@@ -620,6 +620,7 @@ __global__ void k_btab(Work<K> w) {
             w.bsize[j] = 0;
             w.tsc[j] = 0;
             w.mcc[j] = 0;
+            w.brounds[j] = 0;
             continue;
         }
         // the scan of the group sums, bucket-major inside the segment
@@ -635,7 +636,12 @@ __global__ void k_btab(Work<K> w) {
         w.mcc[j] = (int32_t)((sz + w.nv - 1) / w.nv);
         if (d % per == 0) w.bounds_out[11 * (int64_t)s + d / per] = st;
         if (d == 0) w.bounds_out[11 * (int64_t)s + 10] = w.off[s + 1] - a;
-        const int r = merge_rounds(sz, w.tile, w.fanin);
+        // a bucket that spans one key value is in order after the scatter
+        uint64_t lo, width;
+        bucket_span(w.plans[s], nbk, d, lo, width);
+        const bool one = width == 1;
+        const int r = one ? 0 : merge_rounds(sz, w.tile, w.fanin);
+        w.brounds[j] = r | (one ? kConstBucket : 0);
         if (r > 0) atomicMax(w.rounds, r);
     }
 }
@@ -647,13 +653,16 @@ __global__ void k_btab(Work<K> w) {
 // the keys are staged back grouped by digit, in input order inside a digit.
 // dig(key, tag_in) returns the key's digit (bits 0..3) and the byte staged
 // with the key in sd (bits 8..15); with TAGIN, tag_in is the byte the key
-// carried in (a thread's VT = 16 bytes come in one 16-byte LDS read), else 0.
-// tot receives the tile's per-digit totals (packed).
-template <typename K, bool PAIRS, bool FULL, bool TAGIN, typename Dig>
-__device__ __forceinline__ void digit_pass(K* sk, uint32_t* sv, uint8_t* sd, uint32_t (*red)[5],
+// carried in (a thread's VT = 16 tags come in 16-byte LDS reads), else 0.
+// Tags are bytes, or 16-bit words for one thousand buckets.  tot receives
+// the tile's per-digit totals (packed).
+template <typename K, bool PAIRS, bool FULL, bool TAGIN, typename T, typename Dig>
+__device__ __forceinline__ void digit_pass(K* sk, uint32_t* sv, T* sd, uint32_t (*red)[5],
                                            uint16_t (*offs)[kHistNT], int cnt, Dig&& dig, uint32_t (&tot)[5]) {
     constexpr int NT = kHistNT, VT = kHistVT;
-    static_assert(VT == 16, "a thread's tags are one 16-byte word");
+    static_assert(VT == 16, "a thread's tags are whole 16-byte words");
+    static_assert(sizeof(T) == 1 || sizeof(T) == 2, "8- or 16-bit tags");
+    constexpr int TPW = 4 / (int)sizeof(T);  // tags per 32-bit word
     // each thread's staging start per digit, read back by digit: an indexed
     // LDS read is cheaper than selecting among registers, but the 5 KB cost
     // 64-bit keys and pairs a resident workgroup, so they select instead
@@ -662,13 +671,19 @@ __device__ __forceinline__ void digit_pass(K* sk, uint32_t* sv, uint8_t* sd, uin
     K key[VT];
     uint32_t val[PAIRS ? VT : 1];
     uint32_t pk[VT];  // tag << 16 | rank << 4 | digit (digit 15 = no key)
-    uint32_t tg[4] = {0, 0, 0, 0};
+    uint32_t tg[VT / TPW];
+#pragma unroll
+    for (int j = 0; j < VT / TPW; j++) tg[j] = 0;
     if constexpr (TAGIN) {
-        const uint4 x = *reinterpret_cast<const uint4*>(sd + tid * VT);
-        tg[0] = x.x;
-        tg[1] = x.y;
-        tg[2] = x.z;
-        tg[3] = x.w;
+        const uint4* src = reinterpret_cast<const uint4*>(sd + tid * VT);
+#pragma unroll
+        for (int j = 0; j < VT / TPW / 4; j++) {
+            const uint4 x = src[j];
+            tg[4 * j] = x.x;
+            tg[4 * j + 1] = x.y;
+            tg[4 * j + 2] = x.z;
+            tg[4 * j + 3] = x.w;
+        }
     }
     uint64_t c = 0;
 #pragma unroll
@@ -678,10 +693,11 @@ __device__ __forceinline__ void digit_pass(K* sk, uint32_t* sv, uint8_t* sd, uin
         const int qq = ok ? q : 0;
         key[v] = sk[lds_pad<K>(qq)];
         if constexpr (PAIRS) val[v] = sv[qq];
-        const uint32_t dt = dig(key[v], (tg[v >> 2] >> (8 * (v & 3))) & 0xFFu);
+        constexpr uint32_t kTagMask = sizeof(T) == 1 ? 0xFFu : 0xFFFFu;
+        const uint32_t dt = dig(key[v], (tg[v / TPW] >> (8 * (int)sizeof(T) * (v % TPW))) & kTagMask);
         const uint32_t d = dt & 15u;
         const uint32_t r = (((uint32_t)(c >> (5 * d)) & 31u) << 4) | d;
-        pk[v] = ok ? ((dt & 0xFF00u) << 8) | r : 15u;
+        pk[v] = ok ? (((dt >> 8) & kTagMask) << 16) | r : 15u;
         c += ok ? (1ull << (5 * d)) : 0ull;
     }
     uint32_t wd[5];
@@ -711,28 +727,31 @@ __device__ __forceinline__ void digit_pass(K* sk, uint32_t* sv, uint8_t* sd, uin
             const uint32_t start = kOffsLds ? (uint32_t)offs[kOffsLds ? d : 0][tid] : field16(wd, (int)d);
             const int sp = (int)(start + ((pk[v] >> 4) & 31u));
             sk[lds_pad<K>(sp)] = key[v];
-            sd[sp] = (uint8_t)(pk[v] >> 16);
+            sd[sp] = (T)(pk[v] >> 16);
             if constexpr (PAIRS) sv[sp] = val[v];
         }
     }
 }
 
 // Stable one-step MSD scatter (Section 3.4: the master divides the keys into
-// ten parts by most significant digit; NBK = 100 is the finer two-digit
-// splitter, here for stable pairs).  Per tile: the keys are grouped by
-// bucket in LDS -- ten buckets by one counting pass on the digit, one
-// hundred by two passes, first on the second digit and then on the first
-// (each pass stable, so the second keeps the first's order inside a digit)
-// -- and runs of consecutive keys are written to their buckets in the
-// scratch copy.  The bucket of a staged key travels with it in a byte array,
-// so each key's bucket is computed once.
+// ten parts by most significant digit; NBK = 100 and 1000 are the finer two-
+// and three-digit splitters, here for stable pairs).  Per tile: the keys are
+// grouped by bucket in LDS -- ten buckets by one counting pass on the digit,
+// one hundred by two passes and one thousand by three, from the last digit
+// of the bucket to the first (each pass stable, so each keeps the previous
+// one's order inside a digit) -- and runs of consecutive keys are written to
+// their buckets in the scratch copy.  The bucket of a staged key travels
+// with it in a byte (16-bit word for one thousand buckets), so each key's
+// bucket is computed once.
 template <typename K, bool PAIRS, int NBK>
 __global__ __launch_bounds__(kHistNT) void k_scatter(Work<K> w) {
-    static_assert(NBK == 10 || NBK == 100, "ten or one hundred buckets");
+    static_assert(NBK == 10 || NBK == 100 || NBK == 1000, "ten, one hundred or one thousand buckets");
     constexpr int NT = kHistNT, VT = kHistVT, HT = kHistTile;
+    constexpr int BPT = (NBK + NT - 1) / NT;  // buckets per thread for the counts scan
+    using T = std::conditional_t<(NBK > 256), uint16_t, uint8_t>;
     __shared__ K sk[lds_padded_size<K>(HT)];
     __shared__ uint32_t sv[PAIRS ? HT : 1];
-    __shared__ __align__(16) uint8_t sd[HT];
+    __shared__ __align__(16) T sd[HT];
     __shared__ uint32_t red[NT / kWave][5];
     constexpr bool kOffsLds = sizeof(K) == 4 && !PAIRS;
     __shared__ int32_t dbase[NBK];  // element index (n < 2^31) of bucket d's run, minus its staging start
@@ -744,25 +763,39 @@ __global__ __launch_bounds__(kHistNT) void k_scatter(Work<K> w) {
     const int64_t base = td.base;
     const int cnt = td.cnt;
     const DigitPlan<K> pl = w.plans[td.seg];
-    // the tile's write offset in each bucket (and, with one hundred buckets,
-    // its count there), loaded before the keys so that both round trips
-    // overlap
-    uint32_t cb = 0;
-    int64_t gp = 0;
-    if (tid < NBK) {
-        gp = (int64_t)w.gbase[NBK * (int64_t)td.grp + tid] + w.intra[NBK * (int64_t)t + tid];
-        if constexpr (NBK == 100) cb = w.counts[NBK * (int64_t)t + tid];
+    // the tile's write offset in buckets tid*BPT .. tid*BPT+BPT-1 (and, with
+    // one hundred or one thousand buckets, its counts there), loaded before
+    // the keys so that both round trips overlap
+    uint32_t cb[BPT];
+    int64_t gp[BPT];
+#pragma unroll
+    for (int j = 0; j < BPT; j++) {
+        const int b = tid * BPT + j;
+        cb[j] = 0;
+        gp[j] = 0;
+        if (b < NBK) {
+            gp[j] = (int64_t)w.gbase[NBK * (int64_t)td.grp + b] + w.intra[NBK * (int64_t)t + b];
+            if constexpr (NBK >= 100) cb[j] = w.counts[NBK * (int64_t)t + b];
+        }
     }
     // 1. load in natural order (16-byte body)
     load_run<K, NT, HT>(w.keys + base, cnt, [&](int q, K k) { sk[lds_pad<K>(q)] = k; });
     if constexpr (PAIRS) load_run<uint32_t, NT, HT>(w.vals + base, cnt, [&](int q, uint32_t v) { sv[q] = v; });
     if constexpr (NBK == 10) {
-        if (tid < 10) dbase[tid] = (int32_t)(td.seg_base + gp);
+        if (tid < 10) dbase[tid] = (int32_t)(td.seg_base + gp[0]);
     } else {
         // the tile's start of each bucket: exclusive scan of its counts
+        uint32_t mine = 0;
+#pragma unroll
+        for (int j = 0; j < BPT; j++) mine += cb[j];
         uint32_t all;
-        const uint32_t ls = block_excl_scan<uint32_t, NT>(cb, all, &red[0][0]);
-        if (tid < NBK) dbase[tid] = (int32_t)(td.seg_base + gp - (int64_t)ls);
+        uint32_t ls = block_excl_scan<uint32_t, NT>(mine, all, &red[0][0]);
+#pragma unroll
+        for (int j = 0; j < BPT; j++) {
+            const int b = tid * BPT + j;
+            if (b < NBK) dbase[b] = (int32_t)(td.seg_base + gp[j] - (int64_t)ls);
+            ls += cb[j];
+        }
     }
     __syncthreads();
     uint32_t tot[5];
@@ -772,6 +805,23 @@ __global__ __launch_bounds__(kHistNT) void k_scatter(Work<K> w) {
             digit_pass<K, PAIRS, F, false>(sk, sv, sd, red, offs, cnt, [&](K k, uint32_t) {
                 const uint32_t d = (uint32_t)digit_of(pl, k);
                 return d | (d << 8);
+            }, tot);
+        } else if constexpr (NBK == 1000) {
+            // three passes: the last digit of b, the middle one, the first
+            // (b / 10 = b * 205 >> 11 and b / 100 = b * 41 >> 12, exact for
+            // b < 1000)
+            digit_pass<K, PAIRS, F, false>(sk, sv, sd, red, offs, cnt, [&](K k, uint32_t) {
+                const uint32_t b = (uint32_t)bucket3_of(pl, k);
+                return (b - 10u * ((b * 205u) >> 11)) | (b << 8);
+            }, tot);
+            __syncthreads();
+            digit_pass<K, PAIRS, F, true>(sk, sv, sd, red, offs, cnt, [&](K, uint32_t b) {
+                const uint32_t q = (b * 205u) >> 11;
+                return (q - 10u * ((q * 205u) >> 11)) | (b << 8);
+            }, tot);
+            __syncthreads();
+            digit_pass<K, PAIRS, F, true>(sk, sv, sd, red, offs, cnt, [&](K, uint32_t b) {
+                return ((b * 41u) >> 12) | (b << 8);
             }, tot);
         } else {
             // pass 1 on the second digit, pass 2 on the first; b = 10 d1 + d2
@@ -970,7 +1020,9 @@ __global__ void k_sdesc(Work<K> w, int64_t bound) {
         const int64_t size = w.bsize[j];
         d.start = w.bstart[j] + i * w.tile;
         d.cnt = (int)min((int64_t)w.tile, size - i * w.tile);
-        d.odd = (merge_rounds(size, w.tile, w.fanin) & 1) | (int)(i & 1) << 1;  // bit 1: an odd run of its group
+        const int32_t br = w.brounds[j];
+        // bit 1: an odd run of its group; bit 2: a bucket of one key value
+        d.odd = (bucket_rounds(br) & 1) | (int)(i & 1) << 1 | ((br & kConstBucket) ? 4 : 0);
         d.bucket = j;
         d.sbase = (int32_t)(sample_base(w.bstart[j], w.msp[j]) + i * w.tile / kSampleBlock);
     }
@@ -1015,6 +1067,16 @@ __global__ __launch_bounds__(NT) void k_tilesort(Work<K> w) {
         uint32_t* dv = PAIRS ? ((sd.odd & 1) ? w.svals : w.vals) + start : nullptr;
         const K* srck = w.skeys + start;
         const uint32_t* srcv = PAIRS ? w.svals + start : nullptr;
+        if (sd.odd & 4) {
+            // the bucket's keys all share one value: the scatter left them
+            // (and their payload, in input order) as the sort would; copy
+            // them to the caller's buffer (no merge round follows)
+            for (int q = tid; q < cnt; q += NT) {
+                dk[q] = srck[q];
+                if constexpr (PAIRS) dv[q] = srcv[q];
+            }
+            return;
+        }
         if constexpr (PAIRS) {
             // Every key of the partition lies in its bucket's span, so
             // u - lo (u = k - beta) lies in [0, width).  When width fits next
@@ -1081,7 +1143,7 @@ __global__ __launch_bounds__(256) void k_partition(Work<K> w, int pass, int64_t 
         const int64_t i = item - w.msp[j];
         const int64_t size = w.bsize[j];
         const int64_t T = w.tile, NV = w.nv;
-        const int P = merge_rounds(size, T);
+        const int P = bucket_rounds(w.brounds[j]);
         if (P > pass) {
             const int64_t L = T << pass;
             const int64_t o = i * NV;
@@ -1209,7 +1271,7 @@ __global__ __launch_bounds__(256) void k_part4(Work<K> w, int round, int64_t bou
         const int64_t i = item - w.msp[j];
         const int64_t size = w.bsize[j];
         const int64_t T = w.tile, S = w.nv;
-        const int P = merge_rounds(size, T, 4);
+        const int P = bucket_rounds(w.brounds[j]);
         if (P > round) {
             const int64_t L = T << (2 * round);
             const int64_t o = i * S;
@@ -1632,7 +1694,7 @@ __global__ void k_collect(Work<K> w, int stage) {
     for (int j = blockIdx.x; j < nb; j += gridDim.x) {
         const int64_t size = w.bsize[j];
         if (size == 0) continue;
-        if (stage == 2 && !(merge_rounds(size, w.tile, w.fanin) & 1)) continue;
+        if (stage == 2 && !(bucket_rounds(w.brounds[j]) & 1)) continue;
         const int64_t st = w.bstart[j];
         for (int64_t q = threadIdx.x; q < size; q += blockDim.x) {
             w.keys[st + q] = w.skeys[st + q];
@@ -1875,14 +1937,20 @@ hipError_t launch_setup(const Work<K>& w, int64_t* own_off, hipStream_t st) {
 template <typename K>
 hipError_t launch_range(const Work<K>& w, int64_t tiles_bound, hipStream_t st) {
     if (w.nbk == 1000) {
-        if constexpr (sizeof(K) == 4)
-            k_range<K, 1000><<<grid_of(tiles_bound), PartShape<1000>::NT, 0, st>>>(w);
-        else
-            return hipErrorInvalidValue;  // one thousand buckets: 32-bit keys only
+        // one thousand buckets (32-bit keys only): 16384-key tiles for keys,
+        // 4096 for pairs
+        if constexpr (sizeof(K) == 4) {
+            if (w.ptile == PartShape<1000>::HT)
+                k_range<K, 1000, PartShape<1000>::HT><<<grid_of(tiles_bound), PartShape<1000>::NT, 0, st>>>(w);
+            else
+                k_range<K, 1000, kHistTile><<<grid_of(tiles_bound), kHistNT, 0, st>>>(w);
+        } else {
+            return hipErrorInvalidValue;
+        }
     } else if (w.nbk == 100) {
-        k_range<K, 100><<<grid_of(tiles_bound), kHistNT, 0, st>>>(w);
+        k_range<K, 100, kHistTile><<<grid_of(tiles_bound), kHistNT, 0, st>>>(w);
     } else {
-        k_range<K, 10><<<grid_of(tiles_bound), kHistNT, 0, st>>>(w);
+        k_range<K, 10, kHistTile><<<grid_of(tiles_bound), kHistNT, 0, st>>>(w);
     }
     return hipGetLastError();
 }
@@ -1898,14 +1966,18 @@ template <typename K>
 hipError_t launch_hist(const Work<K>& w, int64_t tiles_bound, hipStream_t st) {
     const int g = grid_of(tiles_bound < kHistGrid ? tiles_bound : kHistGrid);
     if (w.nbk == 1000) {
-        if constexpr (sizeof(K) == 4)
-            k_hist<K, 1000><<<g, kHistNT, 0, st>>>(w, tiles_bound);
-        else
+        if constexpr (sizeof(K) == 4) {
+            if (w.ptile == PartShape<1000>::HT)
+                k_hist<K, 1000, PartShape<1000>::HT><<<g, kHistNT, 0, st>>>(w, tiles_bound);
+            else
+                k_hist<K, 1000, kHistTile><<<g, kHistNT, 0, st>>>(w, tiles_bound);
+        } else {
             return hipErrorInvalidValue;
+        }
     } else if (w.nbk == 100) {
-        k_hist<K, 100><<<g, kHistNT, 0, st>>>(w, tiles_bound);
+        k_hist<K, 100, kHistTile><<<g, kHistNT, 0, st>>>(w, tiles_bound);
     } else {
-        k_hist<K, 10><<<g, kHistNT, 0, st>>>(w, tiles_bound);
+        k_hist<K, 10, kHistTile><<<g, kHistNT, 0, st>>>(w, tiles_bound);
     }
     return hipGetLastError();
 }
@@ -1944,6 +2016,8 @@ hipError_t launch_scatter(const Work<K>& w, int64_t tiles_bound, hipStream_t st)
     if (w.nbk == 1000) {
         if constexpr (sizeof(K) == 4 && !PAIRS)
             k_scatter_keys<K, 1000><<<grid_of(tiles_bound), ScatterShape<1000>::NT, 0, st>>>(w);
+        else if constexpr (sizeof(K) == 4 && PAIRS)
+            k_scatter<K, true, 1000><<<grid_of(tiles_bound), kHistNT, 0, st>>>(w);
         else
             return hipErrorInvalidValue;  // one thousand buckets: 32-bit keys only
     } else if (w.nbk == 100) {

@@ -56,7 +56,8 @@ struct TileDesc {
 struct SortDesc {
     int64_t start;   // first key
     int32_t cnt;     // keys (0: no work)
-    int32_t odd;     // bit 0: write to the scratch copy (odd number of merge rounds); bit 1: odd partition
+    int32_t odd;     // bit 0: write to the scratch copy (odd number of merge rounds); bit 1: odd partition;
+                     // bit 2: the bucket's keys all share one value (copied, not sorted)
     int32_t bucket;  // nbk * segment + bucket of the segment
     int32_t sbase;   // sample index of the partition's first 32-key block
 };
@@ -90,6 +91,12 @@ struct Split4 {
     int32_t flags;  // kActive | kFromScratch | kLastRound | round_tag(round)
 };
 constexpr int32_t kLastRound = 4;  // the bucket's last merge round: its output needs no samples
+
+// brounds[j]: the bucket's merge rounds, with kConstBucket set when the digit
+// plan gives the bucket a span of one value (its keys are all equal, so the
+// scatter has already left it in order: no local sort, no merge round).
+constexpr int32_t kConstBucket = 1 << 30;
+__host__ __device__ inline int bucket_rounds(int32_t x) { return x & 0xFFFF; }
 constexpr int32_t kOddGroup = 8;   // odd group: its output is run 1 or 3 of the next round's group (no last keys)
 
 // Block samples for the split-point searches of fan-in-4 rounds: the runs a
@@ -147,6 +154,7 @@ struct Work {
     int32_t* tsp;  // [nbk * nseg + 1] prefix
     int32_t* mcc;  // merge chunks of the bucket
     int32_t* msp;  // [nbk * nseg + 1] prefix
+    int32_t* brounds;  // merge rounds of the bucket (0 when its keys all share one value)
 
     TileDesc* tiles;   // [tiles bound]
     SortDesc* sdesc;   // [local-sort partitions bound]

@@ -110,9 +110,13 @@ def test_config_roundtrip(lib):
     with pytest.raises(hs.HsortError):  # one thousand buckets: plain int32 keys only
         hs.hsort_set_config(hs.SEG_I32, t, tvt, m, mvt, s, fanin=fanin, digits=3, size_class=3)
     with pytest.raises(hs.HsortError):
-        hs.hsort_set_config(hs.PAIRS_I32_U32, 4096, 16, 4096, 16, 4096, fanin=4, digits=3, size_class=3)
+        hs.hsort_set_config(hs.PAIRS_I64_U32, 4096, 8, 2048, 8, 4096, fanin=4, digits=3, size_class=3)
     with pytest.raises(hs.HsortError):
         hs.hsort_set_config(hs.KEYS_I64, 4096, 16, 4096, 16, 4096, fanin=4, digits=3, size_class=3)
+    pc = hs.hsort_get_config(hs.PAIRS_I32_U32, size_class=3)  # int32 pairs take one thousand buckets too
+    hs.hsort_set_config(hs.PAIRS_I32_U32, *pc[:5], fanin=pc[5], digits=3, local=pc[7], size_class=3)
+    assert hs.hsort_get_config(hs.PAIRS_I32_U32, size_class=3)[6] == 3
+    hs.hsort_set_config(hs.PAIRS_I32_U32, *pc[:5], fanin=pc[5], digits=pc[6], local=pc[7], size_class=3)
     for d in (1, 2, 3):
         hs.hsort_set_config(hs.KEYS_I32, t, tvt, m, mvt, s, fanin=4, digits=d, size_class=3)
         assert hs.hsort_get_config(hs.KEYS_I32, size_class=3)[5:] == (4, d, local)

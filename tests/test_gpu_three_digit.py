@@ -2,12 +2,16 @@
 
 The splitter reads the first three of the D decimal digits of u = k - beta:
 bucket floor(u / 10^(D-3)), or the digits of a shorter u followed by zeros
-(100u when D = 1, 10u when D = 2).  It is offered for plain int32 keys-only
-sorts (and the 32-bit images of hsort_sort), on 16384-key partition tiles.
-Every int32 keys shape is switched to it here; the intermediate results (the
-bucket scatter, as each bucket's multiset of keys; the local sorts, as
-sorted partitions of those buckets), the exported ten-bucket bounds and the
-final sorts are compared with the oracle's three-digit mode.  Inputs reach
+(100u when D = 1, 10u when D = 2).  It is offered for plain int32 sorts,
+keys only (16384-key partition tiles, an unstable cursor scatter) and stable
+pairs (4096-key tiles, three stable counting passes), and for the 32-bit
+images of hsort_sort.  Every int32 keys and pairs shape is switched to it
+here; the intermediate results (the keys-only scatter as each bucket's
+multiset of keys, the pairs scatter bit for bit; the local sorts), the
+exported ten-bucket bounds and the final sorts are compared with the
+oracle's three-digit mode.  Keys of at most three digits put one key value
+in each bucket: such buckets are copied, not sorted, and no merge round
+follows.  Inputs reach
 the cases the range and histogram passes treat apart: tiles whose own power
 of ten is below their array's, negative keys, arrays of one to three digits,
 heavy duplicates, skewed buckets, and sizes around the partition tile.
@@ -35,13 +39,13 @@ def hs():
     import paper_2003_01216_amd as hs
 
     hs.load_library()
-    saved = {c: hs.hsort_get_config(hs.KEYS_I32, size_class=c) for c in range(4)}
-    for c, cfg in saved.items():
-        hs.hsort_set_config(hs.KEYS_I32, *cfg[:5], fanin=cfg[5], digits=3, local=cfg[7], size_class=c)
-    print("three-digit partition on int32 keys", flush=True)
+    saved = {(k, c): hs.hsort_get_config(k, size_class=c) for k in (hs.KEYS_I32, hs.PAIRS_I32_U32) for c in range(4)}
+    for (k, c), cfg in saved.items():
+        hs.hsort_set_config(k, *cfg[:5], fanin=cfg[5], digits=3, local=cfg[7], size_class=c)
+    print("three-digit partition on int32 keys and pairs", flush=True)
     yield hs
-    for c, cfg in saved.items():
-        hs.hsort_set_config(hs.KEYS_I32, *cfg[:5], fanin=cfg[5], digits=cfg[6], local=cfg[7], size_class=c)
+    for (k, c), cfg in saved.items():
+        hs.hsort_set_config(k, *cfg[:5], fanin=cfg[5], digits=cfg[6], local=cfg[7], size_class=c)
 
 
 def say(msg):
@@ -167,3 +171,60 @@ def test_noalloc(hs, orc):
         hs.hsort_keys_i32_noalloc(t)
         torch.cuda.synchronize()
         assert np.array_equal(t.cpu().numpy(), orc.sort_keys(k))
+
+
+def _pair_inputs():
+    r = np.random.default_rng(181)
+    n = 300_007
+    out = {
+        "dup": W.dup_pairs_i32(n, 182),  # keys in [0, 1000): one key value per bucket
+        "narrow": (r.integers(0, 10**7, n).astype(np.int32), np.arange(n, dtype=np.uint32)),
+        "full": (r.integers(I32.min, I32.max, n, dtype=np.int32, endpoint=True),
+                 r.integers(0, 2**32 - 1, n, dtype=np.uint32, endpoint=True)),
+    }
+    k = r.integers(0, 1000, 2_000_003).astype(np.int32)
+    k[r.random(k.size) < 0.7] = 7  # one bucket far above a tile: copied, not merged
+    out["dup_heavy"] = (k, np.arange(k.size, dtype=np.uint32))
+    return out
+
+
+@pytest.mark.parametrize("name", sorted(_pair_inputs().keys()))
+def test_pairs_stages_and_sort(hs, orc, name):
+    k, v = _pair_inputs()[name]
+    cfg = hs.hsort_get_config(hs.PAIRS_I32_U32, n=k.size)
+    assert cfg[6] == 3
+    say(f"three-digit pairs {name} n={k.size} cfg={cfg}")
+    for stage in (1, 2, 3):
+        tk, tv = dev(k), dev(v.view(np.int32))
+        hs.hsort_debug_stage(tk, stage, vals=tv)
+        if stage == 1:
+            ok, ov, _ = orc.scatter(k, v, digits=3)
+        elif stage == 2:
+            ok, ov, _ = orc.bucket_tiles(k, cfg[0], v, digits=3)
+        else:
+            ok, ov = orc.sort_pairs(k, v)
+        assert np.array_equal(tk.cpu().numpy(), ok), stage
+        assert np.array_equal(tv.cpu().numpy().view(np.uint32), ov), stage
+    tk, tv = dev(k), dev(v.view(np.int32))
+    s = scratch(hs, hs.PAIRS_I32_U32, k.size)
+    hs.hsort_pairs(tk, tv, scratch=s)
+    hs.hsort_check(s)
+    assert np.array_equal(hs.read_bounds(s, hs.PAIRS_I32_U32, k.size).cpu().numpy()[0], orc.bounds(k)), "bounds"
+
+
+@pytest.mark.parametrize("n", [5_000, 70_000, 3_000_001])
+def test_keys_one_value_per_bucket(hs, orc, n):
+    # keys of at most three digits: every bucket spans one key value, and the
+    # largest holds many tiles
+    r = np.random.default_rng(n)
+    k = r.integers(0, 1000, n).astype(np.int32)
+    k[r.random(n) < 0.5] = 999
+    say(f"three-digit keys of one value per bucket n={n}")
+    t = dev(k)
+    hs.hsort_debug_stage(t, 2)
+    ok, _, b = orc.scatter(k, digits=3)
+    check_keys_stage(t.cpu().numpy(), ok, b, 2, hs.hsort_get_config(hs.KEYS_I32, n=n)[0], stable=False)
+    t = dev(k)
+    hs.hsort_keys(t)
+    assert np.array_equal(t.cpu().numpy(), orc.sort_keys(k))
+
