@@ -298,6 +298,29 @@ __device__ __forceinline__ void store_run64(int64_t* dst, int cnt, G&& get) {
     }
 }
 
+// dst[q] = src[q] for q in [0, cnt): 16-byte vectors when both pointers
+// share their offset inside 16 bytes (equal offsets into two aligned
+// arrays), element by element otherwise.
+template <typename T, int NT>
+__device__ __forceinline__ void copy_run(T* dst, const T* src, int cnt) {
+    constexpr int E = 16 / (int)sizeof(T);
+    const int tid = threadIdx.x;
+    if ((((uintptr_t)dst ^ (uintptr_t)src) & 15) == 0) {
+        int head = (int)(((16 - ((uintptr_t)src & 15)) & 15) / sizeof(T));
+        head = head < cnt ? head : cnt;
+        const int body = (cnt - head) / E;
+        const int tail = head + body * E;
+        if (tid < head) dst[tid] = src[tid];
+        if (tid < cnt - tail) dst[tail + tid] = src[tail + tid];
+        const uint4* vs = reinterpret_cast<const uint4*>(src + head);
+        uint4* vd = reinterpret_cast<uint4*>(dst + head);
+#pragma unroll 4
+        for (int v = tid; v < body; v += NT) vd[v] = vs[v];
+    } else {
+        for (int q = tid; q < cnt; q += NT) dst[q] = src[q];
+    }
+}
+
 template <typename K, int NT, int MAXCNT, typename G>
 __device__ __forceinline__ void store_keys(K* dst, int cnt, G&& get) {
     if constexpr (sizeof(K) == 8)

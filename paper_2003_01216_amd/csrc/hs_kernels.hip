@@ -1071,10 +1071,8 @@ __global__ __launch_bounds__(NT) void k_tilesort(Work<K> w) {
             // the bucket's keys all share one value: the scatter left them
             // (and their payload, in input order) as the sort would; copy
             // them to the caller's buffer (no merge round follows)
-            for (int q = tid; q < cnt; q += NT) {
-                dk[q] = srck[q];
-                if constexpr (PAIRS) dv[q] = srcv[q];
-            }
+            copy_run<K, NT>(dk, srck, cnt);
+            if constexpr (PAIRS) copy_run<uint32_t, NT>(dv, srcv, cnt);
             return;
         }
         if constexpr (PAIRS) {
