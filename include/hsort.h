@@ -115,8 +115,10 @@ int hsort_pairs(int32_t* keys, uint32_t* vals, int64_t n, void* scratch, size_t 
  * Section 3.4 applied to an order image of the keys: a signed integer of
  * the same width whose order is the order asked for (unsigned: the sign bit
  * flipped; floats: the magnitude bits of negative values flipped;
- * descending: the image complemented), formed in place before the sort and
- * undone after it.  The bucket rule reads that image (unsigned keys keep
+ * descending: the image complemented), taken where the partition reads
+ * the keys and undone where each bucket's final output is written (no
+ * extra pass over the array).  The bucket rule reads that image (unsigned
+ * keys keep
  * their value: u = k, no bias; the bounds left in scratch are the image's).
  * Scratch: hsort_sort_scratch_bytes(key_type, vals != NULL, n) bytes.
  * Unknown key_type or flags: HSORT_ERR_INVALID at once. */
@@ -177,9 +179,11 @@ const char* hsort_last_error(void);
  * finer splitter with the same order, so bucket b of the ten is buckets
  * 10b .. 10b+9 of the hundred; smaller buckets need fewer merge rounds)
  * or 3 (one thousand buckets, floor(u / 10^(D-3)), the digits of a shorter u
- * followed by zeros; plain int32 keys-only sorts only, kind
- * HSORT_KEYS_I32, and with it the uint32/float32 sorts of hsort_sort; its
- * partition tiles hold 16384 keys instead of 4096).  The exported bounds are
+ * followed by zeros; plain 32-bit sorts only, kinds HSORT_KEYS_I32 and
+ * HSORT_PAIRS_I32_U32, and with them the uint32/float32 sorts of
+ * hsort_sort; keys-only partition tiles then hold 16384 keys instead of
+ * 4096, and a bucket whose digits fix one key value is copied, not
+ * sorted).  The exported bounds are
  * the ten-bucket bounds in every case.  local = the
  * local sort: 0 (a register network, merges across lanes, then merge levels
  * in LDS) or 1 (the non-recursive merge sort of Figure 1b: each thread sorts

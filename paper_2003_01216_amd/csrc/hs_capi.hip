@@ -450,6 +450,10 @@ int enqueue_body(int kind, K* keys, uint32_t* vals, int64_t n, const int64_t* of
     char* scr = (char*)scratch;
     Work<K> w = make_work<K>(L, scr, keys, vals, off, n, nseg, c, small_max, seg ? max_seg_len : 0);
     w.ufix = (img & kImgUnsigned) ? 1 : 0;
+    // a full sort applies the order image where the partition reads the keys
+    // and undoes it where each bucket's final output is written; the debug
+    // stage runs image the whole array before and after (enqueue)
+    w.img = stage == 3 ? img : 0;
     const double kb = sizeof(K) + (PAIRS ? 4.0 : 0.0);
     {
         Timer t(st, "setup", 0);
@@ -553,18 +557,21 @@ int enqueue_body(int kind, K* keys, uint32_t* vals, int64_t n, const int64_t* of
     return HSORT_OK;
 }
 
-// Keys of other types (img != 0, plain sorts only) are turned into their
-// order image in place before the pipeline and back after it.
+// Keys of other types (img != 0, plain sorts only): a full sort maps them to
+// their order image inside the kernels (where the partition reads the keys,
+// and back where each bucket's final output is written); the debug stage
+// runs map the whole array in place before and after the pipeline.
 template <typename K, bool PAIRS>
 int enqueue(int kind, K* keys, uint32_t* vals, int64_t n, const int64_t* off, int64_t nseg, int64_t max_seg_len,
             void* scratch, size_t scratch_bytes, hipStream_t st, int stage, int64_t small_override, int img = 0) {
-    if (img) {
+    const bool passes = img && stage != 3;  // debug stage runs: separate image passes
+    if (passes) {
         Timer t(st, "image", 2.0 * sizeof(K) * n);
         HS_TRY(launch_image<K>(keys, n, img, false, st));
     }
     const int rc = enqueue_body<K, PAIRS>(kind, keys, vals, n, off, nseg, max_seg_len, scratch, scratch_bytes, st,
                                           stage, small_override, img);
-    if (rc == HSORT_OK && img) {
+    if (rc == HSORT_OK && passes) {
         Timer t(st, "image", 2.0 * sizeof(K) * n);
         HS_TRY(launch_image<K>(keys, n, img, true, st));
     }

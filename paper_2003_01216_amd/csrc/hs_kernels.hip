@@ -45,6 +45,36 @@ struct WordOf<int64_t, true> {
     using type = W128;
 };
 
+// Keys of other types are sorted through a signed-integer image of the same
+// width whose order is the order asked for (the same order-preserving maps
+// the oracle writes out from each type's definition):
+//   unsigned: flip the sign bit (x + type minimum);
+//   IEEE-754 float: flip the magnitude bits of negative values (the
+//     standard's total order: -NaN < -inf < ... < -0 < +0 < ... < +NaN);
+//   descending: the bitwise complement of the image (-1 - image).
+// A sort applies the forward map where the partition reads the caller's keys
+// and the inverse where a bucket's final output is written (k_image does
+// either in place over a whole array, for the debug stage runs).
+template <typename K>
+__device__ __forceinline__ K image_of(K x, int mode, bool inverse) {
+    constexpr K sign = Traits<K>::kMin;
+    if (inverse && (mode & kImgDesc)) x = ~x;
+    if (mode & kImgUnsigned) x ^= sign;
+    if (mode & kImgFloat) x ^= (x >> (8 * sizeof(K) - 1)) & ~sign;  // arithmetic shift: all ones when negative
+    if (!inverse && (mode & kImgDesc)) x = ~x;
+    return x;
+}
+
+// The forward and inverse maps of a call's mode (0: keys are their own image).
+template <typename K>
+__device__ __forceinline__ K img_in(const Work<K>& w, K x) {
+    return w.img ? image_of(x, w.img, false) : x;
+}
+template <typename K>
+__device__ __forceinline__ K img_out(const Work<K>& w, K x) {
+    return w.img ? image_of(x, w.img, true) : x;
+}
+
 template <typename K, bool PAIRS>
 __device__ __forceinline__ typename WordOf<K, PAIRS>::type make_word(K k, int q) {
     if constexpr (PAIRS)
@@ -393,6 +423,10 @@ __global__ __launch_bounds__(HT / kHistVT) void k_range(Work<K> w) {
             ks[v] = q < cnt ? src[q] : k0;  // k0 leaves the min and max unchanged
         }
     }
+    if (w.img) {
+#pragma unroll
+        for (int v = 0; v < VT; v++) ks[v] = image_of(ks[v], w.img, false);
+    }
     K mn = ks[0], mx = ks[0];
 #pragma unroll
     for (int v = 1; v < VT; v++) {
@@ -518,7 +552,7 @@ __global__ __launch_bounds__(kHistNT) void k_hist(Work<K> w, int64_t tiles_bound
             if constexpr (NBK == 10) {
                 uint64_t c = 0;  // a thread sees at most 16 + 3 + 3 keys: fits the 5-bit fields
                 load_run<K, kHistNT, kHistTile>(w.keys + td.base, td.cnt,
-                                                [&](int, K k) { c += 1ull << (5 * digit_of(pl, k)); });
+                                                [&](int, K k) { c += 1ull << (5 * digit_of(pl, img_in(w, k))); });
                 uint32_t wd[5];
                 unpack5(c, wd);
                 block_sum5<kHistNT>(wd, red);
@@ -529,7 +563,7 @@ __global__ __launch_bounds__(kHistNT) void k_hist(Work<K> w, int64_t tiles_bound
                 // one atomic per run of equal buckets, as in k_range
                 uint32_t rb = 0, rn = 0;
                 load_run<K, kHistNT, HT>(w.keys + td.base, td.cnt, [&](int, K k) {
-                    const uint32_t b = (uint32_t)bucket_of<NBK>(pl, k);
+                    const uint32_t b = (uint32_t)bucket_of<NBK>(pl, img_in(w, k));
                     if (b != rb) {
                         if (rn) atomicAdd(&h[rb], rn);
                         rb = b;
@@ -779,7 +813,7 @@ __global__ __launch_bounds__(kHistNT) void k_scatter(Work<K> w) {
         }
     }
     // 1. load in natural order (16-byte body)
-    load_run<K, NT, HT>(w.keys + base, cnt, [&](int q, K k) { sk[lds_pad<K>(q)] = k; });
+    load_run<K, NT, HT>(w.keys + base, cnt, [&](int q, K k) { sk[lds_pad<K>(q)] = img_in(w, k); });
     if constexpr (PAIRS) load_run<uint32_t, NT, HT>(w.vals + base, cnt, [&](int q, uint32_t v) { sv[q] = v; });
     if constexpr (NBK == 10) {
         if (tid < 10) dbase[tid] = (int32_t)(td.seg_base + gp[0]);
@@ -940,6 +974,10 @@ __global__ __launch_bounds__(ScatterShape<NBK>::NT) void k_scatter_keys(Work<K> 
             ks[v] = q < cnt ? src[q] : src[0];
         }
     }
+    if (w.img) {
+#pragma unroll
+        for (int v = 0; v < VT; v++) ks[v] = image_of(ks[v], w.img, false);
+    }
     // the tile's start of each bucket: exclusive scan of its counts (its
     // barriers order the flag's reset before the writes of 1)
     if (tid == 0) heavy = 0;
@@ -1022,7 +1060,8 @@ __global__ void k_sdesc(Work<K> w, int64_t bound) {
         d.cnt = (int)min((int64_t)w.tile, size - i * w.tile);
         const int32_t br = w.brounds[j];
         // bit 1: an odd run of its group; bit 2: a bucket of one key value
-        d.odd = (bucket_rounds(br) & 1) | (int)(i & 1) << 1 | ((br & kConstBucket) ? 4 : 0);
+        d.odd = (bucket_rounds(br) & 1) | (int)(i & 1) << 1 | ((br & kConstBucket) ? 4 : 0) |
+                (bucket_rounds(br) == 0 ? 8 : 0);
         d.bucket = j;
         d.sbase = (int32_t)(sample_base(w.bstart[j], w.msp[j]) + i * w.tile / kSampleBlock);
     }
@@ -1071,7 +1110,11 @@ __global__ __launch_bounds__(NT) void k_tilesort(Work<K> w) {
             // the bucket's keys all share one value: the scatter left them
             // (and their payload, in input order) as the sort would; copy
             // them to the caller's buffer (no merge round follows)
-            copy_run<K, NT>(dk, srck, cnt);
+            if (w.img) {
+                for (int q = tid; q < cnt; q += NT) dk[q] = image_of(srck[q], w.img, true);
+            } else {
+                copy_run<K, NT>(dk, srck, cnt);
+            }
             if constexpr (PAIRS) copy_run<uint32_t, NT>(dv, srcv, cnt);
             return;
         }
@@ -1100,7 +1143,10 @@ __global__ __launch_bounds__(NT) void k_tilesort(Work<K> w) {
                 __syncthreads();
                 block_sort<NW, NT, VT, BU>(wn, sp, cnt);
                 auto key_at = [&](int q) { return (K)((U)(lds_at_padded(wn, q) >> POS) + base); };
-                store_keys<K, NT, NV>(dk, cnt, key_at);
+                if (sd.odd & 8)
+                    store_keys<K, NT, NV>(dk, cnt, [&](int q) { return img_out(w, key_at(q)); });
+                else
+                    store_keys<K, NT, NV>(dk, cnt, key_at);
                 store_run<uint32_t, NT, NV>(
                     dv, cnt, [&](int q) { return sv[(uint32_t)lds_at_padded(wn, q) & ((1u << POS) - 1)]; });
                 if (w.fanin == 4) store_block_samples<K, NT>(w, sd.sbase, cnt, !(sd.odd & 2), key_at);
@@ -1115,7 +1161,10 @@ __global__ __launch_bounds__(NT) void k_tilesort(Work<K> w) {
         __syncthreads();
         block_sort<W, NT, VT, BU>(words, sp, cnt);
         auto key_at = [&](int q) { return word_key<K, PAIRS>(lds_at_padded(words, q)); };
-        store_keys<K, NT, NV>(dk, cnt, key_at);
+        if (sd.odd & 8)
+            store_keys<K, NT, NV>(dk, cnt, [&](int q) { return img_out(w, key_at(q)); });
+        else
+            store_keys<K, NT, NV>(dk, cnt, key_at);
         if constexpr (PAIRS)
             store_run<uint32_t, NT, NV>(dv, cnt, [&](int q) { return sv[pair_pos(lds_at_padded(words, q))]; });
         if (w.fanin == 4) store_block_samples<K, NT>(w, sd.sbase, cnt, !(sd.odd & 2), key_at);
@@ -1159,7 +1208,7 @@ __global__ __launch_bounds__(256) void k_partition(Work<K> w, int pass, int64_t 
             d.a = base + cs;
             d.b = base + L + (diag - cs);
             d.out = w.bstart[j] + o;
-            d.flags = kActive | (odd ? kFromScratch : 0);
+            d.flags = kActive | (odd ? kFromScratch : 0) | (pass + 1 == P ? kLastPass : 0);
             if (o + NV >= min(ps + 2 * L, size)) {
                 d.flags |= kLastChunk;
                 d.a_end = base + a_len;
@@ -1231,7 +1280,11 @@ __global__ __launch_bounds__(NT) void k_merge(Work<K> w, int64_t bound) {
             if (q < c) words[lds_pad<W>(tid * VT + q)] = v[q];
     }
     __syncthreads();
-    store_keys<K, NT, NV>(dk, tot, [&](int q) { return word_key<K, PAIRS>(lds_at_padded(words, q)); });
+    const bool out = (md.flags & kLastPass) && w.img;
+    store_keys<K, NT, NV>(dk, tot, [&](int q) {
+        const K k = word_key<K, PAIRS>(lds_at_padded(words, q));
+        return out ? image_of(k, w.img, true) : k;
+    });
     if constexpr (PAIRS)
         store_run<uint32_t, NT, NV>(dv, tot, [&](int q) { return sv[pair_pos(lds_at_padded(words, q))]; });
 }
@@ -1357,6 +1410,7 @@ struct Chunk4 {
     uint32_t* dv;
     K* sf;         // block samples of the group's output (first keys), or null in the bucket's last round
     K* sl;         // last keys of full blocks
+    bool fin;      // the bucket's last round: the output is final (order images undone)
     int64_t rank;  // group position of the chunk's first output (outputs start blocks where rank + q is a multiple of 32)
 };
 
@@ -1394,6 +1448,7 @@ __device__ __forceinline__ Chunk4<K> chunk4_of(const Work<K>& w, int round, int6
     g.dv = PAIRS ? (odd ? w.vals : w.svals) + r0.base + r0.rank : nullptr;
     g.rank = r0.rank;
     g.sf = (r0.flags & kLastRound) ? nullptr : w.smpf + r0.sbase;
+    g.fin = (r0.flags & kLastRound) != 0;
     g.sl = (r0.flags & kOddGroup) ? nullptr : w.smpl + r0.sbase;
     // window r at logical at[r] (>= 1; body vectors on multiples of 4), then
     // VT sentinels and VT + 4 spare words (room for X' and Y' rounded down
@@ -1607,16 +1662,29 @@ __global__ __launch_bounds__(NT) void k_merge4(Work<K> w, int round, int64_t bou
             stage4<U>(words, sm.sv, ld, g,
                       [=](int q, K k) { return ((U)((U)k - (U)kmin) << kNarrowPosBits) | (U)q; });
             __syncthreads();
+            const bool out = g.fin && w.img;
+            const int mode = w.img;
             merge4_chunk<U, K, PAIRS, NT, VT, JOBS>(
-                words, sm.sv, g, [=](U x) { return (K)((U)kmin + (x >> kNarrowPosBits)); },
+                words, sm.sv, g,
+                [=](U x) {
+                    const K k = (K)((U)kmin + (x >> kNarrowPosBits));
+                    return out ? image_of(k, mode, true) : k;
+                },
                 [](U x) { return (uint32_t)x & ((1u << kNarrowPosBits) - 1); });
             return;
         }
     }
     stage4<W>(sm.words, sm.sv, ld, g, [](int q, K k) { return make_word<K, PAIRS>(k, q); });
     __syncthreads();
-    merge4_chunk<W, K, PAIRS, NT, VT, JOBS>(sm.words, sm.sv, g, [](W x) { return word_key<K, PAIRS>(x); },
-                                           [](W x) { return pair_pos(x); });
+    const bool out = g.fin && w.img;
+    const int mode = w.img;
+    merge4_chunk<W, K, PAIRS, NT, VT, JOBS>(
+        sm.words, sm.sv, g,
+        [=](W x) {
+            const K k = word_key<K, PAIRS>(x);
+            return out ? image_of(k, mode, true) : k;
+        },
+        [](W x) { return pair_pos(x); });
 }
 
 // --------------------------------------------------------- small segments
@@ -1643,16 +1711,18 @@ __global__ __launch_bounds__(NT) void k_small(Work<K> w, int64_t lo, int64_t hi)
         if (!(m64 > lo && m64 <= hi)) return;
         const int m = (int)m64;
         if (m > 1) {
-            load_run<K, NT, NV>(w.keys + a, m, [&](int q, K k) { words[lds_pad<W>(q)] = make_word<K, PAIRS>(k, q); });
+            load_run<K, NT, NV>(w.keys + a, m,
+                                [&](int q, K k) { words[lds_pad<W>(q)] = make_word<K, PAIRS>(img_in(w, k), q); });
             if constexpr (PAIRS) load_run<uint32_t, NT, NV>(w.vals + a, m, [&](int q, uint32_t x) { sv[q] = x; });
             for (int q = m + tid; q < NV; q += NT) words[lds_pad<W>(q)] = WordMax<W>::v;
             __syncthreads();
             block_sort<W, NT, VT>(words, sp, m);
-            store_keys<K, NT, NV>(w.keys + a, m, [&](int q) { return word_key<K, PAIRS>(lds_at_padded(words, q)); });
+            store_keys<K, NT, NV>(w.keys + a, m,
+                                  [&](int q) { return img_out(w, word_key<K, PAIRS>(lds_at_padded(words, q))); });
             if constexpr (PAIRS)
                 store_run<uint32_t, NT, NV>(w.vals + a, m, [&](int q) { return sv[pair_pos(lds_at_padded(words, q))]; });
         } else {
-            if (tid == 0 && m == 1) words[lds_pad<W>(0)] = make_word<K, PAIRS>(w.keys[a], 0);
+            if (tid == 0 && m == 1) words[lds_pad<W>(0)] = make_word<K, PAIRS>(img_in(w, w.keys[a]), 0);
             __syncthreads();
         }
         // bucket bounds of the segment, from its sorted keys
@@ -1702,25 +1772,6 @@ __global__ void k_collect(Work<K> w, int stage) {
 }
 
 // ------------------------------------------------------- other key types
-// Keys of other types are sorted through a signed-integer image of the same
-// width whose order is the order asked for (the same order-preserving maps
-// the oracle writes out from each type's definition):
-//   unsigned: flip the sign bit (x + type minimum);
-//   IEEE-754 float: flip the magnitude bits of negative values (the
-//     standard's total order: -NaN < -inf < ... < -0 < +0 < ... < +NaN);
-//   descending: the bitwise complement of the image (-1 - image).
-// Forward before the pipeline, inverse after it, in place; both are
-// involutions of the caller's bits.
-template <typename K>
-__device__ __forceinline__ K image_of(K x, int mode, bool inverse) {
-    constexpr K sign = Traits<K>::kMin;
-    if (inverse && (mode & kImgDesc)) x = ~x;
-    if (mode & kImgUnsigned) x ^= sign;
-    if (mode & kImgFloat) x ^= (x >> (8 * sizeof(K) - 1)) & ~sign;  // arithmetic shift: all ones when negative
-    if (!inverse && (mode & kImgDesc)) x = ~x;
-    return x;
-}
-
 template <typename K>
 __global__ __launch_bounds__(256) void k_image(K* keys, int64_t n, int mode, int inverse) {
     using V = typename Vec16<K>::type;

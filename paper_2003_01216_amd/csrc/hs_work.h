@@ -57,7 +57,8 @@ struct SortDesc {
     int64_t start;   // first key
     int32_t cnt;     // keys (0: no work)
     int32_t odd;     // bit 0: write to the scratch copy (odd number of merge rounds); bit 1: odd partition;
-                     // bit 2: the bucket's keys all share one value (copied, not sorted)
+                     // bit 2: the bucket's keys all share one value (copied, not sorted);
+                     // bit 3: no merge round follows (this is the bucket's final output)
     int32_t bucket;  // nbk * segment + bucket of the segment
     int32_t sbase;   // sample index of the partition's first 32-key block
 };
@@ -74,6 +75,7 @@ struct MergeDesc {
 constexpr int32_t kActive = 1;     // the chunk has work this round
 constexpr int32_t kFromScratch = 2;  // source is the scratch copy
 constexpr int32_t kLastChunk = 4;  // last chunk of its pair of runs
+constexpr int32_t kLastPass = 8;   // the bucket's last merge round (its output is final)
 
 // Fan-in-4 merge rounds: a split point of a group of four runs R0..R3 (the
 // first `rank` outputs of the group's stable merge are R0[0..s0), R1[0..s1),
@@ -166,6 +168,8 @@ struct Work {
     int32_t nbk;        // buckets per segment: 10 (one decimal digit), 100 (two) or 1000 (three)
     int32_t ptile;      // keys per partition tile (PartShape<nbk>::HT)
     int32_t ufix;       // keys are images of unsigned keys: beta fixed at the type's minimum
+    int32_t img;        // order-image mode of the caller's keys (kImg* bits, 0: none): applied where the
+                        // partition reads them, undone where a bucket's final output is written
     int32_t tile;       // keys per local-sort tile (T)
     int32_t fanin;      // runs merged per round: 2 or 4
     int32_t nv;         // outputs per merge workgroup (divides T)
