@@ -469,7 +469,7 @@ int enqueue_body(int kind, K* keys, uint32_t* vals, int64_t n, const int64_t* of
         }
         return HSORT_OK;
     }
-    {
+    if (seg) {  // a plain sort's one segment was counted by the setup
         Timer t(st, "scan", 0);
         HS_TRY(launch_scan_i32(ScanSpec{nullptr, 0, nseg}, nseg, w.tilecnt, w.tilepre, (int32_t*)(scr + L.part32), st));
         HS_TRY(launch_scan_i32(ScanSpec{nullptr, 0, nseg}, nseg, w.groupcnt, w.grouppre, (int32_t*)(scr + L.part32), st));
@@ -490,18 +490,27 @@ int enqueue_body(int kind, K* keys, uint32_t* vals, int64_t n, const int64_t* of
             Timer t(st, "hist", 0);
             HS_TRY(launch_hist<K>(w, L.tiles_bound, st));
         }
-        {
+        if (!seg && cdiv(n, L.ptile) <= kGroupTiles) {
+            // one group of partition tiles: offsets and bucket table in one
+            // workgroup
             Timer t(st, "scan", 0);
-            HS_TRY(launch_colsum<K>(w, L.groups_bound, st));
-            HS_TRY(launch_scan_u32_i64(ScanSpec{w.grouppre + nseg, w.nbk, 0}, w.nbk * L.groups_bound, w.gsum, w.gpos,
-                                       (int64_t*)(scr + L.part64), st));
-            HS_TRY(launch_gbase<K>(w, L.groups_bound, st));
-        }
-        {
-            Timer t(st, "btab", 0);
-            HS_TRY(launch_btab<K>(w, st));
-            HS_TRY(launch_scan_i32(ScanSpec{nullptr, 0, L.buckets}, L.buckets, w.tsc, w.tsp, (int32_t*)(scr + L.part32), st));
-            HS_TRY(launch_scan_i32(ScanSpec{nullptr, 0, L.buckets}, L.buckets, w.mcc, w.msp, (int32_t*)(scr + L.part32), st));
+            HS_TRY(launch_offsets1<K>(w, st));
+        } else {
+            {
+                Timer t(st, "scan", 0);
+                HS_TRY(launch_colsum<K>(w, L.groups_bound, st));
+                HS_TRY(launch_scan_u32_i64(ScanSpec{w.grouppre + nseg, w.nbk, 0}, w.nbk * L.groups_bound, w.gsum,
+                                           w.gpos, (int64_t*)(scr + L.part64), st));
+                HS_TRY(launch_gbase<K>(w, L.groups_bound, st));
+            }
+            {
+                Timer t(st, "btab", 0);
+                HS_TRY(launch_btab<K>(w, st));
+                HS_TRY(launch_scan_i32(ScanSpec{nullptr, 0, L.buckets}, L.buckets, w.tsc, w.tsp,
+                                       (int32_t*)(scr + L.part32), st));
+                HS_TRY(launch_scan_i32(ScanSpec{nullptr, 0, L.buckets}, L.buckets, w.mcc, w.msp,
+                                       (int32_t*)(scr + L.part32), st));
+            }
         }
         {
             Timer t(st, "sdesc", 0);

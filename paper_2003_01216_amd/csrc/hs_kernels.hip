@@ -65,14 +65,31 @@ __device__ __forceinline__ K image_of(K x, int mode, bool inverse) {
     return x;
 }
 
-// The forward and inverse maps of a call's mode (0: keys are their own image).
+// The forward map of a call's mode on one key (0: keys are their own image).
 template <typename K>
 __device__ __forceinline__ K img_in(const Work<K>& w, K x) {
     return w.img ? image_of(x, w.img, false) : x;
 }
-template <typename K>
-__device__ __forceinline__ K img_out(const Work<K>& w, K x) {
-    return w.img ? image_of(x, w.img, true) : x;
+
+// load_run of the caller's keys, f(q, image): with mode != 0 the forward
+// map is taken on each key; the mode is tested once, not per key.
+template <typename K, int NT, int CAP, typename F>
+__device__ __forceinline__ void load_keys_imaged(const K* src, int cnt, int mode, F&& f) {
+    if (mode)
+        load_run<K, NT, CAP>(src, cnt, [&](int q, K k) { f(q, image_of(k, mode, false)); });
+    else
+        load_run<K, NT, CAP>(src, cnt, f);
+}
+
+// A run of outputs from LDS to memory: keys by key_of, or by key_fin
+// (the order image undone) when `fin`; the choice is made once per run,
+// so the plain store carries no per-key test.
+template <typename K, int NT, int CAP, typename KeyOf, typename KeyFin>
+__device__ __forceinline__ void store_chunk_keys(K* dst, int c, bool fin, KeyOf&& key_of, KeyFin&& key_fin) {
+    if (fin)
+        store_keys<K, NT, CAP>(dst, c, key_fin);
+    else
+        store_keys<K, NT, CAP>(dst, c, key_of);
 }
 
 template <typename K, bool PAIRS>
@@ -308,9 +325,20 @@ __global__ void k_init(Work<K> w, int64_t* own_off) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         *w.err = 0;
         *w.rounds = 0;
-        if (own_off) {  // a plain sort is one segment [0, n)
+        if (own_off) {
+            // a plain sort is one segment [0, n): its offsets, partition-tile
+            // and group counts and their prefixes are known here (what
+            // k_classify and the two scans after it give a segmented call)
             own_off[0] = 0;
             own_off[1] = w.n;
+            const int32_t nt = w.n > w.small_max ? (int32_t)((w.n + w.ptile - 1) / w.ptile) : 0;
+            const int32_t ng = (nt + kGroupTiles - 1) / kGroupTiles;
+            w.tilecnt[0] = nt;
+            w.groupcnt[0] = ng;
+            w.tilepre[0] = 0;
+            w.tilepre[1] = nt;
+            w.grouppre[0] = 0;
+            w.grouppre[1] = ng;
         }
     }
 }
@@ -551,8 +579,8 @@ __global__ __launch_bounds__(kHistNT) void k_hist(Work<K> w, int64_t tiles_bound
             const DigitPlan<K> pl = w.plans[td.seg];
             if constexpr (NBK == 10) {
                 uint64_t c = 0;  // a thread sees at most 16 + 3 + 3 keys: fits the 5-bit fields
-                load_run<K, kHistNT, kHistTile>(w.keys + td.base, td.cnt,
-                                                [&](int, K k) { c += 1ull << (5 * digit_of(pl, img_in(w, k))); });
+                load_keys_imaged<K, kHistNT, kHistTile>(w.keys + td.base, td.cnt, w.img,
+                                                        [&](int, K k) { c += 1ull << (5 * digit_of(pl, k)); });
                 uint32_t wd[5];
                 unpack5(c, wd);
                 block_sum5<kHistNT>(wd, red);
@@ -562,8 +590,8 @@ __global__ __launch_bounds__(kHistNT) void k_hist(Work<K> w, int64_t tiles_bound
                 __syncthreads();
                 // one atomic per run of equal buckets, as in k_range
                 uint32_t rb = 0, rn = 0;
-                load_run<K, kHistNT, HT>(w.keys + td.base, td.cnt, [&](int, K k) {
-                    const uint32_t b = (uint32_t)bucket_of<NBK>(pl, img_in(w, k));
+                load_keys_imaged<K, kHistNT, HT>(w.keys + td.base, td.cnt, w.img, [&](int, K k) {
+                    const uint32_t b = (uint32_t)bucket_of<NBK>(pl, k);
                     if (b != rb) {
                         if (rn) atomicAdd(&h[rb], rn);
                         rb = b;
@@ -635,15 +663,37 @@ __global__ void k_gbase(Work<K> w, int64_t bound) {
     w.gbase[e] = (int32_t)(w.gpos[base + (int64_t)b * w.groupcnt[s] + (g - w.grouppre[s])] - w.gpos[base]);
 }
 
-// Bucket table: start and size of each bucket (ten or one hundred per
-// segment), its local-sort tiles and merge chunks, and the ten-bucket bounds
-// output (with one hundred buckets, bound b is the start of bucket 10b).
+// Bucket table entry j (bucket d of segment s) from the bucket's start st,
+// relative to the segment's first key, and its size sz: start and size, its
+// local-sort tiles and merge chunks, the ten-bucket bounds output (with one
+// hundred or one thousand buckets, bound b is the start of bucket nbk/10*b)
+// and its merge rounds, which it returns.
+template <typename K>
+__device__ __forceinline__ int btab_entry(const Work<K>& w, int64_t j, int s, int d, int64_t st, int64_t sz) {
+    const int nbk = w.nbk;
+    const int per = nbk / 10;  // buckets per ten-bucket bound
+    const int64_t a = w.off[s];
+    w.bstart[j] = a + st;
+    w.bsize[j] = sz;
+    w.tsc[j] = (int32_t)((sz + w.tile - 1) / w.tile);
+    w.mcc[j] = (int32_t)((sz + w.nv - 1) / w.nv);
+    if (d % per == 0) w.bounds_out[11 * (int64_t)s + d / per] = st;
+    if (d == 0) w.bounds_out[11 * (int64_t)s + 10] = w.off[s + 1] - a;
+    // a bucket that spans one key value is in order after the scatter
+    uint64_t lo, width;
+    bucket_span(w.plans[s], nbk, d, lo, width);
+    const bool one = width == 1;
+    const int r = one ? 0 : merge_rounds(sz, w.tile, w.fanin);
+    w.brounds[j] = r | (one ? kConstBucket : 0);
+    return r;
+}
+
+// Bucket table: btab_entry for every bucket of every segment.
 template <typename K>
 __global__ void k_btab(Work<K> w) {
     if (*w.err) return;
     // one thread per bucket of every segment
     const int nbk = w.nbk;
-    const int per = nbk / 10;  // buckets per ten-bucket bound
     const int64_t nbt = (int64_t)nbk * w.nseg;
     for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < nbt; j += (int64_t)gridDim.x * blockDim.x) {
         const int s = (int)(j / nbk), d = (int)(j - (int64_t)s * nbk);
@@ -663,20 +713,59 @@ __global__ void k_btab(Work<K> w) {
         const int64_t p0 = w.gpos[base];
         const int64_t st = w.gpos[base + (int64_t)d * ng] - p0;
         const int64_t en = w.gpos[base + (int64_t)(d + 1) * ng] - p0;
-        const int64_t sz = en - st;
-        w.bstart[j] = a + st;
-        w.bsize[j] = sz;
-        w.tsc[j] = (int32_t)((sz + w.tile - 1) / w.tile);
-        w.mcc[j] = (int32_t)((sz + w.nv - 1) / w.nv);
-        if (d % per == 0) w.bounds_out[11 * (int64_t)s + d / per] = st;
-        if (d == 0) w.bounds_out[11 * (int64_t)s + 10] = w.off[s + 1] - a;
-        // a bucket that spans one key value is in order after the scatter
-        uint64_t lo, width;
-        bucket_span(w.plans[s], nbk, d, lo, width);
-        const bool one = width == 1;
-        const int r = one ? 0 : merge_rounds(sz, w.tile, w.fanin);
-        w.brounds[j] = r | (one ? kConstBucket : 0);
+        const int r = btab_entry(w, j, s, d, st, en - st);
         if (r > 0) atomicMax(w.rounds, r);
+    }
+}
+
+// A plain sort whose partition tiles form one group (at most kGroupTiles
+// tiles, so every start fits 32 bits): k_colsum, the scan of the group
+// sums, k_gbase, k_btab and the scans of the tile and chunk counts in one
+// workgroup, one thread per bucket.  Such an array waits on the chain of
+// launches, not on this work.
+template <typename K, int NBK>
+__global__ __launch_bounds__(kColNT<NBK>) void k_offsets1(Work<K> w) {
+    constexpr int NT = kColNT<NBK>;
+    __shared__ int32_t red[NT / kWave];
+    if (*w.err) return;
+    const int b = threadIdx.x;
+    const int nt = w.tilecnt[0];
+    // the bucket's column of counts: each tile's in-group prefix, its size
+    int32_t run = 0;
+    if (b < NBK) {
+        const uint32_t* src = w.counts + b;
+        uint32_t* dst = w.intra + b;
+        for (int i0 = 0; i0 < nt; i0 += 8) {  // eight loads in flight before their stores
+            uint32_t c[8];
+#pragma unroll
+            for (int j = 0; j < 8; j++) c[j] = i0 + j < nt ? src[NBK * (i0 + j)] : 0u;
+#pragma unroll
+            for (int j = 0; j < 8; j++) {
+                if (i0 + j < nt) dst[NBK * (i0 + j)] = (uint32_t)run;
+                run += (int32_t)c[j];
+            }
+        }
+    }
+    int32_t all;
+    const int32_t st = block_excl_scan<int32_t, NT>(run, all, red);
+    int32_t tsc = 0, mcc = 0;
+    if (b < NBK) {
+        w.gbase[b] = st;
+        const int r = btab_entry(w, b, 0, b, st, run);
+        if (r > 0) atomicMax(w.rounds, r);
+        tsc = w.tsc[b];
+        mcc = w.mcc[b];
+    }
+    int32_t ttot, mtot;
+    const int32_t tp = block_excl_scan<int32_t, NT>(tsc, ttot, red);
+    const int32_t mp = block_excl_scan<int32_t, NT>(mcc, mtot, red);
+    if (b < NBK) {
+        w.tsp[b] = tp;
+        w.msp[b] = mp;
+    }
+    if (b == 0) {
+        w.tsp[NBK] = ttot;
+        w.msp[NBK] = mtot;
     }
 }
 
@@ -813,7 +902,7 @@ __global__ __launch_bounds__(kHistNT) void k_scatter(Work<K> w) {
         }
     }
     // 1. load in natural order (16-byte body)
-    load_run<K, NT, HT>(w.keys + base, cnt, [&](int q, K k) { sk[lds_pad<K>(q)] = img_in(w, k); });
+    load_run<K, NT, HT>(w.keys + base, cnt, [&](int q, K k) { sk[lds_pad<K>(q)] = k; });
     if constexpr (PAIRS) load_run<uint32_t, NT, HT>(w.vals + base, cnt, [&](int q, uint32_t v) { sv[q] = v; });
     if constexpr (NBK == 10) {
         if (tid < 10) dbase[tid] = (int32_t)(td.seg_base + gp[0]);
@@ -832,6 +921,13 @@ __global__ __launch_bounds__(kHistNT) void k_scatter(Work<K> w) {
         }
     }
     __syncthreads();
+    if (w.img) {
+        // order images taken in LDS, after the load: the plain load keeps
+        // its code
+        const int mode = w.img;
+        for (int q = tid; q < cnt; q += NT) sk[lds_pad<K>(q)] = image_of(sk[lds_pad<K>(q)], mode, false);
+        __syncthreads();
+    }
     uint32_t tot[5];
     auto passes = [&](auto full) {
         constexpr bool F = decltype(full)::value;
@@ -1106,6 +1202,10 @@ __global__ __launch_bounds__(NT) void k_tilesort(Work<K> w) {
         uint32_t* dv = PAIRS ? ((sd.odd & 1) ? w.svals : w.vals) + start : nullptr;
         const K* srck = w.skeys + start;
         const uint32_t* srcv = PAIRS ? w.svals + start : nullptr;
+        // the bucket's output is final (no merge round follows) and the keys
+        // are order images: undo the image as they are stored
+        const int mode = w.img;
+        const bool fin = (sd.odd & 8) && mode != 0;
         if (sd.odd & 4) {
             // the bucket's keys all share one value: the scatter left them
             // (and their payload, in input order) as the sort would; copy
@@ -1143,10 +1243,8 @@ __global__ __launch_bounds__(NT) void k_tilesort(Work<K> w) {
                 __syncthreads();
                 block_sort<NW, NT, VT, BU>(wn, sp, cnt);
                 auto key_at = [&](int q) { return (K)((U)(lds_at_padded(wn, q) >> POS) + base); };
-                if (sd.odd & 8)
-                    store_keys<K, NT, NV>(dk, cnt, [&](int q) { return img_out(w, key_at(q)); });
-                else
-                    store_keys<K, NT, NV>(dk, cnt, key_at);
+                store_chunk_keys<K, NT, NV>(dk, cnt, fin, key_at,
+                                            [&](int q) { return image_of(key_at(q), mode, true); });
                 store_run<uint32_t, NT, NV>(
                     dv, cnt, [&](int q) { return sv[(uint32_t)lds_at_padded(wn, q) & ((1u << POS) - 1)]; });
                 if (w.fanin == 4) store_block_samples<K, NT>(w, sd.sbase, cnt, !(sd.odd & 2), key_at);
@@ -1161,10 +1259,7 @@ __global__ __launch_bounds__(NT) void k_tilesort(Work<K> w) {
         __syncthreads();
         block_sort<W, NT, VT, BU>(words, sp, cnt);
         auto key_at = [&](int q) { return word_key<K, PAIRS>(lds_at_padded(words, q)); };
-        if (sd.odd & 8)
-            store_keys<K, NT, NV>(dk, cnt, [&](int q) { return img_out(w, key_at(q)); });
-        else
-            store_keys<K, NT, NV>(dk, cnt, key_at);
+        store_chunk_keys<K, NT, NV>(dk, cnt, fin, key_at, [&](int q) { return image_of(key_at(q), mode, true); });
         if constexpr (PAIRS)
             store_run<uint32_t, NT, NV>(dv, cnt, [&](int q) { return sv[pair_pos(lds_at_padded(words, q))]; });
         if (w.fanin == 4) store_block_samples<K, NT>(w, sd.sbase, cnt, !(sd.odd & 2), key_at);
@@ -1280,11 +1375,11 @@ __global__ __launch_bounds__(NT) void k_merge(Work<K> w, int64_t bound) {
             if (q < c) words[lds_pad<W>(tid * VT + q)] = v[q];
     }
     __syncthreads();
-    const bool out = (md.flags & kLastPass) && w.img;
-    store_keys<K, NT, NV>(dk, tot, [&](int q) {
-        const K k = word_key<K, PAIRS>(lds_at_padded(words, q));
-        return out ? image_of(k, w.img, true) : k;
-    });
+    const int mode = w.img;
+    store_chunk_keys<K, NT, NV>(
+        dk, tot, (md.flags & kLastPass) && mode != 0,
+        [&](int q) { return word_key<K, PAIRS>(lds_at_padded(words, q)); },
+        [&](int q) { return image_of(word_key<K, PAIRS>(lds_at_padded(words, q)), mode, true); });
     if constexpr (PAIRS)
         store_run<uint32_t, NT, NV>(dv, tot, [&](int q) { return sv[pair_pos(lds_at_padded(words, q))]; });
 }
@@ -1530,11 +1625,13 @@ __device__ __forceinline__ void store_chunk_samples(const Chunk4<K>& g, int c, K
 }
 
 // The two merge levels and the store, on windows staged in LDS (the caller
-// has synchronised after stage4).  Ends with the LDS free for reuse only
-// after the caller's next barrier.
-template <typename W, typename K, bool PAIRS, int NT, int VT, int JOBS, typename KeyOf, typename PosOf>
-__device__ __forceinline__ void merge4_chunk(W* words, const uint32_t* sv, const Chunk4<K>& g, KeyOf&& key_of,
-                                             PosOf&& pos_of) {
+// has synchronised after stage4).  key_of turns a word into its key,
+// key_fin into the caller's key (the order image undone) when `fin`.  Ends
+// with the LDS free for reuse only after the caller's next barrier.
+template <typename W, typename K, bool PAIRS, int NT, int VT, int JOBS, typename KeyOf, typename KeyFin,
+          typename PosOf>
+__device__ __forceinline__ void merge4_chunk(W* words, const uint32_t* sv, const Chunk4<K>& g, bool fin,
+                                             KeyOf&& key_of, KeyFin&& key_fin, PosOf&& pos_of) {
     constexpr int S = NT * VT * JOBS / 2;
     constexpr int CAP = 2 * S;
     const W wmax = WordMax<W>::v;
@@ -1577,7 +1674,9 @@ __device__ __forceinline__ void merge4_chunk(W* words, const uint32_t* sv, const
     }
     if (o2 == 0 || o2 == c) {  // one side empty (a group short of four runs): X' or Y' is the result
         const int r = o2 == 0 ? y0 : x0;
-        store_keys<K, NT, CAP>(g.dk, c, [&](int q) { return key_of(lds_at_padded(words, r + q)); });
+        store_chunk_keys<K, NT, CAP>(
+            g.dk, c, fin, [&](int q) { return key_of(lds_at_padded(words, r + q)); },
+            [&](int q) { return key_fin(lds_at_padded(words, r + q)); });
         if constexpr (PAIRS)
             store_run<uint32_t, NT, CAP>(g.dv, c, [&](int q) { return sv[pos_of(lds_at_padded(words, r + q))]; });
         store_chunk_samples<NT>(g, c, [&](int q) { return key_of(lds_at_padded(words, r + q)); });
@@ -1608,7 +1707,9 @@ __device__ __forceinline__ void merge4_chunk(W* words, const uint32_t* sv, const
         }
         __syncthreads();
     }
-    store_keys<K, NT, CAP>(g.dk, c, [&](int q) { return key_of(lds_at_padded(words, q)); });
+    store_chunk_keys<K, NT, CAP>(
+        g.dk, c, fin, [&](int q) { return key_of(lds_at_padded(words, q)); },
+        [&](int q) { return key_fin(lds_at_padded(words, q)); });
     if constexpr (PAIRS)
         store_run<uint32_t, NT, CAP>(g.dv, c, [&](int q) { return sv[pos_of(lds_at_padded(words, q))]; });
     store_chunk_samples<NT>(g, c, [&](int q) { return key_of(lds_at_padded(words, q)); });
@@ -1662,29 +1763,20 @@ __global__ __launch_bounds__(NT) void k_merge4(Work<K> w, int round, int64_t bou
             stage4<U>(words, sm.sv, ld, g,
                       [=](int q, K k) { return ((U)((U)k - (U)kmin) << kNarrowPosBits) | (U)q; });
             __syncthreads();
-            const bool out = g.fin && w.img;
             const int mode = w.img;
             merge4_chunk<U, K, PAIRS, NT, VT, JOBS>(
-                words, sm.sv, g,
-                [=](U x) {
-                    const K k = (K)((U)kmin + (x >> kNarrowPosBits));
-                    return out ? image_of(k, mode, true) : k;
-                },
+                words, sm.sv, g, g.fin && mode != 0, [=](U x) { return (K)((U)kmin + (x >> kNarrowPosBits)); },
+                [=](U x) { return image_of((K)((U)kmin + (x >> kNarrowPosBits)), mode, true); },
                 [](U x) { return (uint32_t)x & ((1u << kNarrowPosBits) - 1); });
             return;
         }
     }
     stage4<W>(sm.words, sm.sv, ld, g, [](int q, K k) { return make_word<K, PAIRS>(k, q); });
     __syncthreads();
-    const bool out = g.fin && w.img;
     const int mode = w.img;
     merge4_chunk<W, K, PAIRS, NT, VT, JOBS>(
-        sm.words, sm.sv, g,
-        [=](W x) {
-            const K k = word_key<K, PAIRS>(x);
-            return out ? image_of(k, mode, true) : k;
-        },
-        [](W x) { return pair_pos(x); });
+        sm.words, sm.sv, g, g.fin && mode != 0, [](W x) { return word_key<K, PAIRS>(x); },
+        [=](W x) { return image_of(word_key<K, PAIRS>(x), mode, true); }, [](W x) { return pair_pos(x); });
 }
 
 // --------------------------------------------------------- small segments
@@ -1711,14 +1803,16 @@ __global__ __launch_bounds__(NT) void k_small(Work<K> w, int64_t lo, int64_t hi)
         if (!(m64 > lo && m64 <= hi)) return;
         const int m = (int)m64;
         if (m > 1) {
-            load_run<K, NT, NV>(w.keys + a, m,
-                                [&](int q, K k) { words[lds_pad<W>(q)] = make_word<K, PAIRS>(img_in(w, k), q); });
+            load_keys_imaged<K, NT, NV>(w.keys + a, m, w.img,
+                                        [&](int q, K k) { words[lds_pad<W>(q)] = make_word<K, PAIRS>(k, q); });
             if constexpr (PAIRS) load_run<uint32_t, NT, NV>(w.vals + a, m, [&](int q, uint32_t x) { sv[q] = x; });
             for (int q = m + tid; q < NV; q += NT) words[lds_pad<W>(q)] = WordMax<W>::v;
             __syncthreads();
             block_sort<W, NT, VT>(words, sp, m);
-            store_keys<K, NT, NV>(w.keys + a, m,
-                                  [&](int q) { return img_out(w, word_key<K, PAIRS>(lds_at_padded(words, q))); });
+            const int mode = w.img;
+            store_chunk_keys<K, NT, NV>(
+                w.keys + a, m, mode != 0, [&](int q) { return word_key<K, PAIRS>(lds_at_padded(words, q)); },
+                [&](int q) { return image_of(word_key<K, PAIRS>(lds_at_padded(words, q)), mode, true); });
             if constexpr (PAIRS)
                 store_run<uint32_t, NT, NV>(w.vals + a, m, [&](int q) { return sv[pair_pos(lds_at_padded(words, q))]; });
         } else {
@@ -1979,7 +2073,8 @@ template <typename K>
 hipError_t launch_setup(const Work<K>& w, int64_t* own_off, hipStream_t st) {
     const int g = (int)min((int64_t)1024, (int64_t)cdiv64(w.nseg, 256));
     k_init<K><<<1, 64, 0, st>>>(w, own_off);
-    k_classify<K><<<g < 1 ? 1 : g, 256, 0, st>>>(w);
+    // a plain sort (own_off) gets its one segment's counts from k_init
+    if (!own_off) k_classify<K><<<g < 1 ? 1 : g, 256, 0, st>>>(w);
     return hipGetLastError();
 }
 
@@ -2043,6 +2138,18 @@ hipError_t launch_colsum(const Work<K>& w, int64_t groups_bound, hipStream_t st)
     else
         k_colsum<10><<<g, kColNT<10>, 0, st>>>(w.tilepre, w.tilecnt, w.grouppre, w.groupcnt, w.nseg, w.err, w.counts,
                                        w.intra, w.gsum);
+    return hipGetLastError();
+}
+
+template <typename K>
+hipError_t launch_offsets1(const Work<K>& w, hipStream_t st) {
+    if (w.nbk == 1000) {
+        k_offsets1<K, 1000><<<1, kColNT<1000>, 0, st>>>(w);
+    } else if (w.nbk == 100) {
+        k_offsets1<K, 100><<<1, kColNT<100>, 0, st>>>(w);
+    } else {
+        k_offsets1<K, 10><<<1, kColNT<10>, 0, st>>>(w);
+    }
     return hipGetLastError();
 }
 
@@ -2159,6 +2266,7 @@ hipError_t launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t st
     template hipError_t launch_btab<K>(const Work<K>&, hipStream_t);                     \
     template hipError_t launch_colsum<K>(const Work<K>&, int64_t, hipStream_t);          \
     template hipError_t launch_gbase<K>(const Work<K>&, int64_t, hipStream_t);           \
+    template hipError_t launch_offsets1<K>(const Work<K>&, hipStream_t);                 \
     template hipError_t launch_partition<K>(const Work<K>&, int, int64_t, hipStream_t);  \
     template hipError_t launch_tiles<K>(const Work<K>&, int64_t, hipStream_t);           \
     template hipError_t launch_sdesc<K>(const Work<K>&, int64_t, hipStream_t);           \

@@ -62,6 +62,10 @@ template <typename K>
 hipError_t launch_btab(const Work<K>& w, hipStream_t st);
 template <typename K>
 hipError_t launch_colsum(const Work<K>& w, int64_t groups_bound, hipStream_t st);
+// A plain sort whose partition tiles form one group: the bucket offsets,
+// the bucket table and the scans of its tile and chunk counts in one launch.
+template <typename K>
+hipError_t launch_offsets1(const Work<K>& w, hipStream_t st);
 template <typename K>
 hipError_t launch_gbase(const Work<K>& w, int64_t groups_bound, hipStream_t st);
 template <typename K, bool PAIRS>
