@@ -457,7 +457,7 @@ int enqueue_body(int kind, K* keys, uint32_t* vals, int64_t n, const int64_t* of
     const double kb = sizeof(K) + (PAIRS ? 4.0 : 0.0);
     {
         Timer t(st, "setup", 0);
-        HS_TRY(launch_setup<K>(w, seg ? nullptr : (int64_t*)(scr + L.own_off), st));
+        HS_TRY(launch_setup<K>(w, seg ? nullptr : (int64_t*)(scr + L.own_off), L.tiles_bound, st));
     }
     const bool any_large = seg ? (n > small_max) : (n > small_max);
     if (!seg && !any_large) {  // a plain sort that fits one tile
@@ -475,7 +475,7 @@ int enqueue_body(int kind, K* keys, uint32_t* vals, int64_t n, const int64_t* of
         HS_TRY(launch_scan_i32(ScanSpec{nullptr, 0, nseg}, nseg, w.groupcnt, w.grouppre, (int32_t*)(scr + L.part32), st));
     }
     if (any_large) {
-        {
+        if (seg) {  // a plain sort's tile list was written by the setup
             Timer t(st, "tiles", 0);
             HS_TRY(launch_tiles<K>(w, L.tiles_bound, st));
         }
@@ -490,11 +490,12 @@ int enqueue_body(int kind, K* keys, uint32_t* vals, int64_t n, const int64_t* of
             Timer t(st, "hist", 0);
             HS_TRY(launch_hist<K>(w, L.tiles_bound, st));
         }
-        if (!seg && cdiv(n, L.ptile) <= kGroupTiles) {
-            // one group of partition tiles: offsets and bucket table in one
-            // workgroup
+        const bool one_group = !seg && cdiv(n, L.ptile) <= kGroupTiles;
+        if (one_group) {
+            // one group of partition tiles: offsets, bucket table and the
+            // local-sort descriptors in one workgroup
             Timer t(st, "scan", 0);
-            HS_TRY(launch_offsets1<K>(w, st));
+            HS_TRY(launch_offsets1<K>(w, L.ts_bound, st));
         } else {
             {
                 Timer t(st, "scan", 0);
@@ -512,7 +513,7 @@ int enqueue_body(int kind, K* keys, uint32_t* vals, int64_t n, const int64_t* of
                                        (int32_t*)(scr + L.part32), st));
             }
         }
-        {
+        if (!one_group) {
             Timer t(st, "sdesc", 0);
             HS_TRY(launch_sdesc<K>(w, L.ts_bound, st));
         }

@@ -321,7 +321,25 @@ __device__ __forceinline__ void block_sort(W* words, int* sp, int cnt) {
 // ------------------------------------------------------------- setup kernels
 // own_off: where a plain sort's one-segment offsets live (w.off points there).
 template <typename K>
-__global__ void k_init(Work<K> w, int64_t* own_off) {
+__global__ void k_init(Work<K> w, int64_t* own_off, int64_t tiles_bound) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (own_off && t < tiles_bound) {
+        // a plain sort's partition-tile list (what k_tiles gives a segmented
+        // call): tile t covers [t * ptile, min(n, (t + 1) * ptile))
+        const int32_t nt = w.n > w.small_max ? (int32_t)((w.n + w.ptile - 1) / w.ptile) : 0;
+        TileDesc d{0, 0, 0, 0, 0, 0, 0, 0};
+        if (t < nt) {
+            d.base = t * w.ptile;
+            d.seg_base = 0;
+            d.cnt = (int)min((int64_t)w.ptile, w.n - d.base);
+            d.seg = 0;
+            d.idx = (int)t;
+            d.nt = nt;
+            d.grp = (int)(t / kGroupTiles);
+            d.pad = 0;
+        }
+        w.tiles[t] = d;
+    }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         *w.err = 0;
         *w.rounds = 0;
@@ -688,6 +706,28 @@ __device__ __forceinline__ int btab_entry(const Work<K>& w, int64_t j, int s, in
     return r;
 }
 
+// Local-sort descriptor `item` (partitions of all buckets in bucket order,
+// then empty slots up to the bound).
+template <typename K>
+__device__ __forceinline__ void sdesc_item(const Work<K>& w, int64_t item) {
+    const int nb = w.nbk * w.nseg;
+    SortDesc d{0, 0, 0, 0, 0};
+    if (!*w.err && item < w.tsp[nb]) {
+        const int j = owner_of(w.tsp, nb, (int)item);
+        const int64_t i = item - w.tsp[j];
+        const int64_t size = w.bsize[j];
+        d.start = w.bstart[j] + i * w.tile;
+        d.cnt = (int)min((int64_t)w.tile, size - i * w.tile);
+        const int32_t br = w.brounds[j];
+        // bit 1: an odd run of its group; bit 2: a bucket of one key value
+        d.odd = (bucket_rounds(br) & 1) | (int)(i & 1) << 1 | ((br & kConstBucket) ? 4 : 0) |
+                (bucket_rounds(br) == 0 ? 8 : 0);
+        d.bucket = j;
+        d.sbase = (int32_t)(sample_base(w.bstart[j], w.msp[j]) + i * w.tile / kSampleBlock);
+    }
+    w.sdesc[item] = d;
+}
+
 // Bucket table: btab_entry for every bucket of every segment.
 template <typename K>
 __global__ void k_btab(Work<K> w) {
@@ -720,15 +760,18 @@ __global__ void k_btab(Work<K> w) {
 
 // A plain sort whose partition tiles form one group (at most kGroupTiles
 // tiles, so every start fits 32 bits): k_colsum, the scan of the group
-// sums, k_gbase, k_btab and the scans of the tile and chunk counts in one
-// workgroup, one thread per bucket.  Such an array waits on the chain of
-// launches, not on this work.
+// sums, k_gbase, k_btab, the scans of the tile and chunk counts and k_sdesc
+// (descriptors 0 .. ts_bound-1) in one workgroup, one thread per bucket.
+// Such an array waits on the chain of launches, not on this work.
 template <typename K, int NBK>
-__global__ __launch_bounds__(kColNT<NBK>) void k_offsets1(Work<K> w) {
+__global__ __launch_bounds__(kColNT<NBK>) void k_offsets1(Work<K> w, int64_t ts_bound) {
     constexpr int NT = kColNT<NBK>;
     __shared__ int32_t red[NT / kWave];
-    if (*w.err) return;
     const int b = threadIdx.x;
+    if (*w.err) {
+        for (int64_t item = b; item < ts_bound; item += NT) w.sdesc[item] = SortDesc{0, 0, 0, 0, 0};
+        return;
+    }
     const int nt = w.tilecnt[0];
     // the bucket's column of counts: each tile's in-group prefix, its size
     int32_t run = 0;
@@ -767,6 +810,10 @@ __global__ __launch_bounds__(kColNT<NBK>) void k_offsets1(Work<K> w) {
         w.tsp[NBK] = ttot;
         w.msp[NBK] = mtot;
     }
+    // the bucket table and its scans, written by every thread above, are
+    // visible to the whole workgroup after the barrier
+    __syncthreads();
+    for (int64_t item = b; item < ts_bound; item += NT) sdesc_item(w, item);
 }
 
 // ---------------------------------------------------------------- scatter
@@ -1145,23 +1192,7 @@ __global__ __launch_bounds__(ScatterShape<NBK>::NT) void k_scatter_keys(Work<K> 
 template <typename K>
 __global__ void k_sdesc(Work<K> w, int64_t bound) {
     const int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (item >= bound) return;
-    const int nb = w.nbk * w.nseg;
-    SortDesc d{0, 0, 0, 0, 0};
-    if (!*w.err && item < w.tsp[nb]) {
-        const int j = owner_of(w.tsp, nb, (int)item);
-        const int64_t i = item - w.tsp[j];
-        const int64_t size = w.bsize[j];
-        d.start = w.bstart[j] + i * w.tile;
-        d.cnt = (int)min((int64_t)w.tile, size - i * w.tile);
-        const int32_t br = w.brounds[j];
-        // bit 1: an odd run of its group; bit 2: a bucket of one key value
-        d.odd = (bucket_rounds(br) & 1) | (int)(i & 1) << 1 | ((br & kConstBucket) ? 4 : 0) |
-                (bucket_rounds(br) == 0 ? 8 : 0);
-        d.bucket = j;
-        d.sbase = (int32_t)(sample_base(w.bstart[j], w.msp[j]) + i * w.tile / kSampleBlock);
-    }
-    w.sdesc[item] = d;
+    if (item < bound) sdesc_item(w, item);
 }
 
 // First and last key of every 32-key block of a sorted partition that starts
@@ -2070,9 +2101,11 @@ static int cu_count() {
 static int grid_of(int64_t items) { return (int)(items < 1 ? 1 : items); }
 
 template <typename K>
-hipError_t launch_setup(const Work<K>& w, int64_t* own_off, hipStream_t st) {
+hipError_t launch_setup(const Work<K>& w, int64_t* own_off, int64_t tiles_bound, hipStream_t st) {
     const int g = (int)min((int64_t)1024, (int64_t)cdiv64(w.nseg, 256));
-    k_init<K><<<1, 64, 0, st>>>(w, own_off);
+    // a plain sort's tile list is written here too (one thread per slot)
+    const int64_t ti = own_off ? tiles_bound : 0;
+    k_init<K><<<ti > 256 ? cdiv64(ti, 256) : 1, 256, 0, st>>>(w, own_off, ti);
     // a plain sort (own_off) gets its one segment's counts from k_init
     if (!own_off) k_classify<K><<<g < 1 ? 1 : g, 256, 0, st>>>(w);
     return hipGetLastError();
@@ -2142,13 +2175,13 @@ hipError_t launch_colsum(const Work<K>& w, int64_t groups_bound, hipStream_t st)
 }
 
 template <typename K>
-hipError_t launch_offsets1(const Work<K>& w, hipStream_t st) {
+hipError_t launch_offsets1(const Work<K>& w, int64_t ts_bound, hipStream_t st) {
     if (w.nbk == 1000) {
-        k_offsets1<K, 1000><<<1, kColNT<1000>, 0, st>>>(w);
+        k_offsets1<K, 1000><<<1, kColNT<1000>, 0, st>>>(w, ts_bound);
     } else if (w.nbk == 100) {
-        k_offsets1<K, 100><<<1, kColNT<100>, 0, st>>>(w);
+        k_offsets1<K, 100><<<1, kColNT<100>, 0, st>>>(w, ts_bound);
     } else {
-        k_offsets1<K, 10><<<1, kColNT<10>, 0, st>>>(w);
+        k_offsets1<K, 10><<<1, kColNT<10>, 0, st>>>(w, ts_bound);
     }
     return hipGetLastError();
 }
@@ -2259,14 +2292,14 @@ hipError_t launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t st
 
 // ---------------------------------------------------- explicit instances
 #define HS_INST_K(K)                                                                 \
-    template hipError_t launch_setup<K>(const Work<K>&, int64_t*, hipStream_t);          \
+    template hipError_t launch_setup<K>(const Work<K>&, int64_t*, int64_t, hipStream_t); \
     template hipError_t launch_range<K>(const Work<K>&, int64_t, hipStream_t);           \
     template hipError_t launch_plans<K>(const Work<K>&, hipStream_t);                    \
     template hipError_t launch_hist<K>(const Work<K>&, int64_t, hipStream_t);            \
     template hipError_t launch_btab<K>(const Work<K>&, hipStream_t);                     \
     template hipError_t launch_colsum<K>(const Work<K>&, int64_t, hipStream_t);          \
     template hipError_t launch_gbase<K>(const Work<K>&, int64_t, hipStream_t);           \
-    template hipError_t launch_offsets1<K>(const Work<K>&, hipStream_t);                 \
+    template hipError_t launch_offsets1<K>(const Work<K>&, int64_t, hipStream_t);        \
     template hipError_t launch_partition<K>(const Work<K>&, int, int64_t, hipStream_t);  \
     template hipError_t launch_tiles<K>(const Work<K>&, int64_t, hipStream_t);           \
     template hipError_t launch_sdesc<K>(const Work<K>&, int64_t, hipStream_t);           \

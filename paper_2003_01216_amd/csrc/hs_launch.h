@@ -51,7 +51,7 @@ struct ScanSpec {
 // Each launcher sizes its own (persistent) grid from an upper bound on the
 // number of work items it can be handed.
 template <typename K>
-hipError_t launch_setup(const Work<K>& w, int64_t* own_off, hipStream_t st);
+hipError_t launch_setup(const Work<K>& w, int64_t* own_off, int64_t tiles_bound, hipStream_t st);
 template <typename K>
 hipError_t launch_range(const Work<K>& w, int64_t tiles_bound, hipStream_t st);
 template <typename K>
@@ -65,7 +65,7 @@ hipError_t launch_colsum(const Work<K>& w, int64_t groups_bound, hipStream_t st)
 // A plain sort whose partition tiles form one group: the bucket offsets,
 // the bucket table and the scans of its tile and chunk counts in one launch.
 template <typename K>
-hipError_t launch_offsets1(const Work<K>& w, hipStream_t st);
+hipError_t launch_offsets1(const Work<K>& w, int64_t ts_bound, hipStream_t st);
 template <typename K>
 hipError_t launch_gbase(const Work<K>& w, int64_t groups_bound, hipStream_t st);
 template <typename K, bool PAIRS>
