@@ -358,7 +358,8 @@ __device__ __forceinline__ void bitonic_merge(W (&v)[VT]) {
 // one exists (0xB1 = lane ^ 1, 0x4E = lane ^ 2, 0x1B = lane ^ 3 within
 // quads, 0x141 = lane ^ 7 within half-rows, 0x140 = lane ^ 15 within rows,
 // 0x128 = lane ^ 8 as a rotation by eight within rows), else a bit-mode
-// swizzle (xor mask within 32 lanes).
+// swizzle (xor mask within 32 lanes); masks that cross the two halves of the
+// wave go through a backward permute.
 template <int MASK>
 __device__ __forceinline__ int lane_xor32(int x) {
     if constexpr (MASK == 1) return __builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, false);
@@ -367,7 +368,8 @@ __device__ __forceinline__ int lane_xor32(int x) {
     else if constexpr (MASK == 7) return __builtin_amdgcn_mov_dpp(x, 0x141, 0xF, 0xF, false);
     else if constexpr (MASK == 15) return __builtin_amdgcn_mov_dpp(x, 0x140, 0xF, 0xF, false);
     else if constexpr (MASK == 8) return __builtin_amdgcn_mov_dpp(x, 0x128, 0xF, 0xF, false);
-    else return __builtin_amdgcn_ds_swizzle(x, 0x1F | (MASK << 10));
+    else if constexpr (MASK < 32) return __builtin_amdgcn_ds_swizzle(x, 0x1F | (MASK << 10));
+    else return __shfl_xor(x, MASK, kWave);
 }
 
 template <int MASK, typename W>
@@ -437,7 +439,7 @@ __device__ __forceinline__ void lane_half_cleaners(W (&v)[VT], int lane) {
 
 template <typename W, int VT, int G>
 __device__ __forceinline__ void lane_merge(W (&v)[VT], int lane) {
-    static_assert(G >= 2 && G <= 32 && (G & (G - 1)) == 0, "groups of 2 to 32 lanes");
+    static_assert(G >= 2 && G <= kWave && (G & (G - 1)) == 0, "groups of 2 to 64 lanes");
     lane_stage<W, VT, G - 1, true>(v, !(lane & (G / 2)));
     lane_half_cleaners<W, VT, G / 4>(v, lane);
     bitonic_merge<W, VT>(v);

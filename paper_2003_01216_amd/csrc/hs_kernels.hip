@@ -266,7 +266,7 @@ __device__ __forceinline__ void block_sort_levels(W* words, int* sp, W (&v)[VT],
 
 // Sorts words[0..NT*VT) (padded layout) ascending in LDS: a register sorting
 // network per thread, merge levels across groups of 2, 4, 8, 16 (and, for
-// 32-bit words, 32) lanes (lane permutations, in registers), then the
+// 32-bit words, 32 and 64) lanes (lane permutations, in registers), then the
 // remaining merge levels in LDS, fully unrolled.  Result in blocked layout
 // (thread t holds outputs t*VT .. t*VT+VT-1, also in LDS).  Slots at or past
 // cnt must hold the largest word: a wave whose slots all lie there has
@@ -280,7 +280,7 @@ __device__ __forceinline__ void block_sort_levels(W* words, int* sp, W (&v)[VT],
 template <typename W, int NT, int VT, bool BU = false>
 __device__ __forceinline__ void block_sort(W* words, int* sp, int cnt) {
     static_assert((128 / (int)sizeof(W)) % VT == 0, "a VT-run must not straddle a pad word");
-    static_assert(NT >= 32, "lane merges need groups of 32 threads");
+    static_assert(NT >= kWave, "lane merges need whole waves");
     const int tid = threadIdx.x;
     const int base = lds_pad<W>(tid * VT);
     W v[VT];
@@ -302,13 +302,17 @@ __device__ __forceinline__ void block_sort(W* words, int* sp, int cnt) {
         lane_merge<W, VT, 4>(v, tid);
         lane_merge<W, VT, 8>(v, tid);
         lane_merge<W, VT, 16>(v, tid);
-        // 32-bit words: a fifth lane level (lane ^ 31 by a swizzle) is
-        // cheaper than the LDS level it replaces; 64-bit words need two
-        // exchanges and a compare-and-select per register, and it is not
-        if constexpr (sizeof(W) == 4) lane_merge<W, VT, 32>(v, tid);
+        // 32-bit words: a fifth and a sixth lane level (lane ^ 31 by a
+        // swizzle, lane ^ 63 by a backward permute) cost about what the LDS
+        // levels they replace do, without their barriers; 64-bit words need
+        // two exchanges and a compare-and-select per register, and they do not
+        if constexpr (sizeof(W) == 4) {
+            lane_merge<W, VT, 32>(v, tid);
+            lane_merge<W, VT, 64>(v, tid);
+        }
     }
     if constexpr (sizeof(W) == 4) {
-        block_sort_levels<W, NT, VT, 32 * VT>(words, sp, v, tid, base, cnt);
+        block_sort_levels<W, NT, VT, kWave * VT>(words, sp, v, tid, base, cnt);
     } else {
         block_sort_levels<W, NT, VT, 16 * VT>(words, sp, v, tid, base, cnt);
     }
