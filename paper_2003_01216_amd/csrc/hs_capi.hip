@@ -179,15 +179,25 @@ struct Timer {
             std::lock_guard<std::mutex> lk(g_mu);
             on = g_timing && !g_capturing;
         }
-        if (on) {
-            hipEventCreate(&a);
-            hipEventCreate(&b);
-            hipEventRecord(a, st);
+        // timing is best effort: a timer whose events cannot be made or
+        // recorded is switched off, and the sort goes on untimed
+        if (on && (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess ||
+                   hipEventRecord(a, st) != hipSuccess)) {
+            drop();
+            on = false;
         }
+    }
+    void drop() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+        a = b = nullptr;
     }
     ~Timer() {
         if (!on) return;
-        hipEventRecord(b, st);
+        if (hipEventRecord(b, st) != hipSuccess) {
+            drop();
+            return;
+        }
         Rec r = deferred;
         r.name = name;
         r.a = a;
@@ -1039,23 +1049,29 @@ int64_t hsort_timing_read(char* out, int64_t cap) {
     std::vector<int32_t> rounds;
     for (Rec& r : recs) {
         float ms = 0;
-        hipEventSynchronize(r.b);
+        // a record whose events cannot be read is left out
+        const bool timed = hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess;
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+        if (!timed) continue;
         if (r.bsize) {
             if (r.bsize != cached_ptr || (int64_t)sizes.size() != r.nb) {
                 sizes.assign((size_t)r.nb, 0);
                 rounds.assign((size_t)r.nb, 0);
-                hipMemcpy(sizes.data(), r.bsize, sizeof(int64_t) * r.nb, hipMemcpyDeviceToHost);
-                hipMemcpy(rounds.data(), r.brounds, sizeof(int32_t) * r.nb, hipMemcpyDeviceToHost);
-                cached_ptr = r.bsize;
+                const bool got =
+                    hipMemcpy(sizes.data(), r.bsize, sizeof(int64_t) * r.nb, hipMemcpyDeviceToHost) == hipSuccess &&
+                    hipMemcpy(rounds.data(), r.brounds, sizeof(int32_t) * r.nb, hipMemcpyDeviceToHost) == hipSuccess;
+                if (!got) {  // bucket sizes unknown: the record keeps its time, with no bytes
+                    sizes.clear();
+                    rounds.clear();
+                }
+                cached_ptr = got ? r.bsize : nullptr;
             }
             double active = 0;
             for (size_t b = 0; b < sizes.size(); b++)
                 if (bucket_rounds(rounds[b]) > r.pass) active += (double)sizes[b];
             r.bytes = r.per_key * active;
         }
-        hipEventElapsedTime(&ms, r.a, r.b);
-        hipEventDestroy(r.a);
-        hipEventDestroy(r.b);
         auto it = std::find_if(agg.begin(), agg.end(), [&](const Agg& a) { return a.name == r.name; });
         if (it == agg.end()) {
             agg.push_back({r.name, 0, 0, 0});
