@@ -10,7 +10,6 @@ three-digit refinements).  No GPU is needed: the functions
 are host-callable and the program launches nothing.
 """
 import os
-import shutil
 import subprocess
 
 import pytest
