@@ -239,13 +239,19 @@ int hsort_graph_mode(int on);
 int hsort_graph_clear(void);
 int64_t hsort_graph_count(void);
 
-/* Per-kernel timing.  While enabled, every kernel launch of the library is
- * bracketed by HIP events recorded on the call's stream.  hsort_timing_read
- * synchronises those events and writes, for each kernel name, the number of
- * launches, the total milliseconds and the algorithmic HBM bytes those
- * launches had to move, as text lines "name launches total_ms bytes"; it
- * returns the number of bytes written (or needed, if cap is too small) and
- * clears the records. */
+/* Per-kernel timing.  While enabled, every group of kernel launches of the
+ * library (a pass: "range", "scatter", "tilesort", one "merge" per round,
+ * ...) is bracketed by HIP events recorded on the call's stream; launches
+ * inside a captured graph (graph mode, or a caller's capture) are not
+ * recorded.  hsort_timing_read synchronises those events and writes, for
+ * each name, the number of launches, the total milliseconds and the
+ * algorithmic HBM bytes those launches had to move (a merge round's from
+ * the keys of the buckets still merging in it), as text lines "name
+ * launches total_ms bytes"; it returns the number of bytes written (or
+ * needed, if cap is too small) and clears the records.  Timing is best
+ * effort and never fails a sort: a pass whose events cannot be created or
+ * read is left out, and a merge round whose bucket table cannot be read
+ * reports zero bytes. */
 int hsort_timing_enable(int on);
 int64_t hsort_timing_read(char* out, int64_t cap);
 
