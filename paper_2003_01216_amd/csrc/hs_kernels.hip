@@ -842,8 +842,6 @@ __device__ __forceinline__ void digit_pass(K* sk, uint32_t* sv, T* sd, uint32_t 
     // 64-bit keys and pairs a resident workgroup, so they select instead
     constexpr bool kOffsLds = sizeof(K) == 4 && !PAIRS;
     const int tid = threadIdx.x;
-    K key[VT];
-    uint32_t val[PAIRS ? VT : 1];
     uint32_t pk[VT];  // tag << 16 | rank << 4 | digit (digit 15 = no key)
     uint32_t tg[VT / TPW];
 #pragma unroll
@@ -865,10 +863,8 @@ __device__ __forceinline__ void digit_pass(K* sk, uint32_t* sv, T* sd, uint32_t 
         const int q = tid * VT + v;
         const bool ok = FULL || q < cnt;
         const int qq = ok ? q : 0;
-        key[v] = sk[lds_pad<K>(qq)];
-        if constexpr (PAIRS) val[v] = sv[qq];
         constexpr uint32_t kTagMask = sizeof(T) == 1 ? 0xFFu : 0xFFFFu;
-        const uint32_t dt = dig(key[v], (tg[v / TPW] >> (8 * (int)sizeof(T) * (v % TPW))) & kTagMask);
+        const uint32_t dt = dig(sk[lds_pad<K>(qq)], (tg[v / TPW] >> (8 * (int)sizeof(T) * (v % TPW))) & kTagMask);
         const uint32_t d = dt & 15u;
         const uint32_t r = (((uint32_t)(c >> (5 * d)) & 31u) << 4) | d;
         pk[v] = ok ? (((dt >> 8) & kTagMask) << 16) | r : 15u;
@@ -894,6 +890,19 @@ __device__ __forceinline__ void digit_pass(K* sk, uint32_t* sv, T* sd, uint32_t 
             offs[2 * m + 1][tid] = (uint16_t)(wd[m] >> 16);
         }
     }
+    // the thread's keys (and payload) again, read by every thread before any
+    // thread stages its own: holding them in registers across the scan
+    // above cost a resident wave per SIMD
+    K key[VT];
+    uint32_t val[PAIRS ? VT : 1];
+#pragma unroll
+    for (int v = 0; v < VT; v++) {
+        const int q = tid * VT + v;
+        const int qq = (FULL || q < cnt) ? q : 0;
+        key[v] = sk[lds_pad<K>(qq)];
+        if constexpr (PAIRS) val[v] = sv[qq];
+    }
+    __syncthreads();
 #pragma unroll
     for (int v = 0; v < VT; v++) {
         const uint32_t d = pk[v] & 15u;
@@ -918,7 +927,7 @@ __device__ __forceinline__ void digit_pass(K* sk, uint32_t* sv, T* sd, uint32_t 
 // with it in a byte (16-bit word for one thousand buckets), so each key's
 // bucket is computed once.
 template <typename K, bool PAIRS, int NBK>
-__global__ __launch_bounds__(kHistNT) void k_scatter(Work<K> w) {
+__global__ __launch_bounds__(kHistNT, (PAIRS && NBK >= 100 && sizeof(K) == 4) ? 3 : 1) void k_scatter(Work<K> w) {
     static_assert(NBK == 10 || NBK == 100 || NBK == 1000, "ten, one hundred or one thousand buckets");
     constexpr int NT = kHistNT, VT = kHistVT, HT = kHistTile;
     constexpr int BPT = (NBK + NT - 1) / NT;  // buckets per thread for the counts scan
