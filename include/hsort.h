@@ -190,8 +190,10 @@ const char* hsort_last_error(void);
  * its tile_vt keys -- pairs when tile_vt = 2 -- and every merge level runs
  * bottom up in LDS).  merge_nv must
  * divide tile.  Only compiled shapes are accepted (HSORT_ERR_UNSUPPORTED
- * otherwise).  kind: any hsort_kind (the two segmented kinds share the
- * table of their key type).  Size classes 0..3 hold calls whose deciding
+ * otherwise).  kind: any hsort_kind; every kind has rows of its own (a
+ * segmented kind is tuned apart from the plain sort of its key type, accepts
+ * that key type's compiled shapes, and at most two digits).  Size classes
+ * 0..3 hold calls whose deciding
  * size -- n, or max_seg_len of a segmented call when given -- is at most
  * 2^18, 2^22, 2^26, or larger (hsort_size_class(n) maps a size to its
  * class); size_cls = -1 sets every class.  The table is process-wide, and

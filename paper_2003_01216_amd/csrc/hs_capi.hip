@@ -38,7 +38,7 @@ struct Config {
 
 std::mutex g_mu;
 // [kind][size class], kind as hsort_kind (0 int32 keys, 1 int64 keys,
-// 2 int32 pairs, 3 segmented int32, 4 segmented int64); size class by the
+// 2 int32 pairs, 3 segmented int32, 4 segmented int64, 5 int64 pairs); size class by the
 // number of keys that decides the merge depth (n for a plain sort, the
 // longest segment for a segmented one when the caller gives it).
 constexpr int kKinds = 6;
