@@ -74,7 +74,7 @@ def test_keys(hs, orc, dt, desc, n):
 
 @pytest.mark.parametrize("desc", [False, True], ids=["asc", "desc"])
 @pytest.mark.parametrize("dt", DTYPES, ids=lambda d: np.dtype(d).name)
-@pytest.mark.parametrize("n", [3, 5000, 300_007])
+@pytest.mark.parametrize("n", [3, 5000, 200_003, 300_007])
 def test_pairs(hs, orc, dt, desc, n):
     k = W.typed_keys(dt, n, n + 11)
     v = np.arange(n, dtype=np.uint32)
