@@ -1618,8 +1618,15 @@ struct Merge4Lds {
     static constexpr int CAP = 2 * S;
     static constexpr int LOGICAL = CAP + 8 * VT + 32;  // four windows, sentinels, spacing, alignment
     static_assert((128 / sizeof(W)) % VT == 0, "a VT block fits one pad period");
+    // int32 pairs stage the payload after the narrow words, in the part of
+    // `words` that 32-bit sort words leave free, and wide chunks read it
+    // from the source windows instead: no separate payload array, a quarter
+    // less LDS per workgroup.  int64 pairs keep one.
+    static constexpr bool kLdsVals = PAIRS && sizeof(K) == 8;
+    static constexpr int kNarrowWords = lds_padded_size<typename Traits<K>::U>(LOGICAL);
     W words[lds_padded_size<W>(LOGICAL)];
-    uint32_t sv[PAIRS ? CAP : 1];
+    uint32_t sv[kLdsVals ? CAP : 1];
+    static_assert(!PAIRS || kLdsVals || (kNarrowWords + CAP) * 4 <= (int)sizeof(words), "payload fits after the narrow words");
 };
 
 template <typename K, bool PAIRS, int NT, int VT, int JOBS>
@@ -1642,7 +1649,9 @@ __device__ __forceinline__ void stage4(W* words, uint32_t* sv, const Merge4Loads
                                        const Chunk4<K>& g, MK&& mk) {
     const int tid = threadIdx.x;
     ld.keys.commit_padded(words, mk);
-    if constexpr (PAIRS) ld.vals.commit_dense(sv);
+    if constexpr (PAIRS) {
+        if (sv) ld.vals.commit_dense(sv);  // null: the payload is read from the windows at the store
+    }
     if (tid < 4 * VT) {
         const int r = tid / VT;
         int p = g.at[0] + g.c[0];
@@ -1670,12 +1679,14 @@ __device__ __forceinline__ void store_chunk_samples(const Chunk4<K>& g, int c, K
 
 // The two merge levels and the store, on windows staged in LDS (the caller
 // has synchronised after stage4).  key_of turns a word into its key,
-// key_fin into the caller's key (the order image undone) when `fin`.  Ends
-// with the LDS free for reuse only after the caller's next barrier.
+// key_fin into the caller's key (the order image undone) when `fin`,
+// pos_of into its index in the concatenated windows, and val_at that index
+// into its payload.  Ends with the LDS free for reuse only after the
+// caller's next barrier.
 template <typename W, typename K, bool PAIRS, int NT, int VT, int JOBS, typename KeyOf, typename KeyFin,
-          typename PosOf>
-__device__ __forceinline__ void merge4_chunk(W* words, const uint32_t* sv, const Chunk4<K>& g, bool fin,
-                                             KeyOf&& key_of, KeyFin&& key_fin, PosOf&& pos_of) {
+          typename PosOf, typename ValAt>
+__device__ __forceinline__ void merge4_chunk(W* words, const Chunk4<K>& g, bool fin, KeyOf&& key_of,
+                                             KeyFin&& key_fin, PosOf&& pos_of, ValAt&& val_at) {
     constexpr int S = NT * VT * JOBS / 2;
     constexpr int CAP = 2 * S;
     const W wmax = WordMax<W>::v;
@@ -1722,7 +1733,7 @@ __device__ __forceinline__ void merge4_chunk(W* words, const uint32_t* sv, const
             g.dk, c, fin, [&](int q) { return key_of(lds_at_padded(words, r + q)); },
             [&](int q) { return key_fin(lds_at_padded(words, r + q)); });
         if constexpr (PAIRS)
-            store_run<uint32_t, NT, CAP>(g.dv, c, [&](int q) { return sv[pos_of(lds_at_padded(words, r + q))]; });
+            store_run<uint32_t, NT, CAP>(g.dv, c, [&](int q) { return val_at(pos_of(lds_at_padded(words, r + q))); });
         store_chunk_samples<NT>(g, c, [&](int q) { return key_of(lds_at_padded(words, r + q)); });
         return;
     }
@@ -1755,7 +1766,7 @@ __device__ __forceinline__ void merge4_chunk(W* words, const uint32_t* sv, const
         g.dk, c, fin, [&](int q) { return key_of(lds_at_padded(words, q)); },
         [&](int q) { return key_fin(lds_at_padded(words, q)); });
     if constexpr (PAIRS)
-        store_run<uint32_t, NT, CAP>(g.dv, c, [&](int q) { return sv[pos_of(lds_at_padded(words, q))]; });
+        store_run<uint32_t, NT, CAP>(g.dv, c, [&](int q) { return val_at(pos_of(lds_at_padded(words, q))); });
     store_chunk_samples<NT>(g, c, [&](int q) { return key_of(lds_at_padded(words, q)); });
 }
 
@@ -1797,6 +1808,7 @@ __global__ __launch_bounds__(NT) void k_merge4(Work<K> w, int round, int64_t bou
     if (!g.active) return;
     Merge4Loads<K, PAIRS, NT, VT, JOBS> ld;
     ld.issue(g);
+    using L = Merge4Lds<K, PAIRS, NT, VT, JOBS>;
     if constexpr (PAIRS) {
         using U = typename Traits<K>::U;
         static_assert(NT * VT * JOBS <= (1 << kNarrowPosBits), "window indices fit the narrow word");
@@ -1804,23 +1816,45 @@ __global__ __launch_bounds__(NT) void k_merge4(Work<K> w, int round, int64_t bou
         const bool narrow = narrow_chunk(g, kmin);  // the same on every lane
         if (narrow) {
             U* words = reinterpret_cast<U*>(sm.words);
-            stage4<U>(words, sm.sv, ld, g,
+            uint32_t* sv = L::kLdsVals ? sm.sv : reinterpret_cast<uint32_t*>(sm.words) + L::kNarrowWords;
+            stage4<U>(words, sv, ld, g,
                       [=](int q, K k) { return ((U)((U)k - (U)kmin) << kNarrowPosBits) | (U)q; });
             __syncthreads();
             const int mode = w.img;
             merge4_chunk<U, K, PAIRS, NT, VT, JOBS>(
-                words, sm.sv, g, g.fin && mode != 0, [=](U x) { return (K)((U)kmin + (x >> kNarrowPosBits)); },
+                words, g, g.fin && mode != 0, [=](U x) { return (K)((U)kmin + (x >> kNarrowPosBits)); },
                 [=](U x) { return image_of((K)((U)kmin + (x >> kNarrowPosBits)), mode, true); },
-                [](U x) { return (uint32_t)x & ((1u << kNarrowPosBits) - 1); });
+                [](U x) { return (uint32_t)x & ((1u << kNarrowPosBits) - 1); }, [=](uint32_t p) { return sv[p]; });
             return;
         }
     }
-    stage4<W>(sm.words, sm.sv, ld, g, [](int q, K k) { return make_word<K, PAIRS>(k, q); });
+    stage4<W>(sm.words, L::kLdsVals ? sm.sv : nullptr, ld, g, [](int q, K k) { return make_word<K, PAIRS>(k, q); });
     __syncthreads();
     const int mode = w.img;
+    // the payload of window index p: from LDS, or for int32 pairs with wide
+    // words straight from its source window (p lies in window r when
+    // o_r <= p < o_(r+1), o_r the windows' prefix of lengths)
+    const int o1 = g.c[0], o2 = o1 + g.c[1], o3 = o2 + g.c[2];
+    const uint32_t *v0 = g.vs[0], *v1 = g.vs[1], *v2 = g.vs[2], *v3 = g.vs[3];
+    const uint32_t* lv = sm.sv;
+    auto val_at = [=](uint32_t p) -> uint32_t {  // by value: a reference would keep g in scratch memory
+        if constexpr (L::kLdsVals) {
+            return lv[p];
+        } else {
+            // selects of the four candidate addresses (a chain of pointer
+            // assignments becomes a lookup table in scratch memory)
+            const int q = (int)p;
+            uint64_t a = (uint64_t)(v0 + q);
+            a = q >= o1 ? (uint64_t)(v1 + (q - o1)) : a;
+            a = q >= o2 ? (uint64_t)(v2 + (q - o2)) : a;
+            a = q >= o3 ? (uint64_t)(v3 + (q - o3)) : a;
+            asm volatile("" : "+v"(a));
+            return *global_at<uint32_t>((uintptr_t)a);
+        }
+    };
     merge4_chunk<W, K, PAIRS, NT, VT, JOBS>(
-        sm.words, sm.sv, g, g.fin && mode != 0, [](W x) { return word_key<K, PAIRS>(x); },
-        [=](W x) { return image_of(word_key<K, PAIRS>(x), mode, true); }, [](W x) { return pair_pos(x); });
+        sm.words, g, g.fin && mode != 0, [](W x) { return word_key<K, PAIRS>(x); },
+        [=](W x) { return image_of(word_key<K, PAIRS>(x), mode, true); }, [](W x) { return pair_pos(x); }, val_at);
 }
 
 // --------------------------------------------------------- small segments
