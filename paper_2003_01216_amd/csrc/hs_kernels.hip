@@ -1618,15 +1618,14 @@ struct Merge4Lds {
     static constexpr int CAP = 2 * S;
     static constexpr int LOGICAL = CAP + 8 * VT + 32;  // four windows, sentinels, spacing, alignment
     static_assert((128 / sizeof(W)) % VT == 0, "a VT block fits one pad period");
-    // int32 pairs stage the payload after the narrow words, in the part of
-    // `words` that 32-bit sort words leave free, and wide chunks read it
-    // from the source windows instead: no separate payload array, a quarter
-    // less LDS per workgroup.  int64 pairs keep one.
-    static constexpr bool kLdsVals = PAIRS && sizeof(K) == 8;
-    static constexpr int kNarrowWords = lds_padded_size<typename Traits<K>::U>(LOGICAL);
+    // Pairs stage the payload after the narrow words, in the half of `words`
+    // that narrow sort words (the key's width) leave free, and wide chunks
+    // read it from the source windows instead: no separate payload array.
+    using U = typename Traits<K>::U;
+    static constexpr int kNarrowWords = lds_padded_size<U>(LOGICAL);
     W words[lds_padded_size<W>(LOGICAL)];
-    uint32_t sv[kLdsVals ? CAP : 1];
-    static_assert(!PAIRS || kLdsVals || (kNarrowWords + CAP) * 4 <= (int)sizeof(words), "payload fits after the narrow words");
+    static_assert(!PAIRS || kNarrowWords * (int)sizeof(U) + CAP * 4 <= (int)sizeof(words),
+                  "payload fits after the narrow words");
 };
 
 template <typename K, bool PAIRS, int NT, int VT, int JOBS>
@@ -1816,7 +1815,7 @@ __global__ __launch_bounds__(NT) void k_merge4(Work<K> w, int round, int64_t bou
         const bool narrow = narrow_chunk(g, kmin);  // the same on every lane
         if (narrow) {
             U* words = reinterpret_cast<U*>(sm.words);
-            uint32_t* sv = L::kLdsVals ? sm.sv : reinterpret_cast<uint32_t*>(sm.words) + L::kNarrowWords;
+            uint32_t* sv = reinterpret_cast<uint32_t*>(reinterpret_cast<U*>(sm.words) + L::kNarrowWords);
             stage4<U>(words, sv, ld, g,
                       [=](int q, K k) { return ((U)((U)k - (U)kmin) << kNarrowPosBits) | (U)q; });
             __syncthreads();
@@ -1828,29 +1827,25 @@ __global__ __launch_bounds__(NT) void k_merge4(Work<K> w, int round, int64_t bou
             return;
         }
     }
-    stage4<W>(sm.words, L::kLdsVals ? sm.sv : nullptr, ld, g, [](int q, K k) { return make_word<K, PAIRS>(k, q); });
+    stage4<W>(sm.words, nullptr, ld, g, [](int q, K k) { return make_word<K, PAIRS>(k, q); });
     __syncthreads();
     const int mode = w.img;
-    // the payload of window index p: from LDS, or for int32 pairs with wide
-    // words straight from its source window (p lies in window r when
-    // o_r <= p < o_(r+1), o_r the windows' prefix of lengths)
+    // wide words: the payload of window index p straight from its source
+    // window (p lies in window r when o_r <= p < o_(r+1), o_r the windows'
+    // prefix of lengths); captured by value, since a reference would keep g
+    // in scratch memory, and chosen by selects of the four candidate
+    // addresses, which a chain of pointer assignments would turn into a
+    // lookup table there
     const int o1 = g.c[0], o2 = o1 + g.c[1], o3 = o2 + g.c[2];
     const uint32_t *v0 = g.vs[0], *v1 = g.vs[1], *v2 = g.vs[2], *v3 = g.vs[3];
-    const uint32_t* lv = sm.sv;
-    auto val_at = [=](uint32_t p) -> uint32_t {  // by value: a reference would keep g in scratch memory
-        if constexpr (L::kLdsVals) {
-            return lv[p];
-        } else {
-            // selects of the four candidate addresses (a chain of pointer
-            // assignments becomes a lookup table in scratch memory)
-            const int q = (int)p;
-            uint64_t a = (uint64_t)(v0 + q);
-            a = q >= o1 ? (uint64_t)(v1 + (q - o1)) : a;
-            a = q >= o2 ? (uint64_t)(v2 + (q - o2)) : a;
-            a = q >= o3 ? (uint64_t)(v3 + (q - o3)) : a;
-            asm volatile("" : "+v"(a));
-            return *global_at<uint32_t>((uintptr_t)a);
-        }
+    auto val_at = [=](uint32_t p) -> uint32_t {
+        const int q = (int)p;
+        uint64_t a = (uint64_t)(v0 + q);
+        a = q >= o1 ? (uint64_t)(v1 + (q - o1)) : a;
+        a = q >= o2 ? (uint64_t)(v2 + (q - o2)) : a;
+        a = q >= o3 ? (uint64_t)(v3 + (q - o3)) : a;
+        asm volatile("" : "+v"(a));
+        return *global_at<uint32_t>((uintptr_t)a);
     };
     merge4_chunk<W, K, PAIRS, NT, VT, JOBS>(
         sm.words, g, g.fin && mode != 0, [](W x) { return word_key<K, PAIRS>(x); },
